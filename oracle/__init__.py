@@ -1,0 +1,270 @@
+"""Oracle: plain binary64 CPU reference of the MPM step, its adjoint and the
+learned-field network.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The solver never
+imports it and the two share no code: this package and the HIP library are
+independent implementations of the same equations.
+
+``build()`` compiles ``mpm_oracle.c`` (and the adjoint) with gcc into
+``liborc.so`` beside this file; ``lib()`` loads it.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["mpm_oracle.c", "mpm_oracle_adjoint.c"]
+LIB_PATH = os.path.join(HERE, "liborc.so")
+
+ORC_FLUID, ORC_DP_HENCKY, ORC_HENCKY_ELASTIC = 0, 1, 2
+_MAT = {"fluid": ORC_FLUID, "sand": ORC_DP_HENCKY, "elastic": ORC_HENCKY_ELASTIC}
+_WALL = {"slip": 0, "stick": 1, "coulomb": 2}
+
+
+def build(opt: str = "-O2", extra=()) -> str:
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    cmd = ["gcc", opt, "-ffp-contract=off", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC",
+           "-shared", *extra, *srcs, "-o", LIB_PATH + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OrcConfig(ct.Structure):
+    _fields_ = [
+        ("dim", ct.c_int32), ("n", ct.c_int32 * 3), ("ghost", ct.c_int32),
+        ("tile", ct.c_int32), ("material", ct.c_int32), ("key_f32", ct.c_int32),
+        ("wall_mode", ct.c_int32 * 6),
+        ("dx", ct.c_double), ("gravity", ct.c_double * 3), ("wall_mu", ct.c_double * 6),
+        ("rho0", ct.c_double), ("bulk", ct.c_double), ("gamma", ct.c_double),
+        ("youngs", ct.c_double), ("poisson", ct.c_double), ("phi_deg", ct.c_double),
+        ("vol0", ct.c_double), ("mass", ct.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = ct.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def _declare(L):
+    P = ct.c_void_p
+    i64, i32, f64 = ct.c_int64, ct.c_int32, ct.c_double
+    L.orc_phibar.restype = f64
+    L.orc_phibar.argtypes = [f64]
+    L.orc_dphibar.restype = f64
+    L.orc_dphibar.argtypes = [f64]
+    L.orc_stencil_1d.argtypes = [f64, f64, ct.c_int, P, P, P]
+    L.orc_node_dims.restype = i64
+    L.orc_node_dims.argtypes = [P, P]
+    L.orc_num_keys.restype = i64
+    L.orc_num_keys.argtypes = [P]
+    L.orc_cell_keys.argtypes = [P, i64, P, P]
+    L.orc_sort_perm.argtypes = [i64, P, P]
+    L.orc_p2g.argtypes = [P, i64, f64, P, P, P, P, P, P]
+    L.orc_grid_update.argtypes = [P, f64, P, P, P, P]
+    L.orc_g2p.argtypes = [P, i64, f64, P, P, P, P, P]
+    L.orc_sym_eig.argtypes = [ct.c_int, P, P, P]
+    L.orc_fluid_pressure.restype = f64
+    L.orc_fluid_pressure.argtypes = [P, f64]
+    L.orc_cone_alpha.restype = f64
+    L.orc_cone_alpha.argtypes = [P]
+    L.orc_hencky_return.restype = ct.c_int
+    L.orc_hencky_return.argtypes = [P, ct.c_int, P, P, P, P]
+    L.orc_constitutive.argtypes = [P, i64, f64, P, P, P, P]
+    L.orc_step.restype = ct.c_int
+    L.orc_step.argtypes = [P, i64, f64, P, P, P, P, P, P, P, P, P, P, P, P]
+    if hasattr(L, "orc_adjoint_step"):
+        _declare_adjoint(L)
+
+
+def _declare_adjoint(L):
+    P = ct.c_void_p
+    i64, f64 = ct.c_int64, ct.c_double
+    L.orc_adjoint_step.restype = ct.c_int
+    L.orc_adjoint_step.argtypes = [P, i64, f64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def make_config(cfg, key_f32: bool = False) -> OrcConfig:
+    """Translate a workloads.SimConfig into the oracle's C struct."""
+    c = OrcConfig()
+    c.dim = cfg.dim
+    for a in range(3):
+        c.n[a] = int(cfg.n[a])
+        c.gravity[a] = float(cfg.gravity[a])
+    c.ghost = cfg.ghost
+    c.tile = cfg.tile
+    c.material = _MAT[cfg.material]
+    c.key_f32 = 1 if key_f32 else 0
+    for f in range(6):
+        c.wall_mode[f] = _WALL[cfg.wall_mode[f]]
+        c.wall_mu[f] = float(cfg.wall_mu[f])
+    c.dx = float(cfg.dx)
+    c.rho0, c.bulk, c.gamma = float(cfg.rho0), float(cfg.bulk), float(cfg.gamma)
+    c.youngs, c.poisson, c.phi_deg = float(cfg.youngs), float(cfg.poisson), float(cfg.phi_deg)
+    c.vol0, c.mass = float(cfg.vol0), float(cfg.mass)
+    return c
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class State:
+    """Particle state in the oracle's layout (component-major float64)."""
+
+    def __init__(self, cfg, x, v=None, C=None, F=None, J=None, S=None, pid=None):
+        d = cfg.dim
+        x = _f64(x).reshape(d, -1)
+        N = x.shape[1]
+        self.N = N
+        self.x = x.copy()
+        self.v = np.zeros((d, N)) if v is None else _f64(v).reshape(d, N).copy()
+        self.C = np.zeros((d * d, N)) if C is None else _f64(C).reshape(d * d, N).copy()
+        if F is None:
+            F = np.zeros((d * d, N))
+            for a in range(d):
+                F[a * d + a] = 1.0
+        self.F = _f64(F).reshape(d * d, N).copy()
+        self.J = np.ones(N) if J is None else _f64(J).reshape(N).copy()
+        self.S = np.zeros((d * d, N)) if S is None else _f64(S).reshape(d * d, N).copy()
+        self.pid = np.arange(N, dtype=np.int32) if pid is None else \
+            np.ascontiguousarray(pid, dtype=np.int32).copy()
+
+    def copy(self):
+        s = State.__new__(State)
+        s.N = self.N
+        for k in ("x", "v", "C", "F", "J", "S", "pid"):
+            setattr(s, k, getattr(self, k).copy())
+        return s
+
+    def by_pid(self, name):
+        """Field reordered so that column p belongs to particle id p."""
+        a = getattr(self, name)
+        out = np.empty_like(a)
+        if a.ndim == 1:
+            out[self.pid] = a
+        else:
+            out[:, self.pid] = a
+        return out
+
+
+class Oracle:
+    def __init__(self, cfg, key_f32: bool = False):
+        self.cfg = cfg
+        self.c = make_config(cfg, key_f32)
+        self.L = lib()
+        dims = (ct.c_int32 * 3)()
+        self.NN = int(self.L.orc_node_dims(ct.byref(self.c), dims))
+        self.dims = tuple(dims)
+
+    # single stages -------------------------------------------------------
+    def keys(self, x):
+        x = _f64(x)
+        N = x.shape[-1]
+        k = np.empty(N, dtype=np.int32)
+        self.L.orc_cell_keys(ct.byref(self.c), N, _ptr(x), _ptr(k))
+        return k
+
+    def num_keys(self):
+        return int(self.L.orc_num_keys(ct.byref(self.c)))
+
+    @staticmethod
+    def sort_perm(key):
+        key = np.ascontiguousarray(key, dtype=np.int32)
+        perm = np.empty_like(key)
+        lib().orc_sort_perm(key.shape[0], _ptr(key), _ptr(perm))
+        return perm
+
+    def p2g(self, st: State, dt):
+        d = self.cfg.dim
+        gm = np.empty(self.NN)
+        gp = np.empty((d, self.NN))
+        self.L.orc_p2g(ct.byref(self.c), st.N, dt, _ptr(st.x), _ptr(st.v), _ptr(st.C),
+                       _ptr(st.S), _ptr(gm), _ptr(gp))
+        return gm, gp
+
+    def grid_update(self, gm, gp, dt, floor_mu=None):
+        d = self.cfg.dim
+        gv = np.empty((d, self.NN))
+        fm = None if floor_mu is None else _f64(floor_mu)
+        self.L.orc_grid_update(ct.byref(self.c), dt, _ptr(fm), _ptr(_f64(gm)), _ptr(_f64(gp)),
+                               _ptr(gv))
+        return gv
+
+    def g2p(self, st: State, gv, dt):
+        """Updates st.x, st.v, st.C in place; returns the velocity gradient L."""
+        d = self.cfg.dim
+        L = np.empty((d * d, st.N))
+        self.L.orc_g2p(ct.byref(self.c), st.N, dt, _ptr(_f64(gv)), _ptr(st.x), _ptr(st.v),
+                       _ptr(st.C), _ptr(L))
+        return L
+
+    def constitutive(self, st: State, L, dt):
+        self.L.orc_constitutive(ct.byref(self.c), st.N, dt, _ptr(_f64(L)), _ptr(st.F),
+                                _ptr(st.J), _ptr(st.S))
+
+    def hencky_return(self, Ftr, elastic_only=False):
+        d = self.cfg.dim
+        Ftr = _f64(Ftr).reshape(d * d)
+        Fe = np.empty(d * d)
+        tau = np.empty(d * d)
+        dg = ct.c_double(0.0)
+        cas = self.L.orc_hencky_return(ct.byref(self.c), 1 if elastic_only else 0, _ptr(Ftr),
+                                       _ptr(Fe), _ptr(tau), ct.byref(dg))
+        return Fe.reshape(d, d), tau.reshape(d, d), int(cas), dg.value
+
+    def sym_eig(self, A):
+        A = _f64(A)
+        d = A.shape[0]
+        ev = np.empty(3)
+        V = np.empty(d * d)
+        self.L.orc_sym_eig(d, _ptr(A.reshape(-1)), _ptr(ev), _ptr(V))
+        return ev[:d], V.reshape(d, d)
+
+    def pressure(self, J):
+        return float(self.L.orc_fluid_pressure(ct.byref(self.c), float(J)))
+
+    def cone_alpha(self):
+        return float(self.L.orc_cone_alpha(ct.byref(self.c)))
+
+    # whole step ------------------------------------------------------------
+    def step(self, st: State, dt, floor_mu=None, want_grid=False):
+        """One step in place (sort, P2G, grid, G2P, constitutive).
+        Returns (perm, key[, grid_m, grid_v])."""
+        d = self.cfg.dim
+        perm = np.empty(st.N, dtype=np.int32)
+        key = np.empty(st.N, dtype=np.int32)
+        gm = np.empty(self.NN) if want_grid else None
+        gv = np.empty((d, self.NN)) if want_grid else None
+        fm = None if floor_mu is None else _f64(floor_mu)
+        rc = self.L.orc_step(ct.byref(self.c), st.N, dt, _ptr(fm), _ptr(st.x), _ptr(st.v),
+                             _ptr(st.C), _ptr(st.F), _ptr(st.J), _ptr(st.S), _ptr(st.pid),
+                             _ptr(perm), _ptr(key), _ptr(gm), _ptr(gv))
+        if rc != 0:
+            raise MemoryError("oracle step failed to allocate")
+        if want_grid:
+            return perm, key, gm, gv
+        return perm, key
+
+    def run(self, st: State, steps, dt, floor_mu=None):
+        for _ in range(steps):
+            self.step(st, dt, floor_mu)
+        return st

@@ -1,0 +1,700 @@
+/*
+ * Reference explicit MPM step in binary64, written for checking only.
+ *
+ * TEST INFRASTRUCTURE: this file is the oracle.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header or table with the HIP library: it is written from
+ * the paper's equations, one stage per function, with plain scalar loops.
+ *
+ * Paper: "JAX-MPM: A Learning-Augmented Differentiable Meshfree Framework"
+ * (Du & He, arXiv 2507.04192).
+ *   - quadratic B-spline basis                 Sec. 2.1, eq. for phi-bar
+ *   - lumped mass, explicit Euler              Sec. 2.1, eq:semi_eq
+ *   - P2G / grid update / G2P (USL order)      Sec. 2.2
+ *   - APIC transfer, D_p^{-1} = 4/h^2 I        App. B
+ *   - weakly compressible EOS                  Sec. 2.3, eq:eos (Tait form)
+ *   - Drucker-Prager cone slope q_phi          App. A
+ *   - Coulomb wall friction                    Sec. 5.3, eq:coulomb_friction
+ *   - Hencky-strain return on the D-P cone     (Klar et al. 2016, cited in
+ *                                               Sec. 4.2.3)
+ *
+ * Readings taken where the paper is silent (all listed with reasons in the
+ * design notes):
+ *   - node i sits at i*h, i in [-G, n+G]; stored index I = i + G;
+ *   - stencil base b = floor(fl(x*inv) - 0.5), inv = 1/h rounded once;
+ *   - particles are clamped into [0, n*h] after advection;
+ *   - walls: every node on or beyond a wall plane, faces in the order
+ *     x-, x+, y-, y+, z-, z+; act only when the normal velocity points into
+ *     the wall; slip / stick / Coulomb(mu);
+ *   - fluid: p = (K/gamma)((1/J)^gamma - 1), J' = J det(I + dt L);
+ *   - sand: Hencky strain of b = F F^T, radial return onto the cone
+ *     ||dev eps|| + alpha (d lam + 2 mu)/(2 mu) tr eps <= 0 with
+ *     alpha = (sqrt 2 / 3) q_phi, apex when tr eps > 0;
+ *   - cell key: tile-major linear index of the stencil base, so that a
+ *     stable sort by key groups particles by tile, then by cell.
+ *
+ * Arrays are structure-of-arrays, component-major: component a of particle p
+ * is at arr[a*N + p]; a d x d matrix entry (a,b) is at arr[(a*d+b)*N + p].
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "mpm_oracle.h"
+
+/* ------------------------------------------------------------------ */
+/* Quadratic B-spline (Sec. 2.1, the piecewise definition of phi-bar) */
+/* ------------------------------------------------------------------ */
+
+double orc_phibar(double xi)
+{
+    double a = fabs(xi);
+    if (a < 0.5)
+        return 0.75 - a * a;
+    if (a < 1.5)
+        return 0.5 * a * a - 1.5 * a + 1.125;
+    return 0.0;
+}
+
+/* d phibar / d xi */
+double orc_dphibar(double xi)
+{
+    double a = fabs(xi);
+    double s = (xi < 0.0) ? -1.0 : 1.0;
+    if (a < 0.5)
+        return -2.0 * xi;
+    if (a < 1.5)
+        return s * (a - 1.5);
+    return 0.0;
+}
+
+/* Base node and the three 1-D weights / derivatives (per unit length) for
+ * one coordinate.  key_f32 selects binary32 for t = x*inv so that keys can
+ * be compared bit for bit with a binary32 solver. */
+void orc_stencil_1d(double x, double h, int key_f32, int32_t* base,
+                    double w[3], double dw[3])
+{
+    double t;
+    if (key_f32) {
+        float invf = 1.0f / (float)h;
+        float tf = (float)x * invf;
+        t = (double)tf;
+    } else {
+        double inv = 1.0 / h;
+        t = x * inv;
+    }
+    int32_t b = (int32_t)floor(t - 0.5);
+    *base = b;
+    for (int k = 0; k < 3; ++k) {
+        double xi = t - (double)(b + k); /* (x - x_i)/h */
+        w[k] = orc_phibar(xi);
+        dw[k] = orc_dphibar(xi) / h;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Grid bookkeeping                                                    */
+/* ------------------------------------------------------------------ */
+
+static int dimv(const orc_config* c) { return c->dim; }
+
+int64_t orc_node_dims(const orc_config* c, int32_t dims[3])
+{
+    int64_t nn = 1;
+    for (int a = 0; a < 3; ++a) {
+        dims[a] = (a < c->dim) ? c->n[a] + 1 + 2 * c->ghost : 1;
+        nn *= dims[a];
+    }
+    return nn;
+}
+
+static int64_t node_lin(const int32_t dims[3], const int32_t I[3])
+{
+    return ((int64_t)I[2] * dims[1] + I[1]) * dims[0] + I[0];
+}
+
+/* ------------------------------------------------------------------ */
+/* Cell key and stable sort                                            */
+/* ------------------------------------------------------------------ */
+
+int64_t orc_num_keys(const orc_config* c)
+{
+    int64_t k = 1;
+    for (int a = 0; a < c->dim; ++a) {
+        int32_t span = c->n[a] + 2 * c->ghost + 1; /* possible B values */
+        int32_t nt = (span + c->tile - 1) / c->tile;
+        k *= (int64_t)nt * c->tile;
+    }
+    return k;
+}
+
+/* Key of a base index triple B (= base + ghost): tiles ordered x fastest,
+ * then cells inside the tile ordered x fastest. */
+int64_t orc_key_of_base(const orc_config* c, const int32_t B[3])
+{
+    int d = c->dim, T = c->tile;
+    int64_t tile_lin = 0, cell_lin = 0, tiles_stride = 1, cells_stride = 1;
+    for (int a = 0; a < d; ++a) {
+        int32_t span = c->n[a] + 2 * c->ghost + 1;
+        int32_t nt = (span + T - 1) / T;
+        tile_lin += (int64_t)(B[a] / T) * tiles_stride;
+        cell_lin += (int64_t)(B[a] % T) * cells_stride;
+        tiles_stride *= nt;
+        cells_stride *= T;
+    }
+    return tile_lin * cells_stride + cell_lin;
+}
+
+void orc_cell_keys(const orc_config* c, int64_t N, const double* x, int32_t* key)
+{
+    int d = dimv(c);
+    for (int64_t p = 0; p < N; ++p) {
+        int32_t B[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) {
+            int32_t b;
+            double w[3], dw[3];
+            orc_stencil_1d(x[a * N + p], c->dx, c->key_f32, &b, w, dw);
+            B[a] = b + c->ghost;
+        }
+        key[p] = (int32_t)orc_key_of_base(c, B);
+    }
+}
+
+typedef struct { int32_t key; int32_t slot; } keyslot;
+
+static int cmp_keyslot(const void* pa, const void* pb)
+{
+    const keyslot* a = (const keyslot*)pa;
+    const keyslot* b = (const keyslot*)pb;
+    if (a->key != b->key) return (a->key < b->key) ? -1 : 1;
+    if (a->slot != b->slot) return (a->slot < b->slot) ? -1 : 1;
+    return 0;
+}
+
+/* Stable order by key: ties keep the current slot order.  Comparing the
+ * (key, slot) pair makes every element distinct, so any sort gives it. */
+void orc_sort_perm(int64_t N, const int32_t* key, int32_t* perm)
+{
+    keyslot* ks = (keyslot*)malloc(sizeof(keyslot) * (size_t)(N > 0 ? N : 1));
+    for (int64_t p = 0; p < N; ++p) {
+        ks[p].key = key[p];
+        ks[p].slot = (int32_t)p;
+    }
+    qsort(ks, (size_t)N, sizeof(keyslot), cmp_keyslot);
+    for (int64_t s = 0; s < N; ++s)
+        perm[s] = ks[s].slot;
+    free(ks);
+}
+
+static void gather_d(int64_t N, int ncomp, double* a, const int32_t* perm, double* tmp)
+{
+    for (int c = 0; c < ncomp; ++c) {
+        for (int64_t s = 0; s < N; ++s)
+            tmp[s] = a[c * N + perm[s]];
+        memcpy(a + c * N, tmp, sizeof(double) * (size_t)N);
+    }
+}
+
+static void gather_i(int64_t N, int32_t* a, const int32_t* perm, int32_t* tmp)
+{
+    for (int64_t s = 0; s < N; ++s)
+        tmp[s] = a[perm[s]];
+    memcpy(a, tmp, sizeof(int32_t) * (size_t)N);
+}
+
+/* ------------------------------------------------------------------ */
+/* P2G (Sec. 2.2 eq:update_m, momentum, force; App. B APIC)            */
+/* ------------------------------------------------------------------ */
+
+/* Per-particle stencil: node indices and phi, grad phi, x_i - x_p. */
+typedef struct {
+    int32_t base[3];
+    double w[3][3];  /* [axis][k] */
+    double dw[3][3];
+} stencil;
+
+static void make_stencil(const orc_config* c, int64_t N, const double* x, int64_t p, stencil* st)
+{
+    for (int a = 0; a < 3; ++a) {
+        st->base[a] = 0;
+        for (int k = 0; k < 3; ++k) {
+            st->w[a][k] = (k == 0) ? 1.0 : 0.0;
+            st->dw[a][k] = 0.0;
+        }
+    }
+    for (int a = 0; a < c->dim; ++a) {
+        orc_stencil_1d(x[a * N + p], c->dx, c->key_f32, &st->base[a], st->w[a], st->dw[a]);
+    }
+}
+
+/* For stencil offset (k0,k1,k2): phi, grad phi and dpos = x_i - x_p. */
+static void stencil_node(const orc_config* c, const double* xp, const stencil* st,
+                         const int k[3], double* phi, double grad[3], double dpos[3], int32_t I[3])
+{
+    int d = c->dim;
+    double ph = 1.0;
+    for (int a = 0; a < d; ++a)
+        ph *= st->w[a][k[a]];
+    *phi = ph;
+    for (int a = 0; a < 3; ++a) {
+        grad[a] = 0.0;
+        dpos[a] = 0.0;
+        I[a] = 0;
+    }
+    for (int a = 0; a < d; ++a) {
+        double g = st->dw[a][k[a]];
+        for (int b = 0; b < d; ++b)
+            if (b != a) g *= st->w[b][k[b]];
+        grad[a] = g;
+        int32_t node = st->base[a] + k[a];
+        dpos[a] = (double)node * c->dx - xp[a];
+        I[a] = node + c->ghost;
+    }
+}
+
+void orc_p2g(const orc_config* c, int64_t N, double dt,
+             const double* x, const double* v, const double* C, const double* S,
+             double* gm, double* gp)
+{
+    int d = dimv(c);
+    int32_t dims[3];
+    int64_t NN = orc_node_dims(c, dims);
+    memset(gm, 0, sizeof(double) * (size_t)NN);
+    memset(gp, 0, sizeof(double) * (size_t)(NN * d));
+    int kz_max = (d == 3) ? 3 : 1;
+    for (int64_t p = 0; p < N; ++p) {
+        stencil st;
+        make_stencil(c, N, x, p, &st);
+        double xp[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) {
+            xp[a] = x[a * N + p];
+            vp[a] = v[a * N + p];
+        }
+        for (int k2 = 0; k2 < kz_max; ++k2)
+            for (int k1 = 0; k1 < 3; ++k1)
+                for (int k0 = 0; k0 < 3; ++k0) {
+                    int k[3] = {k0, k1, k2};
+                    double phi, grad[3], dpos[3];
+                    int32_t I[3];
+                    stencil_node(c, xp, &st, k, &phi, grad, dpos, I);
+                    int64_t li = node_lin(dims, I);
+                    gm[li] += phi * c->mass;
+                    for (int a = 0; a < d; ++a) {
+                        double aff = 0.0;   /* (C_p (x_i - x_p))_a */
+                        double frc = 0.0;   /* (S_p grad phi)_a */
+                        for (int b = 0; b < d; ++b) {
+                            aff += C[(a * d + b) * N + p] * dpos[b];
+                            frc += S[(a * d + b) * N + p] * grad[b];
+                        }
+                        gp[a * NN + li] += phi * c->mass * (vp[a] + aff) - dt * frc;
+                    }
+                }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Grid update and walls (Sec. 2.2 grid update; Sec. 5.3 friction)     */
+/* ------------------------------------------------------------------ */
+
+/* Coulomb / slip / stick on one node for the wall with outward normal nrm. */
+static void wall_apply(int d, int mode, double mu, const double nrm[3], double vel[3])
+{
+    double vn = 0.0;
+    for (int a = 0; a < d; ++a)
+        vn += vel[a] * nrm[a];
+    if (!(vn > 0.0))
+        return; /* separating or resting: no constraint */
+    double vt[3] = {0, 0, 0}, vtn2 = 0.0;
+    for (int a = 0; a < d; ++a) {
+        vt[a] = vel[a] - vn * nrm[a];
+        vtn2 += vt[a] * vt[a];
+    }
+    if (mode == ORC_WALL_SLIP) {
+        for (int a = 0; a < d; ++a)
+            vel[a] = vt[a];
+        return;
+    }
+    if (mode == ORC_WALL_STICK) {
+        for (int a = 0; a < d; ++a)
+            vel[a] = 0.0;
+        return;
+    }
+    /* Coulomb with a resting wall (v_cm = 0): remove the normal part and
+     * reduce the tangential speed by mu * v_n, stopping if it would reverse. */
+    double vtn = sqrt(vtn2);
+    if (vtn <= mu * vn) {
+        for (int a = 0; a < d; ++a)
+            vel[a] = 0.0;
+    } else {
+        double scale = 1.0 - mu * vn / vtn;
+        for (int a = 0; a < d; ++a)
+            vel[a] = vt[a] * scale;
+    }
+}
+
+void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
+                     const double* gm, const double* gp, double* gv)
+{
+    int d = dimv(c);
+    int32_t dims[3];
+    int64_t NN = orc_node_dims(c, dims);
+    int fl = d - 1; /* floor = minus face of the last axis */
+    for (int32_t Iz = 0; Iz < dims[2]; ++Iz)
+        for (int32_t Iy = 0; Iy < dims[1]; ++Iy)
+            for (int32_t Ix = 0; Ix < dims[0]; ++Ix) {
+                int32_t I[3] = {Ix, Iy, Iz};
+                int64_t li = node_lin(dims, I);
+                double vel[3] = {0, 0, 0};
+                if (gm[li] > 0.0) {
+                    for (int a = 0; a < d; ++a)
+                        vel[a] = gp[a * NN + li] / gm[li] + dt * c->gravity[a];
+                }
+                for (int a = 0; a < d; ++a) {
+                    int32_t i = I[a] - c->ghost; /* physical node index */
+                    for (int side = 0; side < 2; ++side) {
+                        int face = 2 * a + side;
+                        int beyond = side == 0 ? (i <= 0) : (i >= c->n[a]);
+                        if (!beyond)
+                            continue;
+                        double nrm[3] = {0, 0, 0};
+                        nrm[a] = side == 0 ? -1.0 : 1.0;
+                        double mu = c->wall_mu[face];
+                        if (floor_mu && a == fl && side == 0) {
+                            int64_t fi = (d == 3) ? ((int64_t)Iy * dims[0] + Ix) : Ix;
+                            mu = floor_mu[fi];
+                        }
+                        wall_apply(d, c->wall_mode[face], mu, nrm, vel);
+                    }
+                }
+                for (int a = 0; a < d; ++a)
+                    gv[a * NN + li] = vel[a];
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* G2P (Sec. 2.2 PIC velocity, position, velocity gradient; App. B)   */
+/* ------------------------------------------------------------------ */
+
+void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
+             double* x, double* v, double* C, double* L)
+{
+    int d = dimv(c);
+    int32_t dims[3];
+    int64_t NN = orc_node_dims(c, dims);
+    double Dinv = 4.0 / (c->dx * c->dx);
+    int kz_max = (d == 3) ? 3 : 1;
+    for (int64_t p = 0; p < N; ++p) {
+        stencil st;
+        make_stencil(c, N, x, p, &st);
+        double xp[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a)
+            xp[a] = x[a * N + p];
+        double vn[3] = {0, 0, 0}, Bm[3][3] = {{0}}, Lm[3][3] = {{0}};
+        for (int k2 = 0; k2 < kz_max; ++k2)
+            for (int k1 = 0; k1 < 3; ++k1)
+                for (int k0 = 0; k0 < 3; ++k0) {
+                    int k[3] = {k0, k1, k2};
+                    double phi, grad[3], dpos[3];
+                    int32_t I[3];
+                    stencil_node(c, xp, &st, k, &phi, grad, dpos, I);
+                    int64_t li = node_lin(dims, I);
+                    for (int a = 0; a < d; ++a) {
+                        double vi = gv[a * NN + li];
+                        vn[a] += phi * vi;
+                        for (int b = 0; b < d; ++b) {
+                            Bm[a][b] += phi * vi * dpos[b];
+                            Lm[a][b] += vi * grad[b];
+                        }
+                    }
+                }
+        for (int a = 0; a < d; ++a) {
+            v[a * N + p] = vn[a];
+            double xn = xp[a] + dt * vn[a];
+            double hi = (double)c->n[a] * c->dx;
+            if (xn < 0.0) xn = 0.0;
+            if (xn > hi) xn = hi;
+            x[a * N + p] = xn;
+            for (int b = 0; b < d; ++b) {
+                C[(a * d + b) * N + p] = Dinv * Bm[a][b];
+                L[(a * d + b) * N + p] = Lm[a][b];
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Small dense linear algebra                                           */
+/* ------------------------------------------------------------------ */
+
+static void matmul(int d, const double A[3][3], const double B[3][3], double R[3][3])
+{
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k)
+                s += A[i][k] * B[k][j];
+            R[i][j] = s;
+        }
+}
+
+static double det(int d, const double A[3][3])
+{
+    if (d == 2)
+        return A[0][0] * A[1][1] - A[0][1] * A[1][0];
+    return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1])
+         - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0])
+         + A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+
+/* Cyclic Jacobi eigen-decomposition of a symmetric d x d matrix A:
+ * A = V diag(ev) V^T, iterated until the off-diagonal part is negligible. */
+void orc_sym_eig(int d, const double Ain[9], double ev[3], double Vout[9])
+{
+    double A[3][3], V[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            A[i][j] = (i < d && j < d) ? Ain[i * d + j] : 0.0;
+            V[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                tot += A[i][j] * A[i][j];
+                if (i != j) off += A[i][j] * A[i][j];
+            }
+        if (off <= 1e-36 * tot || off == 0.0)
+            break;
+        for (int p = 0; p < d - 1; ++p)
+            for (int q = p + 1; q < d; ++q) {
+                if (A[p][q] == 0.0)
+                    continue;
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                /* A <- J^T A J with J the rotation in the (p,q) plane */
+                for (int k = 0; k < d; ++k) {
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq;
+                    A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < d; ++k) {
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk;
+                    A[q][k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < d; ++k) {
+                    double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = cs * vkp - sn * vkq;
+                    V[k][q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    for (int i = 0; i < 3; ++i)
+        ev[i] = (i < d) ? A[i][i] : 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            Vout[i * d + j] = V[i][j];
+}
+
+/* ------------------------------------------------------------------ */
+/* Constitutive models                                                  */
+/* ------------------------------------------------------------------ */
+
+/* Tait form of the weakly compressible EOS; gamma = 1 with K = rho0 c^2
+ * is eq:eos of Sec. 2.3 written in J = rho0/rho. */
+double orc_fluid_pressure(const orc_config* c, double J)
+{
+    return (c->bulk / c->gamma) * (pow(1.0 / J, c->gamma) - 1.0);
+}
+
+double orc_cone_alpha(const orc_config* c)
+{
+    double s = sin(c->phi_deg * M_PI / 180.0);
+    double q_phi = 6.0 * s / (sqrt(3.0) * (3.0 + s)); /* App. A */
+    return sqrt(2.0) / 3.0 * q_phi;
+}
+
+/* Hencky-strain return mapping onto the Drucker-Prager cone.
+ * Ftr: trial elastic deformation gradient (d x d, row-major).
+ * Outputs the returned elastic F, the Kirchhoff stress tau and the case
+ * (0 apex, 1 elastic, 2 cone).  elastic_only forces the elastic case. */
+int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9],
+                      double Fe[9], double tau[9], double* dgamma)
+{
+    int d = c->dim;
+    double E = c->youngs, nu = c->poisson;
+    double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    double mu = E / (2.0 * (1.0 + nu));
+    double F[3][3] = {{0}}, b[9] = {0};
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            F[i][j] = Ftr[i * d + j];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k)
+                s += F[i][k] * F[j][k];
+            b[i * d + j] = s;
+        }
+    double ev[3], U[9];
+    orc_sym_eig(d, b, ev, U);
+    double eps[3] = {0, 0, 0}, sv[3] = {1, 1, 1}, tr = 0.0;
+    for (int i = 0; i < d; ++i) {
+        sv[i] = sqrt(ev[i]);
+        eps[i] = log(sv[i]);
+        tr += eps[i];
+    }
+    double dev[3] = {0, 0, 0}, devn = 0.0;
+    for (int i = 0; i < d; ++i) {
+        dev[i] = eps[i] - tr / d;
+        devn += dev[i] * dev[i];
+    }
+    devn = sqrt(devn);
+    double H[3] = {0, 0, 0};
+    int cas;
+    double dg = 0.0;
+    if (elastic_only) {
+        cas = 1;
+        for (int i = 0; i < d; ++i) H[i] = eps[i];
+    } else if (tr > 0.0) {
+        cas = 0; /* apex: stress free */
+        double en = 0.0;
+        for (int i = 0; i < d; ++i) en += eps[i] * eps[i];
+        dg = sqrt(en);
+    } else {
+        double alpha = orc_cone_alpha(c);
+        dg = devn + (d * lam + 2.0 * mu) / (2.0 * mu) * alpha * tr;
+        if (dg <= 0.0) {
+            cas = 1;
+            dg = 0.0;
+            for (int i = 0; i < d; ++i) H[i] = eps[i];
+        } else {
+            cas = 2;
+            for (int i = 0; i < d; ++i) H[i] = eps[i] - dg * dev[i] / devn;
+        }
+    }
+    double trH = 0.0;
+    for (int i = 0; i < d; ++i) trH += H[i];
+    /* Fe = U diag(exp(H)/s) U^T Ftr ; tau = U diag(2 mu H + lam trH) U^T */
+    double M[3][3] = {{0}}, T[3][3] = {{0}};
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double m = 0.0, t = 0.0;
+            for (int k = 0; k < d; ++k) {
+                m += U[i * d + k] * (exp(H[k]) / sv[k]) * U[j * d + k];
+                t += U[i * d + k] * (2.0 * mu * H[k] + lam * trH) * U[j * d + k];
+            }
+            M[i][j] = m;
+            T[i][j] = t;
+        }
+    double R[3][3];
+    if (cas == 1) {
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j)
+                R[i][j] = F[i][j];
+    } else {
+        matmul(d, M, F, R);
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            Fe[i * d + j] = R[i][j];
+            tau[i * d + j] = T[i][j];
+        }
+    if (dgamma) *dgamma = dg;
+    return cas;
+}
+
+/* Kinematics (F or J update with the velocity gradient L) followed by the
+ * stress of the material; S = V0 * tau (Kirchhoff stress times initial
+ * volume, equal to V_p sigma_p). */
+void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L,
+                      double* F, double* J, double* S)
+{
+    int d = dimv(c);
+    for (int64_t p = 0; p < N; ++p) {
+        double M[3][3] = {{0}}; /* I + dt L */
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b)
+                M[a][b] = (a == b ? 1.0 : 0.0) + dt * L[(a * d + b) * N + p];
+        double tau[3][3] = {{0}};
+        if (c->material == ORC_FLUID) {
+            double Jn = J[p] * det(d, M);
+            J[p] = Jn;
+            double pr = orc_fluid_pressure(c, Jn);
+            for (int a = 0; a < d; ++a)
+                tau[a][a] = -Jn * pr;
+        } else {
+            double Fo[3][3] = {{0}}, Ft[3][3];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b)
+                    Fo[a][b] = F[(a * d + b) * N + p];
+            matmul(d, M, Fo, Ft);
+            double ftr[9], fe[9], tu[9];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b)
+                    ftr[a * d + b] = Ft[a][b];
+            orc_hencky_return(c, c->material == ORC_HENCKY_ELASTIC, ftr, fe, tu, NULL);
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) {
+                    F[(a * d + b) * N + p] = fe[a * d + b];
+                    tau[a][b] = tu[a * d + b];
+                }
+        }
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b)
+                S[(a * d + b) * N + p] = c->vol0 * tau[a][b];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* One full step: sort, P2G, grid update with walls, G2P, constitutive  */
+/* ------------------------------------------------------------------ */
+
+int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
+             double* x, double* v, double* C, double* F, double* J, double* S,
+             int32_t* pid, int32_t* perm_out, int32_t* key_out,
+             double* grid_m_out, double* grid_v_out)
+{
+    int d = dimv(c);
+    int32_t dims[3];
+    int64_t NN = orc_node_dims(c, dims);
+    size_t NP = (size_t)(N > 0 ? N : 1);
+    int32_t* key = (int32_t*)malloc(sizeof(int32_t) * NP);
+    int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * NP);
+    int32_t* itmp = (int32_t*)malloc(sizeof(int32_t) * NP);
+    double* tmp = (double*)malloc(sizeof(double) * NP);
+    double* L = (double*)malloc(sizeof(double) * NP * (size_t)(d * d));
+    double* gm = (double*)malloc(sizeof(double) * (size_t)NN);
+    double* gp = (double*)malloc(sizeof(double) * (size_t)(NN * d));
+    double* gv = (double*)malloc(sizeof(double) * (size_t)(NN * d));
+    if (!key || !perm || !itmp || !tmp || !L || !gm || !gp || !gv) {
+        free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv);
+        return -1;
+    }
+
+    orc_cell_keys(c, N, x, key);
+    orc_sort_perm(N, key, perm);
+    gather_d(N, d, x, perm, tmp);
+    gather_d(N, d, v, perm, tmp);
+    gather_d(N, d * d, C, perm, tmp);
+    gather_d(N, d * d, S, perm, tmp);
+    if (c->material == ORC_FLUID)
+        gather_d(N, 1, J, perm, tmp);
+    else
+        gather_d(N, d * d, F, perm, tmp);
+    gather_i(N, pid, perm, itmp);
+    if (perm_out) memcpy(perm_out, perm, sizeof(int32_t) * (size_t)N);
+    if (key_out) memcpy(key_out, key, sizeof(int32_t) * (size_t)N);
+
+    orc_p2g(c, N, dt, x, v, C, S, gm, gp);
+    orc_grid_update(c, dt, floor_mu, gm, gp, gv);
+    if (grid_m_out) memcpy(grid_m_out, gm, sizeof(double) * (size_t)NN);
+    if (grid_v_out) memcpy(grid_v_out, gv, sizeof(double) * (size_t)(NN * d));
+    orc_g2p(c, N, dt, gv, x, v, C, L);
+    orc_constitutive(c, N, dt, L, F, J, S);
+
+    free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv);
+    return 0;
+}

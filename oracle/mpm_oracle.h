@@ -1,0 +1,55 @@
+/*
+ * Oracle (test infrastructure only): binary64 reference MPM step.
+ * Declarations for mpm_oracle.c and mpm_oracle_adjoint.c.  Nothing in the
+ * HIP library includes this header.
+ */
+#ifndef MPM_ORACLE_H
+#define MPM_ORACLE_H
+#include <stdint.h>
+
+enum { ORC_FLUID = 0, ORC_DP_HENCKY = 1, ORC_HENCKY_ELASTIC = 2 };
+enum { ORC_WALL_SLIP = 0, ORC_WALL_STICK = 1, ORC_WALL_COULOMB = 2 };
+
+typedef struct orc_config {
+    int32_t dim;          /* 2 or 3 */
+    int32_t n[3];         /* cells per axis */
+    int32_t ghost;        /* ghost node layers per side */
+    int32_t tile;         /* tile edge in cells, for the cell key */
+    int32_t material;     /* ORC_FLUID / ORC_DP_HENCKY / ORC_HENCKY_ELASTIC */
+    int32_t key_f32;      /* 1: stencil base computed in binary32 */
+    int32_t wall_mode[6]; /* faces x-, x+, y-, y+, z-, z+ */
+    double dx;
+    double gravity[3];
+    double wall_mu[6];
+    double rho0, bulk, gamma;          /* fluid */
+    double youngs, poisson, phi_deg;   /* sand */
+    double vol0, mass;                 /* per particle */
+} orc_config;
+
+double orc_phibar(double xi);
+double orc_dphibar(double xi);
+void orc_stencil_1d(double x, double h, int key_f32, int32_t* base, double w[3], double dw[3]);
+int64_t orc_node_dims(const orc_config* c, int32_t dims[3]);
+int64_t orc_num_keys(const orc_config* c);
+int64_t orc_key_of_base(const orc_config* c, const int32_t B[3]);
+void orc_cell_keys(const orc_config* c, int64_t N, const double* x, int32_t* key);
+void orc_sort_perm(int64_t N, const int32_t* key, int32_t* perm);
+void orc_p2g(const orc_config* c, int64_t N, double dt, const double* x, const double* v,
+             const double* C, const double* S, double* gm, double* gp);
+void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
+                     const double* gm, const double* gp, double* gv);
+void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
+             double* x, double* v, double* C, double* L);
+void orc_sym_eig(int d, const double A[9], double ev[3], double V[9]);
+double orc_fluid_pressure(const orc_config* c, double J);
+double orc_cone_alpha(const orc_config* c);
+int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9],
+                      double Fe[9], double tau[9], double* dgamma);
+void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L,
+                      double* F, double* J, double* S);
+int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
+             double* x, double* v, double* C, double* F, double* J, double* S,
+             int32_t* pid, int32_t* perm_out, int32_t* key_out,
+             double* grid_m_out, double* grid_v_out);
+
+#endif

@@ -1,0 +1,201 @@
+"""Seeded synthetic inputs and simulation settings.
+
+This module is shared by the solver's tests, the benchmark and the oracle's
+tests.  It holds configuration values and random draws only -- no step of the
+method's arithmetic -- so that both the HIP solver and the oracle can be fed
+the very same arrays.
+
+Particle seeding: lattice points at (k + (j + 1/2)/m) h per axis, j < m for m
+particles per cell per axis, kept when the *unjittered* point lies inside
+the body, then jittered by a uniform draw in [-0.1 h, 0.1 h] per component.
+All random numbers come from ``numpy.random.default_rng(seed)``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional, Sequence, Tuple
+
+import numpy as np
+
+FLUID = "fluid"          # weakly compressible Tait fluid
+SAND = "sand"            # Drucker-Prager sand, Hencky-strain return
+ELASTIC = "elastic"      # Hencky elastic (no return), used by checks
+
+SLIP, STICK, COULOMB = "slip", "stick", "coulomb"
+
+
+@dataclasses.dataclass
+class SimConfig:
+    dim: int
+    n: Tuple[int, int, int]
+    dx: float
+    dt: float
+    material: str
+    ppc: int                         # particles per cell (total)
+    gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    wall_mode: Tuple[str, ...] = (SLIP,) * 6   # x-, x+, y-, y+, z-, z+
+    wall_mu: Tuple[float, ...] = (0.0,) * 6
+    rho0: float = 1000.0
+    bulk: float = 1.0e5
+    gamma: float = 7.0
+    youngs: float = 1.0e7
+    poisson: float = 0.3
+    phi_deg: float = 30.0
+    ghost: int = 2
+    tile: int = 0                    # 0: 4 in 3D, 8 in 2D
+
+    def __post_init__(self):
+        n = tuple(int(v) for v in self.n) + (1,) * (3 - len(self.n))
+        self.n = n[:3]
+        if self.tile == 0:
+            self.tile = 4 if self.dim == 3 else 8
+
+    @property
+    def vol0(self) -> float:
+        return self.dx ** self.dim / self.ppc
+
+    @property
+    def mass(self) -> float:
+        return self.rho0 * self.vol0
+
+    @property
+    def extent(self) -> Tuple[float, ...]:
+        return tuple(self.n[a] * self.dx for a in range(self.dim))
+
+    def node_dims(self) -> Tuple[int, int, int]:
+        """Nodes per axis of the dense padded grid (ghost layers included)."""
+        return tuple(self.n[a] + 1 + 2 * self.ghost if a < self.dim else 1 for a in range(3))
+
+    def floor_nodes(self) -> int:
+        nd = self.node_dims()
+        return nd[0] if self.dim == 2 else nd[0] * nd[1]
+
+    def replace(self, **kw) -> "SimConfig":
+        return dataclasses.replace(self, **kw)
+
+
+def lattice_particles(cfg: SimConfig, inside: Callable[[np.ndarray], np.ndarray],
+                      lo: Sequence[float], hi: Sequence[float], seed: int,
+                      per_axis: int = 2, jitter: float = 0.1) -> np.ndarray:
+    """Seeded particles, shape (dim, N), float64, component-major."""
+    d, h = cfg.dim, cfg.dx
+    axes = []
+    for a in range(d):
+        c0 = int(math.floor(lo[a] / h))
+        c1 = int(math.ceil(hi[a] / h))
+        cells = np.arange(c0, c1, dtype=np.float64)
+        offs = (np.arange(per_axis, dtype=np.float64) + 0.5) / per_axis
+        axes.append(((cells[:, None] + offs[None, :]) * h).reshape(-1))
+    grids = np.meshgrid(*axes, indexing="ij")
+    # x varies fastest in the particle order
+    pts = np.stack([g.transpose(*range(d)[::-1]).reshape(-1) for g in grids], axis=0)
+    keep = inside(pts)
+    pts = pts[:, keep]
+    rng = np.random.default_rng(seed)
+    pts = pts + rng.uniform(-jitter * h, jitter * h, size=pts.shape)
+    for a in range(d):
+        np.clip(pts[a], 0.0, cfg.n[a] * h, out=pts[a])
+    return np.ascontiguousarray(pts)
+
+
+def box_inside(lo, hi):
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+
+    def f(p):
+        ok = np.ones(p.shape[1], dtype=bool)
+        for a in range(p.shape[0]):
+            ok &= (p[a] >= lo[a]) & (p[a] < hi[a])
+        return ok
+    return f
+
+
+def cylinder_inside(cx, cy, radius, height):
+    def f(p):
+        r2 = (p[0] - cx) ** 2 + (p[1] - cy) ** 2
+        return (r2 < radius * radius) & (p[2] >= 0.0) & (p[2] < height)
+    return f
+
+
+# ---------------------------------------------------------------------------
+# Workloads (sizes follow the benchmark definitions; see the design notes)
+# ---------------------------------------------------------------------------
+
+def dam_break_2d(scale: int = 1, seed: int = 0):
+    """2-D dam-break: 2.0 x 1.0 m domain at 128 x 64 cells (scale 1),
+    water column 0.5 x 1.0 m, 2 x 2 particles per cell, Tait K=1e5,
+    rho=1000, gamma=7, gravity -9.81, slip walls, dt = 1e-4 s."""
+    n = (128 * scale, 64 * scale, 1)
+    dx = 1.0 / (64 * scale)
+    cfg = SimConfig(dim=2, n=n, dx=dx, dt=1e-4 / scale, material=FLUID, ppc=4,
+                    gravity=(0.0, -9.81, 0.0), rho0=1000.0, bulk=1.0e5, gamma=7.0)
+    x = lattice_particles(cfg, box_inside((0.0, 0.0), (0.5, 1.0)), (0.0, 0.0), (0.5, 1.0), seed)
+    return cfg, x
+
+
+def cylinder_collapse_3d(scale_div: int = 1, seed: int = 0):
+    """3-D granular cylinder collapse: 256 x 256 x 64 cells, dx = 0.005 m,
+    cylinder of radius and height 48 cells at the domain centre, 2x2x2
+    particles per cell, Drucker-Prager sand E=1e7, nu=0.3, phi=30 deg,
+    rho=2000, floor Coulomb mu = 0.5, other walls slip, dt = 2e-5 s.
+    scale_div > 1 shrinks every length (cells and cylinder) by that factor
+    at the same dx."""
+    s = scale_div
+    n = (256 // s, 256 // s, 64 // s)
+    dx = 0.005
+    modes = (SLIP, SLIP, SLIP, SLIP, COULOMB, SLIP)
+    mus = (0.0, 0.0, 0.0, 0.0, 0.5, 0.0)
+    cfg = SimConfig(dim=3, n=n, dx=dx, dt=2e-5, material=SAND, ppc=8,
+                    gravity=(0.0, 0.0, -9.81), wall_mode=modes, wall_mu=mus,
+                    rho0=2000.0, youngs=1.0e7, poisson=0.3, phi_deg=30.0)
+    R = 48 * dx / s
+    cx, cy = n[0] * dx / 2, n[1] * dx / 2
+    x = lattice_particles(cfg, cylinder_inside(cx, cy, R, R),
+                          (cx - R, cy - R, 0.0), (cx + R, cy + R, R), seed)
+    return cfg, x
+
+
+def friction_dam_break_2d(seed_mu: int = 2, seed_eval: int = 3, seed_tracers: int = 4,
+                          scale: int = 2):
+    """Dam-break at 256 x 128 cells with 32 floor segments of friction."""
+    cfg, x = dam_break_2d(scale=scale, seed=0)
+    modes = (SLIP, SLIP, COULOMB, SLIP, SLIP, SLIP)
+    cfg = cfg.replace(wall_mode=modes)
+    return cfg, x
+
+
+def segment_mu(cfg: SimConfig, mu_seg: np.ndarray, seg_len: float = 0.0625) -> np.ndarray:
+    """Expand per-segment floor friction to one value per floor node
+    (node x = i*h, segment = clamp(floor(x / seg_len), 0, nseg-1))."""
+    nd = cfg.node_dims()
+    i = np.arange(nd[0]) - cfg.ghost
+    xs = i * cfg.dx
+    seg = np.clip(np.floor(xs / seg_len).astype(np.int64), 0, len(mu_seg) - 1)
+    return np.ascontiguousarray(np.asarray(mu_seg, dtype=np.float64)[seg])
+
+
+def uniform_mu_segments(seed: int, count: int = 32, lo: float = 0.1, hi: float = 0.6):
+    return np.random.default_rng(seed).uniform(lo, hi, size=count)
+
+
+def pick_tracers(n_particles: int, count: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n_particles, size=count, replace=False)).astype(np.int32)
+
+
+def random_state(cfg: SimConfig, n_particles: int, seed: int, vscale: float = 0.1,
+                 cscale: float = 1.0, fscale: float = 1e-3, margin: float = 2.0):
+    """Random particle state for kernel-level checks: positions uniform in
+    the interior (margin cells from each wall), small random v, C, F - I."""
+    rng = np.random.default_rng(seed)
+    d = cfg.dim
+    x = np.empty((d, n_particles))
+    for a in range(d):
+        lo = margin * cfg.dx
+        hi = cfg.n[a] * cfg.dx - margin * cfg.dx
+        x[a] = rng.uniform(lo, hi, size=n_particles)
+    v = rng.normal(0.0, vscale, size=(d, n_particles))
+    C = rng.normal(0.0, cscale, size=(d * d, n_particles))
+    G = rng.normal(0.0, fscale, size=(d * d, n_particles))
+    return x, v, C, G
