@@ -1,0 +1,201 @@
+#!/usr/bin/env python
+"""Throughput of the explicit MPM step on one MI355X.
+
+Workload: 3-D granular cylinder collapse -- 256 x 256 x 64 cells, dx = 5 mm,
+a sand cylinder of radius and height 48 cells at 2x2x2 particles per cell
+(2,780,928 particles), Drucker-Prager sand with the Hencky return, floor
+Coulomb mu = 0.5, dt = 2e-5 s.  Synthetic seeded input (no dataset).
+
+A step is one pass of the whole hot path: cell-key sort, P2G, grid update,
+G2P with the constitutive update.  Inputs are resident in HBM before the
+timed region starts.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s fwd & fwd+adjoint, 3D 2.7M-particle collapse; % of HBM peak"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E peak
+
+# Algorithmic scalars per particle moved by each kernel (3-D sand): the state
+# is x3 v3 C9 F9.  G2P reads x, F and writes x, v, C, F and the stress cache
+# (6); P2G reads x, v, C and the stress cache.  Bucket moves a key and an
+# index (int32).  The whole step's figure is the state read once and written
+# once: 48 scalars.
+ALG_SCALARS = {"g2p": 3 + 9 + 3 + 3 + 9 + 9 + 6, "p2g": 3 + 3 + 9 + 6}
+ALG_INT_BYTES = {"bucket": 8}
+STEP_SCALARS = 48
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(cfg, x, precision, steps, warmup):
+    import torch
+    from paper_2507_04192_amd.native import Solver
+    s = Solver(cfg, precision, capacity=x.shape[1])
+    s.mpm_init_particles(x)
+    s.mpm_step(warmup)
+    rc, bad = s.mpm_sync_status()
+    if rc != 0:
+        raise RuntimeError(f"solver status {rc} (pid {bad}) during warm-up")
+    torch.cuda.synchronize()
+    s.mpm_profile_enable(True)
+    s.mpm_profile_read()                     # reset
+    t0 = time.perf_counter()
+    s.mpm_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.mpm_profile_read()
+    s.mpm_profile_enable(False)
+    rc, bad = s.mpm_sync_status()
+    if rc != 0:
+        raise RuntimeError(f"solver status {rc} (pid {bad}) in the timed region")
+    # same number of steps without events, to show their cost
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.mpm_step(steps)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    s.close()
+    return (t1 - t0), (t3 - t2), prof
+
+
+def roofline(prof, n_particles, elem):
+    kernels = {}
+    for k, (ms, n) in prof.items():
+        if n > 0:
+            kernels[k] = {"avg_ms": ms / n, "launches": n, "total_ms": ms}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    for k, v in kernels.items():
+        if k in ALG_SCALARS:
+            v["alg_bytes"] = ALG_SCALARS[k] * elem * n_particles
+        elif k in ALG_INT_BYTES:
+            v["alg_bytes"] = ALG_INT_BYTES[k] * n_particles
+        if "alg_bytes" in v:
+            v["gbs"] = v["alg_bytes"] / (v["avg_ms"] * 1e-3) / 1e9
+    d = kernels[dom]
+    ach = d.get("gbs")
+    return dom, kernels, {
+        "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": None,
+        "kernel": dom, "alg_bytes_per_launch": d.get("alg_bytes"), "avg_launch_ms": d["avg_ms"],
+    }
+
+
+def cpu_baseline(cfg, x, steps):
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(cfg)
+    st = oracle.State(cfg, x)
+    t0 = time.perf_counter()
+    o.run(st, steps, cfg.dt)
+    t1 = time.perf_counter()
+    n = x.shape[1]
+    return {
+        "value": n * steps / (t1 - t0), "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+        "sample": f"{steps} step(s) of the full {n}-particle cylinder from rest, binary64 C oracle, "
+                  f"1 thread ({t1 - t0:.1f} s)",
+        "host_cpu": _cpu_name(), "nproc": os.cpu_count(),
+    }
+
+
+def _cpu_name():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--f64-steps", type=int, default=None, help="binary64 timed steps (default steps/2)")
+    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--scale-div", type=int, default=1, help="shrink the cylinder (tests only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(multi-GPU sharding is designed but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_04192_amd import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cfg, x = W.cylinder_collapse_3d(scale_div=args.scale_div, seed=0)
+    n = x.shape[1]
+    log(f"[bench] cylinder collapse N={n} grid={cfg.n} device={torch.cuda.get_device_name(0)}")
+
+    t32, t32_noev, prof32 = run_gpu(cfg, x, "f32", args.steps, args.warmup)
+    ms32 = t32 / args.steps * 1e3
+    val32 = n * args.steps / t32
+    log(f"[bench] f32: {ms32:.4f} ms/step, {val32:.4e} particle-steps/s "
+        f"(no events: {t32_noev / args.steps * 1e3:.4f} ms/step)")
+    dom, kernels, roof = roofline(prof32, n, 4)
+    for k, v in kernels.items():
+        log(f"[bench]   {k:7s} {v['avg_ms'] * 1e3:9.2f} us/launch" +
+            (f"  {v['gbs']:8.1f} GB/s algorithmic" if "gbs" in v else ""))
+
+    out_f64 = None
+    if not args.no_f64:
+        k64 = args.f64_steps or max(1, args.steps // 2)
+        t64, t64_noev, prof64 = run_gpu(cfg, x, "f64", k64, args.warmup)
+        _, kern64, roof64 = roofline(prof64, n, 8)
+        out_f64 = {"value": n * k64 / t64, "unit": "particle-steps/s", "steps": k64,
+                   "ms_per_step": t64 / k64 * 1e3, "ms_per_step_no_events": t64_noev / k64 * 1e3,
+                   "hbm_frac_step": n * k64 / t64 * STEP_SCALARS * 8 / (HBM_PEAK_GBS * 1e9),
+                   "roofline": roof64,
+                   "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kern64.items()}}
+        log(f"[bench] f64: {out_f64['ms_per_step']:.4f} ms/step, {out_f64['value']:.4e} particle-steps/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] timing the oracle for {args.cpu_steps} step(s) on the host ...")
+        cpu = cpu_baseline(cfg, x, args.cpu_steps)
+        log(f"[bench] oracle: {cpu['value']:.4e} particle-steps/s")
+
+    res = {
+        "metric": METRIC, "value": val32, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms32,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3D granular cylinder collapse: 256x256x64 cells, dx=0.005 m, "
+                               "cylinder R=H=48 cells, 8 particles/cell, Drucker-Prager sand "
+                               "(Hencky return), floor mu=0.5, dt=2e-5 s",
+                   "particles": n, "grid": list(cfg.n), "precision": "f32",
+                   "scale_div": args.scale_div},
+        "ms_per_step_no_events": t32_noev / args.steps * 1e3,
+        "hbm_frac_step": val32 * STEP_SCALARS * 4 / (HBM_PEAK_GBS * 1e9),
+        "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kernels.items()},
+        "f64": out_f64,
+        "paper_context": {"value_f32": 1.22e8, "value_f64": 2.76e7,
+                          "note": "paper, one A100, 2,712,960-particle cylinder on 400x400x100; "
+                                  "a different machine and grid, not this workload"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * mpm.h -- C-ABI of the MI355X explicit MPM solver (gfx950, HIP).
+ *
+ * The calls follow the paper's statement of the problem (Du & He,
+ * "JAX-MPM", arXiv 2507.04192):
+ *   - a state S = {x, v, F, rho} advanced by one map per step,
+ *     S^{t+1} = Phi(S^t; alpha), Phi = G2P o GU o P2G      (Sec. 3.1, eq:mapping)
+ *   - P2G, grid update and G2P as in Sec. 2.2, APIC as in App. B,
+ *     stress update last (USL, Sec. 2.2 remark)
+ *   - extraction operators Q_l (Lagrangian tracer, Eulerian box mean) and the
+ *     masked least-squares loss                           (Sec. 3.2, eq:inverse_loss)
+ *   - dL/dalpha by a reverse sweep over checkpointed segments (Sec. 3.1
+ *     eq:dzda; Sec. 3.3 checkpointing and segmentation)
+ *   - parameters alpha as an initial velocity field or a per-node floor
+ *     friction, optionally produced by a small network   (Sec. 3.2, eq:nn_apprx)
+ *
+ * Conventions (all calls):
+ *   - Return value: MPM_OK (0) or a negative mpm_status.  No exception crosses
+ *     the ABI.  mpm_last_error() gives a message for the last failure.
+ *   - Pointers are device pointers on the context's device unless the name
+ *     starts with host_.  Floating-point buffers use the context's precision
+ *     (binary32 or binary64) unless stated otherwise.
+ *   - Particle arrays are structure-of-arrays, component-major: component a
+ *     of particle p at [a*n + p]; matrix entry (a,b) at [(a*dim+b)*n + p].
+ *   - The caller owns every buffer it passes in; the context keeps only
+ *     views into the workspace bound by mpm_bind_workspace().
+ *   - Work is queued on the stream given to mpm_create() and is asynchronous
+ *     unless the call says it synchronizes.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mpm_status {
+    MPM_OK = 0,
+    MPM_EINVAL = -1,      /* bad argument or configuration */
+    MPM_ENOMEM = -2,      /* workspace missing or too small */
+    MPM_EHIP = -3,        /* a HIP runtime call or launch failed */
+    MPM_ENONFINITE = -4,  /* a particle's state became NaN or Inf */
+    MPM_EDOMAIN = -5,     /* reserved: particle outside the padded grid */
+    MPM_ESTATE = -6       /* call made in the wrong order */
+} mpm_status;
+
+enum { MPM_F32 = 0, MPM_F64 = 1 };
+
+/* Materials (Sec. 2.3):
+ *  FLUID_TAIT     weakly compressible fluid, p = (K/gamma)((1/J)^gamma - 1);
+ *                 gamma = 1 with K = rho0 c^2 is eq:eos
+ *  DP_HENCKY      Drucker-Prager sand: Hencky strain of F_e, radial return onto
+ *                 the cone with slope (sqrt2/3) q_phi (q_phi of App. A),
+ *                 stress-free apex for tr(eps) > 0
+ *  HENCKY_ELASTIC the same elastic law without the return (checks only) */
+enum { MPM_FLUID_TAIT = 0, MPM_DP_HENCKY = 1, MPM_HENCKY_ELASTIC = 2 };
+
+/* Wall behaviour on a face (Sec. 2.2 ghost cells; Sec. 5.3 eq:coulomb_friction
+ * with a resting wall).  Applies to nodes on or beyond the wall plane and only
+ * while the node velocity points into the wall. */
+enum { MPM_WALL_SLIP = 0, MPM_WALL_STICK = 1, MPM_WALL_COULOMB = 2 };
+
+/* Particle fields for mpm_read_state / mpm_write_state. */
+enum {
+    MPM_FIELD_X = 0,      /* position, dim comps */
+    MPM_FIELD_V = 1,      /* velocity, dim comps */
+    MPM_FIELD_C = 2,      /* APIC affine matrix, dim*dim comps */
+    MPM_FIELD_F = 3,      /* elastic deformation gradient, dim*dim (sand) */
+    MPM_FIELD_FMI = 4,    /* F - I, dim*dim (sand); stored form, exact */
+    MPM_FIELD_J = 5,      /* volume ratio J = rho0/rho, 1 comp (fluid) */
+    MPM_FIELD_JM1 = 6,    /* J - 1, 1 comp (fluid); stored form, exact */
+    MPM_FIELD_STRESS = 7, /* V0 * Kirchhoff stress = V_p sigma_p, dim*dim */
+    MPM_FIELD_PID = 8     /* original particle index, int32 */
+};
+enum { MPM_ORDER_MEMORY = 0, MPM_ORDER_PID = 1 };
+
+/* Grid fields for mpm_read_grid: last step's nodal mass and nodal velocity
+ * after the grid update and walls, on the dense node box of
+ * (n[a] + 1 + 2*ghost) nodes per axis, x fastest. */
+enum { MPM_GRID_MASS = 0, MPM_GRID_VEL = 1 };
+
+typedef struct mpm_config {
+    int32_t dim;           /* 2 or 3 */
+    int32_t precision;     /* MPM_F32 or MPM_F64 */
+    int32_t n[3];          /* cells per axis; domain is [0, n[a]*dx] */
+    int32_t ghost;         /* ghost node layers per side, >= 1 */
+    int32_t tile;          /* tile edge in cells: 4 (3D) or 8 (2D); 0 = default */
+    int32_t material;      /* MPM_FLUID_TAIT, MPM_DP_HENCKY, MPM_HENCKY_ELASTIC */
+    int32_t wall_mode[6];  /* faces x-, x+, y-, y+, z-, z+ */
+    int32_t keep_grid;     /* 1: keep nodal mass for mpm_read_grid */
+    double dx;             /* grid spacing */
+    double gravity[3];     /* body force per unit mass */
+    double wall_mu[6];     /* Coulomb coefficient per face */
+    double rho0, bulk, gamma;         /* fluid: reference density, K, gamma */
+    double youngs, poisson, phi_deg;  /* sand: E, nu, friction angle */
+} mpm_config;
+
+typedef struct mpm_ctx mpm_ctx;
+
+/* Validates cfg and creates a context on the current device, bound to
+ * hip_stream (a hipStream_t; NULL = default stream).  Allocates no device
+ * memory.  *out receives the context; EINVAL on a bad configuration. */
+int mpm_create(const mpm_config* cfg, void* hip_stream, mpm_ctx** out);
+
+/* Device bytes needed for n_particles and, if tape_steps > 0, for a
+ * forward-plus-adjoint rollout of tape_steps steps checkpointed every
+ * ckpt_every steps (Sec. 3.3: memory O(N_t / n) per segment). */
+int mpm_workspace_bytes(const mpm_config* cfg, int64_t n_particles, int32_t tape_steps,
+                        int32_t ckpt_every, size_t* bytes);
+
+/* Binds caller-owned device memory (>= mpm_workspace_bytes for the same
+ * arguments, 256-byte aligned).  The memory must stay valid until
+ * mpm_destroy.  Clears the grid.  ENOMEM if too small. */
+int mpm_bind_workspace(mpm_ctx* ctx, void* dev_ptr, size_t bytes, int64_t n_particles,
+                       int32_t tape_steps, int32_t ckpt_every);
+
+/* Sets n particles (n <= the bound capacity) from x[dim][n] and v[dim][n]
+ * (device, context precision), with C = 0, F = I (sand) or J = 1 (fluid),
+ * zero stress cache and pid = 0..n-1; mass and vol0 per particle (eq:semi:
+ * m_p and V_p at rest).  Computes the first cell keys. */
+int mpm_init_particles(mpm_ctx* ctx, int64_t n, const void* x, const void* v,
+                       double vol0, double mass);
+
+/* Per-node Coulomb coefficient of the floor (minus face of the last axis),
+ * overriding wall_mu for that face: count = n[0]+1+2G values in 2D,
+ * (n[0]+1+2G)*(n[1]+1+2G) in 3D, x fastest (device, context precision).
+ * mu = NULL restores the face constant.  The pointer is kept, not copied. */
+int mpm_set_floor_mu(mpm_ctx* ctx, const void* mu, int64_t count);
+
+/* Advances n steps of size dt (Sec. 2.2, USL): per step the particles are
+ * sorted by cell key, P2G, grid update with gravity and walls, G2P with the
+ * velocity gradient, then the constitutive update.  Asynchronous; data errors
+ * (non-finite state) are latched and reported by mpm_sync_status. */
+int mpm_step(mpm_ctx* ctx, int32_t n, double dt);
+
+/* Synchronizes the stream and returns the latched data status (MPM_OK or
+ * MPM_ENONFINITE); *bad_pid (may be NULL) gets the smallest offending pid or
+ * -1.  Clears the latch. */
+int mpm_sync_status(mpm_ctx* ctx, int64_t* bad_pid);
+
+/* Copies a particle field to dst (device; int32 for PID), in memory order or
+ * in pid order.  EINVAL for a field the material does not carry. */
+int mpm_read_state(mpm_ctx* ctx, int32_t field, int32_t order, void* dst);
+
+/* Overwrites a particle field from src (same layout as mpm_read_state).
+ * Writing X recomputes the cell keys.  PID cannot be written. */
+int mpm_write_state(mpm_ctx* ctx, int32_t field, int32_t order, const void* src);
+
+/* Last step's grid field (see MPM_GRID_*), dense node box, device dst.
+ * MASS needs keep_grid = 1. */
+int mpm_read_grid(mpm_ctx* ctx, int32_t which, void* dst);
+
+/* Last step's sort: perm[s] = memory slot, before the step, of the particle
+ * now in slot s; key[s] = cell key of the current positions (used by the
+ * next step).  int32 device arrays of n; either may be NULL. */
+int mpm_read_sort(mpm_ctx* ctx, void* perm, void* key);
+
+/* Per-kernel-class timing of mpm_step: with profiling on, HIP events are
+ * recorded on the context's stream between the kernel classes below, and
+ * mpm_profile_read (synchronizes) returns, per class, the summed event time
+ * in milliseconds and the number of launches since the last read, then
+ * resets.  Arrays hold MPM_PROF_N entries (host memory). */
+enum { MPM_PROF_SCAN = 0, MPM_PROF_BUCKET = 1, MPM_PROF_P2G = 2, MPM_PROF_GRID = 3, MPM_PROF_G2P = 4,
+       MPM_PROF_N = 8 };
+int mpm_profile_enable(mpm_ctx* ctx, int on);
+int mpm_profile_read(mpm_ctx* ctx, double* host_ms, int64_t* host_launches);
+
+/* Number of particles currently set. */
+int64_t mpm_num_particles(const mpm_ctx* ctx);
+
+/* Message of the last failure on ctx (or of the last mpm_create failure when
+ * ctx is NULL).  Valid until the next call on ctx. */
+const char* mpm_last_error(const mpm_ctx* ctx);
+
+/* Frees the context (not the caller's workspace).  Synchronizes the stream. */
+int mpm_destroy(mpm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPM_H */

@@ -1,0 +1,396 @@
+// C-ABI of the solver: configuration checks, workspace layout and binding,
+// and dispatch to the per-precision operation tables.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <string>
+
+#include "mpm_runtime.hpp"
+
+using namespace mpm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int nsym_of(int dim) { return dim * (dim + 1) / 2; }
+
+int nsc_of(const mpm_config& c)
+{
+    int D = c.dim;
+    if (c.material == MPM_FLUID_TAIT) return 2 * D + D * D + 1 + 1;
+    return 2 * D + D * D + D * D + nsym_of(D);
+}
+
+int check_config(const mpm_config* c, std::string& why)
+{
+    if (!c) { why = "config is NULL"; return MPM_EINVAL; }
+    if (c->dim != 2 && c->dim != 3) { why = "dim must be 2 or 3"; return MPM_EINVAL; }
+    if (c->precision != MPM_F32 && c->precision != MPM_F64) { why = "precision must be MPM_F32 or MPM_F64"; return MPM_EINVAL; }
+    for (int a = 0; a < c->dim; ++a)
+        if (c->n[a] < 1 || c->n[a] > 8192) { why = "cells per axis must be in [1, 8192]"; return MPM_EINVAL; }
+    if (c->ghost < 1 || c->ghost > 8) { why = "ghost must be in [1, 8]"; return MPM_EINVAL; }
+    int want_tile = c->dim == 3 ? 4 : 8;
+    if (c->tile != 0 && c->tile != want_tile) { why = "tile must be 4 in 3D and 8 in 2D (64 cells per tile)"; return MPM_EINVAL; }
+    if (!(c->dx > 0.0) || !isfinite(c->dx)) { why = "dx must be positive"; return MPM_EINVAL; }
+    if (c->material < MPM_FLUID_TAIT || c->material > MPM_HENCKY_ELASTIC) { why = "unknown material"; return MPM_EINVAL; }
+    for (int f = 0; f < 6; ++f) {
+        if (c->wall_mode[f] < MPM_WALL_SLIP || c->wall_mode[f] > MPM_WALL_COULOMB) { why = "unknown wall mode"; return MPM_EINVAL; }
+        if (!(c->wall_mu[f] >= 0.0)) { why = "wall friction must be >= 0"; return MPM_EINVAL; }
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(c->gravity[a])) { why = "gravity must be finite"; return MPM_EINVAL; }
+    if (c->material == MPM_FLUID_TAIT) {
+        if (!(c->rho0 > 0.0) || !(c->bulk > 0.0) || !(c->gamma > 0.0)) { why = "fluid needs rho0, bulk, gamma > 0"; return MPM_EINVAL; }
+    } else {
+        if (!(c->youngs > 0.0) || !(c->poisson > -1.0 && c->poisson < 0.5)) { why = "need E > 0 and -1 < nu < 0.5"; return MPM_EINVAL; }
+        if (!(c->phi_deg >= 0.0 && c->phi_deg < 90.0)) { why = "friction angle must be in [0, 90)"; return MPM_EINVAL; }
+    }
+    return MPM_OK;
+}
+
+Geo make_geo(const mpm_config& c)
+{
+    Geo g{};
+    g.dim = c.dim;
+    g.T = c.dim == 3 ? 4 : 8;
+    g.G = c.ghost;
+    g.NN = 1;
+    g.ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < c.dim) {
+            g.n[a] = c.n[a];
+            g.bmax[a] = c.n[a] + 2 * c.ghost;
+            int span = c.n[a] + 2 * c.ghost + 1;
+            g.ntile[a] = (span + g.T - 1) / g.T;
+            g.nd[a] = g.ntile[a] * g.T + 2;
+            g.box[a] = c.n[a] + 1 + 2 * c.ghost;
+        } else {
+            g.n[a] = 1;
+            g.bmax[a] = 0;
+            g.ntile[a] = 1;
+            g.nd[a] = 1;
+            g.box[a] = 1;
+        }
+        g.NN *= g.nd[a];
+        g.ntiles *= g.ntile[a];
+    }
+    return g;
+}
+
+struct Layout {
+    size_t st[2], pid[2], key, perm, tmp, count, tile_off, tile_slot, active, part, meta, status;
+    size_t gm, gp, gv, gmass;
+    size_t total;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap)
+{
+    Layout L{};
+    size_t elem = c.precision == MPM_F64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    size_t ucap = (size_t)(cap > 0 ? cap : 1);
+    for (int b = 0; b < 2; ++b) L.st[b] = take((size_t)nsc_of(c) * ucap * elem);
+    for (int b = 0; b < 2; ++b) L.pid[b] = take(ucap * 4);
+    L.key = take(ucap * 4);
+    L.perm = take(ucap * 4);
+    L.tmp = take(ucap * 4);
+    L.count = take((size_t)g.ntiles * 4);
+    L.tile_off = take((size_t)g.ntiles * 4);
+    L.tile_slot = take((size_t)g.ntiles * 4);
+    L.active = take((size_t)g.ntiles * sizeof(ActiveTile));
+    size_t nsb = (size_t)((g.ntiles + kScanChunk - 1) / kScanChunk);
+    L.part = take(nsb * 2 * 4);
+    L.meta = take(64 * 4);
+    L.status = take(64 * 4);
+    L.gm = take((size_t)g.NN * elem);
+    L.gp = take((size_t)g.NN * c.dim * elem);
+    L.gv = take((size_t)g.NN * c.dim * elem);
+    L.gmass = take((size_t)g.NN * elem);
+    L.total = off;
+    return L;
+}
+
+const Ops* pick_ops(const mpm_config& c)
+{
+    if (c.precision == MPM_F32) return c.dim == 2 ? &ops_f32_2d : &ops_f32_3d;
+    return c.dim == 2 ? &ops_f64_2d : &ops_f64_3d;
+}
+
+int need_bound(mpm_ctx* c)
+{
+    if (!c) return MPM_EINVAL;
+    if (!c->bound) return set_err(c, MPM_ESTATE, "no workspace bound (call mpm_bind_workspace)");
+    return MPM_OK;
+}
+
+int need_particles(mpm_ctx* c)
+{
+    int rc = need_bound(c);
+    if (rc) return rc;
+    if (!c->has_particles) return set_err(c, MPM_ESTATE, "no particles (call mpm_init_particles)");
+    return MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpm_create(const mpm_config* cfg, void* hip_stream, mpm_ctx** out)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return MPM_EINVAL;
+    }
+    *out = nullptr;
+    std::string why;
+    int rc = check_config(cfg, why);
+    if (rc) {
+        g_create_error = why;
+        return rc;
+    }
+    mpm_ctx* c = new (std::nothrow) mpm_ctx();
+    if (!c) {
+        g_create_error = "out of host memory";
+        return MPM_ENOMEM;
+    }
+    c->cfg = *cfg;
+    c->cfg.tile = cfg->dim == 3 ? 4 : 8;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        g_create_error = "hipGetDevice failed";
+        delete c;
+        return MPM_EHIP;
+    }
+    c->geo = make_geo(c->cfg);
+    if ((long long)c->geo.ntiles * 64 >= (1ll << 31)) {
+        g_create_error = "grid too large for 32-bit cell keys";
+        delete c;
+        return MPM_EINVAL;
+    }
+    c->elem = cfg->precision == MPM_F64 ? 8 : 4;
+    c->nsc = nsc_of(c->cfg);
+    c->nsym = nsym_of(cfg->dim);
+    c->ops = pick_ops(c->cfg);
+    *out = c;
+    return MPM_OK;
+}
+
+int mpm_workspace_bytes(const mpm_config* cfg, int64_t n_particles, int32_t tape_steps, int32_t ckpt_every,
+                        size_t* bytes)
+{
+    std::string why;
+    int rc = check_config(cfg, why);
+    if (rc) {
+        g_create_error = why;
+        return rc;
+    }
+    if (!bytes || n_particles < 0 || n_particles >= (1ll << 31) || tape_steps < 0 || ckpt_every < 0) {
+        g_create_error = "bad workspace arguments";
+        return MPM_EINVAL;
+    }
+    mpm_config c = *cfg;
+    Geo g = make_geo(c);
+    *bytes = make_layout(c, g, n_particles).total;
+    return MPM_OK;
+}
+
+int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_particles, int32_t tape_steps,
+                       int32_t ckpt_every)
+{
+    if (!c) return MPM_EINVAL;
+    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return set_err(c, MPM_EINVAL, "workspace must be non-null and 256-byte aligned");
+    if (n_particles < 0 || n_particles >= (1ll << 31) || tape_steps < 0 || ckpt_every < 0)
+        return set_err(c, MPM_EINVAL, "bad workspace arguments");
+    Layout L = make_layout(c->cfg, c->geo, n_particles);
+    if (bytes < L.total)
+        return set_err(c, MPM_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    char* b = (char*)dev_ptr;
+    c->ws = b;
+    c->ws_bytes = bytes;
+    c->cap = n_particles;
+    c->tape_steps = tape_steps;
+    c->ckpt_every = ckpt_every;
+    for (int i = 0; i < 2; ++i) {
+        c->st[i] = b + L.st[i];
+        c->pid[i] = (int32_t*)(b + L.pid[i]);
+    }
+    c->key = (int32_t*)(b + L.key);
+    c->perm = (int32_t*)(b + L.perm);
+    c->tmp = (int32_t*)(b + L.tmp);
+    c->count = (int32_t*)(b + L.count);
+    c->tile_off = (int32_t*)(b + L.tile_off);
+    c->tile_slot = (int32_t*)(b + L.tile_slot);
+    c->active = (ActiveTile*)(b + L.active);
+    c->part = (int32_t*)(b + L.part);
+    c->meta = (int32_t*)(b + L.meta);
+    c->status = (int32_t*)(b + L.status);
+    c->gm = b + L.gm;
+    c->gp = b + L.gp;
+    c->gv = b + L.gv;
+    c->gmass = b + L.gmass;
+    c->cur = 0;
+    c->N = 0;
+    c->has_particles = false;
+    c->stepped = false;
+    c->bound = true;
+    return c->ops->clear_grid(c);
+}
+
+int mpm_init_particles(mpm_ctx* c, int64_t n, const void* x, const void* v, double vol0, double mass)
+{
+    int rc = need_bound(c);
+    if (rc) return rc;
+    if (n < 0 || n > c->cap) return set_err(c, MPM_EINVAL, "particle count exceeds the bound capacity");
+    if (n > 0 && (!x || !v)) return set_err(c, MPM_EINVAL, "x and v must be non-null");
+    if (!(vol0 > 0.0) || !(mass > 0.0)) return set_err(c, MPM_EINVAL, "vol0 and mass must be positive");
+    c->N = n;
+    c->mass = mass;
+    c->vol0 = vol0;
+    c->cur = 0;
+    rc = c->ops->init_particles(c, x, v);
+    if (rc) return rc;
+    c->has_particles = true;
+    c->stepped = false;
+    return MPM_OK;
+}
+
+int mpm_set_floor_mu(mpm_ctx* c, const void* mu, int64_t count)
+{
+    if (!c) return MPM_EINVAL;
+    int64_t want = c->cfg.dim == 3 ? (int64_t)c->geo.box[0] * c->geo.box[1] : c->geo.box[0];
+    if (mu && count != want)
+        return set_err(c, MPM_EINVAL, "floor friction needs " + std::to_string(want) + " values");
+    c->floor_mu = mu;
+    return MPM_OK;
+}
+
+int mpm_step(mpm_ctx* c, int32_t n, double dt)
+{
+    int rc = need_particles(c);
+    if (rc) return rc;
+    if (n < 0) return set_err(c, MPM_EINVAL, "negative step count");
+    if (!(dt >= 0.0) || !isfinite(dt)) return set_err(c, MPM_EINVAL, "dt must be finite and >= 0");
+    if (n == 0 || c->N == 0) return MPM_OK;
+    rc = c->ops->step(c, n, dt);
+    if (!rc) c->stepped = true;
+    return rc;
+}
+
+int mpm_sync_status(mpm_ctx* c, int64_t* bad_pid)
+{
+    int rc = need_bound(c);
+    if (rc) return rc;
+    if (bad_pid) *bad_pid = -1;
+    rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (rc) return rc;
+    int32_t h[2];
+    rc = hip_check(c, hipMemcpy(h, c->status, sizeof(h), hipMemcpyDeviceToHost), "status read");
+    if (rc) return rc;
+    int32_t clear[2] = {0, 0x7fffffff};
+    rc = hip_check(c, hipMemcpy(c->status, clear, sizeof(clear), hipMemcpyHostToDevice), "status clear");
+    if (rc) return rc;
+    if (h[0] & 1) {
+        if (bad_pid) *bad_pid = h[1];
+        return set_err(c, MPM_ENONFINITE, "non-finite particle state (pid " + std::to_string(h[1]) + ")");
+    }
+    return MPM_OK;
+}
+
+int mpm_read_state(mpm_ctx* c, int32_t field, int32_t order, void* dst)
+{
+    int rc = need_particles(c);
+    if (rc) return rc;
+    if (!dst && c->N > 0) return set_err(c, MPM_EINVAL, "dst is NULL");
+    if (order != MPM_ORDER_MEMORY && order != MPM_ORDER_PID) return set_err(c, MPM_EINVAL, "bad order");
+    return c->ops->read_state(c, field, order, dst);
+}
+
+int mpm_write_state(mpm_ctx* c, int32_t field, int32_t order, const void* src)
+{
+    int rc = need_particles(c);
+    if (rc) return rc;
+    if (!src && c->N > 0) return set_err(c, MPM_EINVAL, "src is NULL");
+    if (order != MPM_ORDER_MEMORY && order != MPM_ORDER_PID) return set_err(c, MPM_EINVAL, "bad order");
+    return c->ops->write_state(c, field, order, src);
+}
+
+int mpm_read_grid(mpm_ctx* c, int32_t which, void* dst)
+{
+    int rc = need_bound(c);
+    if (rc) return rc;
+    if (!dst) return set_err(c, MPM_EINVAL, "dst is NULL");
+    return c->ops->read_grid(c, which, dst);
+}
+
+int mpm_read_sort(mpm_ctx* c, void* perm, void* key)
+{
+    int rc = need_particles(c);
+    if (rc) return rc;
+    size_t bytes = sizeof(int32_t) * (size_t)c->N;
+    if (perm && c->N > 0) {
+        if (!c->stepped) return set_err(c, MPM_ESTATE, "no step taken yet");
+        rc = hip_check(c, hipMemcpyAsync(perm, c->perm, bytes, hipMemcpyDeviceToDevice, c->stream), "read perm");
+        if (rc) return rc;
+    }
+    if (key && c->N > 0)
+        return hip_check(c, hipMemcpyAsync(key, c->key, bytes, hipMemcpyDeviceToDevice, c->stream), "read key");
+    return MPM_OK;
+}
+
+int mpm_profile_enable(mpm_ctx* c, int on)
+{
+    if (!c) return MPM_EINVAL;
+    c->prof = on != 0;
+    return MPM_OK;
+}
+
+int mpm_profile_read(mpm_ctx* c, double* host_ms, int64_t* host_launches)
+{
+    if (!c) return MPM_EINVAL;
+    for (int k = 0; k < MPM_PROF_N; ++k) {
+        if (host_ms) host_ms[k] = 0.0;
+        if (host_launches) host_launches[k] = 0;
+    }
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    if (rc) return rc;
+    for (size_t i = 1; i < c->marks.size(); ++i) {
+        int cls = c->marks[i].first;
+        if (cls < 0 || cls >= MPM_PROF_N) continue;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->marks[i - 1].second, c->marks[i].second) != hipSuccess) continue;
+        if (host_ms) host_ms[cls] += ms;
+        if (host_launches) host_launches[cls] += 1;
+    }
+    for (auto& m : c->marks) c->ev_pool.push_back(m.second);
+    c->marks.clear();
+    return MPM_OK;
+}
+
+int64_t mpm_num_particles(const mpm_ctx* c) { return c ? c->N : -1; }
+
+const char* mpm_last_error(const mpm_ctx* c)
+{
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+int mpm_destroy(mpm_ctx* c)
+{
+    if (!c) return MPM_OK;
+    if (c->bound) (void)hipStreamSynchronize(c->stream);
+    for (auto& m : c->marks) c->ev_pool.push_back(m.second);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+    return MPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,425 @@
+// Device-side building blocks of the MPM step for gfx950: quadratic B-spline
+// stencil, small symmetric eigen-solver, constitutive updates, wall rules and
+// wave-level helpers.  Templated on the working precision T (float/double)
+// and the dimension D (2/3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mpm_types.hpp"
+
+namespace mpm {
+
+// ---------------------------------------------------------------------------
+// Scalar helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float mul_exact(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double mul_exact(double a, double b) { return __dmul_rn(a, b); }
+
+template <class T> __device__ __forceinline__ T sq(T a) { return a * a; }
+
+template <class T> __device__ __forceinline__ bool finite(T a) { return isfinite(a); }
+
+// ---------------------------------------------------------------------------
+// Quadratic B-spline stencil (Sec. 2.1).  For t = x/h (rounded product,
+// never fused) the base node is b = floor(t - 1/2) and f = t - b lies in
+// [1/2, 3/2); node b+k has xi = f - k.  The three weights are the pieces of
+// phi-bar evaluated there, and dw is d phi / dx.
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ void stencil_axis(T x, T inv, int& b, T& f, T w[3], T dw[3])
+{
+    T t = mul_exact(x, inv);
+    T fb = floor(t - T(0.5));
+    b = (int)fb;
+    f = t - fb;
+    T a0 = T(1.5) - f, a1 = f - T(1), a2 = f - T(0.5);
+    w[0] = T(0.5) * a0 * a0;
+    w[1] = T(0.75) - a1 * a1;
+    w[2] = T(0.5) * a2 * a2;
+    dw[0] = -a0 * inv;
+    dw[1] = T(-2) * a1 * inv;
+    dw[2] = a2 * inv;
+}
+
+template <class T>
+__device__ __forceinline__ int base_of(T x, T inv)
+{
+    T t = mul_exact(x, inv);
+    return (int)floor(t - T(0.5));
+}
+
+// ---------------------------------------------------------------------------
+// Cell key: tile-major linear index of the base node (base + ghost), tiles
+// ordered x fastest, then the cells inside a tile x fastest.  Every tile has
+// 64 cells (4^3 in 3D, 8^2 in 2D), so key >> 6 is the tile and key & 63 the
+// cell inside it.
+// ---------------------------------------------------------------------------
+
+template <class T, int D>
+__device__ __forceinline__ int cell_key(const Geo& g, const T* xp, T inv)
+{
+    int tl = 0, cl = 0, ts = 1, cs = 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        int B = base_of(xp[a], inv) + g.G;
+        B = B < 0 ? 0 : (B > g.bmax[a] ? g.bmax[a] : B);   // memory guard only
+        tl += (B / g.T) * ts;
+        cl += (B % g.T) * cs;
+        ts *= g.ntile[a];
+        cs *= g.T;
+    }
+    return tl * 64 + cl;
+}
+
+// Tile coordinates of a tile index.
+__device__ __forceinline__ void tile_coords(const Geo& g, int tile, int tc[3])
+{
+    tc[0] = tile % g.ntile[0];
+    int r = tile / g.ntile[0];
+    tc[1] = r % g.ntile[1];
+    tc[2] = r / g.ntile[1];
+}
+
+__device__ __forceinline__ long long node_index(const Geo& g, int I0, int I1, int I2)
+{
+    return ((long long)I2 * g.nd[1] + I1) * g.nd[0] + I0;
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers (wave64)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Groups consecutive lanes holding the same value v (valid lanes only) into
+// runs.  Returns the run's first lane, its length and this lane's rank.
+__device__ __forceinline__ void wave_runs(int v, bool valid, int& head_lane, int& run_len, int& rank)
+{
+    int lane = lane_id();
+    int prev = __shfl_up(v, 1);
+    int prev_valid = __shfl_up((int)valid, 1);
+    bool head = valid && (lane == 0 || !prev_valid || prev != v);
+    unsigned long long heads = __ballot(head);
+    unsigned long long le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    unsigned long long mine = heads & le;
+    head_lane = 63 - __clzll(mine ? mine : 1ull);
+    unsigned long long above = heads & ~le;
+    unsigned long long vmask = __ballot(valid);
+    int next_head = above ? (__ffsll((long long)above) - 1) : 64;
+    // a run ends at the next head or at the first invalid lane after it
+    unsigned long long inval_above = ~vmask & ~le;
+    int next_inval = inval_above ? (__ffsll((long long)inval_above) - 1) : 64;
+    int end = next_head < next_inval ? next_head : next_inval;
+    run_len = end - head_lane;
+    rank = lane - head_lane;
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigen-decomposition by cyclic Jacobi rotations, in registers.
+// A = V diag(ev) V^T.  Packed input: 3D (a00,a11,a22,a01,a02,a12);
+// 2D (a00,a11,a01).  Float stops after a fixed sweep budget; double iterates
+// until the off-diagonal part is negligible.
+// ---------------------------------------------------------------------------
+
+template <class T> struct JacobiTol;
+template <> struct JacobiTol<float> { static constexpr int sweeps = 6; static constexpr float rel = 1e-14f; static constexpr float big = 1e7f; };
+template <> struct JacobiTol<double> { static constexpr int sweeps = 12; static constexpr double rel = 1e-32; static constexpr double big = 1e15; };
+
+template <class T>
+__device__ __forceinline__ void jacobi_rot(T& app, T& aqq, T& apq, T& c, T& s)
+{
+    T theta = (aqq - app) / (T(2) * apq);
+    T at = fabs(theta);
+    T t = (at > JacobiTol<T>::big) ? T(0.5) / theta
+                                   : copysign(T(1), theta) / (at + sqrt(theta * theta + T(1)));
+    c = T(1) / sqrt(t * t + T(1));
+    s = t * c;
+    app -= t * apq;
+    aqq += t * apq;
+    apq = T(0);
+}
+
+template <class T>
+__device__ __forceinline__ void sym_eig3(const T a_in[6], T ev[3], T V[3][3])
+{
+    T a00 = a_in[0], a11 = a_in[1], a22 = a_in[2], a01 = a_in[3], a02 = a_in[4], a12 = a_in[5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) V[i][j] = (i == j) ? T(1) : T(0);
+    for (int sw = 0; sw < JacobiTol<T>::sweeps; ++sw) {
+        T off = a01 * a01 + a02 * a02 + a12 * a12;
+        T dia = a00 * a00 + a11 * a11 + a22 * a22;
+        if (off <= JacobiTol<T>::rel * dia || off == T(0)) break;
+        T c, s;
+        // (p,q) = (0,1), r = 2
+        if (a01 != T(0)) {
+            jacobi_rot(a00, a11, a01, c, s);
+            T r0 = a02, r1 = a12;
+            a02 = c * r0 - s * r1;
+            a12 = s * r0 + c * r1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T vp = V[k][0], vq = V[k][1];
+                V[k][0] = c * vp - s * vq;
+                V[k][1] = s * vp + c * vq;
+            }
+        }
+        // (p,q) = (0,2), r = 1
+        if (a02 != T(0)) {
+            jacobi_rot(a00, a22, a02, c, s);
+            T r0 = a01, r1 = a12;
+            a01 = c * r0 - s * r1;
+            a12 = s * r0 + c * r1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T vp = V[k][0], vq = V[k][2];
+                V[k][0] = c * vp - s * vq;
+                V[k][2] = s * vp + c * vq;
+            }
+        }
+        // (p,q) = (1,2), r = 0
+        if (a12 != T(0)) {
+            jacobi_rot(a11, a22, a12, c, s);
+            T r0 = a01, r1 = a02;
+            a01 = c * r0 - s * r1;
+            a02 = s * r0 + c * r1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                T vp = V[k][1], vq = V[k][2];
+                V[k][1] = c * vp - s * vq;
+                V[k][2] = s * vp + c * vq;
+            }
+        }
+    }
+    ev[0] = a00;
+    ev[1] = a11;
+    ev[2] = a22;
+}
+
+template <class T>
+__device__ __forceinline__ void sym_eig2(const T a_in[3], T ev[2], T V[2][2])
+{
+    T a00 = a_in[0], a11 = a_in[1], a01 = a_in[2];
+    T c = T(1), s = T(0);
+    if (a01 != T(0)) jacobi_rot(a00, a11, a01, c, s);
+    V[0][0] = c;  V[0][1] = s;
+    V[1][0] = -s; V[1][1] = c;
+    ev[0] = a00;
+    ev[1] = a11;
+}
+
+// ---------------------------------------------------------------------------
+// Constitutive updates.  S is V0 * Kirchhoff stress (= V_p sigma_p), stored
+// symmetric: 3D (xx,yy,zz,xy,xz,yz), 2D (xx,yy,xy); a fluid stores the single
+// isotropic value s with S = s I.
+// ---------------------------------------------------------------------------
+
+// Fluid: J' = J det(I + dt L), p = (K/gamma)((1/J')^gamma - 1), S = -V0 J' p I.
+// Uses dJ = J - 1 and det(I + A) - 1 expanded in the invariants of A so that
+// small volume changes keep their relative accuracy.
+template <class T, int D>
+__device__ __forceinline__ void fluid_update(const Phys<T>& P, const T L[D][D], T& dJ, T& s_iso)
+{
+    T dt = P.dt;
+    T dD;
+    if constexpr (D == 3) {
+        T A[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A[i][j] = dt * L[i][j];
+        T tr = A[0][0] + A[1][1] + A[2][2];
+        T m2 = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) + (A[0][0] * A[2][2] - A[0][2] * A[2][0]) +
+               (A[1][1] * A[2][2] - A[1][2] * A[2][1]);
+        T det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        dD = tr + m2 + det;
+    } else {
+        T a00 = dt * L[0][0], a01 = dt * L[0][1], a10 = dt * L[1][0], a11 = dt * L[1][1];
+        dD = (a00 + a11) + (a00 * a11 - a01 * a10);
+    }
+    dJ = dJ + dD + dJ * dD;
+    T J = T(1) + dJ;
+    T p = P.k_over_gamma * expm1(-P.gamma * log1p(dJ));
+    s_iso = -P.vol0 * J * p;
+}
+
+// Sand / elastic: F_tr = (I + dt L) F_e with F_e = I + G, so
+// G_tr = G + dt (L + L G).  Hencky strain from b - I = G_tr + G_tr^T +
+// G_tr G_tr^T: eps_i = log1p(eig_i)/2.  Return onto the Drucker-Prager cone:
+//   apex (tr eps > 0)                 H = 0
+//   elastic (dgamma <= 0)             H = eps
+//   cone                              H = eps - dgamma dev/|dev|
+// with dgamma = |dev| + (d lam + 2 mu)/(2 mu) alpha tr(eps).  Then
+// F_e' = U diag(exp(H - eps)) U^T F_tr and tau = U diag(2 mu H + lam tr H) U^T.
+template <class T, int D>
+__device__ __forceinline__ void hencky_update(const Phys<T>& P, bool plastic, const T L[D][D],
+                                              T G[D][D], T S[D * (D + 1) / 2])
+{
+    T dt = P.dt;
+    T Gt[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T lg = L[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) lg += L[i][k] * G[k][j];
+            Gt[i][j] = G[i][j] + dt * lg;
+        }
+    // b - I
+    T B[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            T s = Gt[i][j] + Gt[j][i];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += Gt[i][k] * Gt[j][k];
+            B[i][j] = s;
+            B[j][i] = s;
+        }
+    T ev[D], U[D][D];
+    if constexpr (D == 3) {
+        T pk[6] = {B[0][0], B[1][1], B[2][2], B[0][1], B[0][2], B[1][2]};
+        T V[3][3];
+        sym_eig3(pk, ev, V);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) U[i][j] = V[i][j];
+    } else {
+        T pk[3] = {B[0][0], B[1][1], B[0][1]};
+        T V[2][2];
+        sym_eig2(pk, ev, V);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) U[i][j] = V[i][j];
+    }
+    T eps[D], tr = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        eps[i] = T(0.5) * log1p(ev[i]);
+        tr += eps[i];
+    }
+    T H[D];
+    int cas = 1;   // 0 apex, 1 elastic, 2 cone
+    if (!plastic) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) H[i] = eps[i];
+    } else if (tr > T(0)) {
+        cas = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) H[i] = T(0);
+    } else {
+        T dev[D], dn2 = T(0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            dev[i] = eps[i] - tr / T(D);
+            dn2 += dev[i] * dev[i];
+        }
+        T dn = sqrt(dn2);
+        T dg = dn + P.cone_coef * tr;
+        if (dg <= T(0)) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) H[i] = eps[i];
+        } else {
+            cas = 2;
+            T r = dg / dn;
+#pragma unroll
+            for (int i = 0; i < D; ++i) H[i] = eps[i] - r * dev[i];
+        }
+    }
+    T trH = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) trH += H[i];
+    // stress
+    T sig[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) sig[i] = P.vol0 * (T(2) * P.mu * H[i] + P.lam * trH);
+    T Sf[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += U[i][k] * sig[k] * U[j][k];
+            Sf[i][j] = s;
+        }
+    if constexpr (D == 3) {
+        S[0] = Sf[0][0]; S[1] = Sf[1][1]; S[2] = Sf[2][2];
+        S[3] = Sf[0][1]; S[4] = Sf[0][2]; S[5] = Sf[1][2];
+    } else {
+        S[0] = Sf[0][0]; S[1] = Sf[1][1]; S[2] = Sf[0][1];
+    }
+    if (cas == 1) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) G[i][j] = Gt[i][j];
+        return;
+    }
+    // G' = U diag(expm1(H - eps)) U^T (I + G_tr) + G_tr
+    T e1[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) e1[i] = expm1(H[i] - eps[i]);
+    T M[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += U[i][k] * e1[k] * U[j][k];
+            M[i][j] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = M[i][j];   // M * I
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += M[i][k] * Gt[k][j];
+            G[i][j] = Gt[i][j] + s;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Walls (Sec. 2.2 ghost cells; Sec. 5.3 Coulomb law at a resting wall).
+// ---------------------------------------------------------------------------
+
+template <class T, int D>
+__device__ __forceinline__ void wall_node(int mode, T mu, int axis, T sign, T v[D])
+{
+    T vn = sign * v[axis];
+    if (!(vn > T(0))) return;
+    if (mode == WALL_STICK) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[a] = T(0);
+        return;
+    }
+    v[axis] = T(0);   // tangential part left
+    if (mode == WALL_SLIP) return;
+    T vt2 = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) vt2 += v[a] * v[a];
+    T vt = sqrt(vt2);
+    if (vt <= mu * vn) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[a] = T(0);
+    } else {
+        T sc = T(1) - mu * vn / vt;
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[a] *= sc;
+    }
+}
+
+}  // namespace mpm

@@ -1,0 +1,953 @@
+// Forward MPM step kernels for gfx950 and their host launchers.
+//
+// One step (Sec. 2.2, update-stress-last):
+//   1. scan_reduce / scan_down  tile histogram -> tile offsets, active tiles
+//   2. bucket                   particles scattered into their tile's range
+//   3. p2g                      per active tile: cell-level stable sort in LDS,
+//                               then P2G (eq:update_m, momentum with the APIC
+//                               affine term of App. B, internal force from the
+//                               stress cache) into an LDS node block, flushed
+//                               with global atomics
+//   4. grid                     v = P/m + dt g, walls (Sec. 5.3 friction law)
+//   5. g2p                      per active tile: LDS node block, velocity,
+//                               APIC C, velocity gradient, position, then the
+//                               constitutive update; writes the state in the
+//                               new sorted order and counts the next keys
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include <algorithm>
+
+#include "mpm_device.hpp"
+#include "mpm_runtime.hpp"
+
+namespace mpm {
+
+template <int D> struct TileShape;
+template <> struct TileShape<3> { static constexpr int TE = 4, BE = 6, NB = 216; };
+template <> struct TileShape<2> { static constexpr int TE = 8, BE = 10, NB = 100; };
+
+constexpr int kSortCap = 2048;   // particles per tile sorted in LDS (larger: global)
+
+// Active-list entry handled by this workgroup on iteration `it`.  Workgroup b
+// runs on XCD b % 8; each XCD gets one contiguous chunk of the active list so
+// that neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int tile_entry(int it, int n_active)
+{
+    int nx = 8;
+    int per = gridDim.x / nx;
+    int xcd = blockIdx.x % nx;
+    int lb = blockIdx.x / nx;
+    int chunk = (n_active + nx - 1) / nx;
+    int e = xcd * chunk + lb + it * per;
+    int end = min((xcd + 1) * chunk, n_active);
+    return e < end ? e : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide exclusive scan of two ints (256 threads).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void block_scan2(int a, int b, int& ex_a, int& ex_b, int& tot_a, int& tot_b)
+{
+    __shared__ int sa[4], sb[4];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int ia = a, ib = b;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int ta = __shfl_up(ia, o), tb = __shfl_up(ib, o);
+        if (lane >= o) { ia += ta; ib += tb; }
+    }
+    if (lane == 63) { sa[w] = ia; sb[w] = ib; }
+    __syncthreads();
+    int pa = 0, pb = 0;
+    for (int k = 0; k < w; ++k) { pa += sa[k]; pb += sb[k]; }
+    tot_a = sa[0] + sa[1] + sa[2] + sa[3];
+    tot_b = sb[0] + sb[1] + sb[2] + sb[3];
+    ex_a = pa + ia - a;
+    ex_b = pb + ib - b;
+    __syncthreads();
+}
+
+template <int Unused = 0>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int* __restrict__ count, int ntiles,
+                                                        int* __restrict__ part)
+{
+    int base = blockIdx.x * kScanChunk;
+    int s = 0, a = 0;
+    for (int i = threadIdx.x; i < kScanChunk; i += kBlock) {
+        int t = base + i;
+        if (t < ntiles) {
+            int c = count[t];
+            s += c;
+            a += (c > 0);
+        }
+    }
+    int es, ea, ts, ta;
+    block_scan2(s, a, es, ea, ts, ta);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ts;
+        part[2 * blockIdx.x + 1] = ta;
+    }
+}
+
+template <int Unused = 0>
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ count, int ntiles,
+                                                      const int* __restrict__ part,
+                                                      int* __restrict__ tile_off, int* __restrict__ tile_slot,
+                                                      ActiveTile* __restrict__ active, int* __restrict__ meta)
+{
+    // prefix of the earlier chunks
+    int ps = 0, pa = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += kBlock) {
+        ps += part[2 * i];
+        pa += part[2 * i + 1];
+    }
+    int e0, e1, base_s, base_a;
+    block_scan2(ps, pa, e0, e1, base_s, base_a);
+    constexpr int PER = kScanChunk / kBlock;
+    int t0 = blockIdx.x * kScanChunk + threadIdx.x * PER;
+    int c[PER];
+    int ls = 0, la = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int t = t0 + k;
+        c[k] = (t < ntiles) ? count[t] : 0;
+        ls += c[k];
+        la += (c[k] > 0);
+    }
+    int ex_s, ex_a, tot_s, tot_a;
+    block_scan2(ls, la, ex_s, ex_a, tot_s, tot_a);
+    int off = base_s + ex_s, slot = base_a + ex_a;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int t = t0 + k;
+        if (t < ntiles) {
+            tile_off[t] = off;
+            if (c[k] > 0) {
+                tile_slot[t] = slot;
+                ActiveTile e;
+                e.tile = t;
+                e.off = off;
+                e.cnt = c[k];
+                e.pad = 0;
+                active[slot] = e;
+                ++slot;
+            } else {
+                tile_slot[t] = -1;
+            }
+        }
+        off += c[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kBlock - 1) {
+        meta[0] = slot;
+        meta[1] = off;
+    }
+}
+
+// Scatter every particle into its tile's range (order inside a tile is
+// arbitrary here; the P2G kernel sorts it).  Leaves count[] at zero.
+template <int Unused = 0>
+__global__ __launch_bounds__(kBlock) void k_bucket(long long N, const int* __restrict__ key,
+                                                   int* __restrict__ count, const int* __restrict__ tile_off,
+                                                   int* __restrict__ tmp)
+{
+    long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+    bool valid = j < N;
+    int t = valid ? (key[j] >> 6) : -1;
+    int head, len, rank;
+    wave_runs(t, valid, head, len, rank);
+    int base = 0;
+    if (valid && rank == 0) base = atomicSub(&count[t], len) - len;
+    base = __shfl(base, head);
+    if (valid) tmp[tile_off[t] + base + rank] = (int)j;
+}
+
+template <class T, int D>
+__global__ __launch_bounds__(kBlock) void k_keys(Geo g, Phys<T> P, PView<T> cur, long long N,
+                                                 int* __restrict__ key, int* __restrict__ count)
+{
+    long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
+    bool valid = j < N;
+    int k = 0;
+    if (valid) {
+        T xp[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) xp[a] = cur.x[a * cur.cap + j];
+        k = cell_key<T, D>(g, xp, P.inv);
+        key[j] = k;
+    }
+    int head, len, rank;
+    wave_runs(valid ? (k >> 6) : -1, valid, head, len, rank);
+    if (valid && rank == 0) atomicAdd(&count[k >> 6], len);
+}
+
+// ---------------------------------------------------------------------------
+// P2G
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ void weights_from_f(T f, T inv, T w[3], T dw[3])
+{
+    T a0 = T(1.5) - f, a1 = f - T(1), a2 = f - T(0.5);
+    w[0] = T(0.5) * a0 * a0;
+    w[1] = T(0.75) - a1 * a1;
+    w[2] = T(0.5) * a2 * a2;
+    dw[0] = -a0 * inv;
+    dw[1] = T(-2) * a1 * inv;
+    dw[2] = a2 * inv;
+}
+
+template <class T, int D, int MAT>
+__device__ __forceinline__ void p2g_particle(const Phys<T>& P, const PView<T>& cur, int j, const int lb[3],
+                                             const int gb[3], T* s_m, T (*s_p)[TileShape<D>::NB])
+{
+    constexpr int BE = TileShape<D>::BE;
+    const long long cap = cur.cap;
+    T w[D][3], dw[D][3], dd[D][3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T x = cur.x[a * cap + j];
+        T t = mul_exact(x, P.inv);
+        T f = t - T(gb[a]);
+        weights_from_f(f, P.inv, w[a], dw[a]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dd[a][k] = (T(k) - f) * P.h;
+    }
+    T mv[D], mC[D][D], fs[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        mv[a] = P.mass * cur.v[a * cap + j];
+#pragma unroll
+        for (int b = 0; b < D; ++b) mC[a][b] = P.mass * cur.C[(a * D + b) * cap + j];
+    }
+    if constexpr (MAT == MAT_FLUID) {
+        T s = -P.dt * cur.S[j];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) fs[a][b] = (a == b) ? s : T(0);
+    } else {
+        if constexpr (D == 3) {
+            T s0 = cur.S[0 * cap + j], s1 = cur.S[1 * cap + j], s2 = cur.S[2 * cap + j];
+            T s3 = cur.S[3 * cap + j], s4 = cur.S[4 * cap + j], s5 = cur.S[5 * cap + j];
+            fs[0][0] = -P.dt * s0; fs[1][1] = -P.dt * s1; fs[2][2] = -P.dt * s2;
+            fs[0][1] = fs[1][0] = -P.dt * s3;
+            fs[0][2] = fs[2][0] = -P.dt * s4;
+            fs[1][2] = fs[2][1] = -P.dt * s5;
+        } else {
+            T s0 = cur.S[0 * cap + j], s1 = cur.S[1 * cap + j], s2 = cur.S[2 * cap + j];
+            fs[0][0] = -P.dt * s0; fs[1][1] = -P.dt * s1;
+            fs[0][1] = fs[1][0] = -P.dt * s2;
+        }
+    }
+    constexpr int KZ = (D == 3) ? 3 : 1;
+#pragma unroll
+    for (int kz = 0; kz < KZ; ++kz)
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                int k[3] = {kx, ky, kz};
+                T phi = T(1);
+                T gr[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) phi *= w[a][k[a]];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    T gg = dw[a][k[a]];
+#pragma unroll
+                    for (int b = 0; b < D; ++b)
+                        if (b != a) gg *= w[b][k[b]];
+                    gr[a] = gg;
+                }
+                int n;
+                if constexpr (D == 3) n = ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
+                else n = (lb[1] + ky) * BE + lb[0] + kx;
+                atomicAdd(&s_m[n], phi * P.mass);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    T aff = mv[a];
+#pragma unroll
+                    for (int b = 0; b < D; ++b) aff += mC[a][b] * dd[b][k[b]];
+                    T frc = T(0);
+#pragma unroll
+                    for (int b = 0; b < D; ++b) frc += fs[a][b] * gr[b];
+                    atomicAdd(&s_p[a][n], phi * aff + frc);
+                }
+            }
+}
+
+template <class T, int D, int MAT>
+__global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                const ActiveTile* __restrict__ active, const int* __restrict__ tmp,
+                                                const int* __restrict__ key, PView<T> cur, int* __restrict__ perm,
+                                                T* __restrict__ gm, T* __restrict__ gp)
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    __shared__ T s_m[NB];
+    __shared__ T s_p[D][NB];
+    __shared__ int s_cnt[64], s_off[64], s_cur[64];
+    __shared__ int s_sorted[kSortCap];
+    __shared__ int s_max;
+    const int n_active = meta[0];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int it = 0;; ++it) {
+        int e = tile_entry(it, n_active);
+        if (e < 0) break;
+        ActiveTile at = active[e];
+        for (int i = tid; i < NB; i += kBlock) {
+            s_m[i] = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) s_p[a][i] = T(0);
+        }
+        if (tid < 64) { s_cnt[tid] = 0; s_cur[tid] = 0; }
+        __syncthreads();
+        // cell histogram of the tile
+        for (int k = tid; k < at.cnt; k += kBlock) {
+            int j = tmp[at.off + k];
+            atomicAdd(&s_cnt[key[j] & 63], 1);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            int v = s_cnt[lane], inc = v, mx = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                int t = __shfl_up(inc, o);
+                if (lane >= o) inc += t;
+                mx = max(mx, __shfl_xor(mx, o));
+            }
+            s_off[lane] = inc - v;
+            if (lane == 0) s_max = mx;
+        }
+        __syncthreads();
+        const bool in_lds = at.cnt <= kSortCap;
+        int* sorted = in_lds ? s_sorted : (perm + at.off);
+        for (int k = tid; k < at.cnt; k += kBlock) {
+            int j = tmp[at.off + k];
+            int c = key[j] & 63;
+            int pos = atomicAdd(&s_cur[c], 1);
+            sorted[s_off[c] + pos] = j;
+        }
+        if (!in_lds) __threadfence();
+        __syncthreads();
+        // stable order inside each cell: ascending previous slot
+        if (tid < 64) {
+            int* a = sorted + s_off[lane];
+            int n = s_cnt[lane];
+            for (int i = 1; i < n; ++i) {
+                int v = a[i], q = i - 1;
+                while (q >= 0 && a[q] > v) { a[q + 1] = a[q]; --q; }
+                a[q + 1] = v;
+            }
+        }
+        if (!in_lds) __threadfence();
+        __syncthreads();
+        if (in_lds)
+            for (int k = tid; k < at.cnt; k += kBlock) perm[at.off + k] = s_sorted[k];
+        // rounds: lane c takes the r-th particle of cell c, so the lanes of a
+        // wave write distinct nodes at every stencil offset
+        int tc[3];
+        tile_coords(g, at.tile, tc);
+        int lb[3], gb[3];
+        lb[0] = lane % TE;
+        lb[1] = (lane / TE) % TE;
+        lb[2] = (D == 3) ? lane / (TE * TE) : 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gb[a] = tc[a] * TE + lb[a] - g.G;
+        const int mycnt = s_cnt[lane], myoff = s_off[lane], maxc = s_max;
+        for (int r = wave; r < maxc; r += kBlock / 64) {
+            if (r < mycnt) {
+                int j = sorted[myoff + r];
+                p2g_particle<T, D, MAT>(P, cur, j, lb, gb, s_m, s_p);
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < NB; i += kBlock) {
+            T m = s_m[i];
+            if (m != T(0)) {
+                int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
+                long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
+                unsafeAtomicAdd(gm + node, m);
+#pragma unroll
+                for (int a = 0; a < D; ++a) unsafeAtomicAdd(gp + a * g.NN + node, s_p[a][i]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid update over the node blocks of the active tiles.  A node shared by
+// several blocks is handled by exactly one of them: the first active tile
+// among its candidates, own tile first.
+// ---------------------------------------------------------------------------
+
+template <class T, int D>
+__global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                 const ActiveTile* __restrict__ active,
+                                                 const int* __restrict__ tile_slot, T* __restrict__ gm,
+                                                 T* __restrict__ gp, T* __restrict__ gv, T* __restrict__ gmass)
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    const int n_active = meta[0];
+    for (int it = 0;; ++it) {
+        int e = tile_entry(it, n_active);
+        if (e < 0) break;
+        int tile = active[e].tile;
+        int tc[3];
+        tile_coords(g, tile, tc);
+        for (int i = threadIdx.x; i < NB; i += kBlock) {
+            int l[3] = {i % BE, (i / BE) % BE, (D == 3) ? i / (BE * BE) : 0};
+            int I[3], own[3];
+            bool down[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                I[a] = (a < D) ? tc[a] * TE + l[a] : 0;
+                own[a] = I[a] / TE;
+                down[a] = (a < D) && (I[a] % TE < 2) && own[a] >= 1;
+            }
+            int des = -1;
+            for (int m = 0; m < (1 << D) && des < 0; ++m) {
+                bool ok = true;
+                int ct[3] = {own[0], own[1], own[2]};
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    if ((m >> a) & 1) {
+                        if (!down[a]) ok = false;
+                        ct[a] -= 1;
+                    }
+                    if (ct[a] >= g.ntile[a]) ok = false;
+                }
+                if (!ok) continue;
+                int tl = (ct[2] * g.ntile[1] + ct[1]) * g.ntile[0] + ct[0];
+                if (tile_slot[tl] >= 0) des = tl;
+            }
+            if (des != tile) continue;
+            long long node = node_index(g, I[0], I[1], I[2]);
+            T m = gm[node];
+            T v[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) v[a] = T(0);
+            if (m > T(0)) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) v[a] = gp[a * g.NN + node] / m + P.dt * P.g[a];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    int ip = I[a] - g.G;
+                    if (ip <= 0) {
+                        T mu = P.wall_mu[2 * a];
+                        if (a == D - 1 && P.floor_mu) {
+                            int fx = min(I[0], g.box[0] - 1);
+                            int fi = (D == 3) ? min(I[1], g.box[1] - 1) * P.floor_stride + fx : fx;
+                            mu = P.floor_mu[fi];
+                        }
+                        wall_node<T, D>(P.wall_mode[2 * a], mu, a, T(-1), v);
+                    }
+                    if (ip >= g.n[a]) wall_node<T, D>(P.wall_mode[2 * a + 1], P.wall_mu[2 * a + 1], a, T(1), v);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                gv[a * g.NN + node] = v[a];
+                gp[a * g.NN + node] = T(0);
+            }
+            if (P.keep_grid) gmass[node] = m;
+            gm[node] = T(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// G2P + kinematics + constitutive
+// ---------------------------------------------------------------------------
+
+template <class T, int D, int MAT>
+__global__ __launch_bounds__(kBlock) void k_g2p(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                const ActiveTile* __restrict__ active, const int* __restrict__ perm,
+                                                PView<T> cur, PView<T> nxt, const T* __restrict__ gv,
+                                                int* __restrict__ key_out, int* __restrict__ count,
+                                                int* __restrict__ status)
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    constexpr int NS = D * (D + 1) / 2;
+    __shared__ T s_v[D][NB];
+    const int n_active = meta[0];
+    const int tid = threadIdx.x;
+    const long long cap = cur.cap;
+    for (int it = 0;; ++it) {
+        int e = tile_entry(it, n_active);
+        if (e < 0) break;
+        ActiveTile at = active[e];
+        int tc[3];
+        tile_coords(g, at.tile, tc);
+        for (int i = tid; i < NB; i += kBlock) {
+            int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
+            long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) s_v[a][i] = gv[a * g.NN + node];
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < at.cnt; k0 += kBlock) {
+            int k = k0 + tid;
+            bool valid = k < at.cnt;
+            int newkey = 0;
+            if (valid) {
+                long long s = at.off + k;
+                int j = perm[s];
+                T xp[D], w[D][3], dw[D][3], dd[D][3];
+                int lb[3] = {0, 0, 0};
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    xp[a] = cur.x[a * cap + j];
+                    int b;
+                    T f;
+                    stencil_axis(xp[a], P.inv, b, f, w[a], dw[a]);
+                    int l = b + g.G - tc[a] * TE;
+                    lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);   // memory guard only
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
+                }
+                T vn[D], Bm[D][D], Lm[D][D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    vn[a] = T(0);
+#pragma unroll
+                    for (int b = 0; b < D; ++b) { Bm[a][b] = T(0); Lm[a][b] = T(0); }
+                }
+                constexpr int KZ = (D == 3) ? 3 : 1;
+#pragma unroll
+                for (int kz = 0; kz < KZ; ++kz)
+#pragma unroll
+                    for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                        for (int kx = 0; kx < 3; ++kx) {
+                            int kk[3] = {kx, ky, kz};
+                            int n;
+                            if constexpr (D == 3) n = ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
+                            else n = (lb[1] + ky) * BE + lb[0] + kx;
+                            T phi = T(1), gr[D];
+#pragma unroll
+                            for (int a = 0; a < D; ++a) phi *= w[a][kk[a]];
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                T gg = dw[a][kk[a]];
+#pragma unroll
+                                for (int b = 0; b < D; ++b)
+                                    if (b != a) gg *= w[b][kk[b]];
+                                gr[a] = gg;
+                            }
+#pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                T vi = s_v[a][n];
+                                T pv = phi * vi;
+                                vn[a] += pv;
+#pragma unroll
+                                for (int b = 0; b < D; ++b) {
+                                    Bm[a][b] += pv * dd[b][kk[b]];
+                                    Lm[a][b] += vi * gr[b];
+                                }
+                            }
+                        }
+                bool bad = false;
+                T xn[D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    T xv = xp[a] + P.dt * vn[a];
+                    bad |= !finite(xv) || !finite(vn[a]);
+                    xv = fmin(fmax(xv, T(0)), P.ext[a]);
+                    xn[a] = xv;
+                    nxt.x[a * cap + s] = xv;
+                    nxt.v[a * cap + s] = vn[a];
+#pragma unroll
+                    for (int b = 0; b < D; ++b) nxt.C[(a * D + b) * cap + s] = P.Dinv * Bm[a][b];
+                }
+                if constexpr (MAT == MAT_FLUID) {
+                    T dJ = cur.G[j], si;
+                    fluid_update<T, D>(P, Lm, dJ, si);
+                    bad |= !finite(si) || !finite(dJ);
+                    nxt.G[s] = dJ;
+                    nxt.S[s] = si;
+                } else {
+                    T Gm[D][D], Sv[NS];
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+#pragma unroll
+                        for (int b = 0; b < D; ++b) Gm[a][b] = cur.G[(a * D + b) * cap + j];
+                    hencky_update<T, D>(P, MAT == MAT_SAND, Lm, Gm, Sv);
+#pragma unroll
+                    for (int a = 0; a < D; ++a)
+#pragma unroll
+                        for (int b = 0; b < D; ++b) nxt.G[(a * D + b) * cap + s] = Gm[a][b];
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        bad |= !finite(Sv[q]);
+                        nxt.S[q * cap + s] = Sv[q];
+                    }
+                }
+                int pid = cur.pid[j];
+                nxt.pid[s] = pid;
+                if (bad) {
+                    atomicOr(&status[0], 1);
+                    atomicMin(&status[1], pid);
+                }
+                newkey = cell_key<T, D>(g, xn, P.inv);
+                key_out[s] = newkey;
+            }
+            int head, len, rank;
+            wave_runs(valid ? (newkey >> 6) : -1, valid, head, len, rank);
+            if (valid && rank == 0) atomicAdd(&count[newkey >> 6], len);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void k_fill(T* p, long long n, T v)
+{
+    long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    long long stride = (long long)gridDim.x * kBlock;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// Particle field copy between the ABI layout (ncomp x N, memory or pid order)
+// and the workspace layout (ncomp x cap, memory order), with the stored-form
+// conversions: F = I + G, J = 1 + dJ, symmetric S <-> full dim x dim.
+enum { CONV_COPY = 0, CONV_ADD_IDENTITY = 1, CONV_ADD_ONE = 2, CONV_SYM = 3, CONV_ISO = 4 };
+
+template <class T, int D>
+__global__ void k_read_field(const T* __restrict__ src, long long cap, const int32_t* __restrict__ pid,
+                             long long N, int ncomp, int conv, int by_pid, T* __restrict__ dst)
+{
+    long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    long long o = by_pid ? pid[s] : s;
+    for (int c = 0; c < ncomp; ++c) {
+        T v;
+        int a = c / D, b = c % D;
+        switch (conv) {
+        case CONV_ADD_IDENTITY: v = src[c * cap + s] + ((a == b) ? T(1) : T(0)); break;
+        case CONV_ADD_ONE: v = src[s] + T(1); break;
+        case CONV_SYM: {
+            int q;
+            if (D == 3) q = (a == b) ? a : ((a + b == 1) ? 3 : ((a + b == 2) ? 4 : 5));
+            else q = (a == b) ? a : 2;
+            v = src[q * cap + s];
+            break;
+        }
+        case CONV_ISO: v = (a == b) ? src[s] : T(0); break;
+        default: v = src[c * cap + s];
+        }
+        dst[c * N + o] = v;
+    }
+}
+
+template <class T, int D>
+__global__ void k_write_field(T* __restrict__ dst, long long cap, const int32_t* __restrict__ pid,
+                              long long N, int ncomp, int conv, int by_pid, const T* __restrict__ src)
+{
+    long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    long long o = by_pid ? pid[s] : s;
+    if (conv == CONV_SYM) {
+        if (D == 3) {
+            dst[0 * cap + s] = src[0 * N + o];
+            dst[1 * cap + s] = src[4 * N + o];
+            dst[2 * cap + s] = src[8 * N + o];
+            dst[3 * cap + s] = T(0.5) * (src[1 * N + o] + src[3 * N + o]);
+            dst[4 * cap + s] = T(0.5) * (src[2 * N + o] + src[6 * N + o]);
+            dst[5 * cap + s] = T(0.5) * (src[5 * N + o] + src[7 * N + o]);
+        } else {
+            dst[0 * cap + s] = src[0 * N + o];
+            dst[1 * cap + s] = src[3 * N + o];
+            dst[2 * cap + s] = T(0.5) * (src[1 * N + o] + src[2 * N + o]);
+        }
+        return;
+    }
+    if (conv == CONV_ISO) {
+        T tr = T(0);
+        for (int a = 0; a < D; ++a) tr += src[(a * D + a) * N + o];
+        dst[s] = tr / T(D);
+        return;
+    }
+    for (int c = 0; c < ncomp; ++c) {
+        int a = c / D, b = c % D;
+        T v = src[c * N + o];
+        if (conv == CONV_ADD_IDENTITY) v -= (a == b) ? T(1) : T(0);
+        if (conv == CONV_ADD_ONE) v -= T(1);
+        dst[c * cap + s] = v;
+    }
+}
+
+template <int Unused = 0>
+__global__ void k_iota(int32_t* p, long long n)
+{
+    long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+// Dense node box (n + 1 + 2G per axis) from the tile-padded grid.
+template <class T>
+__global__ void k_read_grid(Geo g, const T* __restrict__ src, int ncomp, T* __restrict__ dst)
+{
+    long long nbox = (long long)g.box[0] * g.box[1] * g.box[2];
+    long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= nbox) return;
+    int I0 = (int)(i % g.box[0]);
+    long long r = i / g.box[0];
+    int I1 = (int)(r % g.box[1]);
+    int I2 = (int)(r / g.box[1]);
+    long long node = node_index(g, I0, I1, I2);
+    for (int c = 0; c < ncomp; ++c) dst[c * nbox + i] = src[c * g.NN + node];
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <class T>
+Phys<T> make_phys(const mpm_ctx* c, double dt)
+{
+    Phys<T> P{};
+    const mpm_config& k = c->cfg;
+    int D = k.dim;
+    P.h = (T)k.dx;
+    P.inv = T(1) / (T)k.dx;
+    P.Dinv = T(4) / ((T)k.dx * (T)k.dx);
+    P.dt = (T)dt;
+    P.mass = (T)c->mass;
+    P.vol0 = (T)c->vol0;
+    for (int a = 0; a < 3; ++a) {
+        P.g[a] = (T)k.gravity[a];
+        P.ext[a] = (a < D) ? (T)((double)k.n[a] * k.dx) : T(0);
+    }
+    double E = k.youngs, nu = k.poisson;
+    double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    double mu = E / (2.0 * (1.0 + nu));
+    double s = sin(k.phi_deg * M_PI / 180.0);
+    double q_phi = 6.0 * s / (sqrt(3.0) * (3.0 + s));
+    double alpha = sqrt(2.0) / 3.0 * q_phi;
+    P.lam = (T)lam;
+    P.mu = (T)mu;
+    P.cone_coef = (T)((D * lam + 2.0 * mu) / (2.0 * mu) * alpha);
+    P.k_over_gamma = (T)(k.bulk / k.gamma);
+    P.gamma = (T)k.gamma;
+    P.material = k.material;
+    for (int f = 0; f < 6; ++f) {
+        P.wall_mode[f] = k.wall_mode[f];
+        P.wall_mu[f] = (T)k.wall_mu[f];
+    }
+    P.floor_mu = (const T*)c->floor_mu;
+    P.floor_stride = c->geo.box[0];
+    P.keep_grid = k.keep_grid;
+    return P;
+}
+
+template <class T>
+PView<T> view(const mpm_ctx* c, int which)
+{
+    PView<T> v{};
+    T* base = (T*)c->st[which];
+    long long cap = c->cap;
+    int D = c->cfg.dim;
+    v.cap = cap;
+    v.x = base;
+    v.v = base + D * cap;
+    v.C = base + 2 * D * cap;
+    v.G = base + (2 * D + D * D) * cap;
+    bool fluid = c->cfg.material == MAT_FLUID;
+    v.S = v.G + (fluid ? 1 : D * D) * cap;
+    v.pid = c->pid[which];
+    return v;
+}
+
+template <class T, int D>
+struct Solver {
+    static int launch_err(mpm_ctx* c, const char* what) { return hip_check(c, hipGetLastError(), what); }
+
+    static int init_particles(mpm_ctx* c, const void* x, const void* v)
+    {
+        PView<T> s = view<T>(c, c->cur);
+        long long N = c->N, cap = c->cap;
+        hipStream_t st = c->stream;
+        for (int a = 0; a < D; ++a) {
+            if (hipMemcpyAsync(s.x + a * cap, (const T*)x + a * N, sizeof(T) * N, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(s.v + a * cap, (const T*)v + a * N, sizeof(T) * N, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return launch_err(c, "init copy");
+        }
+        // C, G (or dJ) and S start at zero: they follow v contiguously
+        long long rest = (long long)(c->nsc - 2 * D) * cap;
+        if (rest > 0) k_fill<T><<<std::min<long long>(nblocks(rest), 4096), kBlock, 0, st>>>(s.C, rest, T(0));
+        if (N > 0) k_iota<0><<<nblocks(N), kBlock, 0, st>>>(s.pid, N);
+        return recompute_keys(c);
+    }
+
+    static int recompute_keys(mpm_ctx* c)
+    {
+        hipStream_t st = c->stream;
+        k_fill<int><<<std::min<long long>(nblocks(c->geo.ntiles), 4096), kBlock, 0, st>>>(c->count, c->geo.ntiles, 0);
+        if (c->N > 0) {
+            Phys<T> P = make_phys<T>(c, 0.0);
+            k_keys<T, D><<<nblocks(c->N), kBlock, 0, st>>>(c->geo, P, view<T>(c, c->cur), c->N, c->key, c->count);
+        }
+        return launch_err(c, "keys");
+    }
+
+    static int clear_grid(mpm_ctx* c)
+    {
+        hipStream_t st = c->stream;
+        long long NN = c->geo.NN;
+        k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gm, NN, T(0));
+        k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gp, D * NN, T(0));
+        k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gv, D * NN, T(0));
+        k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gmass, NN, T(0));
+        k_fill<int><<<1, kBlock, 0, st>>>(c->status, 16, 0);
+        k_fill<int><<<1, kBlock, 0, st>>>(c->status + 1, 1, 0x7fffffff);
+        return launch_err(c, "clear grid");
+    }
+
+    template <int MAT>
+    static void one_step(mpm_ctx* c, const Phys<T>& P)
+    {
+        hipStream_t st = c->stream;
+        const Geo& g = c->geo;
+        unsigned nsb = (unsigned)((g.ntiles + kScanChunk - 1) / kScanChunk);
+        prof_mark(c, -1);
+        k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
+        k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, c->tile_slot, c->active, c->meta);
+        prof_mark(c, MPM_PROF_SCAN);
+        k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp);
+        prof_mark(c, MPM_PROF_BUCKET);
+        PView<T> cur = view<T>(c, c->cur), nxt = view<T>(c, 1 - c->cur);
+        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->key, cur, c->perm,
+                                                      (T*)c->gm, (T*)c->gp);
+        prof_mark(c, MPM_PROF_P2G);
+        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (T*)c->gm, (T*)c->gp,
+                                                  (T*)c->gv, (T*)c->gmass);
+        prof_mark(c, MPM_PROF_GRID);
+        k_g2p<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, cur, nxt, (const T*)c->gv,
+                                                      c->key, c->count, c->status);
+        prof_mark(c, MPM_PROF_G2P);
+        c->cur = 1 - c->cur;
+    }
+
+    static int step(mpm_ctx* c, int n, double dt)
+    {
+        Phys<T> P = make_phys<T>(c, dt);
+        for (int i = 0; i < n; ++i) {
+            switch (c->cfg.material) {
+            case MAT_FLUID: one_step<MAT_FLUID>(c, P); break;
+            case MAT_SAND: one_step<MAT_SAND>(c, P); break;
+            default: one_step<MAT_ELASTIC>(c, P); break;
+            }
+        }
+        return launch_err(c, "step");
+    }
+
+    // field -> (pointer into state, ncomp in ABI layout, conversion)
+    static int field_desc(mpm_ctx* c, int field, T** ptr, int* ncomp, int* conv)
+    {
+        PView<T> s = view<T>(c, c->cur);
+        bool fluid = c->cfg.material == MAT_FLUID;
+        switch (field) {
+        case MPM_FIELD_X: *ptr = s.x; *ncomp = D; *conv = CONV_COPY; return MPM_OK;
+        case MPM_FIELD_V: *ptr = s.v; *ncomp = D; *conv = CONV_COPY; return MPM_OK;
+        case MPM_FIELD_C: *ptr = s.C; *ncomp = D * D; *conv = CONV_COPY; return MPM_OK;
+        case MPM_FIELD_F:
+            if (fluid) break;
+            *ptr = s.G; *ncomp = D * D; *conv = CONV_ADD_IDENTITY; return MPM_OK;
+        case MPM_FIELD_FMI:
+            if (fluid) break;
+            *ptr = s.G; *ncomp = D * D; *conv = CONV_COPY; return MPM_OK;
+        case MPM_FIELD_J:
+            if (!fluid) break;
+            *ptr = s.G; *ncomp = 1; *conv = CONV_ADD_ONE; return MPM_OK;
+        case MPM_FIELD_JM1:
+            if (!fluid) break;
+            *ptr = s.G; *ncomp = 1; *conv = CONV_COPY; return MPM_OK;
+        case MPM_FIELD_STRESS:
+            *ptr = s.S; *ncomp = D * D; *conv = fluid ? CONV_ISO : CONV_SYM; return MPM_OK;
+        default: break;
+        }
+        return set_err(c, MPM_EINVAL, "field not available for this material");
+    }
+
+    static int read_state(mpm_ctx* c, int field, int order, void* dst)
+    {
+        hipStream_t st = c->stream;
+        PView<T> s = view<T>(c, c->cur);
+        long long N = c->N;
+        if (field == MPM_FIELD_PID) {
+            if (order == MPM_ORDER_PID) return set_err(c, MPM_EINVAL, "pid in pid order is the identity");
+            if (hipMemcpyAsync(dst, s.pid, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                return launch_err(c, "read pid");
+            return MPM_OK;
+        }
+        T* src;
+        int ncomp, conv;
+        int rc = field_desc(c, field, &src, &ncomp, &conv);
+        if (rc) return rc;
+        if (N > 0)
+            k_read_field<T, D><<<nblocks(N), kBlock, 0, st>>>(src, c->cap, s.pid, N, ncomp, conv,
+                                                             order == MPM_ORDER_PID, (T*)dst);
+        return launch_err(c, "read state");
+    }
+
+    static int write_state(mpm_ctx* c, int field, int order, const void* src)
+    {
+        hipStream_t st = c->stream;
+        PView<T> s = view<T>(c, c->cur);
+        long long N = c->N;
+        if (field == MPM_FIELD_PID) return set_err(c, MPM_EINVAL, "pid cannot be written");
+        T* dstp;
+        int ncomp, conv;
+        int rc = field_desc(c, field, &dstp, &ncomp, &conv);
+        if (rc) return rc;
+        if (N > 0)
+            k_write_field<T, D><<<nblocks(N), kBlock, 0, st>>>(dstp, c->cap, s.pid, N, ncomp, conv,
+                                                              order == MPM_ORDER_PID, (const T*)src);
+        rc = launch_err(c, "write state");
+        if (rc) return rc;
+        if (field == MPM_FIELD_X) return recompute_keys(c);
+        return MPM_OK;
+    }
+
+    static int read_grid(mpm_ctx* c, int which, void* dst)
+    {
+        const Geo& g = c->geo;
+        long long nbox = (long long)g.box[0] * g.box[1] * g.box[2];
+        if (which == MPM_GRID_MASS) {
+            if (!c->cfg.keep_grid) return set_err(c, MPM_EINVAL, "grid mass needs keep_grid = 1");
+            k_read_grid<T><<<nblocks(nbox), kBlock, 0, c->stream>>>(g, (const T*)c->gmass, 1, (T*)dst);
+        } else if (which == MPM_GRID_VEL) {
+            k_read_grid<T><<<nblocks(nbox), kBlock, 0, c->stream>>>(g, (const T*)c->gv, D, (T*)dst);
+        } else {
+            return set_err(c, MPM_EINVAL, "unknown grid field");
+        }
+        return launch_err(c, "read grid");
+    }
+
+    static Ops table()
+    {
+        Ops o;
+        o.init_particles = &init_particles;
+        o.recompute_keys = &recompute_keys;
+        o.clear_grid = &clear_grid;
+        o.step = &step;
+        o.read_state = &read_state;
+        o.write_state = &write_state;
+        o.read_grid = &read_grid;
+        return o;
+    }
+};
+
+}  // namespace mpm

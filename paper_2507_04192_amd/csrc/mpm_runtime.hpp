@@ -1,0 +1,120 @@
+// Host runtime state of one solver context and the per-precision operation
+// tables.  The context owns no device memory: every device pointer below is
+// a view into the caller's workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mpm.h"
+#include "mpm_types.hpp"
+
+namespace mpm {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 waves)
+constexpr int kScanChunk = 2048;   // tiles per scan workgroup
+constexpr int kTileWGs = 2048;     // workgroups of the per-tile kernels (8 XCDs x 256)
+
+struct Ops;
+
+}  // namespace mpm
+
+struct mpm_ctx {
+    mpm_config cfg;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    mpm::Geo geo{};
+    int elem = 4;                  // bytes per floating-point scalar
+    int nsc = 0;                   // scalars per particle per state buffer
+    int nsym = 0;                  // stored stress components
+    const mpm::Ops* ops = nullptr;
+
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t cap = 0;               // particle capacity
+    int64_t N = 0;                 // particles set
+    double mass = 0.0, vol0 = 0.0;  // per particle
+    int tape_steps = 0, ckpt_every = 0;
+
+    void* st[2] = {nullptr, nullptr};        // particle state buffers
+    int32_t* pid[2] = {nullptr, nullptr};
+    int cur = 0;
+    int32_t* key = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* tmp = nullptr;
+    int32_t* count = nullptr;
+    int32_t* tile_off = nullptr;
+    int32_t* tile_slot = nullptr;
+    mpm::ActiveTile* active = nullptr;
+    int32_t* part = nullptr;
+    int32_t* meta = nullptr;       // [0] active tiles, [1] particles sorted
+    int32_t* status = nullptr;     // [0] flags, [1] smallest bad pid
+    void* gm = nullptr;            // nodal mass accumulator
+    void* gp = nullptr;            // nodal momentum accumulator [dim]
+    void* gv = nullptr;            // nodal velocity after the grid update [dim]
+    void* gmass = nullptr;         // nodal mass kept for read-back
+    const void* floor_mu = nullptr;
+
+    // per-kernel-class timing (mpm_profile_enable)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, hipEvent_t>> marks;
+
+    bool bound = false;
+    bool has_particles = false;
+    bool stepped = false;
+    std::string err;
+};
+
+namespace mpm {
+
+struct Ops {
+    int (*init_particles)(mpm_ctx*, const void* x, const void* v);
+    int (*recompute_keys)(mpm_ctx*);
+    int (*clear_grid)(mpm_ctx*);
+    int (*step)(mpm_ctx*, int n, double dt);
+    int (*read_state)(mpm_ctx*, int field, int order, void* dst);
+    int (*write_state)(mpm_ctx*, int field, int order, const void* src);
+    int (*read_grid)(mpm_ctx*, int which, void* dst);
+};
+
+extern const Ops ops_f32_2d, ops_f32_3d, ops_f64_2d, ops_f64_3d;
+
+// Records an event on the context's stream that closes a span of kernel class
+// cls (cls < 0 opens a step).  No-op unless profiling is on.
+inline void prof_mark(mpm_ctx* c, int cls)
+{
+    if (!c->prof || c->marks.size() > 400000) return;
+    hipEvent_t e;
+    if (!c->ev_pool.empty()) {
+        e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return;
+    }
+    if (hipEventRecord(e, c->stream) != hipSuccess) {
+        c->ev_pool.push_back(e);
+        return;
+    }
+    c->marks.push_back({cls, e});
+}
+
+inline int set_err(mpm_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+inline int hip_check(mpm_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return MPM_OK;
+    return set_err(c, MPM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace mpm

@@ -1,0 +1,281 @@
+"""ctypes binding of libmpm.so (the C-ABI declared in include/mpm.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch supplies device memory (the workspace and I/O tensors) and the
+stream.  Loading fails loudly when the library has not been built; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpm.so")
+
+MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EHIP, MPM_ENONFINITE, MPM_EDOMAIN, MPM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "EDOMAIN",
+                -6: "ESTATE"}
+MPM_F32, MPM_F64 = 0, 1
+MATERIAL = {"fluid": 0, "sand": 1, "elastic": 2}
+WALL = {"slip": 0, "stick": 1, "coulomb": 2}
+FIELD = {"x": 0, "v": 1, "C": 2, "F": 3, "FmI": 4, "J": 5, "Jm1": 6, "stress": 7, "pid": 8}
+ORDER = {"memory": 0, "pid": 1}
+GRID = {"mass": 0, "vel": 1}
+
+
+class MPMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MpmConfig(ct.Structure):
+    _fields_ = [
+        ("dim", ct.c_int32), ("precision", ct.c_int32), ("n", ct.c_int32 * 3), ("ghost", ct.c_int32),
+        ("tile", ct.c_int32), ("material", ct.c_int32), ("wall_mode", ct.c_int32 * 6),
+        ("keep_grid", ct.c_int32),
+        ("dx", ct.c_double), ("gravity", ct.c_double * 3), ("wall_mu", ct.c_double * 6),
+        ("rho0", ct.c_double), ("bulk", ct.c_double), ("gamma", ct.c_double),
+        ("youngs", ct.c_double), ("poisson", ct.c_double), ("phi_deg", ct.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2507_04192_amd.build`")
+        L = ct.CDLL(LIB_PATH)
+        P, i32, i64 = ct.c_void_p, ct.c_int32, ct.c_int64
+        sig = {
+            "mpm_create": ([P, P, P], ct.c_int),
+            "mpm_workspace_bytes": ([P, i64, i32, i32, P], ct.c_int),
+            "mpm_bind_workspace": ([P, P, ct.c_size_t, i64, i32, i32], ct.c_int),
+            "mpm_init_particles": ([P, i64, P, P, ct.c_double, ct.c_double], ct.c_int),
+            "mpm_set_floor_mu": ([P, P, i64], ct.c_int),
+            "mpm_step": ([P, i32, ct.c_double], ct.c_int),
+            "mpm_sync_status": ([P, P], ct.c_int),
+            "mpm_read_state": ([P, i32, i32, P], ct.c_int),
+            "mpm_write_state": ([P, i32, i32, P], ct.c_int),
+            "mpm_read_grid": ([P, i32, P], ct.c_int),
+            "mpm_read_sort": ([P, P, P], ct.c_int),
+            "mpm_num_particles": ([P], ct.c_int64),
+            "mpm_profile_enable": ([P, ct.c_int], ct.c_int),
+            "mpm_profile_read": ([P, P, P], ct.c_int),
+            "mpm_last_error": ([P], ct.c_char_p),
+            "mpm_destroy": ([P], ct.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [n for n in _HEADER_NAMES if hasattr(lib(), n)]
+
+
+_HEADER_NAMES = [
+    "mpm_create", "mpm_workspace_bytes", "mpm_bind_workspace", "mpm_init_particles",
+    "mpm_set_floor_mu", "mpm_step", "mpm_sync_status", "mpm_read_state", "mpm_write_state",
+    "mpm_read_grid", "mpm_read_sort", "mpm_num_particles", "mpm_last_error", "mpm_destroy",
+    "mpm_profile_enable", "mpm_profile_read",
+]
+PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p"]
+
+
+def make_config(cfg, precision: str = "f64", keep_grid: bool = False) -> MpmConfig:
+    """mpm_config from a workloads.SimConfig."""
+    c = MpmConfig()
+    c.dim = cfg.dim
+    c.precision = MPM_F64 if precision == "f64" else MPM_F32
+    for a in range(3):
+        c.n[a] = int(cfg.n[a])
+        c.gravity[a] = float(cfg.gravity[a])
+    c.ghost = cfg.ghost
+    c.tile = cfg.tile
+    c.material = MATERIAL[cfg.material]
+    for f in range(6):
+        c.wall_mode[f] = WALL[cfg.wall_mode[f]]
+        c.wall_mu[f] = float(cfg.wall_mu[f])
+    c.keep_grid = 1 if keep_grid else 0
+    c.dx = float(cfg.dx)
+    c.rho0, c.bulk, c.gamma = float(cfg.rho0), float(cfg.bulk), float(cfg.gamma)
+    c.youngs, c.poisson, c.phi_deg = float(cfg.youngs), float(cfg.poisson), float(cfg.phi_deg)
+    return c
+
+
+def _check(ctx, rc):
+    if rc != MPM_OK:
+        msg = lib().mpm_last_error(ctx)
+        raise MPMError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One solver context with its workspace (a torch uint8 tensor)."""
+
+    def __init__(self, cfg, precision: str = "f64", capacity: Optional[int] = None,
+                 tape_steps: int = 0, ckpt_every: int = 0, keep_grid: bool = False, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "f64" else torch.float32
+        self.np_dtype = np.float64 if precision == "f64" else np.float32
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._c = make_config(cfg, precision, keep_grid)
+        self.L = lib()
+        ctx = ct.c_void_p()
+        rc = self.L.mpm_create(ct.byref(self._c), ct.c_void_p(self.stream.cuda_stream), ct.byref(ctx))
+        _check(None, rc)
+        self.ctx = ctx
+        self.capacity = capacity
+        self.tape_steps, self.ckpt_every = tape_steps, ckpt_every
+        self.ws = None
+        self._floor_mu = None
+        if capacity is not None:
+            self.bind(capacity, tape_steps, ckpt_every)
+
+    # -- C-ABI calls ---------------------------------------------------------
+    def mpm_workspace_bytes(self, n_particles, tape_steps=0, ckpt_every=0):
+        b = ct.c_size_t()
+        _check(None, self.L.mpm_workspace_bytes(ct.byref(self._c), n_particles, tape_steps, ckpt_every,
+                                                ct.byref(b)))
+        return b.value
+
+    def bind(self, capacity, tape_steps=0, ckpt_every=0):
+        nbytes = self.mpm_workspace_bytes(capacity, tape_steps, ckpt_every)
+        self.ws = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(self.ctx, self.L.mpm_bind_workspace(self.ctx, ct.c_void_p(aligned), nbytes, capacity,
+                                                   tape_steps, ckpt_every))
+        self.capacity = capacity
+        self.tape_steps, self.ckpt_every = tape_steps, ckpt_every
+
+    def mpm_init_particles(self, x, v=None):
+        """x, v: arrays of shape (dim, N) (numpy or torch)."""
+        torch = self.torch
+        xt = self._dev(x)
+        N = xt.shape[1]
+        vt = torch.zeros_like(xt) if v is None else self._dev(v)
+        if self.ws is None:
+            self.bind(N, self.tape_steps, self.ckpt_every)
+        _check(self.ctx, self.L.mpm_init_particles(self.ctx, N, _ptr(xt), _ptr(vt), float(self.cfg.vol0),
+                                                   float(self.cfg.mass)))
+        self._keep = (xt, vt)
+
+    def mpm_set_floor_mu(self, mu):
+        if mu is None:
+            self._floor_mu = None
+            _check(self.ctx, self.L.mpm_set_floor_mu(self.ctx, None, 0))
+            return
+        t = self._dev(mu).reshape(-1)
+        self._floor_mu = t
+        _check(self.ctx, self.L.mpm_set_floor_mu(self.ctx, _ptr(t), t.numel()))
+
+    def mpm_step(self, n=1, dt=None):
+        dt = self.cfg.dt if dt is None else dt
+        _check(self.ctx, self.L.mpm_step(self.ctx, int(n), float(dt)))
+
+    def mpm_sync_status(self):
+        bad = ct.c_int64(-1)
+        rc = self.L.mpm_sync_status(self.ctx, ct.byref(bad))
+        return rc, bad.value
+
+    def num_particles(self):
+        return int(self.L.mpm_num_particles(self.ctx))
+
+    def mpm_read_state(self, field, order="memory"):
+        torch = self.torch
+        N = self.num_particles()
+        d = self.cfg.dim
+        ncomp = {"x": d, "v": d, "C": d * d, "F": d * d, "FmI": d * d, "J": 1, "Jm1": 1,
+                 "stress": d * d, "pid": 1}[field]
+        dt = torch.int32 if field == "pid" else self.dtype
+        out = torch.empty((ncomp, N), dtype=dt, device=self.device)
+        _check(self.ctx, self.L.mpm_read_state(self.ctx, FIELD[field], ORDER[order], _ptr(out)))
+        return out
+
+    def mpm_write_state(self, field, src, order="memory"):
+        t = self._dev(src)
+        _check(self.ctx, self.L.mpm_write_state(self.ctx, FIELD[field], ORDER[order], _ptr(t)))
+        self._keep_w = t
+
+    def mpm_read_grid(self, which):
+        torch = self.torch
+        nd = self.cfg.node_dims()
+        nbox = nd[0] * nd[1] * nd[2]
+        ncomp = 1 if which == "mass" else self.cfg.dim
+        out = torch.empty((ncomp, nbox), dtype=self.dtype, device=self.device)
+        _check(self.ctx, self.L.mpm_read_grid(self.ctx, GRID[which], _ptr(out)))
+        return out
+
+    def mpm_read_sort(self):
+        torch = self.torch
+        N = self.num_particles()
+        perm = torch.empty(N, dtype=torch.int32, device=self.device)
+        key = torch.empty(N, dtype=torch.int32, device=self.device)
+        _check(self.ctx, self.L.mpm_read_sort(self.ctx, _ptr(perm), _ptr(key)))
+        return perm, key
+
+    def read_keys(self):
+        torch = self.torch
+        N = self.num_particles()
+        key = torch.empty(N, dtype=torch.int32, device=self.device)
+        _check(self.ctx, self.L.mpm_read_sort(self.ctx, None, _ptr(key)))
+        return key
+
+    def mpm_profile_enable(self, on=True):
+        _check(self.ctx, self.L.mpm_profile_enable(self.ctx, 1 if on else 0))
+
+    def mpm_profile_read(self):
+        """{class: (total_ms, launches)} since the last read (synchronizes)."""
+        ms = (ct.c_double * 8)()
+        n = (ct.c_int64 * 8)()
+        _check(self.ctx, self.L.mpm_profile_read(self.ctx, ms, n))
+        return {name: (ms[i], n[i]) for i, name in enumerate(PROF_CLASSES)}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.mpm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------------
+    def _dev(self, a):
+        torch = self.torch
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=self.dtype).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=self.dtype).to(self.device).contiguous()
+
+    def state_numpy(self, order="pid"):
+        """All state fields as float64 numpy arrays (synchronizes)."""
+        out = {}
+        fluid = self.cfg.material == "fluid"
+        names = ["x", "v", "C", "stress"] + (["Jm1"] if fluid else ["FmI"])
+        for f in names:
+            out[f] = self.mpm_read_state(f, order).cpu().numpy().astype(np.float64)
+        if order == "memory":
+            out["pid"] = self.mpm_read_state("pid", "memory").cpu().numpy()[0]
+        return out

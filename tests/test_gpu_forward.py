@@ -1,0 +1,254 @@
+"""Forward-step parity: the HIP solver against the oracle on identical seeded
+inputs, through the C-ABI.
+
+Integers (cell keys, sort permutation) must match bit for bit; floating
+point must meet the stated bounds: relative L2 <= 1e-10 (binary64) and
+<= 1e-4 (binary32 against the binary64 oracle) on positions and velocities
+after 10 steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2507_04192_amd import workloads as W
+from tests.helpers import gpu_fields, gpu_solver, oracle_fields, oracle_state, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"\n[gpu] {torch.cuda.get_device_name(0)}", flush=True)
+
+
+def _small_3d(scale_div=8):
+    return W.cylinder_collapse_3d(scale_div=scale_div, seed=0)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["dam2d", "sand3d"])
+def test_keys_and_sort_bit_exact(orc, precision, case):
+    cfg, x = W.dam_break_2d() if case == "dam2d" else _small_3d()
+    print(f"[case] keys/sort {case} {precision} N={x.shape[1]}", flush=True)
+    o = orc.Oracle(cfg, key_f32=(precision == "f32"))
+    s = gpu_solver(cfg, precision, x)
+    xg = _np(s.mpm_read_state("x")).astype(np.float64)       # positions as the GPU holds them
+    key0 = _np(s.read_keys())
+    assert np.array_equal(key0, o.keys(xg))
+    for step in range(3):
+        xb = _np(s.mpm_read_state("x")).astype(np.float64)
+        kb = _np(s.read_keys())
+        assert np.array_equal(kb, o.keys(xb)), f"keys differ before step {step}"
+        s.mpm_step(1)
+        perm, _ = s.mpm_read_sort()
+        assert np.array_equal(_np(perm), o.sort_perm(kb)), f"perm differs at step {step}"
+    rc, _ = s.mpm_sync_status()
+    assert rc == 0
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["dam2d", "sand3d"])
+def test_ten_steps_match_oracle(orc, precision, case):
+    cfg, x = W.dam_break_2d() if case == "dam2d" else _small_3d()
+    print(f"[case] 10 steps {case} {precision} N={x.shape[1]}", flush=True)
+    o = orc.Oracle(cfg)
+    xin = x.astype(np.float32).astype(np.float64) if precision == "f32" else x
+    st = oracle_state(orc, cfg, xin)
+    s = gpu_solver(cfg, precision, xin)
+    o.run(st, 10, cfg.dt)
+    s.mpm_step(10)
+    rc, bad = s.mpm_sync_status()
+    assert rc == 0, bad
+    g = gpu_fields(s)
+    r = oracle_fields(cfg, st)
+    ex, ev = rel_l2(g["x"], r["x"]), rel_l2(g["v"], r["v"])
+    print(f"  rel L2 x={ex:.3e} v={ev:.3e}", flush=True)
+    assert ex <= TOL[precision]
+    assert ev <= TOL[precision]
+    # the other state fields to the same order of accuracy
+    tolf = 1e-8 if precision == "f64" else 5e-3
+    for f in ("C", "stress", "Jm1" if cfg.material == W.FLUID else "FmI"):
+        e = rel_l2(g[f], r[f])
+        print(f"  rel L2 {f}={e:.3e}", flush=True)
+        assert e <= tolf, f
+    if precision == "f64":
+        # memory order matches too: both sides sort the same way every step
+        assert np.array_equal(_np(s.mpm_read_state("pid"))[0], st.pid)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_grid_fields_after_one_step(orc, precision):
+    cfg, x = W.dam_break_2d()
+    print(f"[case] grid fields {precision}", flush=True)
+    rng = np.random.default_rng(31)
+    v = rng.normal(0, 0.3, size=x.shape)
+    o = orc.Oracle(cfg)
+    st = oracle_state(orc, cfg, x, v=v)
+    _, _, gm, gv = o.step(st, cfg.dt, want_grid=True)
+    s = gpu_solver(cfg, precision, x, v=v, keep_grid=True)
+    s.mpm_step(1)
+    m_gpu = _np(s.mpm_read_grid("mass"))[0].astype(np.float64)
+    v_gpu = _np(s.mpm_read_grid("vel")).astype(np.float64)
+    tol = 1e-12 if precision == "f64" else 1e-6
+    assert rel_l2(m_gpu, gm) <= tol
+    assert rel_l2(v_gpu, gv) <= (1e-11 if precision == "f64" else 1e-5)
+    # nodes the particles never reach stay exactly empty on both sides
+    assert np.array_equal(m_gpu == 0, gm == 0)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("material", [W.SAND, W.ELASTIC, W.FLUID])
+def test_random_state_one_step(orc, precision, material):
+    """Random x, v, C, F and stress cache: one step exercises every branch of
+    the return mapping (apex, elastic, cone) and every stencil position."""
+    cfg = W.SimConfig(dim=3, n=(20, 16, 12), dx=0.01, dt=1e-5, material=material, ppc=8,
+                      gravity=(0, 0, -9.81), youngs=1e6, rho0=1500.0,
+                      wall_mode=(W.SLIP, W.STICK, W.SLIP, W.SLIP, W.COULOMB, W.SLIP),
+                      wall_mu=(0, 0, 0, 0, 0.4, 0))
+    N = 5003       # ragged: not a multiple of the workgroup size
+    print(f"[case] random state {material} {precision} N={N}", flush=True)
+    x, v, C, G = W.random_state(cfg, N, 32, vscale=0.5, cscale=5.0, fscale=2e-3, margin=0.0)
+    rng = np.random.default_rng(33)
+    S = rng.normal(0, 1e-3, size=(3, 3, N))
+    S = (S + S.transpose(1, 0, 2)).reshape(9, N)
+    if material == W.FLUID:
+        S = np.repeat(np.eye(3).reshape(9, 1), N, axis=1) * rng.normal(0, 1e-3, size=N)
+        Jm1 = rng.normal(0, 1e-3, size=N)
+        G = None
+    else:
+        Jm1 = None
+    if precision == "f32":
+        x, v, C, S = (a.astype(np.float32).astype(np.float64) for a in (x, v, C, S))
+        G = None if G is None else G.astype(np.float32).astype(np.float64)
+        Jm1 = None if Jm1 is None else Jm1.astype(np.float32).astype(np.float64)
+    o = orc.Oracle(cfg)
+    st = oracle_state(orc, cfg, x, v=v, C=C, G=G, S=S, Jm1=Jm1)
+    s = gpu_solver(cfg, precision, x, v=v, C=C, G=G, S=S, Jm1=Jm1)
+    o.step(st, cfg.dt)
+    s.mpm_step(1)
+    assert s.mpm_sync_status()[0] == 0
+    g = gpu_fields(s)
+    r = oracle_fields(cfg, st)
+    tol = 1e-12 if precision == "f64" else 2e-5
+    for f in g:
+        e = rel_l2(g[f], r[f])
+        print(f"  {f}: {e:.3e}", flush=True)
+        assert e <= (tol if f in ("x", "v", "C") else tol * 100), f
+
+
+def test_floor_friction_field(orc):
+    cfg, x = W.friction_dam_break_2d(scale=1)
+    print("[case] per-node floor friction", flush=True)
+    mu = W.segment_mu(cfg, W.uniform_mu_segments(2))
+    rng = np.random.default_rng(34)
+    v = np.stack([rng.uniform(0.5, 1.5, x.shape[1]), rng.uniform(-1.0, 0.0, x.shape[1])])
+    o = orc.Oracle(cfg)
+    st = oracle_state(orc, cfg, x, v=v)
+    s = gpu_solver(cfg, "f64", x, v=v, floor_mu=mu)
+    o.run(st, 5, cfg.dt, floor_mu=mu)
+    s.mpm_step(5)
+    g, r = gpu_fields(s), oracle_fields(cfg, st)
+    assert rel_l2(g["v"], r["v"]) <= 1e-10
+    assert rel_l2(g["x"], r["x"]) <= 1e-10
+
+
+def test_crowded_tile_uses_global_sort(orc):
+    """More particles in one tile than the in-LDS sort holds (2048)."""
+    cfg = W.SimConfig(dim=2, n=(32, 32, 1), dx=0.01, dt=1e-5, material=W.FLUID, ppc=4,
+                      gravity=(0, -9.81, 0))
+    rng = np.random.default_rng(35)
+    N = 3000
+    # all inside cells [10, 18) x [10, 18): one tile (base + ghost in [8, 16))
+    lo, hi = (8 - 2 + 0.5) * cfg.dx + 1e-6, (16 - 2 + 0.5) * cfg.dx - 1e-6
+    x = rng.uniform(lo, hi, size=(2, N))
+    print(f"[case] crowded tile N={N}", flush=True)
+    o = orc.Oracle(cfg)
+    st = oracle_state(orc, cfg, x)
+    s = gpu_solver(cfg, "f64", x)
+    kb = _np(s.read_keys())
+    assert len(np.unique(kb >> 6)) == 1
+    perm_o, _ = o.step(st, cfg.dt)
+    s.mpm_step(1)
+    perm, _ = s.mpm_read_sort()
+    assert np.array_equal(_np(perm), perm_o)
+    g, r = gpu_fields(s), oracle_fields(cfg, st)
+    assert rel_l2(g["x"], r["x"]) <= 1e-12
+    assert rel_l2(g["v"], r["v"]) <= 1e-10
+
+
+def test_walls_and_clamping(orc):
+    """Particles on the walls and moving out of the box are clamped the same
+    way on both sides."""
+    cfg = W.SimConfig(dim=2, n=(24, 24, 1), dx=0.01, dt=2e-4, material=W.FLUID, ppc=4,
+                      gravity=(0, -9.81, 0),
+                      wall_mode=(W.SLIP, W.STICK, W.COULOMB, W.SLIP, W.SLIP, W.SLIP),
+                      wall_mu=(0, 0, 0.3, 0, 0, 0))
+    rng = np.random.default_rng(36)
+    N = 777
+    x = rng.uniform(0, 0.24, size=(2, N))
+    x[:, :40] = 0.0
+    x[0, 40:80] = 0.24
+    v = rng.normal(0, 2.0, size=(2, N))
+    print("[case] walls and clamping", flush=True)
+    o = orc.Oracle(cfg)
+    st = oracle_state(orc, cfg, x, v=v)
+    s = gpu_solver(cfg, "f64", x, v=v)
+    o.run(st, 4, cfg.dt)
+    s.mpm_step(4)
+    assert s.mpm_sync_status()[0] == 0
+    g, r = gpu_fields(s), oracle_fields(cfg, st)
+    assert np.isfinite(r["x"]).all()
+    # some particles were pushed against the walls and held there
+    ext = cfg.n[0] * cfg.dx
+    assert (g["x"] == 0.0).any() and (g["x"][0] == ext).any()
+    assert rel_l2(g["x"], r["x"]) <= 1e-10
+    assert rel_l2(g["v"], r["v"]) <= 1e-10
+    assert g["x"].min() >= 0.0 and g["x"].max() <= ext
+
+
+def test_empty_and_nan(orc):
+    import torch
+    cfg, x = W.dam_break_2d()
+    s = gpu_solver(cfg, "f64", x[:, :0], capacity=16)
+    s.mpm_step(3)
+    assert s.mpm_sync_status()[0] == 0
+    # non-finite state is latched and reported with the particle id
+    s = gpu_solver(cfg, "f64", x)
+    v = s.mpm_read_state("v", "pid")
+    v[0, 123] = float("nan")
+    s.mpm_write_state("v", v, "pid")
+    s.mpm_step(1)
+    rc, bad = s.mpm_sync_status()
+    assert rc == -4
+    # the NaN spreads through the grid to the particles sharing its nodes;
+    # the latch reports the smallest of their ids
+    vn = _np(s.mpm_read_state("v", "pid"))
+    nan_ids = np.where(~np.isfinite(vn).all(axis=0))[0]
+    assert 123 in nan_ids and bad == nan_ids.min()
+    assert s.mpm_sync_status()[0] == 0      # latch cleared
+
+
+def test_read_write_round_trip(orc):
+    cfg, x = _small_3d()
+    s = gpu_solver(cfg, "f64", x)
+    s.mpm_step(2)
+    pid = _np(s.mpm_read_state("pid"))[0]
+    xm = _np(s.mpm_read_state("x", "memory"))
+    xp = _np(s.mpm_read_state("x", "pid"))
+    assert np.array_equal(xp[:, pid], xm)
+    F = _np(s.mpm_read_state("F", "pid"))
+    G = _np(s.mpm_read_state("FmI", "pid"))
+    eye = np.eye(3).reshape(9, 1)
+    assert np.allclose(F, G + eye, atol=1e-15)
+    s.mpm_write_state("FmI", G * 2, "pid")
+    assert np.array_equal(_np(s.mpm_read_state("FmI", "pid")), G * 2)
+    with pytest.raises(Exception):
+        s.mpm_read_state("J")
