@@ -80,8 +80,8 @@ Geo make_geo(const mpm_config& c)
 }
 
 struct Layout {
-    size_t st[2], pid[2], key, perm, tmp, count, tile_off, tile_slot, active, part, meta, status;
-    size_t gm, gp, gv, gmass;
+    size_t st[2], pid[2], key, perm, tmp, tmpk, count, tile_off, tile_slot, active, part, meta, status;
+    size_t part_grid, gv, gmass;
     size_t total;
 };
 
@@ -103,6 +103,7 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap)
     L.key = take(ucap * 4);
     L.perm = take(ucap * 4);
     L.tmp = take(ucap * 4);
+    L.tmpk = take(ucap * 4);
     L.count = take((size_t)g.ntiles * 4);
     L.tile_off = take((size_t)g.ntiles * 4);
     L.tile_slot = take((size_t)g.ntiles * 4);
@@ -111,8 +112,8 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap)
     L.part = take(nsb * 2 * 4);
     L.meta = take(64 * 4);
     L.status = take(64 * 4);
-    L.gm = take((size_t)g.NN * elem);
-    L.gp = take((size_t)g.NN * c.dim * elem);
+    int nb = c.dim == 3 ? 216 : 100;   // node block of a tile
+    L.part_grid = take((size_t)g.ntiles * (c.dim + 1) * nb * elem);
     L.gv = take((size_t)g.NN * c.dim * elem);
     L.gmass = take((size_t)g.NN * elem);
     L.total = off;
@@ -226,6 +227,7 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     c->key = (int32_t*)(b + L.key);
     c->perm = (int32_t*)(b + L.perm);
     c->tmp = (int32_t*)(b + L.tmp);
+    c->tmpk = (int32_t*)(b + L.tmpk);
     c->count = (int32_t*)(b + L.count);
     c->tile_off = (int32_t*)(b + L.tile_off);
     c->tile_slot = (int32_t*)(b + L.tile_slot);
@@ -233,8 +235,7 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     c->part = (int32_t*)(b + L.part);
     c->meta = (int32_t*)(b + L.meta);
     c->status = (int32_t*)(b + L.status);
-    c->gm = b + L.gm;
-    c->gp = b + L.gp;
+    c->part_grid = b + L.part_grid;
     c->gv = b + L.gv;
     c->gmass = b + L.gmass;
     c->cur = 0;

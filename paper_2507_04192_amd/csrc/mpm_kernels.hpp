@@ -3,12 +3,15 @@
 // One step (Sec. 2.2, update-stress-last):
 //   1. scan_reduce / scan_down  tile histogram -> tile offsets, active tiles
 //   2. bucket                   particles scattered into their tile's range
-//   3. p2g                      per active tile: cell-level stable sort in LDS,
-//                               then P2G (eq:update_m, momentum with the APIC
-//                               affine term of App. B, internal force from the
-//                               stress cache) into an LDS node block, flushed
-//                               with global atomics
-//   4. grid                     v = P/m + dt g, walls (Sec. 5.3 friction law)
+//   3. p2g                      one tile per wave: cell-level stable sort in
+//                               LDS, then P2G (eq:update_m, momentum with the
+//                               APIC affine term of App. B, internal force from
+//                               the stress cache) into the wave's LDS node
+//                               block, written out as the tile's partial block
+//   4. grid                     sums the partial blocks covering each node in
+//                               a fixed order; v = P/m + dt g, walls (Sec. 5.3
+//                               friction law).  No floating-point atomics: the
+//                               step is deterministic.
 //   5. g2p                      per active tile: LDS node block, velocity,
 //                               APIC C, velocity gradient, position, then the
 //                               constitutive update; writes the state in the
@@ -30,7 +33,7 @@ template <int D> struct TileShape;
 template <> struct TileShape<3> { static constexpr int TE = 4, BE = 6, NB = 216; };
 template <> struct TileShape<2> { static constexpr int TE = 8, BE = 10, NB = 100; };
 
-constexpr int kSortCap = 2048;   // particles per tile sorted in LDS (larger: global)
+constexpr int kSortCap = 2048;   // particles per tile sorted in LDS (larger: in perm)
 
 // Active-list entry handled by this workgroup on iteration `it`.  Workgroup b
 // runs on XCD b % 8; each XCD gets one contiguous chunk of the active list so
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ co
 template <int Unused = 0>
 __global__ __launch_bounds__(kBlock) void k_bucket(long long N, const int* __restrict__ key,
                                                    int* __restrict__ count, const int* __restrict__ tile_off,
-                                                   int* __restrict__ tmp)
+                                                   int* __restrict__ tmp, int* __restrict__ tmpk)
 {
     long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
     bool valid = j < N;
@@ -163,7 +166,11 @@ __global__ __launch_bounds__(kBlock) void k_bucket(long long N, const int* __res
     int base = 0;
     if (valid && rank == 0) base = atomicSub(&count[t], len) - len;
     base = __shfl(base, head);
-    if (valid) tmp[tile_off[t] + base + rank] = (int)j;
+    if (valid) {
+        int slot = tile_off[t] + base + rank;
+        tmp[slot] = (int)j;
+        tmpk[slot] = key[j];
+    }
 }
 
 template <class T, int D>
@@ -201,9 +208,38 @@ __device__ __forceinline__ void weights_from_f(T f, T inv, T w[3], T dw[3])
     dw[2] = a2 * inv;
 }
 
-template <class T, int D, int MAT>
+// Orders this wave's LDS accesses: the compiler may not move LDS reads or
+// writes across it, and the hardware executes one wave's LDS operations in
+// order, so a lane sees what another lane of the same wave wrote before.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Active-list entry handled by wave w of this workgroup on iteration `it`
+// (one tile per wave; XCD chunking as in tile_entry).
+__device__ __forceinline__ int wave_tile_entry(int it, int n_active, int w)
+{
+    constexpr int NW = kBlock / 64;
+    int nx = 8;
+    int per = (gridDim.x / nx) * NW;
+    int xcd = blockIdx.x % nx;
+    int lw = (blockIdx.x / nx) * NW + w;
+    int chunk = (n_active + nx - 1) / nx;
+    int e = xcd * chunk + lw + it * per;
+    int end = min((xcd + 1) * chunk, n_active);
+    return e < end ? e : -1;
+}
+
+// One particle's P2G contribution (eq:update_m, the momentum with the APIC
+// affine term of App. B, and the internal force -dt V_p sigma_p grad phi):
+// for each of the 3^D stencil nodes, sink(k, n, add) receives the offset
+// index k, the node's index n in the tile's LDS block and the D+1 values
+// (mass, momentum) to add there.
+template <class T, int D, int MAT, class Sink>
 __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const PView<T>& cur, int j, const int lb[3],
-                                             const int gb[3], T* s_m, T (*s_p)[TileShape<D>::NB])
+                                             const int gb[3], Sink&& sink)
 {
     constexpr int BE = TileShape<D>::BE;
     const long long cap = cur.cap;
@@ -267,7 +303,8 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const PView<T>& c
                 int n;
                 if constexpr (D == 3) n = ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
                 else n = (lb[1] + ky) * BE + lb[0] + kx;
-                atomicAdd(&s_m[n], phi * P.mass);
+                T add[D + 1];
+                add[0] = phi * P.mass;
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     T aff = mv[a];
@@ -276,41 +313,55 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const PView<T>& c
                     T frc = T(0);
 #pragma unroll
                     for (int b = 0; b < D; ++b) frc += fs[a][b] * gr[b];
-                    atomicAdd(&s_p[a][n], phi * aff + frc);
+                    add[1 + a] = phi * aff + frc;
                 }
+                sink((kz * 3 + ky) * 3 + kx, n, add);
             }
 }
 
+// Node index in the tile's LDS block of stencil offset k for a lane whose
+// cell sits at lb.
+template <int D>
+__device__ __forceinline__ int block_node(const int lb[3], int k)
+{
+    constexpr int BE = TileShape<D>::BE;
+    int kx = k % 3, ky = (k / 3) % 3, kz = k / 9;
+    if constexpr (D == 3) return ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
+    else return (lb[1] + ky) * BE + lb[0] + kx;
+}
+
+// P2G, one tile per workgroup.  The workgroup (1) sorts the tile's particles
+// by cell, ties by previous slot, into perm; (2) takes them in rounds, lane c
+// of wave w holding the r-th particle of cell c for r = w, w+4, ...; (3)
+// writes the sum of the waves' node blocks (mass, momentum), in wave order,
+// to the tile's partial block.
 template <class T, int D, int MAT>
 __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, const int* __restrict__ tmp,
-                                                const int* __restrict__ key, PView<T> cur, int* __restrict__ perm,
-                                                T* __restrict__ gm, T* __restrict__ gp)
+                                                const int* __restrict__ tmpk, PView<T> cur, int* __restrict__ perm,
+                                                T* __restrict__ part)
 {
-    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
-    __shared__ T s_m[NB];
-    __shared__ T s_p[D][NB];
+    constexpr int TE = TileShape<D>::TE, NB = TileShape<D>::NB;
+    constexpr int NW = kBlock / 64;
+    constexpr bool kRegAcc = sizeof(T) == 4;            // binary32: sums in registers
+    constexpr int NBLK = NW;                             // one LDS node block per wave
+    constexpr int NK = (D == 3) ? 27 : 9;
+    __shared__ T s_node[NBLK][D + 1][NB];
     __shared__ int s_cnt[64], s_off[64], s_cur[64];
-    __shared__ int s_sorted[kSortCap];
+    __shared__ int s_unord[kSortCap], s_sorted[kSortCap];
     __shared__ int s_max;
     const int n_active = meta[0];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int it = 0;; ++it) {
         int e = tile_entry(it, n_active);
         if (e < 0) break;
-        ActiveTile at = active[e];
-        for (int i = tid; i < NB; i += kBlock) {
-            s_m[i] = T(0);
-#pragma unroll
-            for (int a = 0; a < D; ++a) s_p[a][i] = T(0);
-        }
+        const ActiveTile at = active[e];
+        for (int i = tid; i < NBLK * (D + 1) * NB; i += kBlock) (&s_node[0][0][0])[i] = T(0);
         if (tid < 64) { s_cnt[tid] = 0; s_cur[tid] = 0; }
         __syncthreads();
-        // cell histogram of the tile
-        for (int k = tid; k < at.cnt; k += kBlock) {
-            int j = tmp[at.off + k];
-            atomicAdd(&s_cnt[key[j] & 63], 1);
-        }
+        const bool in_lds = at.cnt <= kSortCap;
+        // cell histogram; the cell of a particle is the low 6 bits of its key
+        for (int k = tid; k < at.cnt; k += kBlock) atomicAdd(&s_cnt[tmpk[at.off + k] & 63], 1);
         __syncthreads();
         if (tid < 64) {
             int v = s_cnt[lane], inc = v, mx = v;
@@ -324,32 +375,41 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
             if (lane == 0) s_max = mx;
         }
         __syncthreads();
-        const bool in_lds = at.cnt <= kSortCap;
-        int* sorted = in_lds ? s_sorted : (perm + at.off);
+        // place each particle in its cell's range (arbitrary order inside)
+        int* unord = in_lds ? s_unord : (perm + at.off);
         for (int k = tid; k < at.cnt; k += kBlock) {
-            int j = tmp[at.off + k];
-            int c = key[j] & 63;
+            int c = tmpk[at.off + k] & 63;
             int pos = atomicAdd(&s_cur[c], 1);
-            sorted[s_off[c] + pos] = j;
+            unord[s_off[c] + pos] = tmp[at.off + k];
         }
-        if (!in_lds) __threadfence();
+        if (!in_lds) __threadfence_block();
         __syncthreads();
-        // stable order inside each cell: ascending previous slot
-        if (tid < 64) {
-            int* a = sorted + s_off[lane];
-            int n = s_cnt[lane];
-            for (int i = 1; i < n; ++i) {
-                int v = a[i], q = i - 1;
-                while (q >= 0 && a[q] > v) { a[q + 1] = a[q]; --q; }
-                a[q + 1] = v;
+        if (in_lds) {
+            // rank inside the cell by previous slot: a stable order
+            for (int k = tid; k < at.cnt; k += kBlock) {
+                int c = tmpk[at.off + k] & 63;
+                int j = tmp[at.off + k];
+                int o = s_off[c], n = s_cnt[c], rank = 0;
+                for (int q = 0; q < n; ++q) rank += unord[o + q] < j;
+                s_sorted[o + rank] = j;
             }
-        }
-        if (!in_lds) __threadfence();
-        __syncthreads();
-        if (in_lds)
+            __syncthreads();
             for (int k = tid; k < at.cnt; k += kBlock) perm[at.off + k] = s_sorted[k];
-        // rounds: lane c takes the r-th particle of cell c, so the lanes of a
-        // wave write distinct nodes at every stencil offset
+        } else {
+            // crowded tile: insertion sort of each cell's range in perm
+            if (tid < 64) {
+                int* a = unord + s_off[tid];
+                int n = s_cnt[tid];
+                for (int i = 1; i < n; ++i) {
+                    int v = a[i], q = i - 1;
+                    while (q >= 0 && a[q] > v) { a[q + 1] = a[q]; --q; }
+                    a[q + 1] = v;
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+        const int* sorted = in_lds ? s_sorted : (perm + at.off);
         int tc[3];
         tile_coords(g, at.tile, tc);
         int lb[3], gb[3];
@@ -359,22 +419,60 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
 #pragma unroll
         for (int a = 0; a < 3; ++a) gb[a] = tc[a] * TE + lb[a] - g.G;
         const int mycnt = s_cnt[lane], myoff = s_off[lane], maxc = s_max;
-        for (int r = wave; r < maxc; r += kBlock / 64) {
-            if (r < mycnt) {
+        if constexpr (kRegAcc) {
+            // a lane sums its cell's particles in registers (they all hit the
+            // same 3^D nodes), then adds the sums to its wave's block; lanes
+            // write distinct nodes per offset and wave_sync orders the offsets
+            T acc[NK][D + 1];
+#pragma unroll
+            for (int k = 0; k < NK; ++k)
+#pragma unroll
+                for (int q = 0; q <= D; ++q) acc[k][q] = T(0);
+            for (int r = w; r < mycnt; r += NW) {
                 int j = sorted[myoff + r];
-                p2g_particle<T, D, MAT>(P, cur, j, lb, gb, s_m, s_p);
+                p2g_particle<T, D, MAT>(P, cur, j, lb, gb, [&](int k, int, const T* add) {
+#pragma unroll
+                    for (int q = 0; q <= D; ++q) acc[k][q] += add[q];
+                });
+            }
+            T (*node)[NB] = s_node[w];
+            if (w < mycnt) {
+#pragma unroll
+                for (int k = 0; k < NK; ++k) {
+                    int n = block_node<D>(lb, k);
+                    T cv[D + 1];
+#pragma unroll
+                    for (int q = 0; q <= D; ++q) cv[q] = node[q][n];
+#pragma unroll
+                    for (int q = 0; q <= D; ++q) node[q][n] = cv[q] + acc[k][q];
+                    wave_sync();
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NK; ++k) wave_sync();
+            }
+        } else {
+            // binary64: hardware LDS atomics (ds_add_f64) into the wave's own
+            // block, issued without waiting; lanes hit distinct nodes per
+            // offset, so the summation order is fixed
+            T (*node)[NB] = s_node[w];
+            for (int r = w; r < maxc; r += NW) {
+                if (r < mycnt) {
+                    int j = sorted[myoff + r];
+                    p2g_particle<T, D, MAT>(P, cur, j, lb, gb, [&](int, int n, const T* add) {
+#pragma unroll
+                        for (int q = 0; q <= D; ++q) atomicAdd(&node[q][n], add[q]);
+                    });
+                }
             }
         }
         __syncthreads();
-        for (int i = tid; i < NB; i += kBlock) {
-            T m = s_m[i];
-            if (m != T(0)) {
-                int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
-                long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
-                unsafeAtomicAdd(gm + node, m);
+        T* dst = part + (long long)e * (D + 1) * NB;
+        for (int i = tid; i < (D + 1) * NB; i += kBlock) {
+            T v = (&s_node[0][0][0])[i];
 #pragma unroll
-                for (int a = 0; a < D; ++a) unsafeAtomicAdd(gp + a * g.NN + node, s_p[a][i]);
-            }
+            for (int b = 1; b < NBLK; ++b) v += (&s_node[b][0][0])[i];
+            dst[i] = v;
         }
         __syncthreads();
     }
@@ -383,14 +481,15 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
 // ---------------------------------------------------------------------------
 // Grid update over the node blocks of the active tiles.  A node shared by
 // several blocks is handled by exactly one of them: the first active tile
-// among its candidates, own tile first.
+// among its candidates, own tile first.  Its mass and momentum are the sum of
+// the partial blocks that cover it, in that same fixed order.
 // ---------------------------------------------------------------------------
 
 template <class T, int D>
 __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                  const ActiveTile* __restrict__ active,
-                                                 const int* __restrict__ tile_slot, T* __restrict__ gm,
-                                                 T* __restrict__ gp, T* __restrict__ gv, T* __restrict__ gmass)
+                                                 const int* __restrict__ tile_slot, const T* __restrict__ part,
+                                                 T* __restrict__ gv, T* __restrict__ gmass)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     const int n_active = meta[0];
@@ -411,12 +510,15 @@ __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __
                 down[a] = (a < D) && (I[a] % TE < 2) && own[a] >= 1;
             }
             int des = -1;
-            for (int m = 0; m < (1 << D) && des < 0; ++m) {
+            T m = T(0), p[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) p[a] = T(0);
+            for (int msk = 0; msk < (1 << D); ++msk) {
                 bool ok = true;
                 int ct[3] = {own[0], own[1], own[2]};
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    if ((m >> a) & 1) {
+                    if ((msk >> a) & 1) {
                         if (!down[a]) ok = false;
                         ct[a] -= 1;
                     }
@@ -424,17 +526,28 @@ __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __
                 }
                 if (!ok) continue;
                 int tl = (ct[2] * g.ntile[1] + ct[1]) * g.ntile[0] + ct[0];
-                if (tile_slot[tl] >= 0) des = tl;
+                int slot = tile_slot[tl];
+                if (slot < 0) continue;
+                if (des < 0) {
+                    des = tl;
+                    if (des != tile) break;
+                }
+                int li;
+                if constexpr (D == 3) li = ((I[2] - ct[2] * TE) * BE + I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
+                else li = (I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
+                const T* src = part + (long long)slot * (D + 1) * NB;
+                m += src[li];
+#pragma unroll
+                for (int a = 0; a < D; ++a) p[a] += src[(1 + a) * NB + li];
             }
             if (des != tile) continue;
             long long node = node_index(g, I[0], I[1], I[2]);
-            T m = gm[node];
             T v[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) v[a] = T(0);
             if (m > T(0)) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) v[a] = gp[a * g.NN + node] / m + P.dt * P.g[a];
+                for (int a = 0; a < D; ++a) v[a] = p[a] / m + P.dt * P.g[a];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     int ip = I[a] - g.G;
@@ -451,12 +564,8 @@ __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __
                 }
             }
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                gv[a * g.NN + node] = v[a];
-                gp[a * g.NN + node] = T(0);
-            }
+            for (int a = 0; a < D; ++a) gv[a * g.NN + node] = v[a];
             if (P.keep_grid) gmass[node] = m;
-            gm[node] = T(0);
         }
     }
 }
@@ -806,8 +915,6 @@ struct Solver {
     {
         hipStream_t st = c->stream;
         long long NN = c->geo.NN;
-        k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gm, NN, T(0));
-        k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gp, D * NN, T(0));
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gv, D * NN, T(0));
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gmass, NN, T(0));
         k_fill<int><<<1, kBlock, 0, st>>>(c->status, 16, 0);
@@ -825,13 +932,13 @@ struct Solver {
         k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
         k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, c->tile_slot, c->active, c->meta);
         prof_mark(c, MPM_PROF_SCAN);
-        k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp);
+        k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
         prof_mark(c, MPM_PROF_BUCKET);
         PView<T> cur = view<T>(c, c->cur), nxt = view<T>(c, 1 - c->cur);
-        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->key, cur, c->perm,
-                                                      (T*)c->gm, (T*)c->gp);
+        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->tmpk, cur, c->perm,
+                                                      (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
-        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (T*)c->gm, (T*)c->gp,
+        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (const T*)c->part_grid,
                                                   (T*)c->gv, (T*)c->gmass);
         prof_mark(c, MPM_PROF_GRID);
         k_g2p<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, cur, nxt, (const T*)c->gv,

@@ -48,6 +48,7 @@ struct mpm_ctx {
     int32_t* key = nullptr;
     int32_t* perm = nullptr;
     int32_t* tmp = nullptr;
+    int32_t* tmpk = nullptr;       // key of each bucketed particle
     int32_t* count = nullptr;
     int32_t* tile_off = nullptr;
     int32_t* tile_slot = nullptr;
@@ -55,8 +56,7 @@ struct mpm_ctx {
     int32_t* part = nullptr;
     int32_t* meta = nullptr;       // [0] active tiles, [1] particles sorted
     int32_t* status = nullptr;     // [0] flags, [1] smallest bad pid
-    void* gm = nullptr;            // nodal mass accumulator
-    void* gp = nullptr;            // nodal momentum accumulator [dim]
+    void* part_grid = nullptr;     // per active tile: P2G node block, mass + momentum
     void* gv = nullptr;            // nodal velocity after the grid update [dim]
     void* gmass = nullptr;         // nodal mass kept for read-back
     const void* floor_mu = nullptr;

@@ -252,3 +252,17 @@ def test_read_write_round_trip(orc):
     assert np.array_equal(_np(s.mpm_read_state("FmI", "pid")), G * 2)
     with pytest.raises(Exception):
         s.mpm_read_state("J")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_step_is_deterministic(orc, precision):
+    """No floating-point atomics anywhere in the step: two runs from the same
+    input agree bit for bit."""
+    cfg, x = _small_3d()
+    out = []
+    for _ in range(2):
+        s = gpu_solver(cfg, precision, x)
+        s.mpm_step(5)
+        out.append({f: _np(s.mpm_read_state(f, "memory")) for f in ("x", "v", "C", "FmI", "stress", "pid")})
+    for f in out[0]:
+        assert np.array_equal(out[0][f], out[1][f]), f
