@@ -95,7 +95,7 @@ def _declare_adjoint(L):
     P = ct.c_void_p
     i64, f64 = ct.c_int64, ct.c_double
     L.orc_adjoint_step.restype = ct.c_int
-    L.orc_adjoint_step.argtypes = [P, i64, f64, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    L.orc_adjoint_step.argtypes = [P, i64, f64, P] + [P] * 6 + [P] * 6 + [P] * 6 + [P]
 
 
 def _ptr(a):
@@ -268,3 +268,150 @@ class Oracle:
         for _ in range(steps):
             self.step(st, dt, floor_mu)
         return st
+
+
+# ---------------------------------------------------------------------------
+# Observation operators, loss and its gradient (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+class Observations:
+    """Masked least-squares supervision (eq:inverse_loss).
+
+    frames      steps after which the state is observed (1-based, ascending)
+    tracer_pid  particle ids tracked by the Lagrangian operator Q_l(z) = z_l
+    lag_field   'x' or 'v'
+    lag_target  (n_frames, dim, n_tracers); lag_mask (n_frames, n_tracers)
+    box_lo/hi   (n_boxes, dim): Eulerian regions [lo, hi) (half-open)
+    eul_field   'x' or 'v'; Q_l = mean over the particles inside the box
+    eul_target  (n_frames, dim, n_boxes); eul_mask (n_frames, n_boxes)
+    An empty box contributes nothing at that frame; membership is held fixed
+    when differentiating.
+    """
+
+    def __init__(self, frames, tracer_pid=None, lag_field="x", lag_target=None, lag_mask=None,
+                 box_lo=None, box_hi=None, eul_field="v", eul_target=None, eul_mask=None):
+        self.frames = [int(f) for f in frames]
+        self.tracer_pid = None if tracer_pid is None else np.asarray(tracer_pid, dtype=np.int64)
+        self.lag_field = lag_field
+        self.lag_target = None if lag_target is None else np.asarray(lag_target, dtype=np.float64)
+        self.lag_mask = None if lag_mask is None else np.asarray(lag_mask, dtype=np.float64)
+        self.box_lo = None if box_lo is None else np.asarray(box_lo, dtype=np.float64)
+        self.box_hi = None if box_hi is None else np.asarray(box_hi, dtype=np.float64)
+        self.eul_field = eul_field
+        self.eul_target = None if eul_target is None else np.asarray(eul_target, dtype=np.float64)
+        self.eul_mask = None if eul_mask is None else np.asarray(eul_mask, dtype=np.float64)
+
+
+def observe(st, obs, fi):
+    """Q values at frame index fi: (lagrangian (dim, n_tr) or None, eulerian
+    (dim, n_box) or None, eulerian counts)."""
+    lag = eul = cnt = None
+    if obs.tracer_pid is not None:
+        slot = np.empty(st.N, dtype=np.int64)
+        slot[st.pid] = np.arange(st.N)
+        z = getattr(st, obs.lag_field)
+        lag = z[:, slot[obs.tracer_pid]]
+    if obs.box_lo is not None:
+        z = getattr(st, obs.eul_field)
+        nb = obs.box_lo.shape[0]
+        eul = np.zeros((z.shape[0], nb))
+        cnt = np.zeros(nb, dtype=np.int64)
+        for b in range(nb):
+            inside = np.all((st.x >= obs.box_lo[b][:, None]) & (st.x < obs.box_hi[b][:, None]), axis=0)
+            cnt[b] = inside.sum()
+            if cnt[b] > 0:
+                eul[:, b] = z[:, inside].mean(axis=1)
+    return lag, eul, cnt
+
+
+def frame_loss_and_seed(st, obs, fi):
+    """Loss of frame fi and its gradient with respect to st's x and v (arrays
+    in st's memory order)."""
+    loss = 0.0
+    gx = np.zeros_like(st.x)
+    gv = np.zeros_like(st.v)
+    lag, eul, cnt = observe(st, obs, fi)
+    if lag is not None:
+        m = np.ones(lag.shape[1]) if obs.lag_mask is None else obs.lag_mask[fi]
+        r = lag - obs.lag_target[fi]
+        loss += float((m * (r * r).sum(axis=0)).sum())
+        slot = np.empty(st.N, dtype=np.int64)
+        slot[st.pid] = np.arange(st.N)
+        g = gx if obs.lag_field == "x" else gv
+        np.add.at(g.T, slot[obs.tracer_pid], (2.0 * m * r).T)
+    if eul is not None:
+        nb = eul.shape[1]
+        m = np.ones(nb) if obs.eul_mask is None else obs.eul_mask[fi]
+        g = gx if obs.eul_field == "x" else gv
+        for b in range(nb):
+            if cnt[b] == 0 or m[b] == 0:
+                continue
+            r = eul[:, b] - obs.eul_target[fi][:, b]
+            loss += float(m[b] * (r * r).sum())
+            inside = np.all((st.x >= obs.box_lo[b][:, None]) & (st.x < obs.box_hi[b][:, None]), axis=0)
+            g[:, inside] += (2.0 * m[b] * r / cnt[b])[:, None]
+    return loss, gx, gv
+
+
+def rollout(cfg, x0, v0, steps, dt, floor_mu=None, obs=None, keep_states=False):
+    """Forward rollout; returns (loss, states S^0..S^steps if kept, observed Q per frame)."""
+    o = Oracle(cfg)
+    st = State(cfg, x0, v=v0)
+    states = [st.copy()] if keep_states else None
+    loss = 0.0
+    frames = {} if obs is None else {f: i for i, f in enumerate(obs.frames)}
+    qs = []
+    for t in range(steps):
+        o.step(st, dt, floor_mu)
+        if keep_states:
+            states.append(st.copy())
+        if (t + 1) in frames:
+            fi = frames[t + 1]
+            qs.append(observe(st, obs, fi))
+            loss += frame_loss_and_seed(st, obs, fi)[0]
+    return loss, (states if keep_states else st), qs
+
+
+def adjoint_step(cfg, st_in, adj_out, dt, floor_mu=None, amu=None):
+    """Vector-Jacobian product of one step.  st_in: the step's input state;
+    adj_out: dict of adjoints of the step's outputs (x, v, C, F or J, S), in
+    the output memory order.  Returns the input adjoints (input order)."""
+    L = lib()
+    c = make_config(cfg)
+    d, N = cfg.dim, st_in.N
+    z = lambda *shape: np.zeros(shape)
+    out = {"x": z(d, N), "v": z(d, N), "C": z(d * d, N), "F": z(d * d, N), "J": z(N), "S": z(d * d, N)}
+    a = {k: np.ascontiguousarray(adj_out.get(k, out[k] * 0), dtype=np.float64) for k in out}
+    fm = None if floor_mu is None else _f64(floor_mu)
+    rc = L.orc_adjoint_step(ct.byref(c), N, dt, _ptr(fm),
+                            _ptr(st_in.x), _ptr(st_in.v), _ptr(st_in.C), _ptr(st_in.F), _ptr(st_in.J),
+                            _ptr(st_in.S),
+                            _ptr(a["x"]), _ptr(a["v"]), _ptr(a["C"]), _ptr(a["F"]), _ptr(a["J"]), _ptr(a["S"]),
+                            _ptr(out["x"]), _ptr(out["v"]), _ptr(out["C"]), _ptr(out["F"]), _ptr(out["J"]),
+                            _ptr(out["S"]), _ptr(amu))
+    if rc != 0:
+        raise MemoryError("oracle adjoint failed to allocate")
+    return out
+
+
+def rollout_grad(cfg, x0, v0, steps, dt, floor_mu=None, obs=None):
+    """Loss and its gradient with respect to the initial velocity (pid order)
+    and the per-node floor friction, by a reverse sweep over the stored
+    states (Sec. 3.1, eq:dzda)."""
+    loss, states, _ = rollout(cfg, x0, v0, steps, dt, floor_mu, obs, keep_states=True)
+    frames = {} if obs is None else {f: i for i, f in enumerate(obs.frames)}
+    d = cfg.dim
+    N = states[0].N
+    adj = {"x": np.zeros((d, N)), "v": np.zeros((d, N)), "C": np.zeros((d * d, N)),
+           "F": np.zeros((d * d, N)), "J": np.zeros(N), "S": np.zeros((d * d, N))}
+    amu = None if floor_mu is None else np.zeros_like(np.asarray(floor_mu, dtype=np.float64))
+    for t in range(steps - 1, -1, -1):
+        if (t + 1) in frames:
+            _, gx, gv = frame_loss_and_seed(states[t + 1], obs, frames[t + 1])
+            adj["x"] = adj["x"] + gx
+            adj["v"] = adj["v"] + gv
+        adj = adjoint_step(cfg, states[t], adj, dt, floor_mu, amu)
+    # S^0 is in pid order (fresh state)
+    gv0 = np.empty_like(adj["v"])
+    gv0[:, states[0].pid] = adj["v"]
+    return loss, gv0, amu

@@ -1,0 +1,195 @@
+"""Pins of the oracle's hand-written adjoint against central finite
+differences of the oracle's forward step (binary64, h ~ 1e-6).
+
+A dropped term, a wrong sign or a transposed operand anywhere in the reverse
+sweep (constitutive, G2P, walls, grid, P2G, un-permute) changes the
+directional derivative and fails these checks."""
+import numpy as np
+import pytest
+
+from paper_2507_04192_amd import workloads as W
+
+
+def _cfg(dim, material, **kw):
+    n = (10, 9, 8) if dim == 3 else (16, 12, 1)
+    base = dict(dim=dim, n=n, dx=0.02, dt=2e-4, material=material, ppc=2 ** dim,
+                gravity=(0.0, -9.81, 0.0) if dim == 2 else (0.0, 0.0, -9.81),
+                youngs=2e5, rho0=1000.0, bulk=1e5, gamma=7.0,
+                wall_mode=(W.SLIP, W.STICK, W.COULOMB, W.SLIP, W.COULOMB, W.SLIP),
+                wall_mu=(0.0, 0.0, 0.3, 0.0, 0.3, 0.0))
+    if dim == 2:
+        base["wall_mode"] = (W.SLIP, W.STICK, W.COULOMB, W.SLIP, W.SLIP, W.SLIP)
+    base.update(kw)
+    return W.SimConfig(**base)
+
+
+def _state(orc, cfg, N, seed):
+    x, v, C, G = W.random_state(cfg, N, seed, vscale=0.3, cscale=3.0, fscale=3e-3, margin=0.3)
+    d = cfg.dim
+    rng = np.random.default_rng(seed + 1)
+    S = rng.normal(0, 1e-2, size=(d, d, N))
+    S = (S + S.transpose(1, 0, 2)).reshape(d * d, N)
+    F = G + np.eye(d).reshape(-1, 1)
+    J = 1.0 + rng.normal(0, 1e-3, size=N)
+    if cfg.material == W.FLUID:
+        S = np.repeat(np.eye(d).reshape(-1, 1), N, axis=1) * rng.normal(0, 1e-2, size=N)
+    return orc.State(cfg, x, v=v, C=C, F=F, J=J, S=S)
+
+
+def _outputs(cfg, st):
+    d = cfg.dim
+    out = {"x": st.x, "v": st.v, "C": st.C, "S": st.S}
+    if cfg.material == W.FLUID:
+        out["J"] = st.J
+    else:
+        out["F"] = st.F
+    return out
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("material", [W.FLUID, W.SAND, W.ELASTIC])
+def test_adjoint_step_directional_derivative(orc, dim, material):
+    cfg = _cfg(dim, material)
+    o = orc.Oracle(cfg)
+    N = 300 if dim == 3 else 400
+    st0 = _state(orc, cfg, N, 50 + dim)
+    rng = np.random.default_rng(60 + dim)
+    # random output weights: L = sum <w_f, out_f>
+    st1 = st0.copy()
+    perm, _ = o.step(st1, cfg.dt)
+    w = {k: rng.normal(size=v.shape) for k, v in _outputs(cfg, st1).items()}
+
+    def L(st):
+        s = st.copy()
+        o.step(s, cfg.dt)
+        return sum(float((w[k] * v).sum()) for k, v in _outputs(cfg, s).items())
+
+    adj_out = {k: w[k] for k in w}
+    g = orc.adjoint_step(cfg, st0, adj_out, cfg.dt)
+    fields = ["x", "v", "C", "S"] + (["J"] if material == W.FLUID else ["F"])
+    scale = {"x": 1e-4 * cfg.dx, "v": 1e-3, "C": 1e-2, "S": 1e-4, "J": 1e-5, "F": 1e-5}
+    for f in fields:
+        delta = rng.normal(size=getattr(st0, f).shape) * scale[f]
+        sp, sm = st0.copy(), st0.copy()
+        eps = 1e-2
+        setattr(sp, f, getattr(st0, f) + eps * delta)
+        setattr(sm, f, getattr(st0, f) - eps * delta)
+        fd = (L(sp) - L(sm)) / (2 * eps)
+        ad = float((g[f] * delta).sum())
+        assert abs(fd - ad) <= 2e-6 * max(abs(fd), 1e-12) + 1e-12, (f, fd, ad)
+
+
+@pytest.mark.parametrize("mode", [W.SLIP, W.STICK, W.COULOMB])
+def test_adjoint_walls_and_friction_gradient(orc, mode):
+    """Particles pressed onto and sliding along the floor; derivative of the
+    outputs with respect to the per-node floor friction."""
+    cfg = _cfg(2, W.ELASTIC, wall_mode=(W.SLIP, W.SLIP, mode, W.SLIP, W.SLIP, W.SLIP),
+               wall_mu=(0, 0, 0.3, 0, 0, 0))
+    o = orc.Oracle(cfg)
+    rng = np.random.default_rng(70)
+    N = 300
+    x = np.stack([rng.uniform(0.05, 0.27, N), rng.uniform(0.0, 0.03, N)])
+    v = np.stack([rng.uniform(0.5, 1.5, N), rng.uniform(-1.5, -0.5, N)])
+    st0 = orc.State(cfg, x, v=v)
+    mu = rng.uniform(0.2, 0.4, cfg.floor_nodes())
+    st1 = st0.copy()
+    o.step(st1, cfg.dt, mu)
+    w = {k: rng.normal(size=v.shape) for k, v in _outputs(cfg, st1).items()}
+
+    def L(st, m):
+        s = st.copy()
+        o.step(s, cfg.dt, m)
+        return sum(float((w[k] * v).sum()) for k, v in _outputs(cfg, s).items())
+
+    amu = np.zeros_like(mu)
+    g = orc.adjoint_step(cfg, st0, w, cfg.dt, mu, amu)
+    dmu = rng.normal(size=mu.shape) * 1e-3
+    fd = (L(st0, mu + dmu) - L(st0, mu - dmu)) / 2
+    ad = float((amu * dmu).sum())
+    if mode == W.COULOMB:
+        assert abs(ad) > 0
+    else:
+        assert ad == 0.0
+    assert abs(fd - ad) <= 1e-6 * max(abs(fd), 1e-9) + 1e-12, (fd, ad)
+    dv = rng.normal(size=v.shape) * 1e-4
+    sp, sm = st0.copy(), st0.copy()
+    sp.v = st0.v + dv
+    sm.v = st0.v - dv
+    fd = (L(sp, mu) - L(sm, mu)) / 2
+    ad = float((g["v"] * dv).sum())
+    assert abs(fd - ad) <= 1e-6 * max(abs(fd), 1e-9), (fd, ad)
+
+
+def test_rollout_gradient_friction_and_v0(orc):
+    """Loss on tracer positions of a small dam-break over a Coulomb floor with
+    per-node friction: gradient with respect to the segment friction values
+    and to the initial velocity against central differences."""
+    cfg = W.SimConfig(dim=2, n=(24, 12, 1), dx=1 / 32, dt=2e-4, material=W.FLUID, ppc=4,
+                      gravity=(0, -9.81, 0), rho0=1000.0, bulk=2e4, gamma=7.0,
+                      wall_mode=(W.SLIP, W.SLIP, W.COULOMB, W.SLIP, W.SLIP, W.SLIP))
+    x0 = W.lattice_particles(cfg, W.box_inside((0, 0), (0.25, 0.2)), (0, 0), (0.25, 0.2), seed=71)
+    N = x0.shape[1]
+    rng = np.random.default_rng(72)
+    v0 = np.stack([rng.uniform(0.3, 0.6, N), np.zeros(N)])
+    seg = rng.uniform(0.1, 0.6, 6)
+    seg_len = 0.125
+
+    def mu_of(s):
+        return W.segment_mu(cfg, s, seg_len)
+
+    steps = 40
+    tr = W.pick_tracers(N, 16, 73)
+    frames = [10, 20, 30, 40]
+    # synthetic targets: a run with other friction values
+    _, _, qs = orc.rollout(cfg, x0, v0, steps, cfg.dt, mu_of(seg * 0.5),
+                           orc.Observations(frames, tr, "x", np.zeros((4, 2, 16))))
+    target = np.stack([q[0] for q in qs])
+    obs = orc.Observations(frames, tr, "x", target)
+    loss, gv0, gmu_node = orc.rollout_grad(cfg, x0, v0, steps, cfg.dt, mu_of(seg), obs)
+    assert loss > 0
+    # chain to the segments
+    nd = cfg.node_dims()
+    i = np.arange(nd[0]) - cfg.ghost
+    sidx = np.clip(np.floor(i * cfg.dx / seg_len).astype(int), 0, len(seg) - 1)
+    gseg = np.bincount(sidx, weights=gmu_node, minlength=len(seg))
+
+    def Lval(s, v):
+        return orc.rollout(cfg, x0, v, steps, cfg.dt, mu_of(s), obs)[0]
+
+    h = 1e-6
+    for k in range(len(seg)):
+        e = np.zeros(len(seg))
+        e[k] = h
+        fd = (Lval(seg + e, v0) - Lval(seg - e, v0)) / (2 * h)
+        assert abs(fd - gseg[k]) <= 1e-5 * max(abs(fd), 1e-3 * abs(gseg).max()) + 1e-12, (k, fd, gseg[k])
+    dv = rng.normal(size=v0.shape)
+    fd = (Lval(seg, v0 + h * dv) - Lval(seg, v0 - h * dv)) / (2 * h)
+    ad = float((gv0 * dv).sum())
+    assert abs(fd - ad) <= 1e-5 * abs(fd), (fd, ad)
+    # segments the flow never reaches get an exact zero
+    assert gseg[-1] == 0.0
+
+
+def test_eulerian_loss_gradient(orc):
+    """Eulerian box means of velocity (Sec. 3.2): gradient with respect to v0."""
+    cfg = W.SimConfig(dim=2, n=(16, 16, 1), dx=1 / 32, dt=2e-4, material=W.SAND, ppc=4,
+                      gravity=(0, -9.81, 0), rho0=2000.0, youngs=1e6,
+                      wall_mode=(W.SLIP, W.SLIP, W.COULOMB, W.SLIP, W.SLIP, W.SLIP),
+                      wall_mu=(0, 0, 0.5, 0, 0, 0))
+    x0 = W.lattice_particles(cfg, W.box_inside((0.1, 0), (0.4, 0.15)), (0.1, 0), (0.4, 0.15), seed=74)
+    N = x0.shape[1]
+    rng = np.random.default_rng(75)
+    v0 = rng.normal(0, 0.3, size=(2, N))
+    lo = np.array([[0.12, 0.02], [0.25, 0.05], [0.3, 0.0]])
+    hi = lo + 0.06
+    frames = [5, 15, 25]
+    target = rng.normal(0, 0.1, size=(3, 2, 3))
+    obs = orc.Observations(frames, box_lo=lo, box_hi=hi, eul_field="v", eul_target=target)
+    loss, gv0, _ = orc.rollout_grad(cfg, x0, v0, 25, cfg.dt, None, obs)
+    h = 1e-6
+    dv = rng.normal(size=v0.shape)
+    Lp = orc.rollout(cfg, x0, v0 + h * dv, 25, cfg.dt, None, obs)[0]
+    Lm = orc.rollout(cfg, x0, v0 - h * dv, 25, cfg.dt, None, obs)[0]
+    fd = (Lp - Lm) / (2 * h)
+    ad = float((gv0 * dv).sum())
+    assert abs(fd - ad) <= 1e-5 * abs(fd), (fd, ad)
