@@ -158,6 +158,49 @@ int mpm_read_grid(mpm_ctx* ctx, int32_t which, void* dst);
  * next step).  int32 device arrays of n; either may be NULL. */
 int mpm_read_sort(mpm_ctx* ctx, void* perm, void* key);
 
+/* Observations for the inverse problem (Sec. 3.2, eq:inverse_loss):
+ *   L = sum over frames t and indices l of m_{l,t} |Q_l(z^t) - z^obs_{l,t}|^2
+ * with the Lagrangian operator Q_l(z) = z of tracked particle l and the
+ * Eulerian operator Q_l = mean of z over the particles inside box l.  An
+ * empty box contributes nothing; box membership is held fixed when
+ * differentiating.  Device arrays are kept (not copied) until the next call
+ * and must stay valid; host arrays are copied. */
+#define MPM_MAX_BOXES 64
+typedef struct mpm_obs {
+    int32_t n_frames;
+    const int32_t* host_frames;  /* steps after which the state is observed: ascending, >= 1 */
+    int32_t n_tracers;           /* Lagrangian operator; 0 for none */
+    const int32_t* tracer_pid;   /* device int32[n_tracers]: particle ids */
+    int32_t lag_field;           /* MPM_FIELD_X or MPM_FIELD_V */
+    const void* lag_target;      /* device [n_frames][dim][n_tracers], context precision */
+    const void* lag_mask;        /* device [n_frames][n_tracers] 0/1 weights, or NULL for all 1 */
+    int32_t n_boxes;             /* Eulerian operator; 0 for none, at most MPM_MAX_BOXES */
+    const double* host_box_lo;   /* host [n_boxes][dim]: box is [lo, hi) on every axis */
+    const double* host_box_hi;
+    int32_t eul_field;           /* MPM_FIELD_X or MPM_FIELD_V */
+    const void* eul_target;      /* device [n_frames][dim][n_boxes] */
+    const void* eul_mask;        /* device [n_frames][n_boxes] or NULL */
+} mpm_obs;
+
+int mpm_set_observations(mpm_ctx* ctx, const mpm_obs* obs);
+
+/* Runs n_steps steps from the current state (the parameters alpha being the
+ * current particle velocities and the floor friction set by
+ * mpm_set_floor_mu), storing a checkpoint every ckpt_every steps (the values
+ * given to mpm_bind_workspace; n_steps <= its tape_steps) and accumulating
+ * the loss of the observations in binary64.  Synchronizes; *host_loss gets
+ * the loss.  The state afterwards is the state after n_steps. */
+int mpm_forward_loss(mpm_ctx* ctx, int32_t n_steps, double dt, double* host_loss);
+
+/* Gradient of the last mpm_forward_loss by the hand-written reverse sweep:
+ * each segment between checkpoints is recomputed, then every step is
+ * reversed (constitutive update, G2P, walls, grid, P2G, sort).  grad_v0
+ * (device [dim][n], pid order) receives dL/dv of the rollout's initial
+ * state, grad_mu (device, floor layout of mpm_set_floor_mu) dL/dmu per floor
+ * node (zero without a friction field).  Either may be NULL.  Synchronizes.
+ * ESTATE without a preceding mpm_forward_loss. */
+int mpm_backward(mpm_ctx* ctx, void* grad_v0, void* grad_mu);
+
 /* Per-kernel-class timing of mpm_step: with profiling on, HIP events are
  * recorded on the context's stream between the kernel classes below, and
  * mpm_profile_read (synchronizes) returns, per class, the summed event time

@@ -82,12 +82,14 @@ Geo make_geo(const mpm_config& c)
 struct Layout {
     size_t st[2], pid[2], key, perm, tmp, tmpk, count, tile_off, tile_slot, active, part, meta, status;
     size_t part_grid, gv, gmass;
+    size_t inv, loss, box_sum, box_cnt, box_coef;
+    size_t ckpt, ckpt_pid, tape, tape_pid, adj[2], mid, gvt, amu;
     size_t total;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap)
+Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_steps, int ckpt_every)
 {
     Layout L{};
     size_t elem = c.precision == MPM_F64 ? 8 : 4;
@@ -116,6 +118,25 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap)
     L.part_grid = take((size_t)g.ntiles * (c.dim + 1) * nb * elem);
     L.gv = take((size_t)g.NN * c.dim * elem);
     L.gmass = take((size_t)g.NN * elem);
+    L.inv = take(ucap * 4);
+    L.loss = take(4 * 8);
+    L.box_sum = take(kMaxBoxes * 3 * 8);
+    L.box_cnt = take(kMaxBoxes * 4);
+    L.box_coef = take(kMaxBoxes * 3 * 8);
+    if (tape_steps > 0 && ckpt_every > 0) {
+        size_t sb = (size_t)nsc_of(c) * ucap * elem;
+        size_t nck = (size_t)((tape_steps + ckpt_every - 1) / ckpt_every);
+        L.ckpt = take(nck * sb);
+        L.ckpt_pid = take(nck * ucap * 4);
+        L.tape = take((size_t)(ckpt_every + 1) * sb);
+        L.tape_pid = take((size_t)(ckpt_every + 1) * ucap * 4);
+        L.adj[0] = take(sb);
+        L.adj[1] = take(sb);
+        L.mid = take((size_t)(c.dim + c.dim * c.dim) * ucap * elem);
+        L.gvt = take((size_t)g.NN * c.dim * elem);
+        size_t nfl = c.dim == 3 ? (size_t)g.box[0] * g.box[1] : (size_t)g.box[0];
+        L.amu = take(nfl * 8);
+    }
     L.total = off;
     return L;
 }
@@ -200,7 +221,7 @@ int mpm_workspace_bytes(const mpm_config* cfg, int64_t n_particles, int32_t tape
     }
     mpm_config c = *cfg;
     Geo g = make_geo(c);
-    *bytes = make_layout(c, g, n_particles).total;
+    *bytes = make_layout(c, g, n_particles, tape_steps, ckpt_every).total;
     return MPM_OK;
 }
 
@@ -211,7 +232,8 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return set_err(c, MPM_EINVAL, "workspace must be non-null and 256-byte aligned");
     if (n_particles < 0 || n_particles >= (1ll << 31) || tape_steps < 0 || ckpt_every < 0)
         return set_err(c, MPM_EINVAL, "bad workspace arguments");
-    Layout L = make_layout(c->cfg, c->geo, n_particles);
+    if (tape_steps > 0 && ckpt_every < 1) return set_err(c, MPM_EINVAL, "a tape needs ckpt_every >= 1");
+    Layout L = make_layout(c->cfg, c->geo, n_particles, tape_steps, ckpt_every);
     if (bytes < L.total)
         return set_err(c, MPM_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
     char* b = (char*)dev_ptr;
@@ -238,6 +260,23 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     c->part_grid = b + L.part_grid;
     c->gv = b + L.gv;
     c->gmass = b + L.gmass;
+    c->inv = (int32_t*)(b + L.inv);
+    c->loss = (double*)(b + L.loss);
+    c->loss_scratch = c->loss + 2;
+    c->box_sum = (double*)(b + L.box_sum);
+    c->box_cnt = (int32_t*)(b + L.box_cnt);
+    c->box_coef = (double*)(b + L.box_coef);
+    bool tape = tape_steps > 0 && ckpt_every > 0;
+    c->ckpt = tape ? b + L.ckpt : nullptr;
+    c->ckpt_pid = tape ? (int32_t*)(b + L.ckpt_pid) : nullptr;
+    c->tape = tape ? b + L.tape : nullptr;
+    c->tape_pid = tape ? (int32_t*)(b + L.tape_pid) : nullptr;
+    c->adj[0] = tape ? b + L.adj[0] : nullptr;
+    c->adj[1] = tape ? b + L.adj[1] : nullptr;
+    c->mid = tape ? b + L.mid : nullptr;
+    c->gvt = tape ? b + L.gvt : nullptr;
+    c->amu = tape ? (double*)(b + L.amu) : nullptr;
+    c->has_tape = false;
     c->cur = 0;
     c->N = 0;
     c->has_particles = false;
@@ -345,6 +384,69 @@ int mpm_read_sort(mpm_ctx* c, void* perm, void* key)
     if (key && c->N > 0)
         return hip_check(c, hipMemcpyAsync(key, c->key, bytes, hipMemcpyDeviceToDevice, c->stream), "read key");
     return MPM_OK;
+}
+
+int mpm_set_observations(mpm_ctx* c, const mpm_obs* o)
+{
+    if (!c) return MPM_EINVAL;
+    if (!o) return set_err(c, MPM_EINVAL, "obs is NULL");
+    if (o->n_frames < 0 || (o->n_frames > 0 && !o->host_frames)) return set_err(c, MPM_EINVAL, "bad frames");
+    for (int i = 0; i < o->n_frames; ++i) {
+        if (o->host_frames[i] < 1) return set_err(c, MPM_EINVAL, "frames must be >= 1");
+        if (i > 0 && o->host_frames[i] <= o->host_frames[i - 1]) return set_err(c, MPM_EINVAL, "frames must ascend");
+    }
+    if (o->n_tracers < 0 || (o->n_tracers > 0 && (!o->tracer_pid || !o->lag_target)))
+        return set_err(c, MPM_EINVAL, "tracers need ids and targets");
+    if (o->n_tracers > 0 && o->lag_field != MPM_FIELD_X && o->lag_field != MPM_FIELD_V)
+        return set_err(c, MPM_EINVAL, "tracer field must be X or V");
+    if (o->n_boxes < 0 || o->n_boxes > MPM_MAX_BOXES) return set_err(c, MPM_EINVAL, "too many boxes");
+    if (o->n_boxes > 0 && (!o->host_box_lo || !o->host_box_hi || !o->eul_target))
+        return set_err(c, MPM_EINVAL, "boxes need bounds and targets");
+    if (o->n_boxes > 0 && o->eul_field != MPM_FIELD_X && o->eul_field != MPM_FIELD_V)
+        return set_err(c, MPM_EINVAL, "box field must be X or V");
+    c->obs_frames.assign(o->host_frames, o->host_frames + o->n_frames);
+    c->obs_ntr = o->n_tracers;
+    c->obs_tracer = o->tracer_pid;
+    c->obs_lag_field = o->lag_field;
+    c->obs_lag_target = o->lag_target;
+    c->obs_lag_mask = o->lag_mask;
+    c->obs_nbox = o->n_boxes;
+    for (int b = 0; b < o->n_boxes; ++b)
+        for (int a = 0; a < 3; ++a) {
+            c->box_lo[b][a] = a < c->cfg.dim ? o->host_box_lo[b * c->cfg.dim + a] : 0.0;
+            c->box_hi[b][a] = a < c->cfg.dim ? o->host_box_hi[b * c->cfg.dim + a] : 0.0;
+        }
+    c->obs_eul_field = o->eul_field;
+    c->obs_eul_target = o->eul_target;
+    c->obs_eul_mask = o->eul_mask;
+    return MPM_OK;
+}
+
+int mpm_forward_loss(mpm_ctx* c, int32_t n_steps, double dt, double* host_loss)
+{
+    int rc = need_particles(c);
+    if (rc) return rc;
+    if (!host_loss) return set_err(c, MPM_EINVAL, "host_loss is NULL");
+    if (!c->ckpt) return set_err(c, MPM_ENOMEM, "no tape: bind the workspace with tape_steps > 0");
+    if (n_steps < 1 || n_steps > c->tape_steps) return set_err(c, MPM_EINVAL, "n_steps must be in [1, tape_steps]");
+    if (c->N < 1) return set_err(c, MPM_EINVAL, "a rollout needs at least one particle");
+    if (!(dt >= 0.0) || !isfinite(dt)) return set_err(c, MPM_EINVAL, "dt must be finite and >= 0");
+    c->has_tape = false;
+    rc = c->ops->forward_loss(c, n_steps, dt, host_loss);
+    if (rc) return rc;
+    c->fwd_steps = n_steps;
+    c->fwd_dt = dt;
+    c->has_tape = true;
+    c->stepped = true;
+    return MPM_OK;
+}
+
+int mpm_backward(mpm_ctx* c, void* grad_v0, void* grad_mu)
+{
+    int rc = need_particles(c);
+    if (rc) return rc;
+    if (!c->has_tape) return set_err(c, MPM_ESTATE, "no forward rollout to differentiate (call mpm_forward_loss)");
+    return c->ops->backward(c, grad_v0, grad_mu);
 }
 
 int mpm_profile_enable(mpm_ctx* c, int on)

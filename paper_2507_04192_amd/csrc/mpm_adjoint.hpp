@@ -1,0 +1,828 @@
+// Adjoint of the MPM step for gfx950 and the checkpointed rollout driver.
+//
+// Forward (mpm_forward_loss): the state is copied to a checkpoint every k
+// steps; at observation frames the extraction operators Q_l and the masked
+// squared error are evaluated on the device (loss in binary64).
+//
+// Backward (mpm_backward), segment by segment from the last: the segment's
+// checkpoint is restored and its k steps recomputed into a tape of states;
+// then for each step in reverse (Sec. 3.1, eq:dzda; Sec. 3.3 recomputation):
+//   recompute the sort, P2G and grid of that step (keeping the velocity
+//   before the walls), then
+//   g2p_adj   per particle: reverse of the constitutive update and of G2P;
+//             node adjoints accumulated in LDS and written per tile
+//   grid_adj  per node: reverse of the walls (dL/dmu) and of v = P/m + dt g
+//   p2g_adj   per particle: reverse of P2G, then the sort is undone by
+//             writing each particle's adjoint at its slot before the step.
+#pragma once
+
+#include "mpm_adjoint_device.hpp"
+#include "mpm_kernels.hpp"
+
+namespace mpm {
+
+// Second derivative of the quadratic B-spline weights (per unit length^2):
+// +1, -2, +1 for the three nodes.
+template <class T>
+__device__ __forceinline__ T ddw_of(int k, T inv2) { return (k == 1) ? T(-2) * inv2 : inv2; }
+
+// Stencil terms of one node: phi, grad phi and d(grad phi)/dx.
+template <class T, int D>
+__device__ __forceinline__ void node_grad_hess(const T w[D][3], const T dw[D][3], const int k[3], T inv2, T& phi,
+                                               T gr[D], T H[D][D])
+{
+    phi = T(1);
+#pragma unroll
+    for (int a = 0; a < D; ++a) phi *= w[a][k[a]];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            T h = T(1);
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                if (b == a && b == c) h *= ddw_of<T>(k[b], inv2);
+                else if (b == a || b == c) h *= dw[b][k[b]];
+                else h *= w[b][k[b]];
+            }
+            H[a][c] = h;
+        }
+        T gg = dw[a][k[a]];
+#pragma unroll
+        for (int b = 0; b < D; ++b)
+            if (b != a) gg *= w[b][k[b]];
+        gr[a] = gg;
+    }
+}
+
+template <class T, int D, int MAT>
+__global__ __launch_bounds__(kBlock) void k_g2p_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                    const ActiveTile* __restrict__ active,
+                                                    const int* __restrict__ perm, PView<T> st, PView<T> aout,
+                                                    const T* __restrict__ gv, T* __restrict__ part,
+                                                    T* __restrict__ mid)
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    constexpr int NS = D * (D + 1) / 2;
+    __shared__ T s_v[D][NB];
+    __shared__ double s_b[D][NB];
+    const int n_active = meta[0];
+    const int tid = threadIdx.x;
+    const long long cap = st.cap;
+    const T inv2 = P.inv * P.inv;
+    for (int it = 0;; ++it) {
+        int e = tile_entry(it, n_active);
+        if (e < 0) break;
+        ActiveTile at = active[e];
+        int tc[3];
+        tile_coords(g, at.tile, tc);
+        for (int i = tid; i < NB; i += kBlock) {
+            int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
+            long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                s_v[a][i] = gv[a * g.NN + node];
+                s_b[a][i] = 0.0;
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < at.cnt; k += kBlock) {
+            long long s = at.off + k;
+            int j = perm[s];
+            T xp[D], w[D][3], dw[D][3], dd[D][3];
+            int lb[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                xp[a] = st.x[a * cap + j];
+                int b;
+                T f;
+                stencil_axis(xp[a], P.inv, b, f, w[a], dw[a]);
+                int l = b + g.G - tc[a] * TE;
+                lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
+            }
+            // forward G2P of this particle
+            T vn[D], Lm[D][D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                vn[a] = T(0);
+#pragma unroll
+                for (int b = 0; b < D; ++b) Lm[a][b] = T(0);
+            }
+            constexpr int KZ = (D == 3) ? 3 : 1;
+#pragma unroll
+            for (int kz = 0; kz < KZ; ++kz)
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        int kk[3] = {kx, ky, kz};
+                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
+                        T phi = T(1);
+#pragma unroll
+                        for (int a = 0; a < D; ++a) phi *= w[a][kk[a]];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            T vi = s_v[a][n];
+                            vn[a] += phi * vi;
+#pragma unroll
+                            for (int b = 0; b < D; ++b) {
+                                T gg = dw[b][kk[b]];
+#pragma unroll
+                                for (int c = 0; c < D; ++c)
+                                    if (c != b) gg *= w[c][kk[c]];
+                                Lm[a][b] += vi * gg;
+                            }
+                        }
+                    }
+            // adjoints of the outputs (slot s)
+            T xb[D], vb[D], Cb[D][D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                xb[a] = aout.x[a * cap + s];
+                vb[a] = aout.v[a * cap + s];
+#pragma unroll
+                for (int b = 0; b < D; ++b) Cb[a][b] = aout.C[(a * D + b) * cap + s];
+            }
+            // reverse of the constitutive update
+            T Lb[D][D];
+            if constexpr (MAT == MAT_FLUID) {
+                T Jb_in;
+                fluid_vjp<T, D>(P, Lm, st.G[j], aout.G[s], aout.S[s], Lb, Jb_in);
+                mid[D * cap + s] = Jb_in;
+            } else {
+                T G[D][D], Gb[D][D], Gb_in[D][D], sb[NS];
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        G[a][b] = st.G[(a * D + b) * cap + j];
+                        Gb[a][b] = aout.G[(a * D + b) * cap + s];
+                    }
+#pragma unroll
+                for (int q = 0; q < NS; ++q) sb[q] = aout.S[q * cap + s];
+                hencky_vjp<T, D>(P, MAT == MAT_SAND, Lm, G, Gb, sb, Lb, Gb_in);
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) mid[(D + a * D + b) * cap + s] = Gb_in[a][b];
+            }
+            // x' = clamp(x + dt v'): no gradient through a clamped component
+            T xbar[D], vt[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                T xn = xp[a] + P.dt * vn[a];
+                bool free_ = (xn >= T(0)) && (xn <= P.ext[a]);
+                xbar[a] = free_ ? xb[a] : T(0);
+                vt[a] = vb[a] + (free_ ? P.dt * xb[a] : T(0));
+            }
+            // reverse of G2P
+#pragma unroll
+            for (int kz = 0; kz < KZ; ++kz)
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        int kk[3] = {kx, ky, kz};
+                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
+                        T phi, gr[D], H[D][D];
+                        node_grad_hess<T, D>(w, dw, kk, inv2, phi, gr, H);
+                        T wbar = T(0), dbar[D], gbar[D];
+#pragma unroll
+                        for (int b = 0; b < D; ++b) { dbar[b] = T(0); gbar[b] = T(0); }
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            T vi = s_v[a][n];
+                            T cd = T(0), lg = T(0);
+#pragma unroll
+                            for (int b = 0; b < D; ++b) {
+                                cd += Cb[a][b] * dd[b][kk[b]];
+                                lg += Lb[a][b] * gr[b];
+                                dbar[b] += P.Dinv * phi * Cb[a][b] * vi;
+                                gbar[b] += Lb[a][b] * vi;
+                            }
+                            T nbv = phi * (vt[a] + P.Dinv * cd) + lg;
+                            atomicAdd(&s_b[a][n], (double)nbv);
+                            wbar += vi * (vt[a] + P.Dinv * cd);
+                        }
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            T t = wbar * gr[c] - dbar[c];
+#pragma unroll
+                            for (int b = 0; b < D; ++b) t += gbar[b] * H[b][c];
+                            xbar[c] += t;
+                        }
+                    }
+#pragma unroll
+            for (int a = 0; a < D; ++a) mid[a * cap + s] = xbar[a];
+        }
+        __syncthreads();
+        T* dst = part + (long long)e * (D + 1) * NB;
+        for (int i = tid; i < D * NB; i += kBlock) dst[i] = (T)(&s_b[0][0])[i];
+        __syncthreads();
+    }
+}
+
+template <class T, int D>
+__global__ __launch_bounds__(kBlock) void k_grid_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                     const ActiveTile* __restrict__ active,
+                                                     const int* __restrict__ tile_slot, const T* __restrict__ part,
+                                                     T* __restrict__ gmass, const T* __restrict__ gvt,
+                                                     T* __restrict__ gv, double* __restrict__ amu)
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    const int n_active = meta[0];
+    for (int it = 0;; ++it) {
+        int e = tile_entry(it, n_active);
+        if (e < 0) break;
+        int tile = active[e].tile;
+        int tc[3];
+        tile_coords(g, tile, tc);
+        for (int i = threadIdx.x; i < NB; i += kBlock) {
+            int l[3] = {i % BE, (i / BE) % BE, (D == 3) ? i / (BE * BE) : 0};
+            int I[3], own[3];
+            bool down[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                I[a] = (a < D) ? tc[a] * TE + l[a] : 0;
+                own[a] = I[a] / TE;
+                down[a] = (a < D) && (I[a] % TE < 2) && own[a] >= 1;
+            }
+            int des = -1;
+            T vb[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) vb[a] = T(0);
+            for (int msk = 0; msk < (1 << D); ++msk) {
+                bool ok = true;
+                int ct[3] = {own[0], own[1], own[2]};
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    if ((msk >> a) & 1) {
+                        if (!down[a]) ok = false;
+                        ct[a] -= 1;
+                    }
+                    if (ct[a] >= g.ntile[a]) ok = false;
+                }
+                if (!ok) continue;
+                int tl = (ct[2] * g.ntile[1] + ct[1]) * g.ntile[0] + ct[0];
+                int slot = tile_slot[tl];
+                if (slot < 0) continue;
+                if (des < 0) {
+                    des = tl;
+                    if (des != tile) break;
+                }
+                int li;
+                if constexpr (D == 3) li = ((I[2] - ct[2] * TE) * BE + I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
+                else li = (I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
+                const T* src = part + (long long)slot * (D + 1) * NB;
+#pragma unroll
+                for (int a = 0; a < D; ++a) vb[a] += src[a * NB + li];
+            }
+            if (des != tile) continue;
+            long long node = node_index(g, I[0], I[1], I[2]);
+            T m = gmass[node];
+            T pb[D], mb = T(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) pb[a] = T(0);
+            if (m > T(0)) {
+                T vin[2 * D][D], vel[D];
+                int nf = 0, fc[2 * D];
+                T fmu[2 * D];
+#pragma unroll
+                for (int a = 0; a < D; ++a) vel[a] = gvt[a * g.NN + node];
+                for (int a = 0; a < D; ++a) {
+                    int ip = I[a] - g.G;
+                    for (int side = 0; side < 2; ++side) {
+                        bool beyond = side == 0 ? (ip <= 0) : (ip >= g.n[a]);
+                        if (!beyond) continue;
+                        int face = 2 * a + side;
+                        T mu = P.wall_mu[face];
+                        if (face == 2 * (D - 1) && P.floor_mu) {
+                            int fx = min(I[0], g.box[0] - 1);
+                            int fi = (D == 3) ? min(I[1], g.box[1] - 1) * P.floor_stride + fx : fx;
+                            mu = P.floor_mu[fi];
+                        }
+#pragma unroll
+                        for (int q = 0; q < D; ++q) vin[nf][q] = vel[q];
+                        fc[nf] = face;
+                        fmu[nf] = mu;
+                        ++nf;
+                        wall_node<T, D>(P.wall_mode[face], mu, a, side == 0 ? T(-1) : T(1), vel);
+                    }
+                }
+                for (int f = nf - 1; f >= 0; --f) {
+                    int face = fc[f], a = face / 2;
+                    T sign = (face % 2 == 0) ? T(-1) : T(1);
+                    T mub = wall_node_vjp<T, D>(P.wall_mode[face], fmu[f], a, sign, vin[f], vb);
+                    if (amu && face == 2 * (D - 1) && P.floor_mu && mub != T(0)) {
+                        int fx = min(I[0], g.box[0] - 1);
+                        int fi = (D == 3) ? min(I[1], g.box[1] - 1) * P.floor_stride + fx : fx;
+                        atomicAdd(&amu[fi], (double)mub);
+                    }
+                }
+                T dot = T(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    pb[a] = vb[a] / m;
+                    dot += vb[a] * (gvt[a * g.NN + node] - P.dt * P.g[a]);
+                }
+                mb = -dot / m;
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) gv[a * g.NN + node] = pb[a];
+            gmass[node] = mb;
+        }
+    }
+}
+
+template <class T, int D, int MAT>
+__global__ __launch_bounds__(kBlock) void k_p2g_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                    const ActiveTile* __restrict__ active,
+                                                    const int* __restrict__ perm, PView<T> st,
+                                                    const T* __restrict__ gpb, const T* __restrict__ gmb,
+                                                    const T* __restrict__ mid, PView<T> ain)
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    __shared__ T s_p[D][NB];
+    __shared__ T s_m[NB];
+    const int n_active = meta[0];
+    const int tid = threadIdx.x;
+    const long long cap = st.cap;
+    const T inv2 = P.inv * P.inv;
+    for (int it = 0;; ++it) {
+        int e = tile_entry(it, n_active);
+        if (e < 0) break;
+        ActiveTile at = active[e];
+        int tc[3];
+        tile_coords(g, at.tile, tc);
+        for (int i = tid; i < NB; i += kBlock) {
+            int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
+            long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
+            s_m[i] = gmb[node];
+#pragma unroll
+            for (int a = 0; a < D; ++a) s_p[a][i] = gpb[a * g.NN + node];
+        }
+        __syncthreads();
+        for (int k = tid; k < at.cnt; k += kBlock) {
+            long long s = at.off + k;
+            int j = perm[s];
+            T w[D][3], dw[D][3], dd[D][3], vp[D], Cp[D][D], Sp[D][D];
+            int lb[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                int b;
+                T f;
+                stencil_axis(st.x[a * cap + j], P.inv, b, f, w[a], dw[a]);
+                int l = b + g.G - tc[a] * TE;
+                lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
+                vp[a] = st.v[a * cap + j];
+#pragma unroll
+                for (int b2 = 0; b2 < D; ++b2) Cp[a][b2] = st.C[(a * D + b2) * cap + j];
+            }
+            if constexpr (MAT == MAT_FLUID) {
+                T si = st.S[j];
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) Sp[a][b] = (a == b) ? si : T(0);
+            } else if constexpr (D == 3) {
+                Sp[0][0] = st.S[0 * cap + j]; Sp[1][1] = st.S[1 * cap + j]; Sp[2][2] = st.S[2 * cap + j];
+                Sp[0][1] = Sp[1][0] = st.S[3 * cap + j];
+                Sp[0][2] = Sp[2][0] = st.S[4 * cap + j];
+                Sp[1][2] = Sp[2][1] = st.S[5 * cap + j];
+            } else {
+                Sp[0][0] = st.S[0 * cap + j]; Sp[1][1] = st.S[1 * cap + j];
+                Sp[0][1] = Sp[1][0] = st.S[2 * cap + j];
+            }
+            T xbar[D], vbar[D], Cbar[D][D], Sbar[D][D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                xbar[a] = mid[a * cap + s];
+                vbar[a] = T(0);
+#pragma unroll
+                for (int b = 0; b < D; ++b) { Cbar[a][b] = T(0); Sbar[a][b] = T(0); }
+            }
+            constexpr int KZ = (D == 3) ? 3 : 1;
+#pragma unroll
+            for (int kz = 0; kz < KZ; ++kz)
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        int kk[3] = {kx, ky, kz};
+                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
+                        T phi, gr[D], H[D][D];
+                        node_grad_hess<T, D>(w, dw, kk, inv2, phi, gr, H);
+                        T mbn = s_m[n];
+                        T wbar = P.mass * mbn, dbar[D], gbar[D];
+#pragma unroll
+                        for (int b = 0; b < D; ++b) { dbar[b] = T(0); gbar[b] = T(0); }
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            T pb = s_p[a][n];
+                            T aff = vp[a];
+#pragma unroll
+                            for (int b = 0; b < D; ++b) aff += Cp[a][b] * dd[b][kk[b]];
+                            wbar += P.mass * aff * pb;
+                            T wp = phi * P.mass * pb;
+                            vbar[a] += wp;
+#pragma unroll
+                            for (int b = 0; b < D; ++b) {
+                                Cbar[a][b] += wp * dd[b][kk[b]];
+                                dbar[b] += phi * P.mass * Cp[a][b] * pb;
+                                Sbar[a][b] -= P.dt * pb * gr[b];
+                                gbar[b] -= P.dt * Sp[a][b] * pb;
+                            }
+                        }
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            T t = wbar * gr[c] - dbar[c];
+#pragma unroll
+                            for (int b = 0; b < D; ++b) t += gbar[b] * H[b][c];
+                            xbar[c] += t;
+                        }
+                    }
+            // the particle's adjoint goes to its slot before the step's sort
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                ain.x[a * cap + j] = xbar[a];
+                ain.v[a * cap + j] = vbar[a];
+#pragma unroll
+                for (int b = 0; b < D; ++b) ain.C[(a * D + b) * cap + j] = Cbar[a][b];
+            }
+            if constexpr (MAT == MAT_FLUID) {
+                ain.G[j] = mid[D * cap + s];
+                T tr = T(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a) tr += Sbar[a][a];
+                ain.S[j] = tr;
+            } else {
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) ain.G[(a * D + b) * cap + j] = mid[(D + a * D + b) * cap + s];
+                if constexpr (D == 3) {
+                    ain.S[0 * cap + j] = Sbar[0][0];
+                    ain.S[1 * cap + j] = Sbar[1][1];
+                    ain.S[2 * cap + j] = Sbar[2][2];
+                    ain.S[3 * cap + j] = Sbar[0][1] + Sbar[1][0];
+                    ain.S[4 * cap + j] = Sbar[0][2] + Sbar[2][0];
+                    ain.S[5 * cap + j] = Sbar[1][2] + Sbar[2][1];
+                } else {
+                    ain.S[0 * cap + j] = Sbar[0][0];
+                    ain.S[1 * cap + j] = Sbar[1][1];
+                    ain.S[2 * cap + j] = Sbar[0][1] + Sbar[1][0];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Observation operators and loss (Sec. 3.2, eq:inverse_loss)
+// ---------------------------------------------------------------------------
+
+template <int Unused = 0>
+__global__ void k_inverse_pid(const int32_t* __restrict__ pid, long long N, int32_t* __restrict__ inv)
+{
+    long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s < N) inv[pid[s]] = (int32_t)s;
+}
+
+// Lagrangian tracers: Q_l = z of particle l.  Adds m |Q - z_obs|^2 to the
+// loss and, when seed != 0, 2 m (Q - z_obs) to the adjoint of z.
+template <class T, int D>
+__global__ void k_lag_obs(const T* __restrict__ z, T* __restrict__ zb, long long cap, long long N,
+                          const int32_t* __restrict__ inv, const int32_t* __restrict__ tracer, int ntr,
+                          const T* __restrict__ target, const T* __restrict__ mask, int seed,
+                          double* __restrict__ loss)
+{
+    int l = blockIdx.x * kBlock + threadIdx.x;
+    double part = 0.0;
+    // an id outside [0, N) is skipped (it names no particle)
+    if (l < ntr && tracer[l] >= 0 && tracer[l] < N) {
+        int s = inv[tracer[l]];
+        T m = mask ? mask[l] : T(1);
+        if (m != T(0)) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                T r = z[a * cap + s] - target[a * ntr + l];
+                part += (double)m * (double)r * (double)r;
+                if (seed) zb[a * cap + s] += T(2) * m * r;
+            }
+        }
+    }
+    // wave reduction, one atomic per wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((threadIdx.x & 63) == 0 && part != 0.0) atomicAdd(loss, part);
+}
+
+struct Boxes {
+    double lo[kMaxBoxes][3], hi[kMaxBoxes][3];
+    int n;
+};
+
+template <class T, int D>
+__device__ __forceinline__ bool in_box(const Boxes& bx, int b, const T* x, long long cap, long long s)
+{
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T xv = x[a * cap + s];
+        in = in && (xv >= (T)bx.lo[b][a]) && (xv < (T)bx.hi[b][a]);
+    }
+    return in;
+}
+
+// Eulerian boxes, pass 1: per-box sums of z and particle counts (binary64).
+template <class T, int D>
+__global__ void k_box_sum(Boxes bx, const T* __restrict__ x, const T* __restrict__ z, long long cap, long long N,
+                          double* __restrict__ sum, int* __restrict__ cnt)
+{
+    long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    for (int b = 0; b < bx.n; ++b) {
+        bool in = s < N && in_box<T, D>(bx, b, x, cap, s);
+        unsigned long long msk = __ballot(in);
+        double acc[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double v = in ? (double)z[a * cap + s] : 0.0;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            acc[a] = v;
+        }
+        if ((threadIdx.x & 63) == 0 && msk) {
+            atomicAdd(&cnt[b], __popcll(msk));
+#pragma unroll
+            for (int a = 0; a < D; ++a) atomicAdd(&sum[b * 3 + a], acc[a]);
+        }
+    }
+}
+
+// Eulerian boxes, pass 2 (one thread per box): Q, the loss and the seed
+// coefficient 2 m (Q - z_obs) / |P_l| per box; empty boxes contribute nothing.
+template <class T, int D>
+__global__ void k_box_loss(int nbox, const double* __restrict__ sum, const int* __restrict__ cnt,
+                           const T* __restrict__ target, const T* __restrict__ mask, double* __restrict__ coef,
+                           double* __restrict__ loss)
+{
+    int b = threadIdx.x;
+    if (b >= nbox) return;
+    double m = mask ? (double)mask[b] : 1.0;
+    int c = cnt[b];
+    double part = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double cf = 0.0;
+        if (c > 0 && m != 0.0) {
+            double r = sum[b * 3 + a] / c - (double)target[a * nbox + b];
+            part += m * r * r;
+            cf = 2.0 * m * r / c;
+        }
+        coef[b * 3 + a] = cf;
+    }
+    if (part != 0.0) atomicAdd(loss, part);
+}
+
+template <class T, int D>
+__global__ void k_box_seed(Boxes bx, const T* __restrict__ x, T* __restrict__ zb, long long cap, long long N,
+                           const double* __restrict__ coef)
+{
+    long long s = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= N) return;
+    for (int b = 0; b < bx.n; ++b) {
+        if (!in_box<T, D>(bx, b, x, cap, s)) continue;
+#pragma unroll
+        for (int a = 0; a < D; ++a) zb[a * cap + s] += (T)coef[b * 3 + a];
+    }
+}
+
+template <class T>
+__global__ void k_mu_out(const double* __restrict__ amu, long long n, T* __restrict__ out)
+{
+    long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = (T)amu[i];
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+template <class T, int D>
+struct Adjoint {
+    using S = Solver<T, D>;
+
+    static PView<T> slot_view(const mpm_ctx* c, char* base, int32_t* pid)
+    {
+        PView<T> v{};
+        T* b = (T*)base;
+        long long cap = c->cap;
+        v.cap = cap;
+        v.x = b;
+        v.v = b + D * cap;
+        v.C = b + 2 * D * cap;
+        v.G = b + (2 * D + D * D) * cap;
+        v.S = v.G + (c->cfg.material == MAT_FLUID ? 1 : D * D) * cap;
+        v.pid = pid;
+        return v;
+    }
+    static size_t state_bytes(const mpm_ctx* c) { return (size_t)c->nsc * (size_t)c->cap * sizeof(T); }
+    static PView<T> ckpt(const mpm_ctx* c, int i)
+    {
+        return slot_view(c, c->ckpt + (size_t)i * state_bytes(c), c->ckpt_pid + (size_t)i * c->cap);
+    }
+    static PView<T> tape(const mpm_ctx* c, int i)
+    {
+        return slot_view(c, c->tape + (size_t)i * state_bytes(c), c->tape_pid + (size_t)i * c->cap);
+    }
+    static PView<T> adj(const mpm_ctx* c, int i) { return slot_view(c, c->adj[i], nullptr); }
+
+    static int copy_state(mpm_ctx* c, const PView<T>& dst, const PView<T>& src)
+    {
+        hipStream_t st = c->stream;
+        if (hipMemcpyAsync(dst.x, src.x, state_bytes(c), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(dst.pid, src.pid, sizeof(int32_t) * c->cap, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return S::launch_err(c, "state copy");
+        return MPM_OK;
+    }
+
+    static void keys_of(mpm_ctx* c, const PView<T>& v)
+    {
+        hipStream_t st = c->stream;
+        k_fill<int><<<std::min<long long>(nblocks(c->geo.ntiles), 4096), kBlock, 0, st>>>(c->count, c->geo.ntiles, 0);
+        Phys<T> P = make_phys<T>(c, 0.0);
+        k_keys<T, D><<<nblocks(c->N), kBlock, 0, st>>>(c->geo, P, v, c->N, c->key, c->count);
+    }
+
+    template <int MAT>
+    static void adjoint_step(mpm_ctx* c, const Phys<T>& P0, const PView<T>& st_in, const PView<T>& aout,
+                             const PView<T>& ain)
+    {
+        hipStream_t st = c->stream;
+        const Geo& g = c->geo;
+        Phys<T> P = P0;
+        P.keep_grid = 1;
+        keys_of(c, st_in);
+        unsigned nsb = (unsigned)((g.ntiles + kScanChunk - 1) / kScanChunk);
+        k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
+        k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, c->tile_slot, c->active,
+                                               c->meta);
+        k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
+        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->tmpk, st_in, c->perm,
+                                                      (T*)c->part_grid);
+        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (const T*)c->part_grid,
+                                                  (T*)c->gv, (T*)c->gmass, (T*)c->gvt);
+        k_g2p_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in, aout,
+                                                          (const T*)c->gv, (T*)c->part_grid, (T*)c->mid);
+        k_grid_adj<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot,
+                                                      (const T*)c->part_grid, (T*)c->gmass, (const T*)c->gvt,
+                                                      (T*)c->gv, c->floor_mu ? c->amu : nullptr);
+        k_p2g_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in,
+                                                          (const T*)c->gv, (const T*)c->gmass, (const T*)c->mid,
+                                                          ain);
+    }
+
+    static Boxes boxes(const mpm_ctx* c)
+    {
+        Boxes b{};
+        b.n = c->obs_nbox;
+        for (int i = 0; i < b.n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                b.lo[i][a] = c->box_lo[i][a];
+                b.hi[i][a] = c->box_hi[i][a];
+            }
+        return b;
+    }
+
+    // Loss of frame fi on state v; with zb_* non-null also the seeds.
+    static void observe(mpm_ctx* c, const PView<T>& v, int fi, const PView<T>* ab)
+    {
+        hipStream_t st = c->stream;
+        long long N = c->N;
+        if (c->obs_ntr > 0) {
+            k_inverse_pid<0><<<nblocks(N), kBlock, 0, st>>>(v.pid, N, c->inv);
+            const T* z = c->obs_lag_field == MPM_FIELD_X ? v.x : v.v;
+            T* zb = ab ? (c->obs_lag_field == MPM_FIELD_X ? ab->x : ab->v) : nullptr;
+            const T* tgt = (const T*)c->obs_lag_target + (size_t)fi * D * c->obs_ntr;
+            const T* msk = c->obs_lag_mask ? (const T*)c->obs_lag_mask + (size_t)fi * c->obs_ntr : nullptr;
+            k_lag_obs<T, D><<<nblocks(c->obs_ntr), kBlock, 0, st>>>(z, zb, v.cap, N, c->inv, c->obs_tracer,
+                                                                    c->obs_ntr, tgt, msk, ab ? 1 : 0, c->loss);
+        }
+        if (c->obs_nbox > 0) {
+            Boxes bx = boxes(c);
+            k_fill<double><<<1, kBlock, 0, st>>>(c->box_sum, kMaxBoxes * 3, 0.0);
+            k_fill<int><<<1, kBlock, 0, st>>>(c->box_cnt, kMaxBoxes, 0);
+            const T* z = c->obs_eul_field == MPM_FIELD_X ? v.x : v.v;
+            k_box_sum<T, D><<<nblocks(N), kBlock, 0, st>>>(bx, v.x, z, v.cap, N, c->box_sum, c->box_cnt);
+            const T* tgt = (const T*)c->obs_eul_target + (size_t)fi * D * c->obs_nbox;
+            const T* msk = c->obs_eul_mask ? (const T*)c->obs_eul_mask + (size_t)fi * c->obs_nbox : nullptr;
+            // the seed pass must not add this frame's loss twice
+            double* loss_dst = ab ? c->loss_scratch : c->loss;
+            k_box_loss<T, D><<<1, kMaxBoxes, 0, st>>>(c->obs_nbox, c->box_sum, c->box_cnt, tgt, msk, c->box_coef,
+                                                      loss_dst);
+            if (ab) {
+                T* zb = c->obs_eul_field == MPM_FIELD_X ? ab->x : ab->v;
+                k_box_seed<T, D><<<nblocks(N), kBlock, 0, st>>>(bx, v.x, zb, v.cap, N, c->box_coef);
+            }
+        }
+    }
+
+    static int frame_index(const mpm_ctx* c, int t)
+    {
+        for (size_t i = 0; i < c->obs_frames.size(); ++i)
+            if (c->obs_frames[i] == t) return (int)i;
+        return -1;
+    }
+
+    template <int MAT>
+    static int forward_loss_mat(mpm_ctx* c, int n, double dt, double* loss)
+    {
+        hipStream_t st = c->stream;
+        Phys<T> P = make_phys<T>(c, dt);
+        int k = c->ckpt_every;
+        k_fill<double><<<1, kBlock, 0, st>>>(c->loss, 2, 0.0);
+        for (int t = 0; t < n; ++t) {
+            if (t % k == 0) {
+                int rc = copy_state(c, ckpt(c, t / k), view<T>(c, c->cur));
+                if (rc) return rc;
+            }
+            PView<T> cur = view<T>(c, c->cur), nxt = view<T>(c, 1 - c->cur);
+            S::template step_views<MAT>(c, P, cur, nxt);
+            c->cur = 1 - c->cur;
+            int fi = frame_index(c, t + 1);
+            if (fi >= 0) observe(c, view<T>(c, c->cur), fi, nullptr);
+        }
+        int rc = S::launch_err(c, "forward loss");
+        if (rc) return rc;
+        double h[2];
+        rc = hip_check(c, hipMemcpyAsync(h, c->loss, sizeof(h), hipMemcpyDeviceToHost, st), "loss read");
+        if (rc) return rc;
+        rc = hip_check(c, hipStreamSynchronize(st), "stream synchronize");
+        if (rc) return rc;
+        *loss = h[0];
+        return MPM_OK;
+    }
+
+    template <int MAT>
+    static int backward_mat(mpm_ctx* c, void* grad_v0, void* grad_mu)
+    {
+        hipStream_t st = c->stream;
+        const int n = c->fwd_steps, k = c->ckpt_every;
+        Phys<T> P = make_phys<T>(c, c->fwd_dt);
+        int a = 0;   // adjoint buffer holding the adjoint of the later state
+        k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->adj[0], (long long)c->nsc * c->cap, T(0));
+        long long nfl = c->geo.dim == 3 ? (long long)c->geo.box[0] * c->geo.box[1] : c->geo.box[0];
+        k_fill<double><<<std::min<long long>(nblocks(nfl), 4096), kBlock, 0, st>>>(c->amu, nfl, 0.0);
+        int nseg = (n + k - 1) / k;
+        for (int seg = nseg - 1; seg >= 0; --seg) {
+            int t0 = seg * k, t1 = std::min(t0 + k, n);
+            int rc = copy_state(c, tape(c, 0), ckpt(c, seg));
+            if (rc) return rc;
+            keys_of(c, tape(c, 0));
+            for (int t = t0; t < t1; ++t)
+                S::template step_views<MAT>(c, P, tape(c, t - t0), tape(c, t - t0 + 1));
+            for (int t = t1 - 1; t >= t0; --t) {
+                int fi = frame_index(c, t + 1);
+                PView<T> aout = adj(c, a), ain = adj(c, 1 - a);
+                if (fi >= 0) observe(c, tape(c, t + 1 - t0), fi, &aout);
+                adjoint_step<MAT>(c, P, tape(c, t - t0), aout, ain);
+                a = 1 - a;
+            }
+        }
+        // dL/dv0 in pid order (S^0 is checkpoint 0)
+        if (grad_v0 && c->N > 0)
+            k_read_field<T, D><<<nblocks(c->N), kBlock, 0, st>>>(adj(c, a).v, c->cap, ckpt(c, 0).pid, c->N, D,
+                                                                CONV_COPY, 1, (T*)grad_v0);
+        if (grad_mu) k_mu_out<T><<<nblocks(nfl), kBlock, 0, st>>>(c->amu, nfl, (T*)grad_mu);
+        // the step's key and count arrays again describe the current state
+        int rc = S::recompute_keys(c);
+        if (rc) return rc;
+        rc = S::launch_err(c, "backward");
+        if (rc) return rc;
+        return hip_check(c, hipStreamSynchronize(st), "stream synchronize");
+    }
+
+    static int forward_loss(mpm_ctx* c, int n, double dt, double* loss)
+    {
+        switch (c->cfg.material) {
+        case MAT_FLUID: return forward_loss_mat<MAT_FLUID>(c, n, dt, loss);
+        case MAT_SAND: return forward_loss_mat<MAT_SAND>(c, n, dt, loss);
+        default: return forward_loss_mat<MAT_ELASTIC>(c, n, dt, loss);
+        }
+    }
+    static int backward(mpm_ctx* c, void* gv0, void* gmu)
+    {
+        switch (c->cfg.material) {
+        case MAT_FLUID: return backward_mat<MAT_FLUID>(c, gv0, gmu);
+        case MAT_SAND: return backward_mat<MAT_SAND>(c, gv0, gmu);
+        default: return backward_mat<MAT_ELASTIC>(c, gv0, gmu);
+        }
+    }
+};
+
+}  // namespace mpm

@@ -1,0 +1,386 @@
+// Device-side vector-Jacobian products of the constitutive updates and the
+// walls: the reverse of hencky_update, fluid_update and wall_node.
+//
+// The Hencky map is an isotropic function of b = F_tr F_tr^T: with
+// b = U diag(1 + beta) U^T every intermediate (E = log(b)/2, its deviator,
+// exp of the return) shares the eigenbasis U, and the derivative of a matrix
+// function f in that basis multiplies component (i,j) by the divided
+// difference f[l_i, l_j] (f'(l_i) on the diagonal).  Repeated eigenvalues
+// (F = I at rest) take the limit, evaluated by series.
+#pragma once
+
+#include "mpm_device.hpp"
+
+namespace mpm {
+
+template <class T> struct SeriesTol;
+template <> struct SeriesTol<float> { static constexpr float dl = 1e-3f, de = 1e-3f; };
+template <> struct SeriesTol<double> { static constexpr double dl = 1e-5, de = 1e-6; };
+
+// [f(bi) - f(bj)] / (bi - bj) for f(b) = log1p(b)/2
+template <class T>
+__device__ __forceinline__ T dd_halflog1p(T bi, T bj)
+{
+    T inv = T(1) / (T(1) + bj);
+    T del = (bi - bj) * inv;
+    if (fabs(del) < SeriesTol<T>::dl) return T(0.5) * inv * (T(1) - del * (T(0.5) - del * (T(1) / T(3))));
+    return T(0.5) * log1p(del) / (bi - bj);
+}
+
+// [exp(yi) - exp(yj)] / (yi - yj)
+template <class T>
+__device__ __forceinline__ T dd_exp(T yi, T yj)
+{
+    T del = yi - yj;
+    if (fabs(del) < SeriesTol<T>::de) return exp(yj) * (T(1) + del * (T(0.5) + del * (T(1) / T(6))));
+    return exp(yj) * expm1(del) / del;
+}
+
+template <class T, int D>
+__device__ __forceinline__ void to_eig(const T U[D][D], const T A[D][D], T R[D][D])   // R = U^T A U
+{
+    T tmp[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += A[i][k] * U[k][j];
+            tmp[i][j] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += U[k][i] * tmp[k][j];
+            R[i][j] = s;
+        }
+}
+
+template <class T, int D>
+__device__ __forceinline__ void from_eig(const T U[D][D], const T A[D][D], T R[D][D])   // R = U A U^T
+{
+    T tmp[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += A[i][k] * U[j][k];
+            tmp[i][j] = s;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += U[i][k] * tmp[k][j];
+            R[i][j] = s;
+        }
+}
+
+// Reverse of hencky_update.  Inputs: the velocity gradient L and stored
+// G = F_e - I of the step, the adjoints of the outputs (Gb_out for F_e',
+// sb_out for the stored symmetric stress).  Outputs: Lb and Gb_in.
+template <class T, int D>
+__device__ __forceinline__ void hencky_vjp(const Phys<T>& P, bool plastic, const T L[D][D], const T G[D][D],
+                                           const T Gb_out[D][D], const T sb_out[D * (D + 1) / 2], T Lb[D][D],
+                                           T Gb_in[D][D])
+{
+    const T dt = P.dt;
+    T Gt[D][D], Ft[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T lg = L[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) lg += L[i][k] * G[k][j];
+            Gt[i][j] = G[i][j] + dt * lg;
+            Ft[i][j] = Gt[i][j] + ((i == j) ? T(1) : T(0));
+        }
+    T B[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            T s = Gt[i][j] + Gt[j][i];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += Gt[i][k] * Gt[j][k];
+            B[i][j] = s;
+            B[j][i] = s;
+        }
+    T beta[D], U[D][D];
+    if constexpr (D == 3) {
+        T pk[6] = {B[0][0], B[1][1], B[2][2], B[0][1], B[0][2], B[1][2]};
+        T V[3][3];
+        sym_eig3(pk, beta, V);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) U[i][j] = V[i][j];
+    } else {
+        T pk[3] = {B[0][0], B[1][1], B[0][1]};
+        T V[2][2];
+        sym_eig2(pk, beta, V);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) U[i][j] = V[i][j];
+    }
+    T eps[D], tr = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        eps[i] = T(0.5) * log1p(beta[i]);
+        tr += eps[i];
+    }
+    T dev[D], dn2 = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        dev[i] = eps[i] - tr / T(D);
+        dn2 += dev[i] * dev[i];
+    }
+    T dn = sqrt(dn2);
+    int cas = 1;
+    if (plastic) {
+        if (tr > T(0)) cas = 0;
+        else if (dn + P.cone_coef * tr > T(0)) cas = 2;
+    }
+    // adjoint of the symmetric stress, scaled by V0 (S = V0 tau)
+    T taub[D][D];
+    if constexpr (D == 3) {
+        taub[0][0] = sb_out[0]; taub[1][1] = sb_out[1]; taub[2][2] = sb_out[2];
+        taub[0][1] = taub[1][0] = T(0.5) * sb_out[3];
+        taub[0][2] = taub[2][0] = T(0.5) * sb_out[4];
+        taub[1][2] = taub[2][1] = T(0.5) * sb_out[5];
+    } else {
+        taub[0][0] = sb_out[0]; taub[1][1] = sb_out[1];
+        taub[0][1] = taub[1][0] = T(0.5) * sb_out[2];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) taub[i][j] *= P.vol0;
+    T Tt[D][D];
+    to_eig<T, D>(U, taub, Tt);
+    T trT = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) trT += Tt[i][i];
+
+    T Ftb[D][D], Et[D][D];
+    if (cas == 1) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                Ftb[i][j] = Gb_out[i][j];
+                Et[i][j] = T(2) * P.mu * Tt[i][j] + ((i == j) ? P.lam * trT : T(0));
+            }
+    } else {
+        T kappa = (cas == 2) ? T(1) + P.cone_coef * tr / dn : T(0);
+        T y[D], ey[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            y[i] = (cas == 0) ? -eps[i] : -kappa * dev[i];
+            ey[i] = exp(y[i]);
+        }
+        // X = U diag(exp y) U^T ; F_e' = X F_tr
+        T X[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T s = T(0);
+#pragma unroll
+                for (int k = 0; k < D; ++k) s += U[i][k] * ey[k] * U[j][k];
+                X[i][j] = s;
+            }
+        T Xb[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T f = T(0), xb = T(0);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    f += X[i][k] * Gb_out[k][j];          // X symmetric: X^T Gb
+                    xb += Gb_out[i][k] * Ft[j][k];        // Gb F_tr^T
+                }
+                Ftb[i][j] = f;
+                Xb[i][j] = xb;
+            }
+        T Xs[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Xs[i][j] = T(0.5) * (Xb[i][j] + Xb[j][i]);
+        T Xt[D][D], Yt[D][D];
+        to_eig<T, D>(U, Xs, Xt);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Yt[i][j] = Xt[i][j] * ((i == j) ? ey[i] : dd_exp(y[i], y[j]));
+        if (cas == 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) Et[i][j] = -Yt[i][j];
+        } else {
+            const T a1 = T(2) * P.mu / T(D) + P.lam, b1 = T(2) * P.mu * P.cone_coef, c = P.cone_coef;
+            T Eht[D][D];
+            T kb = T(0), sTd = T(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                kb -= Yt[i][i] * dev[i];
+                sTd += Tt[i][i] * dev[i];
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) Eht[i][j] = -kappa * Yt[i][j] - b1 * tr * Tt[i][j] / dn;
+            T trb = a1 * trT - b1 * sTd / dn + kb * c / dn;
+            T nb = b1 * tr * sTd / (dn * dn) - kb * c * tr / (dn * dn);
+#pragma unroll
+            for (int i = 0; i < D; ++i) Eht[i][i] += nb * dev[i] / dn;
+            T trE = T(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) trE += Eht[i][i];
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+#pragma unroll
+                for (int j = 0; j < D; ++j) Et[i][j] = Eht[i][j] + ((i == j) ? trb - trE / T(D) : T(0));
+        }
+    }
+    // E = log1p(b - I)/2 : b bar in the eigenbasis, then back
+    T bt[D][D], bb[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            bt[i][j] = Et[i][j] * ((i == j) ? T(0.5) / (T(1) + beta[i]) : dd_halflog1p(beta[i], beta[j]));
+    from_eig<T, D>(U, bt, bb);
+    // b = F_tr F_tr^T
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += (bb[i][k] + bb[k][i]) * Ft[k][j];
+            Ftb[i][j] += s;
+        }
+    // F_tr = (I + dt L) F
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T l = T(0), g = Ftb[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                l += Ftb[i][k] * (G[j][k] + ((j == k) ? T(1) : T(0)));
+                g += dt * L[k][i] * Ftb[k][j];
+            }
+            Lb[i][j] = dt * l;
+            Gb_in[i][j] = g;
+        }
+}
+
+// Reverse of fluid_update: Jb_out and sb_out are the adjoints of J' - 1 and
+// of the isotropic stress value; dJ is the stored J - 1 of the step.
+template <class T, int D>
+__device__ __forceinline__ void fluid_vjp(const Phys<T>& P, const T L[D][D], T dJ, T Jb_out, T sb_out,
+                                          T Lb[D][D], T& Jb_in)
+{
+    const T dt = P.dt;
+    T M[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) M[i][j] = ((i == j) ? T(1) : T(0)) + dt * L[i][j];
+    T cof[D][D], detM;
+    if constexpr (D == 3) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                cof[i][j] = M[i1][j1] * M[i2][j2] - M[i1][j2] * M[i2][j1];
+            }
+        T A[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) A[i][j] = dt * L[i][j];
+        T trA = A[0][0] + A[1][1] + A[2][2];
+        T m2 = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) + (A[0][0] * A[2][2] - A[0][2] * A[2][0]) +
+               (A[1][1] * A[2][2] - A[1][2] * A[2][1]);
+        T det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        detM = T(1) + (trA + m2 + det);
+    } else {
+        cof[0][0] = M[1][1]; cof[0][1] = -M[1][0];
+        cof[1][0] = -M[0][1]; cof[1][1] = M[0][0];
+        T a00 = dt * L[0][0], a01 = dt * L[0][1], a10 = dt * L[1][0], a11 = dt * L[1][1];
+        detM = T(1) + ((a00 + a11) + (a00 * a11 - a01 * a10));
+    }
+    T dD = detM - T(1);
+    T dJn = dJ + dD + dJ * dD;
+    // s = -V0 J' p(J'),  p = (K/gamma)(J'^-gamma - 1)
+    T Jmg = exp(-P.gamma * log1p(dJn));
+    T dsdJ = -P.vol0 * P.k_over_gamma * ((T(1) - P.gamma) * Jmg - T(1));
+    T Jb = Jb_out + sb_out * dsdJ;
+    Jb_in = Jb * detM;
+    T J = T(1) + dJ;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) Lb[i][j] = Jb * J * cof[i][j] * dt;
+}
+
+// Reverse of wall_node for one face; vin is the velocity entering the face;
+// vb is replaced by the adjoint of vin; returns dL/dmu.
+template <class T, int D>
+__device__ __forceinline__ T wall_node_vjp(int mode, T mu, int axis, T sign, const T vin[D], T vb[D])
+{
+    T vn = sign * vin[axis];
+    if (!(vn > T(0))) return T(0);
+    if (mode == WALL_STICK) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) vb[a] = T(0);
+        return T(0);
+    }
+    if (mode == WALL_SLIP) {
+        vb[axis] = T(0);
+        return T(0);
+    }
+    T vt[D], t2 = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        vt[a] = (a == axis) ? T(0) : vin[a];
+        t2 += vt[a] * vt[a];
+    }
+    T t = sqrt(t2);
+    if (t <= mu * vn) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) vb[a] = T(0);
+        return T(0);
+    }
+    T s = T(1) - mu * vn / t;
+    T as = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) as += vb[a] * vt[a];
+    T vtb[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) vtb[a] = s * vb[a] + as * mu * vn / (t * t * t) * vt[a];
+    T vnb = -as * mu / t;
+#pragma unroll
+    for (int a = 0; a < D; ++a) vb[a] = (a == axis) ? sign * vnb : vtb[a];
+    return -as * vn / t;
+}
+
+}  // namespace mpm

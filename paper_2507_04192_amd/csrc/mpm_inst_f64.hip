@@ -1,7 +1,16 @@
 // Binary64 instantiation of the forward kernels.
-#include "mpm_kernels.hpp"
+#include "mpm_adjoint.hpp"
 
 namespace mpm {
-const Ops ops_f64_2d = Solver<double, 2>::table();
-const Ops ops_f64_3d = Solver<double, 3>::table();
+template <class T, int D>
+static Ops with_adjoint()
+{
+    Ops o = Solver<T, D>::table();
+    o.forward_loss = &Adjoint<T, D>::forward_loss;
+    o.backward = &Adjoint<T, D>::backward;
+    return o;
+}
+
+const Ops ops_f64_2d = with_adjoint<double, 2>();
+const Ops ops_f64_3d = with_adjoint<double, 3>();
 }  // namespace mpm

@@ -489,7 +489,7 @@ template <class T, int D>
 __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                  const ActiveTile* __restrict__ active,
                                                  const int* __restrict__ tile_slot, const T* __restrict__ part,
-                                                 T* __restrict__ gv, T* __restrict__ gmass)
+                                                 T* __restrict__ gv, T* __restrict__ gmass, T* __restrict__ gvt)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     const int n_active = meta[0];
@@ -548,6 +548,9 @@ __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __
             if (m > T(0)) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) v[a] = p[a] / m + P.dt * P.g[a];
+                if (gvt)
+#pragma unroll
+                    for (int a = 0; a < D; ++a) gvt[a * g.NN + node] = v[a];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     int ip = I[a] - g.G;
@@ -562,6 +565,9 @@ __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __
                     }
                     if (ip >= g.n[a]) wall_node<T, D>(P.wall_mode[2 * a + 1], P.wall_mu[2 * a + 1], a, T(1), v);
                 }
+            } else if (gvt) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) gvt[a * g.NN + node] = T(0);
             }
 #pragma unroll
             for (int a = 0; a < D; ++a) gv[a * g.NN + node] = v[a];
@@ -922,8 +928,9 @@ struct Solver {
         return launch_err(c, "clear grid");
     }
 
+    // One step from state view cur into state view nxt.
     template <int MAT>
-    static void one_step(mpm_ctx* c, const Phys<T>& P)
+    static void step_views(mpm_ctx* c, const Phys<T>& P, const PView<T>& cur, const PView<T>& nxt)
     {
         hipStream_t st = c->stream;
         const Geo& g = c->geo;
@@ -934,16 +941,21 @@ struct Solver {
         prof_mark(c, MPM_PROF_SCAN);
         k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
         prof_mark(c, MPM_PROF_BUCKET);
-        PView<T> cur = view<T>(c, c->cur), nxt = view<T>(c, 1 - c->cur);
         k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->tmpk, cur, c->perm,
                                                       (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
         k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (const T*)c->part_grid,
-                                                  (T*)c->gv, (T*)c->gmass);
+                                                  (T*)c->gv, (T*)c->gmass, (T*)nullptr);
         prof_mark(c, MPM_PROF_GRID);
         k_g2p<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, cur, nxt, (const T*)c->gv,
                                                       c->key, c->count, c->status);
         prof_mark(c, MPM_PROF_G2P);
+    }
+
+    template <int MAT>
+    static void one_step(mpm_ctx* c, const Phys<T>& P)
+    {
+        step_views<MAT>(c, P, view<T>(c, c->cur), view<T>(c, 1 - c->cur));
         c->cur = 1 - c->cur;
     }
 

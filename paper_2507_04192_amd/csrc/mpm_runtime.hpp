@@ -19,6 +19,7 @@ namespace mpm {
 constexpr int kBlock = 256;        // threads per workgroup (4 waves)
 constexpr int kScanChunk = 2048;   // tiles per scan workgroup
 constexpr int kTileWGs = 2048;     // workgroups of the per-tile kernels (8 XCDs x 256)
+constexpr int kMaxBoxes = MPM_MAX_BOXES;   // Eulerian observation regions
 
 struct Ops;
 
@@ -61,6 +62,39 @@ struct mpm_ctx {
     void* gmass = nullptr;         // nodal mass kept for read-back
     const void* floor_mu = nullptr;
 
+    // forward-plus-adjoint rollout (mpm_forward_loss / mpm_backward)
+    char* ckpt = nullptr;          // checkpoints, one state every ckpt_every steps
+    int32_t* ckpt_pid = nullptr;
+    char* tape = nullptr;          // a segment's recomputed states (ckpt_every + 1)
+    int32_t* tape_pid = nullptr;
+    char* adj[2] = {nullptr, nullptr};   // adjoint states (same layout as a state)
+    void* mid = nullptr;           // per slot: partial position adjoint, F or J adjoint
+    void* gvt = nullptr;           // nodal velocity before the walls [dim]
+    int32_t* inv = nullptr;        // slot of each pid
+    double* amu = nullptr;         // dL/dmu per floor node
+    double* loss = nullptr;        // [0] loss of the last forward rollout
+    double* loss_scratch = nullptr;
+    double* box_sum = nullptr;
+    int32_t* box_cnt = nullptr;
+    double* box_coef = nullptr;
+    int fwd_steps = 0;
+    double fwd_dt = 0.0;
+    bool has_tape = false;
+
+    // observations (mpm_set_observations)
+    std::vector<int> obs_frames;
+    int obs_ntr = 0;
+    const int32_t* obs_tracer = nullptr;
+    int obs_lag_field = 0;
+    const void* obs_lag_target = nullptr;
+    const void* obs_lag_mask = nullptr;
+    int obs_nbox = 0;
+    double box_lo[MPM_MAX_BOXES][3] = {};
+    double box_hi[MPM_MAX_BOXES][3] = {};
+    int obs_eul_field = 1;
+    const void* obs_eul_target = nullptr;
+    const void* obs_eul_mask = nullptr;
+
     // per-kernel-class timing (mpm_profile_enable)
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -82,6 +116,8 @@ struct Ops {
     int (*read_state)(mpm_ctx*, int field, int order, void* dst);
     int (*write_state)(mpm_ctx*, int field, int order, const void* src);
     int (*read_grid)(mpm_ctx*, int which, void* dst);
+    int (*forward_loss)(mpm_ctx*, int n, double dt, double* loss);
+    int (*backward)(mpm_ctx*, void* grad_v0, void* grad_mu);
 };
 
 extern const Ops ops_f32_2d, ops_f32_3d, ops_f64_2d, ops_f64_3d;

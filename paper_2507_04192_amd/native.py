@@ -33,6 +33,16 @@ class MPMError(RuntimeError):
         self.code = code
 
 
+class MpmObs(ct.Structure):
+    _fields_ = [
+        ("n_frames", ct.c_int32), ("host_frames", ct.c_void_p),
+        ("n_tracers", ct.c_int32), ("tracer_pid", ct.c_void_p), ("lag_field", ct.c_int32),
+        ("lag_target", ct.c_void_p), ("lag_mask", ct.c_void_p),
+        ("n_boxes", ct.c_int32), ("host_box_lo", ct.c_void_p), ("host_box_hi", ct.c_void_p),
+        ("eul_field", ct.c_int32), ("eul_target", ct.c_void_p), ("eul_mask", ct.c_void_p),
+    ]
+
+
 class MpmConfig(ct.Structure):
     _fields_ = [
         ("dim", ct.c_int32), ("precision", ct.c_int32), ("n", ct.c_int32 * 3), ("ghost", ct.c_int32),
@@ -69,6 +79,9 @@ def lib():
             "mpm_read_sort": ([P, P, P], ct.c_int),
             "mpm_num_particles": ([P], ct.c_int64),
             "mpm_profile_enable": ([P, ct.c_int], ct.c_int),
+            "mpm_set_observations": ([P, P], ct.c_int),
+            "mpm_forward_loss": ([P, i32, ct.c_double, P], ct.c_int),
+            "mpm_backward": ([P, P, P], ct.c_int),
             "mpm_profile_read": ([P, P, P], ct.c_int),
             "mpm_last_error": ([P], ct.c_char_p),
             "mpm_destroy": ([P], ct.c_int),
@@ -89,7 +102,8 @@ _HEADER_NAMES = [
     "mpm_create", "mpm_workspace_bytes", "mpm_bind_workspace", "mpm_init_particles",
     "mpm_set_floor_mu", "mpm_step", "mpm_sync_status", "mpm_read_state", "mpm_write_state",
     "mpm_read_grid", "mpm_read_sort", "mpm_num_particles", "mpm_last_error", "mpm_destroy",
-    "mpm_profile_enable", "mpm_profile_read",
+    "mpm_profile_enable", "mpm_profile_read", "mpm_set_observations", "mpm_forward_loss",
+    "mpm_backward",
 ]
 PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p"]
 
@@ -240,6 +254,59 @@ class Solver:
         key = torch.empty(N, dtype=torch.int32, device=self.device)
         _check(self.ctx, self.L.mpm_read_sort(self.ctx, None, _ptr(key)))
         return key
+
+    def mpm_set_observations(self, frames, tracer_pid=None, lag_field="x", lag_target=None, lag_mask=None,
+                             box_lo=None, box_hi=None, eul_field="v", eul_target=None, eul_mask=None):
+        """Observation operators of the loss (see include/mpm.h, mpm_obs)."""
+        torch = self.torch
+        o = MpmObs()
+        fr = np.ascontiguousarray(frames, dtype=np.int32)
+        keep = [fr]
+        o.n_frames = fr.shape[0]
+        o.host_frames = fr.ctypes.data
+        if tracer_pid is not None:
+            tp = torch.as_tensor(np.asarray(tracer_pid), dtype=torch.int32).to(self.device).contiguous()
+            tg = self._dev(lag_target)
+            keep += [tp, tg]
+            o.n_tracers = tp.numel()
+            o.tracer_pid = tp.data_ptr()
+            o.lag_field = FIELD[lag_field]
+            o.lag_target = tg.data_ptr()
+            if lag_mask is not None:
+                mk = self._dev(lag_mask)
+                keep.append(mk)
+                o.lag_mask = mk.data_ptr()
+        if box_lo is not None:
+            lo = np.ascontiguousarray(box_lo, dtype=np.float64)
+            hi = np.ascontiguousarray(box_hi, dtype=np.float64)
+            tg = self._dev(eul_target)
+            keep += [lo, hi, tg]
+            o.n_boxes = lo.shape[0]
+            o.host_box_lo = lo.ctypes.data
+            o.host_box_hi = hi.ctypes.data
+            o.eul_field = FIELD[eul_field]
+            o.eul_target = tg.data_ptr()
+            if eul_mask is not None:
+                mk = self._dev(eul_mask)
+                keep.append(mk)
+                o.eul_mask = mk.data_ptr()
+        _check(self.ctx, self.L.mpm_set_observations(self.ctx, ct.byref(o)))
+        self._obs_keep = keep
+
+    def mpm_forward_loss(self, n_steps, dt=None):
+        dt = self.cfg.dt if dt is None else dt
+        loss = ct.c_double()
+        _check(self.ctx, self.L.mpm_forward_loss(self.ctx, int(n_steps), float(dt), ct.byref(loss)))
+        return loss.value
+
+    def mpm_backward(self, want_v0=True, want_mu=True):
+        """(dL/dv0 [dim, N] in pid order, dL/dmu per floor node) as tensors."""
+        torch = self.torch
+        N = self.num_particles()
+        gv = torch.empty((self.cfg.dim, N), dtype=self.dtype, device=self.device) if want_v0 else None
+        gm = torch.empty(self.cfg.floor_nodes(), dtype=self.dtype, device=self.device) if want_mu else None
+        _check(self.ctx, self.L.mpm_backward(self.ctx, _ptr(gv), _ptr(gm)))
+        return gv, gm
 
     def mpm_profile_enable(self, on=True):
         _check(self.ctx, self.L.mpm_profile_enable(self.ctx, 1 if on else 0))

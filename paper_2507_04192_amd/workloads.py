@@ -125,10 +125,11 @@ def cylinder_inside(cx, cy, radius, height):
 def dam_break_2d(scale: int = 1, seed: int = 0):
     """2-D dam-break: 2.0 x 1.0 m domain at 128 x 64 cells (scale 1),
     water column 0.5 x 1.0 m, 2 x 2 particles per cell, Tait K=1e5,
-    rho=1000, gamma=7, gravity -9.81, slip walls, dt = 1e-4 s."""
+    rho=1000, gamma=7, gravity -9.81, slip walls, dt = 1e-4 s (the same dt
+    at every scale)."""
     n = (128 * scale, 64 * scale, 1)
     dx = 1.0 / (64 * scale)
-    cfg = SimConfig(dim=2, n=n, dx=dx, dt=1e-4 / scale, material=FLUID, ppc=4,
+    cfg = SimConfig(dim=2, n=n, dx=dx, dt=1e-4, material=FLUID, ppc=4,
                     gravity=(0.0, -9.81, 0.0), rho0=1000.0, bulk=1.0e5, gamma=7.0)
     x = lattice_particles(cfg, box_inside((0.0, 0.0), (0.5, 1.0)), (0.0, 0.0), (0.5, 1.0), seed)
     return cfg, x
