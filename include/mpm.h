@@ -201,6 +201,46 @@ int mpm_forward_loss(mpm_ctx* ctx, int32_t n_steps, double dt, double* host_loss
  * ESTATE without a preceding mpm_forward_loss. */
 int mpm_backward(mpm_ctx* ctx, void* grad_v0, void* grad_mu);
 
+/* Learned parameter field alpha(x) ~ N_theta(x) (Sec. 3.2, eq:nn_apprx): a
+ * small MLP on the matrix cores.  Layers l = 0..n_layers-1 map width[l] to
+ * width[l+1]; hidden layers use tanh; the output layer applies out_act and
+ * then y = out_shift + out_scale * act(z).  Inputs are first mapped
+ * feature-wise to in_scale[k] * x_k + in_shift[k].  math selects the MFMA
+ * operand type: BF16 operands with FP32 accumulation, or FP32 operands.
+ * Parameters are FP32: for each layer W_l (width[l+1] x width[l],
+ * row-major) then b_l, layers concatenated.  x is [width[0]][n] and y, dy
+ * are [width[n_layers]][n] (component-major, like particle fields); cache
+ * and work are scratch of mpm_mlp_cache_floats(n) floats each.  These calls
+ * need no solver context; they queue work on hip_stream. */
+#define MPM_MLP_MAX_LAYERS 4
+#define MPM_MLP_MAX_IN 4
+enum { MPM_ACT_NONE = 0, MPM_ACT_SIGMOID = 1 };
+enum { MPM_MLP_BF16 = 0, MPM_MLP_F32 = 1 };
+typedef struct mpm_mlp {
+    int32_t n_layers;                       /* 1..MPM_MLP_MAX_LAYERS */
+    int32_t width[MPM_MLP_MAX_LAYERS + 1];  /* each in [1, 128]; width[0] <= MPM_MLP_MAX_IN */
+    int32_t out_act;                        /* MPM_ACT_NONE or MPM_ACT_SIGMOID */
+    int32_t math;                           /* MPM_MLP_BF16 or MPM_MLP_F32 */
+    float out_scale, out_shift;
+    float in_scale[MPM_MLP_MAX_IN], in_shift[MPM_MLP_MAX_IN];
+} mpm_mlp;
+
+/* Number of parameters, or -1 for an invalid description. */
+int64_t mpm_mlp_num_params(const mpm_mlp* net);
+/* Floats of the activation cache (and of the backward work buffer) for n samples. */
+int64_t mpm_mlp_cache_floats(const mpm_mlp* net, int64_t n);
+/* y = N_theta(x) for n samples; fills cache for mpm_mlp_backward. */
+int mpm_mlp_forward(const mpm_mlp* net, void* hip_stream, const float* params, int64_t n, const float* x,
+                    float* y, float* cache);
+/* dparams = gradient of sum(dy * y) with respect to the parameters (the
+ * buffer is overwritten), using the cache of the matching forward call. */
+int mpm_mlp_backward(const mpm_mlp* net, void* hip_stream, const float* params, int64_t n, const float* x,
+                     const float* cache, const float* dy, float* work, float* dparams);
+/* One Adam update (Kingma & Ba) of n parameters in place; step >= 1 counts
+ * updates; m and v are the moment buffers (start at zero). */
+int mpm_adam_step(void* hip_stream, int64_t n, float* params, const float* grad, float* m, float* v,
+                  int32_t step, double lr, double beta1, double beta2, double eps);
+
 /* Per-kernel-class timing of mpm_step: with profiling on, HIP events are
  * recorded on the context's stream between the kernel classes below, and
  * mpm_profile_read (synchronizes) returns, per class, the summed event time

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-UNITS = ["mpm_abi.cpp", "mpm_inst_f32.hip", "mpm_inst_f64.hip"]
+UNITS = ["mpm_abi.cpp", "mpm_inst_f32.hip", "mpm_inst_f64.hip", "mpm_mlp.hip"]
 
 COMMON = [
     "-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",

@@ -43,6 +43,14 @@ class MpmObs(ct.Structure):
     ]
 
 
+class MpmMlp(ct.Structure):
+    _fields_ = [
+        ("n_layers", ct.c_int32), ("width", ct.c_int32 * 5), ("out_act", ct.c_int32), ("math", ct.c_int32),
+        ("out_scale", ct.c_float), ("out_shift", ct.c_float),
+        ("in_scale", ct.c_float * 4), ("in_shift", ct.c_float * 4),
+    ]
+
+
 class MpmConfig(ct.Structure):
     _fields_ = [
         ("dim", ct.c_int32), ("precision", ct.c_int32), ("n", ct.c_int32 * 3), ("ghost", ct.c_int32),
@@ -82,6 +90,12 @@ def lib():
             "mpm_set_observations": ([P, P], ct.c_int),
             "mpm_forward_loss": ([P, i32, ct.c_double, P], ct.c_int),
             "mpm_backward": ([P, P, P], ct.c_int),
+            "mpm_mlp_num_params": ([P], ct.c_int64),
+            "mpm_mlp_cache_floats": ([P, i64], ct.c_int64),
+            "mpm_mlp_forward": ([P, P, P, i64, P, P, P], ct.c_int),
+            "mpm_mlp_backward": ([P, P, P, i64, P, P, P, P, P], ct.c_int),
+            "mpm_adam_step": ([P, i64, P, P, P, P, i32, ct.c_double, ct.c_double, ct.c_double, ct.c_double],
+                              ct.c_int),
             "mpm_profile_read": ([P, P, P], ct.c_int),
             "mpm_last_error": ([P], ct.c_char_p),
             "mpm_destroy": ([P], ct.c_int),
@@ -103,7 +117,8 @@ _HEADER_NAMES = [
     "mpm_set_floor_mu", "mpm_step", "mpm_sync_status", "mpm_read_state", "mpm_write_state",
     "mpm_read_grid", "mpm_read_sort", "mpm_num_particles", "mpm_last_error", "mpm_destroy",
     "mpm_profile_enable", "mpm_profile_read", "mpm_set_observations", "mpm_forward_loss",
-    "mpm_backward",
+    "mpm_backward", "mpm_mlp_num_params", "mpm_mlp_cache_floats", "mpm_mlp_forward", "mpm_mlp_backward",
+    "mpm_adam_step",
 ]
 PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p"]
 
@@ -346,3 +361,128 @@ class Solver:
         if order == "memory":
             out["pid"] = self.mpm_read_state("pid", "memory").cpu().numpy()[0]
         return out
+
+
+# ---------------------------------------------------------------------------
+# Learned field: MLP on MFMA, Adam, and autograd glue
+# ---------------------------------------------------------------------------
+
+class MLP:
+    """alpha(x) = N_theta(x) evaluated by the MFMA kernels (mpm_mlp_*).
+
+    widths: [d_in, hidden..., d_out]; hidden tanh; output 'none' or 'sigmoid'
+    followed by out_shift + out_scale * act.  Inputs are mapped feature-wise
+    to in_scale * x + in_shift inside the kernel.  math: 'bf16' or 'f32'."""
+
+    def __init__(self, widths, out_act="none", out_scale=1.0, out_shift=0.0, in_scale=None, in_shift=None,
+                 math="bf16"):
+        import torch
+        self.torch = torch
+        d = MpmMlp()
+        d.n_layers = len(widths) - 1
+        for i, wv in enumerate(widths):
+            d.width[i] = int(wv)
+        d.out_act = {"none": 0, "sigmoid": 1}[out_act]
+        d.math = {"bf16": 0, "f32": 1}[math]
+        d.out_scale, d.out_shift = float(out_scale), float(out_shift)
+        for k in range(4):
+            d.in_scale[k] = float(in_scale[k]) if in_scale is not None and k < len(in_scale) else 1.0
+            d.in_shift[k] = float(in_shift[k]) if in_shift is not None and k < len(in_shift) else 0.0
+        self.desc = d
+        self.widths = list(widths)
+        self.L = lib()
+        self.n_params = int(self.L.mpm_mlp_num_params(ct.byref(d)))
+        if self.n_params < 0:
+            raise MPMError(MPM_EINVAL, "invalid network description")
+
+    def _stream(self):
+        return ct.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def cache_floats(self, n):
+        return int(self.L.mpm_mlp_cache_floats(ct.byref(self.desc), n))
+
+    def forward(self, params, x):
+        """x: float32 cuda tensor [d_in, n]; returns (y [d_out, n], cache)."""
+        torch = self.torch
+        n = x.shape[1]
+        y = torch.empty((self.widths[-1], n), dtype=torch.float32, device=x.device)
+        cache = torch.empty(max(self.cache_floats(n), 1), dtype=torch.float32, device=x.device)
+        rc = self.L.mpm_mlp_forward(ct.byref(self.desc), self._stream(), _ptr(params), n, _ptr(x), _ptr(y),
+                                    _ptr(cache))
+        _check(None, rc)
+        return y, cache
+
+    def backward(self, params, x, cache, dy):
+        torch = self.torch
+        n = x.shape[1]
+        work = torch.empty_like(cache)
+        dp = torch.empty_like(params)
+        rc = self.L.mpm_mlp_backward(ct.byref(self.desc), self._stream(), _ptr(params), n, _ptr(x), _ptr(cache),
+                                     _ptr(dy.contiguous()), _ptr(work), _ptr(dp))
+        _check(None, rc)
+        return dp
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update on float32 cuda tensors (mpm_adam_step)."""
+    import torch
+    L = lib()
+    rc = L.mpm_adam_step(ct.c_void_p(torch.cuda.current_stream().cuda_stream), params.numel(), _ptr(params),
+                         _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1), float(beta2), float(eps))
+    _check(None, rc)
+
+
+def _autograd():
+    import torch
+
+    class MLPFunction(torch.autograd.Function):
+        """y = N_theta(x); gradient with respect to theta only."""
+
+        @staticmethod
+        def forward(ctx, params, x, net):
+            y, cache = net.forward(params, x)
+            ctx.save_for_backward(params, x, cache)
+            ctx.net = net
+            return y
+
+        @staticmethod
+        def backward(ctx, dy):
+            params, x, cache = ctx.saved_tensors
+            return ctx.net.backward(params, x, cache, dy.float()), None, None
+
+    class MPMRollout(torch.autograd.Function):
+        """loss = L(v0, mu): a checkpointed rollout of the solver from its
+        initial positions (forward: mpm_forward_loss) and the hand-written
+        reverse sweep (backward: mpm_backward)."""
+
+        @staticmethod
+        def forward(ctx, v0, mu, solver, x0, steps):
+            solver.mpm_init_particles(x0, v0.to(solver.dtype))
+            if mu is not None:
+                solver.mpm_set_floor_mu(mu.to(solver.dtype))
+            loss = solver.mpm_forward_loss(steps)
+            ctx.solver = solver
+            ctx.has_mu = mu is not None
+            ctx.v0_dtype = v0.dtype
+            ctx.mu_dtype = None if mu is None else mu.dtype
+            return torch.tensor(loss, dtype=torch.float64, device=v0.device)
+
+        @staticmethod
+        def backward(ctx, gl):
+            gv, gm = ctx.solver.mpm_backward(want_v0=True, want_mu=ctx.has_mu)
+            gv = (gv * gl).to(ctx.v0_dtype)
+            gm = None if gm is None else (gm * gl).to(ctx.mu_dtype)
+            return gv, gm, None, None, None
+
+    return MLPFunction, MPMRollout
+
+
+_fns = None
+
+
+def autograd_functions():
+    """(MLPFunction, MPMRollout) torch.autograd.Function classes."""
+    global _fns
+    if _fns is None:
+        _fns = _autograd()
+    return _fns

@@ -1,0 +1,111 @@
+"""The MFMA network kernels against the binary64 oracle network.
+
+FP32-operand MFMA: relative L2 <= 1e-5 on outputs and parameter gradients;
+BF16 operands with FP32 accumulation: <= 1e-2.  Adam against the oracle's
+update."""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+ARCHS = [([2, 64, 64, 2], "none", 1.0, 0.0), ([2, 128, 128, 1], "sigmoid", 1.0, 0.0),
+         ([3, 16, 40, 5], "sigmoid", 0.7, 0.2)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _t(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("math,tol", [("f32", 1e-5), ("bf16", 1e-2)])
+@pytest.mark.parametrize("arch", range(len(ARCHS)))
+@pytest.mark.parametrize("n", [1000, 4099])
+def test_forward_backward_match_oracle(math, tol, arch, n):
+    from paper_2507_04192_amd.native import MLP
+    widths, act, sc, sh = ARCHS[arch]
+    print(f"[case] mlp {widths} {act} {math} n={n}", flush=True)
+    d_in = widths[0]
+    rng = np.random.default_rng(100 + arch)
+    lo, hi = -0.5, 2.0                       # raw inputs mapped to [-1, 1] in the kernel
+    xs = 2.0 / (hi - lo)
+    x = rng.uniform(lo, hi, size=(d_in, n)).astype(np.float32)
+    spec = OM.Spec(widths, act, sc, sh)
+    p = OM.init_params(spec, 7 + arch).astype(np.float32)
+    net = MLP(widths, act, sc, sh, in_scale=[xs] * d_in, in_shift=[-1.0 - lo * xs] * d_in, math=math)
+    assert net.n_params == p.size
+    y, cache = net.forward(_t(p), _t(x))
+    xin = (xs * x.astype(np.float64) + (-1.0 - lo * xs)).T
+    y_o, acts = OM.forward(spec, p.astype(np.float64), xin)
+    e = rel_l2(y.cpu().numpy().T, y_o)
+    dy = rng.normal(size=(widths[-1], n)).astype(np.float32)
+    g = net.backward(_t(p), _t(x), cache, _t(dy)).cpu().numpy()
+    g_o = OM.backward(spec, p.astype(np.float64), acts, dy.T.astype(np.float64))
+    eg = rel_l2(g, g_o)
+    print(f"  y {e:.2e}  dparams {eg:.2e}", flush=True)
+    assert e <= tol and eg <= tol
+
+
+def test_adam_matches_oracle():
+    from paper_2507_04192_amd.native import adam_step
+    rng = np.random.default_rng(9)
+    n = 5000
+    p = rng.normal(size=n)
+    m, v = np.zeros(n), np.zeros(n)
+    tp, tm, tv = _t(p), _t(m), _t(v)
+    for step in range(1, 6):
+        g = rng.normal(size=n)
+        OM.adam(p, g, m, v, step, lr=1e-2)
+        adam_step(tp, _t(g), tm, tv, step, 1e-2)
+    assert rel_l2(tp.cpu().numpy(), p) <= 1e-6
+    assert rel_l2(tm.cpu().numpy(), m) <= 1e-6 and rel_l2(tv.cpu().numpy(), v) <= 1e-6
+
+
+def test_learned_field_gradient_through_solver(orc):
+    """v0(x) = N_theta(x) on the particles, loss through the solver: the
+    chained gradient dL/dtheta (MFMA network + HIP adjoint) against the
+    oracle's network backward applied to the oracle rollout gradient."""
+    import torch
+    from paper_2507_04192_amd import workloads as W
+    from paper_2507_04192_amd.native import MLP, Solver, autograd_functions
+    MLPFunction, MPMRollout = autograd_functions()
+    cfg = W.SimConfig(dim=2, n=(48, 24, 1), dx=1 / 80, dt=2e-5, material=W.SAND, ppc=4,
+                      gravity=(0, -9.81, 0), rho0=2000.0, youngs=1e7, poisson=0.3, phi_deg=35.0,
+                      wall_mode=(W.SLIP, W.SLIP, W.COULOMB, W.SLIP, W.SLIP, W.SLIP),
+                      wall_mu=(0, 0, 0.5, 0, 0, 0))
+    x0 = W.lattice_particles(cfg, W.box_inside((0.1, 0), (0.4, 0.1)), (0.1, 0), (0.4, 0.1), seed=101)
+    N = x0.shape[1]
+    x0 = x0.astype(np.float32).astype(np.float64)
+    widths = [2, 64, 64, 2]
+    spec = OM.Spec(widths)
+    p = OM.init_params(spec, 102).astype(np.float32)
+    net = MLP(widths, in_scale=[2 / 0.6, 2 / 0.3], in_shift=[-1.0, -1.0], math="f32")
+    steps, frames = 20, [10, 20]
+    tr = W.pick_tracers(N, 30, 103)
+    rng = np.random.default_rng(104)
+    tgt = rng.normal(0, 0.1, size=(2, 2, 30)).astype(np.float32).astype(np.float64)
+    s = Solver(cfg, "f64", capacity=N, tape_steps=steps, ckpt_every=10)
+    s.mpm_set_observations(frames=frames, tracer_pid=tr, lag_field="v", lag_target=tgt)
+    theta = _t(p).requires_grad_(True)
+    v0 = MLPFunction.apply(theta, _t(x0), net)
+    loss = MPMRollout.apply(v0, None, s, x0, steps)
+    loss.backward()
+    g = theta.grad.cpu().numpy()
+    # oracle chain
+    xin = np.stack([2 / 0.6 * x0[0] - 1.0, 2 / 0.3 * x0[1] - 1.0]).T
+    v0_o, acts = OM.forward(spec, p.astype(np.float64), xin)
+    loss_o, gv0_o, _ = orc.rollout_grad(cfg, x0, v0_o.T, steps, cfg.dt, None,
+                                        orc.Observations(frames, tr, "v", tgt))
+    g_o = OM.backward(spec, p.astype(np.float64), acts, gv0_o.T)
+    print(f"  loss {loss.item():.6e} vs {loss_o:.6e}; dL/dtheta rel L2 {rel_l2(g, g_o):.2e}", flush=True)
+    assert abs(loss.item() - loss_o) <= 1e-5 * loss_o
+    assert rel_l2(g, g_o) <= 1e-4
