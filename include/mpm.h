@@ -241,6 +241,23 @@ int mpm_mlp_backward(const mpm_mlp* net, void* hip_stream, const float* params, 
 int mpm_adam_step(void* hip_stream, int64_t n, float* params, const float* grad, float* m, float* v,
                   int32_t step, double lr, double beta1, double beta2, double eps);
 
+/* Plain parametric field, the fallback of the learned one (Sec. 3.2,
+ * parameter forms): nc components piecewise constant on an nx x ny cell grid
+ * over [lo, hi) of the first two coordinates (host_lo, host_hi: 2 doubles);
+ * points outside take the nearest cell.  x: [>=2][n] FP32 positions,
+ * table: [nc][ny][nx] FP32, out/dout: [nc][n].  gather: out = table(cell(x));
+ * scatter: dtable (overwritten) = per-cell sums of dout (the adjoint). */
+int mpm_cell_field_gather(void* hip_stream, int32_t nc, int32_t nx, int32_t ny, const double* host_lo,
+                          const double* host_hi, int64_t n, const float* x, const float* table, float* out);
+int mpm_cell_field_scatter(void* hip_stream, int32_t nc, int32_t nx, int32_t ny, const double* host_lo,
+                           const double* host_hi, int64_t n, const float* x, const float* dout, float* dtable);
+
+/* The extraction operators of the set observations applied to the current
+ * state: lag_q [dim][n_tracers] (tracer values) and eul_q [dim][n_boxes]
+ * (box means; zero for an empty box), device, context precision; either may
+ * be NULL.  Used to record synthetic observations from a ground-truth run. */
+int mpm_extract(mpm_ctx* ctx, void* lag_q, void* eul_q);
+
 /* Per-kernel-class timing of mpm_step: with profiling on, HIP events are
  * recorded on the context's stream between the kernel classes below, and
  * mpm_profile_read (synchronizes) returns, per class, the summed event time

@@ -449,6 +449,14 @@ int mpm_backward(mpm_ctx* c, void* grad_v0, void* grad_mu)
     return c->ops->backward(c, grad_v0, grad_mu);
 }
 
+int mpm_extract(mpm_ctx* c, void* lag_q, void* eul_q)
+{
+    int rc = need_particles(c);
+    if (rc) return rc;
+    if (c->N < 1) return set_err(c, MPM_EINVAL, "no particles to observe");
+    return c->ops->extract(c, lag_q, eul_q);
+}
+
 int mpm_profile_enable(mpm_ctx* c, int on)
 {
     if (!c) return MPM_EINVAL;

@@ -602,6 +602,28 @@ __global__ void k_box_seed(Boxes bx, const T* __restrict__ x, T* __restrict__ zb
     }
 }
 
+template <class T, int D>
+__global__ void k_lag_extract(const T* __restrict__ z, long long cap, long long N, const int32_t* __restrict__ inv,
+                              const int32_t* __restrict__ tracer, int ntr, T* __restrict__ q)
+{
+    int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= ntr) return;
+    int id = tracer[l];
+    bool ok = id >= 0 && id < N;
+    int s = ok ? inv[id] : 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) q[a * ntr + l] = ok ? z[a * cap + s] : T(0);
+}
+
+template <class T, int D>
+__global__ void k_box_mean(int nbox, const double* __restrict__ sum, const int* __restrict__ cnt, T* __restrict__ q)
+{
+    int b = threadIdx.x;
+    if (b >= nbox) return;
+#pragma unroll
+    for (int a = 0; a < D; ++a) q[a * nbox + b] = cnt[b] > 0 ? (T)(sum[b * 3 + a] / cnt[b]) : T(0);
+}
+
 template <class T>
 __global__ void k_mu_out(const double* __restrict__ amu, long long n, T* __restrict__ out)
 {
@@ -805,6 +827,28 @@ struct Adjoint {
         rc = S::launch_err(c, "backward");
         if (rc) return rc;
         return hip_check(c, hipStreamSynchronize(st), "stream synchronize");
+    }
+
+    static int extract(mpm_ctx* c, void* lag_q, void* eul_q)
+    {
+        hipStream_t st = c->stream;
+        PView<T> v = view<T>(c, c->cur);
+        long long N = c->N;
+        if (lag_q && c->obs_ntr > 0) {
+            k_inverse_pid<0><<<nblocks(N), kBlock, 0, st>>>(v.pid, N, c->inv);
+            const T* z = c->obs_lag_field == MPM_FIELD_X ? v.x : v.v;
+            k_lag_extract<T, D><<<nblocks(c->obs_ntr), kBlock, 0, st>>>(z, v.cap, N, c->inv, c->obs_tracer,
+                                                                        c->obs_ntr, (T*)lag_q);
+        }
+        if (eul_q && c->obs_nbox > 0) {
+            Boxes bx = boxes(c);
+            k_fill<double><<<1, kBlock, 0, st>>>(c->box_sum, kMaxBoxes * 3, 0.0);
+            k_fill<int><<<1, kBlock, 0, st>>>(c->box_cnt, kMaxBoxes, 0);
+            const T* z = c->obs_eul_field == MPM_FIELD_X ? v.x : v.v;
+            k_box_sum<T, D><<<nblocks(N), kBlock, 0, st>>>(bx, v.x, z, v.cap, N, c->box_sum, c->box_cnt);
+            k_box_mean<T, D><<<1, kMaxBoxes, 0, st>>>(c->obs_nbox, c->box_sum, c->box_cnt, (T*)eul_q);
+        }
+        return S::launch_err(c, "extract");
     }
 
     static int forward_loss(mpm_ctx* c, int n, double dt, double* loss)

@@ -8,6 +8,7 @@ static Ops with_adjoint()
     Ops o = Solver<T, D>::table();
     o.forward_loss = &Adjoint<T, D>::forward_loss;
     o.backward = &Adjoint<T, D>::backward;
+    o.extract = &Adjoint<T, D>::extract;
     return o;
 }
 

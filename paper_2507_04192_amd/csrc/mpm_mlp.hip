@@ -252,6 +252,53 @@ __global__ void k_adam(long long n, float* __restrict__ p, const float* __restri
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Piecewise-constant field on an nx x ny cell grid over [lo, hi) of the first
+// two coordinates; points outside take the nearest cell.
+struct CellGrid {
+    int nc, nx, ny;
+    float lo0, lo1, inv0, inv1;
+};
+
+__device__ __forceinline__ int cell_of(const CellGrid& g, float x0, float x1)
+{
+    int i = (int)floorf((x0 - g.lo0) * g.inv0);
+    int j = (int)floorf((x1 - g.lo1) * g.inv1);
+    i = i < 0 ? 0 : (i >= g.nx ? g.nx - 1 : i);
+    j = j < 0 ? 0 : (j >= g.ny ? g.ny - 1 : j);
+    return j * g.nx + i;
+}
+
+__global__ void k_cell_gather(CellGrid g, long long n, const float* __restrict__ x, const float* __restrict__ table,
+                              float* __restrict__ out)
+{
+    long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int c = cell_of(g, x[p], x[n + p]);
+    for (int k = 0; k < g.nc; ++k) out[k * n + p] = table[k * g.nx * g.ny + c];
+}
+
+__global__ void k_cell_scatter(CellGrid g, long long n, const float* __restrict__ x, const float* __restrict__ dout,
+                               float* __restrict__ dtable)
+{
+    long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    int c = cell_of(g, x[p], x[n + p]);
+    for (int k = 0; k < g.nc; ++k) atomicAdd(&dtable[k * g.nx * g.ny + c], dout[k * n + p]);
+}
+
+int make_cellgrid(int nc, int nx, int ny, const double* lo, const double* hi, CellGrid* g)
+{
+    if (nc < 1 || nx < 1 || ny < 1 || !lo || !hi || !(hi[0] > lo[0]) || !(hi[1] > lo[1])) return MPM_EINVAL;
+    g->nc = nc;
+    g->nx = nx;
+    g->ny = ny;
+    g->lo0 = (float)lo[0];
+    g->lo1 = (float)lo[1];
+    g->inv0 = (float)(nx / (hi[0] - lo[0]));
+    g->inv1 = (float)(ny / (hi[1] - lo[1]));
+    return MPM_OK;
+}
+
 int make_desc(const mpm_mlp* net, MlpDesc* d)
 {
     if (!net || net->n_layers < 1 || net->n_layers > MPM_MLP_MAX_LAYERS) return MPM_EINVAL;
@@ -348,6 +395,30 @@ int mpm_mlp_backward(const mpm_mlp* net, void* hip_stream, const float* params, 
             k_mlp_bwd_weights<0><<<gw, 256, 0, st>>>(d, n, chunk, x, cache, work, dparams);
         }
     }
+    return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
+int mpm_cell_field_gather(void* hip_stream, int32_t nc, int32_t nx, int32_t ny, const double* host_lo,
+                          const double* host_hi, int64_t n, const float* x, const float* table, float* out)
+{
+    CellGrid g;
+    if (make_cellgrid(nc, nx, ny, host_lo, host_hi, &g) || n < 0 || (n > 0 && (!x || !table || !out)))
+        return MPM_EINVAL;
+    if (n == 0) return MPM_OK;
+    k_cell_gather<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>(g, n, x, table, out);
+    return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
+int mpm_cell_field_scatter(void* hip_stream, int32_t nc, int32_t nx, int32_t ny, const double* host_lo,
+                           const double* host_hi, int64_t n, const float* x, const float* dout, float* dtable)
+{
+    CellGrid g;
+    if (make_cellgrid(nc, nx, ny, host_lo, host_hi, &g) || n < 0 || !dtable || (n > 0 && (!x || !dout)))
+        return MPM_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    long long nt = (long long)nc * nx * ny;
+    k_fill_f<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(dtable, nt, 0.f);
+    if (n > 0) k_cell_scatter<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(g, n, x, dout, dtable);
     return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
 }
 

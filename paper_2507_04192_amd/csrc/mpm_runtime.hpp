@@ -118,6 +118,7 @@ struct Ops {
     int (*read_grid)(mpm_ctx*, int which, void* dst);
     int (*forward_loss)(mpm_ctx*, int n, double dt, double* loss);
     int (*backward)(mpm_ctx*, void* grad_v0, void* grad_mu);
+    int (*extract)(mpm_ctx*, void* lag_q, void* eul_q);
 };
 
 extern const Ops ops_f32_2d, ops_f32_3d, ops_f64_2d, ops_f64_3d;

@@ -94,6 +94,9 @@ def lib():
             "mpm_mlp_cache_floats": ([P, i64], ct.c_int64),
             "mpm_mlp_forward": ([P, P, P, i64, P, P, P], ct.c_int),
             "mpm_mlp_backward": ([P, P, P, i64, P, P, P, P, P], ct.c_int),
+            "mpm_cell_field_gather": ([P, i32, i32, i32, P, P, i64, P, P, P], ct.c_int),
+            "mpm_cell_field_scatter": ([P, i32, i32, i32, P, P, i64, P, P, P], ct.c_int),
+            "mpm_extract": ([P, P, P], ct.c_int),
             "mpm_adam_step": ([P, i64, P, P, P, P, i32, ct.c_double, ct.c_double, ct.c_double, ct.c_double],
                               ct.c_int),
             "mpm_profile_read": ([P, P, P], ct.c_int),
@@ -118,7 +121,7 @@ _HEADER_NAMES = [
     "mpm_read_grid", "mpm_read_sort", "mpm_num_particles", "mpm_last_error", "mpm_destroy",
     "mpm_profile_enable", "mpm_profile_read", "mpm_set_observations", "mpm_forward_loss",
     "mpm_backward", "mpm_mlp_num_params", "mpm_mlp_cache_floats", "mpm_mlp_forward", "mpm_mlp_backward",
-    "mpm_adam_step",
+    "mpm_adam_step", "mpm_cell_field_gather", "mpm_cell_field_scatter", "mpm_extract",
 ]
 PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p"]
 
@@ -307,6 +310,22 @@ class Solver:
                 o.eul_mask = mk.data_ptr()
         _check(self.ctx, self.L.mpm_set_observations(self.ctx, ct.byref(o)))
         self._obs_keep = keep
+        self._obs_counts = (o.n_tracers, o.n_boxes)
+
+    def mpm_extract(self):
+        """(tracer values [dim, n_tracers], box means [dim, n_boxes]) of the
+        current state for the set observations."""
+        torch = self.torch
+        d = self.cfg.dim
+        keep = getattr(self, "_obs_keep", None)
+        ntr = nbox = 0
+        if keep is not None:
+            ntr = int(self._obs_counts[0])
+            nbox = int(self._obs_counts[1])
+        lq = torch.empty((d, ntr), dtype=self.dtype, device=self.device) if ntr else None
+        eq = torch.empty((d, nbox), dtype=self.dtype, device=self.device) if nbox else None
+        _check(self.ctx, self.L.mpm_extract(self.ctx, _ptr(lq), _ptr(eq)))
+        return lq, eq
 
     def mpm_forward_loss(self, n_steps, dt=None):
         dt = self.cfg.dt if dt is None else dt
@@ -486,3 +505,55 @@ def autograd_functions():
     if _fns is None:
         _fns = _autograd()
     return _fns
+
+
+class CellField:
+    """Piecewise-constant parametric field (mpm_cell_field_gather/scatter):
+    nc components on an nx x ny grid over [lo, hi) of the first two
+    coordinates."""
+
+    def __init__(self, nc, nx, ny, lo, hi):
+        self.nc, self.nx, self.ny = int(nc), int(nx), int(ny)
+        self.lo = np.ascontiguousarray(lo[:2], dtype=np.float64)
+        self.hi = np.ascontiguousarray(hi[:2], dtype=np.float64)
+        self.n_params = self.nc * self.nx * self.ny
+        self.L = lib()
+
+    def _s(self):
+        import torch
+        return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def gather(self, table, x):
+        import torch
+        n = x.shape[1]
+        out = torch.empty((self.nc, n), dtype=torch.float32, device=x.device)
+        _check(None, self.L.mpm_cell_field_gather(self._s(), self.nc, self.nx, self.ny, self.lo.ctypes.data,
+                                                  self.hi.ctypes.data, n, _ptr(x), _ptr(table), _ptr(out)))
+        return out
+
+    def scatter(self, x, dout):
+        import torch
+        n = x.shape[1]
+        dt = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        _check(None, self.L.mpm_cell_field_scatter(self._s(), self.nc, self.nx, self.ny, self.lo.ctypes.data,
+                                                   self.hi.ctypes.data, n, _ptr(x), _ptr(dout.contiguous()),
+                                                   _ptr(dt)))
+        return dt
+
+
+def cell_field_function():
+    import torch
+
+    class CellFieldFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, table, x, field):
+            ctx.save_for_backward(x)
+            ctx.field = field
+            return field.gather(table, x)
+
+        @staticmethod
+        def backward(ctx, dout):
+            (x,) = ctx.saved_tensors
+            return ctx.field.scatter(x, dout.float()), None, None
+
+    return CellFieldFunction

@@ -200,3 +200,91 @@ def random_state(cfg: SimConfig, n_particles: int, seed: int, vscale: float = 0.
     C = rng.normal(0.0, cscale, size=(d * d, n_particles))
     G = rng.normal(0.0, fscale, size=(d * d, n_particles))
     return x, v, C, G
+
+
+# ---------------------------------------------------------------------------
+# Inverse problems: seeded hidden fields and observation layouts
+# ---------------------------------------------------------------------------
+
+def granular_block_2d(seed: int = 0):
+    """Learned initial velocity: a 0.4 x 0.2 m Drucker-Prager block (friction
+    angle 35 deg, E = 1e7, nu = 0.3, rho = 2000) resting on the floor of a
+    0.8 x 0.4 m domain at 256 x 128 cells (dx = 1/320 m), x in [0.2, 0.6],
+    2 x 2 particles per cell (32,768 particles), floor Coulomb mu = 0.5,
+    other walls slip, dt = 1e-5 s."""
+    n = (256, 128, 1)
+    dx = 1.0 / 320.0
+    cfg = SimConfig(dim=2, n=n, dx=dx, dt=1e-5, material=SAND, ppc=4, gravity=(0.0, -9.81, 0.0),
+                    wall_mode=(SLIP, SLIP, COULOMB, SLIP, SLIP, SLIP), wall_mu=(0.0, 0.0, 0.5, 0.0, 0.0, 0.0),
+                    rho0=2000.0, youngs=1.0e7, poisson=0.3, phi_deg=35.0)
+    lo, hi = (0.2, 0.0), (0.6, 0.2)
+    x = lattice_particles(cfg, box_inside(lo, hi), lo, hi, seed)
+    return cfg, x, np.array(lo), np.array(hi)
+
+
+def gaussian_bumps(seed: int, lo, hi, count: int = 4):
+    """Hidden velocity field: sum of `count` Gaussian bumps with centres
+    uniform in the block, widths uniform in [0.02, 0.06] m, directions uniform
+    and magnitudes uniform in [0.3, 1.0] m/s.  Returns the bump parameters."""
+    rng = np.random.default_rng(seed)
+    c = np.stack([rng.uniform(lo[a], hi[a], count) for a in range(2)], axis=1)
+    sig = rng.uniform(0.02, 0.06, count)
+    ang = rng.uniform(0.0, 2 * np.pi, count)
+    mag = rng.uniform(0.3, 1.0, count)
+    amp = np.stack([mag * np.cos(ang), mag * np.sin(ang)], axis=1)
+    return c, sig, amp
+
+
+def eval_bumps(bumps, x):
+    """v0(x) = sum_k a_k exp(-|x - c_k|^2 / (2 s_k^2)); x: (2, N)."""
+    c, sig, amp = bumps
+    v = np.zeros((2, x.shape[1]))
+    for k in range(len(sig)):
+        r2 = (x[0] - c[k, 0]) ** 2 + (x[1] - c[k, 1]) ** 2
+        v += amp[k][:, None] * np.exp(-r2 / (2 * sig[k] ** 2))[None, :]
+    return v
+
+
+def block_boxes(lo, hi, nx: int = 4, ny: int = 2, half: float = 0.02):
+    """Eulerian monitor boxes: squares of half-side `half` centred on the
+    block's nx x ny sub-cells.  Returns (box_lo, box_hi), each (nx*ny, 2)."""
+    cx = lo[0] + (np.arange(nx) + 0.5) * (hi[0] - lo[0]) / nx
+    cy = lo[1] + (np.arange(ny) + 0.5) * (hi[1] - lo[1]) / ny
+    C = np.array([[x, y] for y in cy for x in cx])
+    return C - half, C + half
+
+
+def dam_break_3d(scale_div: int = 1, seed: int = 0):
+    """Learned base friction: 3-D dam-break on 192 x 96 x 64 cells
+    (dx = 0.01 m), water column 0.6 x 0.96 x 0.4 m at 8 particles per cell
+    (1,843,200 particles), Tait fluid as the 2-D dam-break, gravity -z,
+    friction per floor node, dt = 5e-5 s.  scale_div shrinks every length
+    by that factor at the same dx."""
+    s = scale_div
+    n = (192 // s, 96 // s, 64 // s)
+    dx = 0.01
+    cfg = SimConfig(dim=3, n=n, dx=dx, dt=5e-5, material=FLUID, ppc=8, gravity=(0.0, 0.0, -9.81),
+                    wall_mode=(SLIP, SLIP, SLIP, SLIP, COULOMB, SLIP), rho0=1000.0, bulk=1.0e5, gamma=7.0)
+    hi = (0.6 / s, 0.96 / s, 0.4 / s)
+    x = lattice_particles(cfg, box_inside((0, 0, 0), hi), (0, 0, 0), hi, seed)
+    return cfg, x
+
+
+def floor_node_coords(cfg: SimConfig) -> np.ndarray:
+    """Positions (x, y) of the floor nodes in the order of the per-node
+    friction array (x fastest), shape (2, n_floor)."""
+    nd = cfg.node_dims()
+    xs = (np.arange(nd[0]) - cfg.ghost) * cfg.dx
+    ys = (np.arange(nd[1]) - cfg.ghost) * cfg.dx
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    return np.stack([X.reshape(-1), Y.reshape(-1)])
+
+
+def sinusoid_friction(cfg: SimConfig, seed: int) -> np.ndarray:
+    """Hidden base friction mu(x, y) = 0.3 + 0.2 sin(2 pi x / L) cos(2 pi y / W)
+    plus N(0, 0.02^2) per floor node, clipped to [0, 1]."""
+    L, Wd = cfg.n[0] * cfg.dx, cfg.n[1] * cfg.dx
+    xy = floor_node_coords(cfg)
+    mu = 0.3 + 0.2 * np.sin(2 * np.pi * xy[0] / L) * np.cos(2 * np.pi * xy[1] / Wd)
+    mu = mu + np.random.default_rng(seed).normal(0.0, 0.02, size=mu.shape)
+    return np.clip(mu, 0.0, 1.0)
