@@ -10,6 +10,9 @@ A step is one pass of the whole hot path: cell-key sort, P2G, grid update,
 G2P with the constitutive update.  Inputs are resident in HBM before the
 timed region starts.  Prints one JSON line.
 
+The forward+adjoint leg times a checkpointed rollout with a tracer loss and
+its backward sweep on the same cylinder (FP32 and FP64).
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -32,7 +35,11 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E peak
 # (6); P2G reads x, v, C and the stress cache.  Bucket moves a key and an
 # index (int32).  The whole step's figure is the state read once and written
 # once: 48 scalars.
-ALG_SCALARS = {"g2p": 3 + 9 + 3 + 3 + 9 + 9 + 6, "p2g": 3 + 3 + 9 + 6}
+ALG_SCALARS = {"g2p": 3 + 9 + 3 + 3 + 9 + 9 + 6, "p2g": 3 + 3 + 9 + 6,
+               # reverse kernels: g2p_adj reads x, F, the output adjoint (x v C F
+               # stress: 30) and writes the intermediate (12); p2g_adj reads x v C
+               # stress and the intermediate and writes the input adjoint (30)
+               "g2p_adj": 3 + 9 + 30 + 12, "p2g_adj": 3 + 3 + 9 + 6 + 12 + 30}
 ALG_INT_BYTES = {"bucket": 8}
 STEP_SCALARS = 48
 
@@ -70,6 +77,85 @@ def run_gpu(cfg, x, precision, steps, warmup):
     t3 = time.perf_counter()
     s.close()
     return (t1 - t0), (t3 - t2), prof
+
+
+def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every=20):
+    """Forward rollout with the loss, then the checkpointed backward sweep:
+    tracer positions every frame_every steps against their starting
+    positions; gradients with respect to v0 and a per-node floor friction
+    field (uniform at the floor's mu)."""
+    import numpy as np
+    import torch
+    from paper_2507_04192_amd import workloads as W
+    from paper_2507_04192_amd.native import Solver
+    n = x.shape[1]
+    s = Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=ckpt_every)
+    ws_bytes = s.ws.numel()
+    s.mpm_set_floor_mu(np.full(cfg.floor_nodes(), cfg.wall_mu[4 if cfg.dim == 3 else 2]))
+    tr = W.pick_tracers(n, n_tracers, 7)
+    frames = list(range(frame_every, steps + 1, frame_every))
+    tgt = np.repeat(x[:, tr][None], len(frames), axis=0)
+    s.mpm_set_observations(frames=frames, tracer_pid=tr, lag_field="x", lag_target=tgt)
+
+    def once(prof):
+        s.mpm_init_particles(x)
+        torch.cuda.synchronize()
+        s.mpm_profile_enable(prof)
+        s.mpm_profile_read()
+        t0 = time.perf_counter()
+        loss = s.mpm_forward_loss(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gv, gm = s.mpm_backward(True, True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        p = s.mpm_profile_read()
+        s.mpm_profile_enable(False)
+        return loss, gv, gm, t1 - t0, t2 - t1, p
+
+    once(False)                                  # warm-up
+    loss, gv, gm, tf, tb, prof = once(True)
+    ok = bool(np.isfinite(loss) and torch.isfinite(gv).all().item() and torch.isfinite(gm).all().item())
+    s.close()
+    return {"value": n * steps / (tf + tb), "unit": "particle-steps/s", "steps": steps,
+            "ckpt_every": ckpt_every, "ms_per_step": (tf + tb) / steps * 1e3,
+            "forward_loss_ms": tf * 1e3, "backward_ms": tb * 1e3, "loss": loss, "finite": ok,
+            "workspace_bytes": ws_bytes, "max_memory_allocated": torch.cuda.max_memory_allocated(),
+            "observations": f"{n_tracers} tracer positions every {frame_every} steps; "
+                            f"gradients wrt v0 and the floor friction field"}, prof
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cylinder_f32.txt")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when there is
+    none or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        from paper_2507_04192_amd.rocprof_summary import kernel_sources_hash
+        if t.get("csrc_sha256") != kernel_sources_hash():
+            return None
+        v = t["kernels"][kernel]
+        return v["fetch_bytes"] + v["write_bytes"]
+    except (OSError, KeyError, TypeError, ValueError):
+        return None
+
+
+def calibrate_copy(mib):
+    """A plain device-to-device copy of mib MiB (the scale of the HBM byte
+    counters is read off its FETCH_SIZE and WRITE_SIZE)."""
+    import torch
+    n = mib * 2**20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: 3 copies of {mib * 2**20} bytes")
+    del a, b
 
 
 def roofline(prof, n_particles, elem):
@@ -129,7 +215,12 @@ def main():
     ap.add_argument("--f64-steps", type=int, default=None, help="binary64 timed steps (default steps/2)")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--adj-steps", type=int, default=200, help="rollout length of the forward+adjoint leg")
+    ap.add_argument("--adj-ckpt", type=int, default=50, help="checkpoint interval of the forward+adjoint leg")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--scale-div", type=int, default=1, help="shrink the cylinder (tests only)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -142,6 +233,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
     cfg, x = W.cylinder_collapse_3d(scale_div=args.scale_div, seed=0)
     n = x.shape[1]
     log(f"[bench] cylinder collapse N={n} grid={cfg.n} device={torch.cuda.get_device_name(0)}")
@@ -152,6 +245,8 @@ def main():
     log(f"[bench] f32: {ms32:.4f} ms/step, {val32:.4e} particle-steps/s "
         f"(no events: {t32_noev / args.steps * 1e3:.4f} ms/step)")
     dom, kernels, roof = roofline(prof32, n, 4)
+    if args.scale_div == 1:
+        roof["traffic"] = measured_traffic({"p2g": "k_p2g<float, 3, 1>", "g2p": "k_g2p<float, 3, 1>"}.get(dom, dom))
     for k, v in kernels.items():
         log(f"[bench]   {k:7s} {v['avg_ms'] * 1e3:9.2f} us/launch" +
             (f"  {v['gbs']:8.1f} GB/s algorithmic" if "gbs" in v else ""))
@@ -167,6 +262,24 @@ def main():
                    "roofline": roof64,
                    "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kern64.items()}}
         log(f"[bench] f64: {out_f64['ms_per_step']:.4f} ms/step, {out_f64['value']:.4e} particle-steps/s")
+
+    adj = None
+    if not args.no_adjoint:
+        adj = {}
+        for prec, elem, T in (("f32", 4, args.adj_steps), ("f64", 8, max(args.adj_ckpt, args.adj_steps // 2))):
+            if prec == "f64" and args.no_f64:
+                continue
+            torch.cuda.reset_peak_memory_stats()
+            r, prof = run_adjoint(cfg, x, prec, T, args.adj_ckpt)
+            _, kern, roof_a = roofline({k: prof[k] for k in ("g2p_adj", "p2g_adj") if k in prof}, n, elem)
+            r["roofline"] = roof_a
+            r["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1] > 0}
+            adj[prec] = r
+            log(f"[bench] fwd+adjoint {prec}: {r['ms_per_step']:.4f} ms/step, {r['value']:.4e} particle-steps/s "
+                f"(forward {r['forward_loss_ms']:.1f} ms, backward {r['backward_ms']:.1f} ms, "
+                f"peak memory {r['max_memory_allocated'] / 2**30:.1f} GiB)")
+            for k, v in r["kernels_us"].items():
+                log(f"[bench]   {k:8s} {v:9.2f} us/launch")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -188,6 +301,7 @@ def main():
         "hbm_frac_step": val32 * STEP_SCALARS * 4 / (HBM_PEAK_GBS * 1e9),
         "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kernels.items()},
         "f64": out_f64,
+        "fwd_adjoint": adj,
         "paper_context": {"value_f32": 1.22e8, "value_f64": 2.76e7,
                           "note": "paper, one A100, 2,712,960-particle cylinder on 400x400x100; "
                                   "a different machine and grid, not this workload"},

@@ -258,13 +258,16 @@ int mpm_cell_field_scatter(void* hip_stream, int32_t nc, int32_t nx, int32_t ny,
  * be NULL.  Used to record synthetic observations from a ground-truth run. */
 int mpm_extract(mpm_ctx* ctx, void* lag_q, void* eul_q);
 
-/* Per-kernel-class timing of mpm_step: with profiling on, HIP events are
- * recorded on the context's stream between the kernel classes below, and
- * mpm_profile_read (synchronizes) returns, per class, the summed event time
- * in milliseconds and the number of launches since the last read, then
- * resets.  Arrays hold MPM_PROF_N entries (host memory). */
+/* Per-kernel-class timing of mpm_step, mpm_forward_loss and mpm_backward:
+ * with profiling on, HIP events are recorded on the context's stream between
+ * the kernel classes below, and mpm_profile_read (synchronizes) returns, per
+ * class, the summed event time in milliseconds and the number of launches
+ * since the last read, then resets.  Arrays hold MPM_PROF_N entries (host
+ * memory).  In the backward sweep the recomputed forward kernels count in
+ * their own classes (the key pass of a recomputed step counts as SCAN), the
+ * reverse kernels in the *_ADJ classes. */
 enum { MPM_PROF_SCAN = 0, MPM_PROF_BUCKET = 1, MPM_PROF_P2G = 2, MPM_PROF_GRID = 3, MPM_PROF_G2P = 4,
-       MPM_PROF_N = 8 };
+       MPM_PROF_G2P_ADJ = 5, MPM_PROF_GRID_ADJ = 6, MPM_PROF_P2G_ADJ = 7, MPM_PROF_N = 8 };
 int mpm_profile_enable(mpm_ctx* ctx, int on);
 int mpm_profile_read(mpm_ctx* ctx, double* host_ms, int64_t* host_launches);
 

@@ -689,24 +689,32 @@ struct Adjoint {
         const Geo& g = c->geo;
         Phys<T> P = P0;
         P.keep_grid = 1;
+        prof_mark(c, -1);
         keys_of(c, st_in);
         unsigned nsb = (unsigned)((g.ntiles + kScanChunk - 1) / kScanChunk);
         k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
         k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, c->tile_slot, c->active,
                                                c->meta);
+        prof_mark(c, MPM_PROF_SCAN);
         k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
+        prof_mark(c, MPM_PROF_BUCKET);
         k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->tmpk, st_in, c->perm,
                                                       (T*)c->part_grid);
+        prof_mark(c, MPM_PROF_P2G);
         k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (const T*)c->part_grid,
                                                   (T*)c->gv, (T*)c->gmass, (T*)c->gvt);
+        prof_mark(c, MPM_PROF_GRID);
         k_g2p_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in, aout,
                                                           (const T*)c->gv, (T*)c->part_grid, (T*)c->mid);
+        prof_mark(c, MPM_PROF_G2P_ADJ);
         k_grid_adj<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot,
                                                       (const T*)c->part_grid, (T*)c->gmass, (const T*)c->gvt,
                                                       (T*)c->gv, c->floor_mu ? c->amu : nullptr);
+        prof_mark(c, MPM_PROF_GRID_ADJ);
         k_p2g_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in,
                                                           (const T*)c->gv, (const T*)c->gmass, (const T*)c->mid,
                                                           ain);
+        prof_mark(c, MPM_PROF_P2G_ADJ);
     }
 
     static Boxes boxes(const mpm_ctx* c)

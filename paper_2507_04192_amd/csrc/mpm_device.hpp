@@ -259,20 +259,9 @@ __device__ __forceinline__ void fluid_update(const Phys<T>& P, const T L[D][D], 
 // with dgamma = |dev| + (d lam + 2 mu)/(2 mu) alpha tr(eps).  Then
 // F_e' = U diag(exp(H - eps)) U^T F_tr and tau = U diag(2 mu H + lam tr H) U^T.
 template <class T, int D>
-__device__ __forceinline__ void hencky_update(const Phys<T>& P, bool plastic, const T L[D][D],
-                                              T G[D][D], T S[D * (D + 1) / 2])
+__device__ __forceinline__ void hencky_eig(const Phys<T>& P, bool plastic, const T Gt[D][D], T G[D][D],
+                                       T S[D * (D + 1) / 2])
 {
-    T dt = P.dt;
-    T Gt[D][D];
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            T lg = L[i][j];
-#pragma unroll
-            for (int k = 0; k < D; ++k) lg += L[i][k] * G[k][j];
-            Gt[i][j] = G[i][j] + dt * lg;
-        }
     // b - I
     T B[D][D];
 #pragma unroll
@@ -390,6 +379,189 @@ __device__ __forceinline__ void hencky_update(const Phys<T>& P, bool plastic, co
             for (int k = 0; k < D; ++k) s += M[i][k] * Gt[k][j];
             G[i][j] = Gt[i][j] + s;
         }
+}
+
+// Small symmetric matrices, packed: 3-D (xx,yy,zz,xy,xz,yz), 2-D (xx,yy,xy).
+template <class T, int D> struct Sym;
+template <class T> struct Sym<T, 3> {
+    T a[6];
+    __device__ __forceinline__ T tr() const { return a[0] + a[1] + a[2]; }
+    __device__ __forceinline__ T norm2() const
+    {
+        return a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + T(2) * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
+    }
+    __device__ __forceinline__ T at(int i, int j) const
+    {
+        if (i == j) return a[i];
+        int s = i + j;
+        return a[s == 1 ? 3 : (s == 2 ? 4 : 5)];
+    }
+};
+template <class T> struct Sym<T, 2> {
+    T a[3];
+    __device__ __forceinline__ T tr() const { return a[0] + a[1]; }
+    __device__ __forceinline__ T norm2() const { return a[0] * a[0] + a[1] * a[1] + T(2) * a[2] * a[2]; }
+    __device__ __forceinline__ T at(int i, int j) const { return i == j ? a[i] : a[2]; }
+};
+
+// c I + A B for commuting symmetric A, B (the product is symmetric)
+template <class T>
+__device__ __forceinline__ Sym<T, 3> cI_plus_AB(T c, const Sym<T, 3>& A, const Sym<T, 3>& B)
+{
+    Sym<T, 3> R;
+    R.a[0] = c + A.a[0] * B.a[0] + A.a[3] * B.a[3] + A.a[4] * B.a[4];
+    R.a[1] = c + A.a[3] * B.a[3] + A.a[1] * B.a[1] + A.a[5] * B.a[5];
+    R.a[2] = c + A.a[4] * B.a[4] + A.a[5] * B.a[5] + A.a[2] * B.a[2];
+    R.a[3] = A.a[0] * B.a[3] + A.a[3] * B.a[1] + A.a[4] * B.a[5];
+    R.a[4] = A.a[0] * B.a[4] + A.a[3] * B.a[5] + A.a[4] * B.a[2];
+    R.a[5] = A.a[3] * B.a[4] + A.a[1] * B.a[5] + A.a[5] * B.a[2];
+    return R;
+}
+template <class T>
+__device__ __forceinline__ Sym<T, 2> cI_plus_AB(T c, const Sym<T, 2>& A, const Sym<T, 2>& B)
+{
+    Sym<T, 2> R;
+    R.a[0] = c + A.a[0] * B.a[0] + A.a[2] * B.a[2];
+    R.a[1] = c + A.a[2] * B.a[2] + A.a[1] * B.a[1];
+    R.a[2] = A.a[0] * B.a[2] + A.a[2] * B.a[1];
+    return R;
+}
+
+// Truncated series for the matrix functions of a small symmetric argument:
+// log(I + X) = sum_k (-1)^(k+1) X^k / k and exp(Y) - I = sum_k Y^k / k!, by
+// Horner's rule.  Used when |X|_F, |Y|_F < kMax: the remainder is then below
+// the working precision relative to the result (float: 0.02^6/6 and
+// 0.02^5/5!; double: 0.01^10/10 and 0.01^8/8!).
+template <class T> struct Series;
+template <> struct Series<float> { static constexpr float kMax = 0.02f; static constexpr int kLog = 5, kExp = 4; };
+template <> struct Series<double> { static constexpr double kMax = 0.01; static constexpr int kLog = 9, kExp = 7; };
+
+template <class T, int D>
+__device__ __forceinline__ Sym<T, D> log1p_sym(const Sym<T, D>& X)
+{
+    constexpr int K = Series<T>::kLog;
+    Sym<T, D> Pm;
+    T cK = ((K & 1) ? T(1) : T(-1)) / T(K);
+#pragma unroll
+    for (int q = 0; q < (D == 3 ? 6 : 3); ++q) Pm.a[q] = (q < D) ? cK : T(0);
+#pragma unroll
+    for (int k = K - 1; k >= 1; --k) Pm = cI_plus_AB(((k & 1) ? T(1) : T(-1)) / T(k), X, Pm);
+    return cI_plus_AB(T(0), X, Pm);
+}
+
+template <class T, int D>
+__device__ __forceinline__ Sym<T, D> expm1_sym(const Sym<T, D>& Y)
+{
+    constexpr int K = Series<T>::kExp;
+    Sym<T, D> Pm;
+#pragma unroll
+    for (int q = 0; q < (D == 3 ? 6 : 3); ++q) Pm.a[q] = (q < D) ? T(1) : T(0);
+#pragma unroll
+    for (int k = K; k >= 2; --k) {
+        Sym<T, D> Z = Y;
+#pragma unroll
+        for (int q = 0; q < (D == 3 ? 6 : 3); ++q) Z.a[q] *= T(1) / T(k);
+        Pm = cI_plus_AB(T(1), Z, Pm);
+    }
+    return cI_plus_AB(T(0), Y, Pm);
+}
+
+// Hencky return written on the strain tensor E = log(b)/2 itself: every
+// quantity of the return (trace, deviator, its norm, the projected H, the
+// stress) is a polynomial in E, so no eigenvectors are needed while
+// b - I and the correction exp(H - E) are small enough for the series.
+// Returns false when they are not (the caller then takes hencky_eig).
+template <class T, int D>
+__device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, const T Gt[D][D], T G[D][D],
+                                              T S[D * (D + 1) / 2])
+{
+    constexpr int NS = D * (D + 1) / 2;
+    Sym<T, D> X;   // b - I = Gt + Gt^T + Gt Gt^T
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            T s = Gt[i][j] + Gt[j][i];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += Gt[i][k] * Gt[j][k];
+            int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            X.a[q] = s;
+        }
+    const T lim2 = Series<T>::kMax * Series<T>::kMax;
+    if (!(X.norm2() < lim2)) return false;
+    Sym<T, D> E = log1p_sym(X);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) E.a[q] *= T(0.5);
+    T trE = E.tr();
+    Sym<T, D> Eh = E;
+#pragma unroll
+    for (int i = 0; i < D; ++i) Eh.a[i] -= trE / T(D);
+    T n = sqrt(Eh.norm2());
+    int cas = 1;
+    T r = T(0);   // H = E - r * Ehat (cone), 0 (apex), E (elastic)
+    if (plastic) {
+        if (trE > T(0)) cas = 0;
+        else {
+            T dg = n + P.cone_coef * trE;
+            if (dg > T(0)) {
+                cas = 2;
+                r = dg / n;
+            }
+        }
+    }
+    Sym<T, D> Y;   // H - E
+    if (cas == 0) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Y.a[q] = -E.a[q];
+    } else if (cas == 2) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Y.a[q] = -r * Eh.a[q];
+    }
+    if (cas != 1 && !(Y.norm2() < lim2)) return false;
+    // stress: tau = 2 mu H + lam tr(H) I
+    T trH = (cas == 0) ? T(0) : trE;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        T h = (cas == 0) ? T(0) : (cas == 2 ? E.a[q] - r * Eh.a[q] : E.a[q]);
+        S[q] = P.vol0 * (T(2) * P.mu * h + ((q < D) ? P.lam * trH : T(0)));
+    }
+    if (cas == 1) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) G[i][j] = Gt[i][j];
+        return true;
+    }
+    // F_e' = exp(Y) F_tr:  G' = (exp(Y) - I)(I + Gt) + Gt
+    Sym<T, D> M = expm1_sym(Y);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = M.at(i, j);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += M.at(i, k) * Gt[k][j];
+            G[i][j] = Gt[i][j] + s;
+        }
+    return true;
+}
+
+template <class T, int D>
+__device__ __forceinline__ void hencky_update(const Phys<T>& P, bool plastic, const T L[D][D],
+                                              T G[D][D], T S[D * (D + 1) / 2])
+{
+    T dt = P.dt;
+    T Gt[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T lg = L[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) lg += L[i][k] * G[k][j];
+            Gt[i][j] = G[i][j] + dt * lg;
+        }
+    if (!hencky_series<T, D>(P, plastic, Gt, G, S)) hencky_eig<T, D>(P, plastic, Gt, G, S);
 }
 
 // ---------------------------------------------------------------------------

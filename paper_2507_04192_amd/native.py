@@ -123,7 +123,7 @@ _HEADER_NAMES = [
     "mpm_backward", "mpm_mlp_num_params", "mpm_mlp_cache_floats", "mpm_mlp_forward", "mpm_mlp_backward",
     "mpm_adam_step", "mpm_cell_field_gather", "mpm_cell_field_scatter", "mpm_extract",
 ]
-PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p"]
+PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p", "g2p_adj", "grid_adj", "p2g_adj"]
 
 
 def make_config(cfg, precision: str = "f64", keep_grid: bool = False) -> MpmConfig:

@@ -288,3 +288,17 @@ def sinusoid_friction(cfg: SimConfig, seed: int) -> np.ndarray:
     mu = 0.3 + 0.2 * np.sin(2 * np.pi * xy[0] / L) * np.cos(2 * np.pi * xy[1] / Wd)
     mu = mu + np.random.default_rng(seed).normal(0.0, 0.02, size=mu.shape)
     return np.clip(mu, 0.0, 1.0)
+
+
+def mlp_init_params(widths, seed: int) -> np.ndarray:
+    """Seeded starting parameters of a dense network in the library's layout
+    (per layer: W row-major [out][in], then b), each uniform in
+    +-1/sqrt(fan_in).  FP32."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, o in zip(widths[:-1], widths[1:]):
+        r = 1.0 / np.sqrt(i)
+        parts.append(rng.uniform(-r, r, size=o * i))
+        parts.append(rng.uniform(-r, r, size=o))
+    return np.concatenate(parts).astype(np.float32)
+

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp as OM
+from paper_2507_04192_amd import workloads as W
 from tests.helpers import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +41,7 @@ def test_forward_backward_match_oracle(math, tol, arch, n):
     xs = 2.0 / (hi - lo)
     x = rng.uniform(lo, hi, size=(d_in, n)).astype(np.float32)
     spec = OM.Spec(widths, act, sc, sh)
-    p = OM.init_params(spec, 7 + arch).astype(np.float32)
+    p = W.mlp_init_params(widths, 7 + arch)
     net = MLP(widths, act, sc, sh, in_scale=[xs] * d_in, in_shift=[-1.0 - lo * xs] * d_in, math=math)
     assert net.n_params == p.size
     y, cache = net.forward(_t(p), _t(x))
@@ -75,7 +76,6 @@ def test_learned_field_gradient_through_solver(orc):
     chained gradient dL/dtheta (MFMA network + HIP adjoint) against the
     oracle's network backward applied to the oracle rollout gradient."""
     import torch
-    from paper_2507_04192_amd import workloads as W
     from paper_2507_04192_amd.native import MLP, Solver, autograd_functions
     MLPFunction, MPMRollout = autograd_functions()
     cfg = W.SimConfig(dim=2, n=(48, 24, 1), dx=1 / 80, dt=2e-5, material=W.SAND, ppc=4,
@@ -87,7 +87,7 @@ def test_learned_field_gradient_through_solver(orc):
     x0 = x0.astype(np.float32).astype(np.float64)
     widths = [2, 64, 64, 2]
     spec = OM.Spec(widths)
-    p = OM.init_params(spec, 102).astype(np.float32)
+    p = W.mlp_init_params(widths, 102)
     net = MLP(widths, in_scale=[2 / 0.6, 2 / 0.3], in_shift=[-1.0, -1.0], math="f32")
     steps, frames = 20, [10, 20]
     tr = W.pick_tracers(N, 30, 103)
@@ -108,4 +108,52 @@ def test_learned_field_gradient_through_solver(orc):
     g_o = OM.backward(spec, p.astype(np.float64), acts, gv0_o.T)
     print(f"  loss {loss.item():.6e} vs {loss_o:.6e}; dL/dtheta rel L2 {rel_l2(g, g_o):.2e}", flush=True)
     assert abs(loss.item() - loss_o) <= 1e-5 * loss_o
+    assert rel_l2(g, g_o) <= 1e-4
+
+
+def test_learned_friction_gradient_through_solver(orc):
+    """Floor friction mu(x, y) = N_theta(x, y) (sigmoid output) at the floor
+    nodes of a small 3-D dam-break (sliding start), tracer-position loss: dL/dtheta through
+    the HIP adjoint's dL/dmu and the MFMA network backward, against the
+    oracle network applied to the oracle rollout's dL/dmu."""
+    import torch
+    from paper_2507_04192_amd.native import MLP, Solver, autograd_functions
+    MLPFunction, MPMRollout = autograd_functions()
+    cfg, x0 = W.dam_break_3d(scale_div=8, seed=111)
+    x0 = x0.astype(np.float32).astype(np.float64)
+    N = x0.shape[1]
+    xy = W.floor_node_coords(cfg)
+    L, Wd = cfg.n[0] * cfg.dx, cfg.n[1] * cfg.dx
+    widths = [2, 32, 32, 1]
+    spec = OM.Spec(widths, "sigmoid", 1.0, 0.0)
+    p = W.mlp_init_params(widths, 112)
+    net = MLP(widths, "sigmoid", 1.0, 0.0, in_scale=[2 / L, 2 / Wd], in_shift=[-1.0, -1.0], math="f32")
+    steps, frames = 20, [10, 20]
+    tr = W.pick_tracers(N, 40, 113)
+    rng = np.random.default_rng(114)
+    tgt = (x0[:, tr][None] + rng.normal(0, 2e-3, size=(2, 3, 40))).astype(np.float32).astype(np.float64)
+    print(f"[case] learned friction N={N} floor nodes={xy.shape[1]}", flush=True)
+    s = Solver(cfg, "f64", capacity=N, tape_steps=steps, ckpt_every=10)
+    s.mpm_set_observations(frames=frames, tracer_pid=tr, lag_field="x", lag_target=tgt)
+    theta = _t(p).requires_grad_(True)
+    mu = MLPFunction.apply(theta, _t(xy), net)
+    # sliding start so that the floor is in the slip regime of the Coulomb law
+    v0n = rng.normal(0, 0.3, size=(3, N))
+    v0n[2] = 0.0
+    v0 = torch.as_tensor(v0n, device="cuda")
+    loss = MPMRollout.apply(v0, mu.reshape(-1), s, x0, steps)
+    loss.backward()
+    g = theta.grad.cpu().numpy()
+    xin = np.stack([2 / L * xy[0] - 1.0, 2 / Wd * xy[1] - 1.0]).T
+    mu_o, acts = OM.forward(spec, p.astype(np.float64), xin)
+    # the solver consumes the network's FP32 output
+    mu_in = mu_o[:, 0].astype(np.float32).astype(np.float64)
+    assert rel_l2(mu.detach().cpu().numpy()[0], mu_o[:, 0]) <= 1e-5
+    loss_o, _, amu_o = orc.rollout_grad(cfg, x0, v0n, steps, cfg.dt, mu_in,
+                                        orc.Observations(frames, tr, "x", tgt))
+    g_o = OM.backward(spec, p.astype(np.float64), acts, amu_o[:, None])
+    print(f"  loss {loss.item():.6e} vs {loss_o:.6e}; |dL/dmu| {np.linalg.norm(amu_o):.3e}; "
+          f"dL/dtheta rel L2 {rel_l2(g, g_o):.2e}", flush=True)
+    assert np.linalg.norm(amu_o) > 0
+    assert abs(loss.item() - loss_o) <= 1e-4 * loss_o
     assert rel_l2(g, g_o) <= 1e-4
