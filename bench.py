@@ -93,6 +93,7 @@ def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every
     ws_bytes = s.ws.numel()
     s.mpm_set_floor_mu(np.full(cfg.floor_nodes(), cfg.wall_mu[4 if cfg.dim == 3 else 2]))
     tr = W.pick_tracers(n, n_tracers, 7)
+    frame_every = min(frame_every, steps)
     frames = list(range(frame_every, steps + 1, frame_every))
     tgt = np.repeat(x[:, tr][None], len(frames), axis=0)
     s.mpm_set_observations(frames=frames, tracer_pid=tr, lag_field="x", lag_target=tgt)

@@ -172,18 +172,48 @@ static int cmp_keyslot(const void* pa, const void* pb)
     return 0;
 }
 
-/* Stable order by key: ties keep the current slot order.  Comparing the
- * (key, slot) pair makes every element distinct, so any sort gives it. */
+/* Sort order of a step.  Particles are grouped by tile (key >> 6); inside a
+ * tile they are ordered by their rank within their cell (the number of
+ * particles of the same key at smaller current slots), then by the cell
+ * (key & 63).  So the r-th particles of all cells of a tile sit next to each
+ * other.  Computed in two plain passes: a sort by (key, slot) gives the
+ * ranks, a sort by (tile, rank, cell) the order. */
+typedef struct {
+    int32_t tile, rank, cell, slot;
+} trc;
+
+static int cmp_trc(const void* a, const void* b)
+{
+    const trc* x = (const trc*)a;
+    const trc* y = (const trc*)b;
+    if (x->tile != y->tile) return x->tile < y->tile ? -1 : 1;
+    if (x->rank != y->rank) return x->rank < y->rank ? -1 : 1;
+    if (x->cell != y->cell) return x->cell < y->cell ? -1 : 1;
+    return 0;
+}
+
 void orc_sort_perm(int64_t N, const int32_t* key, int32_t* perm)
 {
-    keyslot* ks = (keyslot*)malloc(sizeof(keyslot) * (size_t)(N > 0 ? N : 1));
+    size_t n1 = (size_t)(N > 0 ? N : 1);
+    keyslot* ks = (keyslot*)malloc(sizeof(keyslot) * n1);
+    trc* t = (trc*)malloc(sizeof(trc) * n1);
     for (int64_t p = 0; p < N; ++p) {
         ks[p].key = key[p];
         ks[p].slot = (int32_t)p;
     }
     qsort(ks, (size_t)N, sizeof(keyslot), cmp_keyslot);
+    int32_t rank = 0;
+    for (int64_t s = 0; s < N; ++s) {
+        rank = (s > 0 && ks[s].key == ks[s - 1].key) ? rank + 1 : 0;
+        t[s].tile = ks[s].key >> 6;
+        t[s].cell = ks[s].key & 63;
+        t[s].rank = rank;
+        t[s].slot = ks[s].slot;
+    }
+    qsort(t, (size_t)N, sizeof(trc), cmp_trc);
     for (int64_t s = 0; s < N; ++s)
-        perm[s] = ks[s].slot;
+        perm[s] = t[s].slot;
+    free(t);
     free(ks);
 }
 

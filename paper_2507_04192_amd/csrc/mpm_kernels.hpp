@@ -330,14 +330,34 @@ __device__ __forceinline__ int block_node(const int lb[3], int k)
     else return (lb[1] + ky) * BE + lb[0] + kx;
 }
 
+// Position inside its tile of the particle of rank q in cell c, for the
+// order (rank, cell): all cells' rank-0 particles first, then rank 1, ...
+//   pos = sum_c' min(cnt[c'], q) + #{c' < c : cnt[c'] > q}.
+// For q < 64 the two sums come from a table (the cells with more than q
+// particles as a 64-bit mask, and the running count of earlier ranks);
+// deeper ranks, which only crowded cells reach, count directly.
+__device__ __forceinline__ int rank_major_pos(int c, int q, const unsigned long long* rmask, const int* roff,
+                                              const int* cnt)
+{
+    if (q < 64) return roff[q] + __popcll(rmask[q] & ((1ull << c) - 1ull));
+    int r = 0;
+    for (int c2 = 0; c2 < 64; ++c2) {
+        int n = cnt[c2];
+        r += min(n, q) + ((c2 < c && n > q) ? 1 : 0);
+    }
+    return r;
+}
+
 // P2G, one tile per workgroup.  The workgroup (1) sorts the tile's particles
-// by cell, ties by previous slot, into perm; (2) takes them in rounds, lane c
-// of wave w holding the r-th particle of cell c for r = w, w+4, ...; (3)
-// writes the sum of the waves' node blocks (mass, momentum), in wave order,
-// to the tile's partial block.
+// into perm: by rank within their cell (previous slot order), then by cell,
+// so that the r-th particles of the 64 cells are adjacent in memory; (2)
+// takes them in rounds, lane c of wave w holding the r-th particle of cell c
+// for r = w, w+4, ... (the lanes of a round read adjacent slots); (3) writes
+// the sum of the waves' node blocks (mass, momentum), in wave order, to the
+// tile's partial block.
 template <class T, int D, int MAT>
 __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
-                                                const ActiveTile* __restrict__ active, const int* __restrict__ tmp,
+                                                const ActiveTile* __restrict__ active, int* __restrict__ tmp,
                                                 const int* __restrict__ tmpk, PView<T> cur, int* __restrict__ perm,
                                                 T* __restrict__ part)
 {
@@ -350,6 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
     __shared__ int s_cnt[64], s_off[64], s_cur[64];
     __shared__ int s_unord[kSortCap], s_sorted[kSortCap];
     __shared__ int s_max;
+    __shared__ unsigned long long s_rmask[64];
+    __shared__ int s_roff[64];
     const int n_active = meta[0];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     for (int it = 0;; ++it) {
@@ -373,6 +395,17 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
             }
             s_off[lane] = inc - v;
             if (lane == 0) s_max = mx;
+            // rank table: cells with more than q particles, earlier ranks' count
+            int run = 0;
+            const int lim = mx < 64 ? mx : 64;
+            for (int q = 0; q < lim; ++q) {
+                unsigned long long m = __ballot(v > q);
+                if (lane == 0) {
+                    s_rmask[q] = m;
+                    s_roff[q] = run;
+                }
+                run += __popcll(m);
+            }
         }
         __syncthreads();
         // place each particle in its cell's range (arbitrary order inside)
@@ -391,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
                 int j = tmp[at.off + k];
                 int o = s_off[c], n = s_cnt[c], rank = 0;
                 for (int q = 0; q < n; ++q) rank += unord[o + q] < j;
-                s_sorted[o + rank] = j;
+                s_sorted[rank_major_pos(c, rank, s_rmask, s_roff, s_cnt)] = j;
             }
             __syncthreads();
             for (int k = tid; k < at.cnt; k += kBlock) perm[at.off + k] = s_sorted[k];
@@ -408,6 +441,22 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
             }
             __threadfence_block();
             __syncthreads();
+            // cell-major -> rank-major, through this tile's range of tmp
+            // (its bucketed input is no longer needed); the cell of position
+            // p is the last cell whose range starts at or before p
+            for (int p = tid; p < at.cnt; p += kBlock) {
+                int lo = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if (lo + step < 64 && s_off[lo + step] <= p) lo += step;
+                tmp[at.off + rank_major_pos(lo, p - s_off[lo], s_rmask, s_roff, s_cnt)] = unord[p];
+            }
+            __threadfence_block();
+            __syncthreads();
+            const volatile int* rm = tmp + at.off;
+            for (int k = tid; k < at.cnt; k += kBlock) unord[k] = rm[k];
+            __threadfence_block();
+            __syncthreads();
         }
         const int* sorted = in_lds ? s_sorted : (perm + at.off);
         int tc[3];
@@ -418,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
         lb[2] = (D == 3) ? lane / (TE * TE) : 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) gb[a] = tc[a] * TE + lb[a] - g.G;
-        const int mycnt = s_cnt[lane], myoff = s_off[lane], maxc = s_max;
+        const int mycnt = s_cnt[lane], maxc = s_max;
         if constexpr (kRegAcc) {
             // a lane sums its cell's particles in registers (they all hit the
             // same 3^D nodes), then adds the sums to its wave's block; lanes
@@ -429,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
 #pragma unroll
                 for (int q = 0; q <= D; ++q) acc[k][q] = T(0);
             for (int r = w; r < mycnt; r += NW) {
-                int j = sorted[myoff + r];
+                int j = sorted[rank_major_pos(lane, r, s_rmask, s_roff, s_cnt)];
                 p2g_particle<T, D, MAT>(P, cur, j, lb, gb, [&](int k, int, const T* add) {
 #pragma unroll
                     for (int q = 0; q <= D; ++q) acc[k][q] += add[q];
@@ -458,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
             T (*node)[NB] = s_node[w];
             for (int r = w; r < maxc; r += NW) {
                 if (r < mycnt) {
-                    int j = sorted[myoff + r];
+                    int j = sorted[rank_major_pos(lane, r, s_rmask, s_roff, s_cnt)];
                     p2g_particle<T, D, MAT>(P, cur, j, lb, gb, [&](int, int n, const T* add) {
 #pragma unroll
                         for (int q = 0; q <= D; ++q) atomicAdd(&node[q][n], add[q]);

@@ -108,13 +108,40 @@ def test_keys_match_base_cells(orc):
         assert k[p] == o.L.orc_key_of_base(ct.byref(o.c), arr)
 
 
-def test_sort_is_stable_argsort(orc):
+def _tile_rank_cell_order(key):
+    """The step's sort order written with numpy: group by key (stable, ties
+    by slot) to get each particle's rank inside its cell, then order by
+    (tile, rank, cell)."""
+    st = np.argsort(key, kind="stable")
+    ks = key[st]
+    idx = np.arange(len(ks))
+    first = np.r_[True, ks[1:] != ks[:-1]] if len(ks) else np.zeros(0, bool)
+    rank = idx - np.maximum.accumulate(np.where(first, idx, 0))
+    return st[np.lexsort((ks & 63, rank, ks >> 6))].astype(np.int32)
+
+
+def test_sort_order_brute_force(orc):
+    """Tiny case by counting: a particle's rank is the number of particles
+    with its key at smaller slots; the order is by (tile, rank, cell)."""
+    rng = np.random.default_rng(41)
+    key = rng.integers(0, 200, size=300).astype(np.int32)
+    t = []
+    for p in range(len(key)):
+        rank = sum(1 for q in range(p) if key[q] == key[p])
+        t.append((int(key[p]) >> 6, rank, int(key[p]) & 63, p))
+    ref = np.array([e[3] for e in sorted(t)], dtype=np.int32)
+    assert np.array_equal(orc.Oracle.sort_perm(key), ref)
+
+
+def test_sort_order_matches_definition(orc):
     rng = np.random.default_rng(4)
-    key = rng.integers(0, 50, size=5000).astype(np.int32)
-    perm = orc.Oracle.sort_perm(key)
-    ref = np.argsort(key, kind="stable").astype(np.int32)
-    assert np.array_equal(perm, ref)
-    assert np.array_equal(np.sort(perm), np.arange(5000))
+    for hi in (50, 640, 5000):
+        key = rng.integers(0, hi, size=5000).astype(np.int32)
+        perm = orc.Oracle.sort_perm(key)
+        assert np.array_equal(perm, _tile_rank_cell_order(key))
+        assert np.array_equal(np.sort(perm), np.arange(5000))
+        # tiles stay contiguous and in order
+        assert np.all(np.diff(key[perm] >> 6) >= 0)
 
 
 def test_key_f32_rounding(orc):
@@ -528,7 +555,7 @@ def test_step_sorts_by_key(orc):
         xb = st.x.copy()
         perm, key = o.step(st, cfg.dt)
         assert np.array_equal(key, o.keys(xb))
-        assert np.array_equal(perm, np.argsort(key, kind="stable"))
+        assert np.array_equal(perm, _tile_rank_cell_order(key))
 
 
 def _bar_setup(orc, nu=0.0):
