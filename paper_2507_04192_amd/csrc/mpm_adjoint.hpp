@@ -55,21 +55,34 @@ __device__ __forceinline__ void node_grad_hess(const T w[D][3], const T dw[D][3]
     }
 }
 
+// Per-slot intermediate of the reverse sweep (mid), component-major with
+// stride cap:
+//   [0, D)              position adjoint (partial after k_g2p_adj_cons,
+//                       complete after k_g2p_adj_grid)
+//   [D, D + D^2)        adjoint of the stored F_e - I (fluid: [D] holds J)
+//   [D + D^2, 2D + D^2) adjoint of the G2P velocity (vt)
+//   [2D + D^2, 2D + 2D^2)  adjoint of the velocity gradient (Lb)
+template <int D> struct MidLayout {
+    static constexpr int X = 0, G = D, VT = D + D * D, LB = 2 * D + D * D, N = 2 * D + 2 * D * D;
+};
+
+// Reverse of the constitutive update and of the kinematics x' = x + dt v,
+// per particle of a tile: recomputes the G2P velocity and velocity gradient
+// from the tile's node block, applies the constitutive VJP, and stores the
+// adjoints that the reverse G2P needs.
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kBlock) void k_g2p_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
-                                                    const ActiveTile* __restrict__ active,
-                                                    const int* __restrict__ perm, PView<T> st, PView<T> aout,
-                                                    const T* __restrict__ gv, T* __restrict__ part,
-                                                    T* __restrict__ mid)
+__global__ __launch_bounds__(kBlock) void k_g2p_adj_cons(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                         const ActiveTile* __restrict__ active,
+                                                         const int* __restrict__ perm, PView<T> st, PView<T> aout,
+                                                         const T* __restrict__ gv, T* __restrict__ mid)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     constexpr int NS = D * (D + 1) / 2;
+    using ML = MidLayout<D>;
     __shared__ T s_v[D][NB];
-    __shared__ double s_b[D][NB];
     const int n_active = meta[0];
     const int tid = threadIdx.x;
     const long long cap = st.cap;
-    const T inv2 = P.inv * P.inv;
     for (int it = 0;; ++it) {
         int e = tile_entry(it, n_active);
         if (e < 0) break;
@@ -80,16 +93,13 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Geo g, Phys<T> P, const int*
             int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
             long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                s_v[a][i] = gv[a * g.NN + node];
-                s_b[a][i] = 0.0;
-            }
+            for (int a = 0; a < D; ++a) s_v[a][i] = gv[a * g.NN + node];
         }
         __syncthreads();
         for (int k = tid; k < at.cnt; k += kBlock) {
             long long s = at.off + k;
             int j = perm[s];
-            T xp[D], w[D][3], dw[D][3], dd[D][3];
+            T xp[D], w[D][3], dw[D][3];
             int lb[3] = {0, 0, 0};
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -99,10 +109,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Geo g, Phys<T> P, const int*
                 stencil_axis(xp[a], P.inv, b, f, w[a], dw[a]);
                 int l = b + g.G - tc[a] * TE;
                 lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
             }
-            // forward G2P of this particle
+            // forward G2P of this particle: velocity and velocity gradient
             T vn[D], Lm[D][D];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
@@ -136,21 +144,12 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Geo g, Phys<T> P, const int*
                             }
                         }
                     }
-            // adjoints of the outputs (slot s)
-            T xb[D], vb[D], Cb[D][D];
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                xb[a] = aout.x[a * cap + s];
-                vb[a] = aout.v[a * cap + s];
-#pragma unroll
-                for (int b = 0; b < D; ++b) Cb[a][b] = aout.C[(a * D + b) * cap + s];
-            }
             // reverse of the constitutive update
             T Lb[D][D];
             if constexpr (MAT == MAT_FLUID) {
                 T Jb_in;
                 fluid_vjp<T, D>(P, Lm, st.G[j], aout.G[s], aout.S[s], Lb, Jb_in);
-                mid[D * cap + s] = Jb_in;
+                mid[ML::G * cap + s] = Jb_in;
             } else {
                 T G[D][D], Gb[D][D], Gb_in[D][D], sb[NS];
 #pragma unroll
@@ -166,18 +165,85 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Geo g, Phys<T> P, const int*
 #pragma unroll
                 for (int a = 0; a < D; ++a)
 #pragma unroll
-                    for (int b = 0; b < D; ++b) mid[(D + a * D + b) * cap + s] = Gb_in[a][b];
+                    for (int b = 0; b < D; ++b) mid[(ML::G + a * D + b) * cap + s] = Gb_in[a][b];
             }
             // x' = clamp(x + dt v'): no gradient through a clamped component
-            T xbar[D], vt[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
+                T xb = aout.x[a * cap + s];
                 T xn = xp[a] + P.dt * vn[a];
                 bool free_ = (xn >= T(0)) && (xn <= P.ext[a]);
-                xbar[a] = free_ ? xb[a] : T(0);
-                vt[a] = vb[a] + (free_ ? P.dt * xb[a] : T(0));
+                mid[(ML::X + a) * cap + s] = free_ ? xb : T(0);
+                mid[(ML::VT + a) * cap + s] = aout.v[a * cap + s] + (free_ ? P.dt * xb : T(0));
+#pragma unroll
+                for (int b = 0; b < D; ++b) mid[(ML::LB + a * D + b) * cap + s] = Lb[a][b];
             }
-            // reverse of G2P
+        }
+        __syncthreads();
+    }
+}
+
+// Reverse of G2P per particle of a tile: node adjoints of the velocity
+// (accumulated in binary64 in LDS, then written as the tile's partial
+// block) and the position adjoint through the weights and x_i - x_p.
+template <class T, int D>
+__global__ __launch_bounds__(kBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                         const ActiveTile* __restrict__ active,
+                                                         const int* __restrict__ perm, PView<T> st, PView<T> aout,
+                                                         const T* __restrict__ gv, T* __restrict__ part,
+                                                         T* __restrict__ mid)
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    using ML = MidLayout<D>;
+    __shared__ T s_v[D][NB];
+    __shared__ double s_b[D][NB];
+    const int n_active = meta[0];
+    const int tid = threadIdx.x;
+    const long long cap = st.cap;
+    const T inv2 = P.inv * P.inv;
+    for (int it = 0;; ++it) {
+        int e = tile_entry(it, n_active);
+        if (e < 0) break;
+        ActiveTile at = active[e];
+        int tc[3];
+        tile_coords(g, at.tile, tc);
+        for (int i = tid; i < NB; i += kBlock) {
+            int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
+            long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                s_v[a][i] = gv[a * g.NN + node];
+                s_b[a][i] = 0.0;
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < at.cnt; k += kBlock) {
+            long long s = at.off + k;
+            int j = perm[s];
+            T w[D][3], dw[D][3], dd[D][3];
+            int lb[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                int b;
+                T f;
+                stencil_axis(st.x[a * cap + j], P.inv, b, f, w[a], dw[a]);
+                int l = b + g.G - tc[a] * TE;
+                lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
+            }
+            T xbar[D], vt[D], Cb[D][D], Lb[D][D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                xbar[a] = mid[(ML::X + a) * cap + s];
+                vt[a] = mid[(ML::VT + a) * cap + s];
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    Cb[a][b] = aout.C[(a * D + b) * cap + s];
+                    Lb[a][b] = mid[(ML::LB + a * D + b) * cap + s];
+                }
+            }
+            constexpr int KZ = (D == 3) ? 3 : 1;
 #pragma unroll
             for (int kz = 0; kz < KZ; ++kz)
 #pragma unroll
@@ -215,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj(Geo g, Phys<T> P, const int*
                         }
                     }
 #pragma unroll
-            for (int a = 0; a < D; ++a) mid[a * cap + s] = xbar[a];
+            for (int a = 0; a < D; ++a) mid[(ML::X + a) * cap + s] = xbar[a];
         }
         __syncthreads();
         T* dst = part + (long long)e * (D + 1) * NB;
@@ -704,7 +770,9 @@ struct Adjoint {
         k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (const T*)c->part_grid,
                                                   (T*)c->gv, (T*)c->gmass, (T*)c->gvt);
         prof_mark(c, MPM_PROF_GRID);
-        k_g2p_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in, aout,
+        k_g2p_adj_cons<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in, aout,
+                                                               (const T*)c->gv, (T*)c->mid);
+        k_g2p_adj_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in, aout,
                                                           (const T*)c->gv, (T*)c->part_grid, (T*)c->mid);
         prof_mark(c, MPM_PROF_G2P_ADJ);
         k_grid_adj<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot,

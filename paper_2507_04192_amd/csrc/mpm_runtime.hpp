@@ -68,7 +68,7 @@ struct mpm_ctx {
     char* tape = nullptr;          // a segment's recomputed states (ckpt_every + 1)
     int32_t* tape_pid = nullptr;
     char* adj[2] = {nullptr, nullptr};   // adjoint states (same layout as a state)
-    void* mid = nullptr;           // per slot: partial position adjoint, F or J adjoint
+    void* mid = nullptr;           // per slot: position, F (or J), G2P velocity and velocity-gradient adjoints
     void* gvt = nullptr;           // nodal velocity before the walls [dim]
     int32_t* inv = nullptr;        // slot of each pid
     double* amu = nullptr;         // dL/dmu per floor node
