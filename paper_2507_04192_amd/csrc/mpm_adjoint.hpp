@@ -463,15 +463,57 @@ __global__ __launch_bounds__(kBlock) void k_p2g_adj(Geo g, Phys<T> P, const int*
                 Sp[0][0] = st.S[0 * cap + j]; Sp[1][1] = st.S[1 * cap + j];
                 Sp[0][1] = Sp[1][0] = st.S[2 * cap + j];
             }
-            T xbar[D], vbar[D], Cbar[D][D], Sbar[D][D];
+            // With p_i, m_i the node adjoints of momentum and mass, the
+            // particle's adjoints are gathers over its stencil:
+            //   vbar = m sum phi p,  Cbar = m sum phi p (x_i - x_p)^T,
+            //   Sbar = -dt sum p (grad phi)^T =: -dt Lp,
+            //   xbar += m [ sum grad phi (m_i + (x_i - x_p).(Cp^T p)) + Lp^T v_p
+            //              - Cp^T (sum phi p) ] - dt sum Hess(phi) (S_p p).
+            T V[D], Bp[D][D], Lp[D][D], X1[D], X2[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                xbar[a] = mid[a * cap + s];
-                vbar[a] = T(0);
+                V[a] = T(0);
+                X1[a] = T(0);
+                X2[a] = T(0);
 #pragma unroll
-                for (int b = 0; b < D; ++b) { Cbar[a][b] = T(0); Sbar[a][b] = T(0); }
+                for (int b = 0; b < D; ++b) { Bp[a][b] = T(0); Lp[a][b] = T(0); }
             }
             constexpr int KZ = (D == 3) ? 3 : 1;
+            // pass 1: the G2P-like gathers of p
+#pragma unroll
+            for (int kz = 0; kz < KZ; ++kz)
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        int kk[3] = {kx, ky, kz};
+                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
+                        T phi = T(1), gr[D];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) phi *= w[a][kk[a]];
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            T gg = dw[a][kk[a]];
+#pragma unroll
+                            for (int b = 0; b < D; ++b)
+                                if (b != a) gg *= w[b][kk[b]];
+                            gr[a] = gg;
+                        }
+#pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            T pa = s_p[a][n];
+                            T fp = phi * pa;
+                            V[a] += fp;
+#pragma unroll
+                            for (int b = 0; b < D; ++b) {
+                                Bp[a][b] += fp * dd[b][kk[b]];
+                                Lp[a][b] += pa * gr[b];
+                            }
+                        }
+                    }
+            // keep the two passes apart so that their live ranges do not overlap
+            __builtin_amdgcn_sched_barrier(0);
+            // pass 2: terms through the weights' derivatives
 #pragma unroll
             for (int kz = 0; kz < KZ; ++kz)
 #pragma unroll
@@ -482,35 +524,44 @@ __global__ __launch_bounds__(kBlock) void k_p2g_adj(Geo g, Phys<T> P, const int*
                         int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
                         T phi, gr[D], H[D][D];
                         node_grad_hess<T, D>(w, dw, kk, inv2, phi, gr, H);
-                        T mbn = s_m[n];
-                        T wbar = P.mass * mbn, dbar[D], gbar[D];
+                        T pb[D];
 #pragma unroll
-                        for (int b = 0; b < D; ++b) { dbar[b] = T(0); gbar[b] = T(0); }
+                        for (int a = 0; a < D; ++a) pb[a] = s_p[a][n];
+                        T sc = s_m[n], sp[D];
 #pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            T pb = s_p[a][n];
-                            T aff = vp[a];
+                        for (int b = 0; b < D; ++b) {
+                            T ub = T(0), sb = T(0);
 #pragma unroll
-                            for (int b = 0; b < D; ++b) aff += Cp[a][b] * dd[b][kk[b]];
-                            wbar += P.mass * aff * pb;
-                            T wp = phi * P.mass * pb;
-                            vbar[a] += wp;
-#pragma unroll
-                            for (int b = 0; b < D; ++b) {
-                                Cbar[a][b] += wp * dd[b][kk[b]];
-                                dbar[b] += phi * P.mass * Cp[a][b] * pb;
-                                Sbar[a][b] -= P.dt * pb * gr[b];
-                                gbar[b] -= P.dt * Sp[a][b] * pb;
+                            for (int a = 0; a < D; ++a) {
+                                ub += Cp[a][b] * pb[a];
+                                sb += Sp[b][a] * pb[a];
                             }
+                            sp[b] = sb;
+                            sc += dd[b][kk[b]] * ub;
                         }
 #pragma unroll
                         for (int c = 0; c < D; ++c) {
-                            T t = wbar * gr[c] - dbar[c];
+                            X1[c] += sc * gr[c];
+                            T h = T(0);
 #pragma unroll
-                            for (int b = 0; b < D; ++b) t += gbar[b] * H[b][c];
-                            xbar[c] += t;
+                            for (int b = 0; b < D; ++b) h += sp[b] * H[b][c];
+                            X2[c] += h;
                         }
                     }
+            T xbar[D], vbar[D], Cbar[D][D], Sbar[D][D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T t = X1[c];
+#pragma unroll
+                for (int a = 0; a < D; ++a) t += Lp[a][c] * vp[a] - Cp[a][c] * V[a];
+                xbar[c] = mid[c * cap + s] + P.mass * t - P.dt * X2[c];
+                vbar[c] = P.mass * V[c];
+#pragma unroll
+                for (int b = 0; b < D; ++b) {
+                    Cbar[c][b] = P.mass * Bp[c][b];
+                    Sbar[c][b] = -P.dt * Lp[c][b];
+                }
+            }
             // the particle's adjoint goes to its slot before the step's sort
 #pragma unroll
             for (int a = 0; a < D; ++a) {
