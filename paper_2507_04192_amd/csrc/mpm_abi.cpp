@@ -83,7 +83,8 @@ struct Layout {
     size_t st[2], pid[2], key, perm, tmp, tmpk, count, tile_off, tile_slot, active, part, meta, status;
     size_t part_grid, gv, gmass;
     size_t inv, loss, box_sum, box_cnt, box_coef;
-    size_t ckpt, ckpt_pid, tape, tape_pid, adj[2], mid, gvt, amu;
+    size_t ckpt, ckpt_pid, tape, tape_pid, adj[2], mid, gtape, amu;
+    GridRec grec;
     size_t total;
 };
 
@@ -133,7 +134,23 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
         L.adj[0] = take(sb);
         L.adj[1] = take(sb);
         L.mid = take((size_t)(2 * c.dim + 2 * c.dim * c.dim) * ucap * elem);
-        L.gvt = take((size_t)g.NN * c.dim * elem);
+        // grid tape: one record per step of a segment
+        GridRec& r = L.grec;
+        size_t ro = 0;
+        auto rtake = [&](size_t bytes) {
+            size_t o = ro;
+            ro = align_up(ro + bytes);
+            return o;
+        };
+        r.gv = rtake((size_t)g.NN * c.dim * elem);
+        r.gvt = rtake((size_t)g.NN * c.dim * elem);
+        r.gmass = rtake((size_t)g.NN * elem);
+        r.perm = rtake(ucap * 4);
+        r.tile_slot = rtake((size_t)g.ntiles * 4);
+        r.active = rtake((size_t)g.ntiles * sizeof(ActiveTile));
+        r.meta = rtake(64 * 4);
+        r.bytes = ro;
+        L.gtape = take((size_t)ckpt_every * r.bytes);
         size_t nfl = c.dim == 3 ? (size_t)g.box[0] * g.box[1] : (size_t)g.box[0];
         L.amu = take(nfl * 8);
     }
@@ -274,7 +291,8 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     c->adj[0] = tape ? b + L.adj[0] : nullptr;
     c->adj[1] = tape ? b + L.adj[1] : nullptr;
     c->mid = tape ? b + L.mid : nullptr;
-    c->gvt = tape ? b + L.gvt : nullptr;
+    c->gtape = tape ? b + L.gtape : nullptr;
+    c->grec = L.grec;
     c->amu = tape ? (double*)(b + L.amu) : nullptr;
     c->has_tape = false;
     c->cur = 0;

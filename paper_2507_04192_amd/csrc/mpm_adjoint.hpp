@@ -5,10 +5,10 @@
 // squared error are evaluated on the device (loss in binary64).
 //
 // Backward (mpm_backward), segment by segment from the last: the segment's
-// checkpoint is restored and its k steps recomputed into a tape of states;
-// then for each step in reverse (Sec. 3.1, eq:dzda; Sec. 3.3 recomputation):
-//   recompute the sort, P2G and grid of that step (keeping the velocity
-//   before the walls), then
+// checkpoint is restored and its k steps recomputed into a tape of states
+// and a grid tape (each step's sort, nodal mass and nodal velocity before
+// and after the walls); then for each step in reverse (Sec. 3.1, eq:dzda;
+// Sec. 3.3 recomputation):
 //   g2p_adj   per particle: reverse of the constitutive update and of G2P;
 //             node adjoints accumulated in LDS and written per tile
 //   grid_adj  per node: reverse of the walls (dL/dmu) and of v = P/m + dt g
@@ -798,40 +798,37 @@ struct Adjoint {
         k_keys<T, D><<<nblocks(c->N), kBlock, 0, st>>>(c->geo, P, v, c->N, c->key, c->count);
     }
 
+    // The grid-tape record of step i of the current segment.
+    static typename S::StepBufs rec_bufs(const mpm_ctx* c, int i)
+    {
+        char* r = c->gtape + (size_t)i * c->grec.bytes;
+        return {(int32_t*)(r + c->grec.perm), (int32_t*)(r + c->grec.tile_slot), (ActiveTile*)(r + c->grec.active),
+                (int32_t*)(r + c->grec.meta), (T*)(r + c->grec.gv), (T*)(r + c->grec.gmass),
+                (T*)(r + c->grec.gvt)};
+    }
+
+    // Reverse of one step whose sort and grid are in record rb (written by
+    // the segment's forward recomputation): aout holds the adjoint of the
+    // step's output state, ain receives that of its input state st_in.  The
+    // record's nodal velocity and mass are overwritten by their adjoints.
     template <int MAT>
-    static void adjoint_step(mpm_ctx* c, const Phys<T>& P0, const PView<T>& st_in, const PView<T>& aout,
-                             const PView<T>& ain)
+    static void adjoint_step(mpm_ctx* c, const Phys<T>& P, const PView<T>& st_in, const PView<T>& aout,
+                             const PView<T>& ain, const typename S::StepBufs& rb)
     {
         hipStream_t st = c->stream;
         const Geo& g = c->geo;
-        Phys<T> P = P0;
-        P.keep_grid = 1;
         prof_mark(c, -1);
-        keys_of(c, st_in);
-        unsigned nsb = (unsigned)((g.ntiles + kScanChunk - 1) / kScanChunk);
-        k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
-        k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, c->tile_slot, c->active,
-                                               c->meta);
-        prof_mark(c, MPM_PROF_SCAN);
-        k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
-        prof_mark(c, MPM_PROF_BUCKET);
-        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->tmpk, st_in, c->perm,
-                                                      (T*)c->part_grid);
-        prof_mark(c, MPM_PROF_P2G);
-        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (const T*)c->part_grid,
-                                                  (T*)c->gv, (T*)c->gmass, (T*)c->gvt);
-        prof_mark(c, MPM_PROF_GRID);
-        k_g2p_adj_cons<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in, aout,
-                                                               (const T*)c->gv, (T*)c->mid);
-        k_g2p_adj_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in, aout,
-                                                          (const T*)c->gv, (T*)c->part_grid, (T*)c->mid);
+        k_g2p_adj_cons<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
+                                                               (const T*)rb.gv, (T*)c->mid);
+        k_g2p_adj_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
+                                                          (const T*)rb.gv, (T*)c->part_grid, (T*)c->mid);
         prof_mark(c, MPM_PROF_G2P_ADJ);
-        k_grid_adj<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot,
-                                                      (const T*)c->part_grid, (T*)c->gmass, (const T*)c->gvt,
-                                                      (T*)c->gv, c->floor_mu ? c->amu : nullptr);
+        k_grid_adj<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.tile_slot,
+                                                      (const T*)c->part_grid, rb.gmass, (const T*)rb.gvt, rb.gv,
+                                                      c->floor_mu ? c->amu : nullptr);
         prof_mark(c, MPM_PROF_GRID_ADJ);
-        k_p2g_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, st_in,
-                                                          (const T*)c->gv, (const T*)c->gmass, (const T*)c->mid,
+        k_p2g_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in,
+                                                          (const T*)rb.gv, (const T*)rb.gmass, (const T*)c->mid,
                                                           ain);
         prof_mark(c, MPM_PROF_P2G_ADJ);
     }
@@ -923,6 +920,8 @@ struct Adjoint {
         hipStream_t st = c->stream;
         const int n = c->fwd_steps, k = c->ckpt_every;
         Phys<T> P = make_phys<T>(c, c->fwd_dt);
+        Phys<T> Pk = P;   // the recomputed steps keep their nodal mass
+        Pk.keep_grid = 1;
         int a = 0;   // adjoint buffer holding the adjoint of the later state
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->adj[0], (long long)c->nsc * c->cap, T(0));
         long long nfl = c->geo.dim == 3 ? (long long)c->geo.box[0] * c->geo.box[1] : c->geo.box[0];
@@ -934,12 +933,12 @@ struct Adjoint {
             if (rc) return rc;
             keys_of(c, tape(c, 0));
             for (int t = t0; t < t1; ++t)
-                S::template step_views<MAT>(c, P, tape(c, t - t0), tape(c, t - t0 + 1));
+                S::template step_views<MAT>(c, Pk, tape(c, t - t0), tape(c, t - t0 + 1), rec_bufs(c, t - t0));
             for (int t = t1 - 1; t >= t0; --t) {
                 int fi = frame_index(c, t + 1);
                 PView<T> aout = adj(c, a), ain = adj(c, 1 - a);
                 if (fi >= 0) observe(c, tape(c, t + 1 - t0), fi, &aout);
-                adjoint_step<MAT>(c, P, tape(c, t - t0), aout, ain);
+                adjoint_step<MAT>(c, P, tape(c, t - t0), aout, ain, rec_bufs(c, t - t0));
                 a = 1 - a;
             }
         }

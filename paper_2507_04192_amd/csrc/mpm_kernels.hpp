@@ -977,28 +977,52 @@ struct Solver {
         return launch_err(c, "clear grid");
     }
 
+    // Where one step keeps its sort and grid: the context's own arrays, or a
+    // record of the grid tape (then the nodal velocity before the walls is
+    // kept too, for the adjoint).
+    struct StepBufs {
+        int32_t* perm;
+        int32_t* tile_slot;
+        ActiveTile* active;
+        int32_t* meta;
+        T* gv;
+        T* gmass;
+        T* gvt;
+    };
+    static StepBufs ctx_bufs(mpm_ctx* c)
+    {
+        return {c->perm, c->tile_slot, c->active, c->meta, (T*)c->gv, (T*)c->gmass, nullptr};
+    }
+
     // One step from state view cur into state view nxt.
     template <int MAT>
-    static void step_views(mpm_ctx* c, const Phys<T>& P, const PView<T>& cur, const PView<T>& nxt)
+    static void step_views(mpm_ctx* c, const Phys<T>& P, const PView<T>& cur, const PView<T>& nxt,
+                           const StepBufs& b)
     {
         hipStream_t st = c->stream;
         const Geo& g = c->geo;
         unsigned nsb = (unsigned)((g.ntiles + kScanChunk - 1) / kScanChunk);
         prof_mark(c, -1);
         k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
-        k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, c->tile_slot, c->active, c->meta);
+        k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, b.tile_slot, b.active, b.meta);
         prof_mark(c, MPM_PROF_SCAN);
         k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
         prof_mark(c, MPM_PROF_BUCKET);
-        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tmp, c->tmpk, cur, c->perm,
+        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
                                                       (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
-        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->tile_slot, (const T*)c->part_grid,
-                                                  (T*)c->gv, (T*)c->gmass, (T*)nullptr);
+        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,
+                                                  b.gv, b.gmass, b.gvt);
         prof_mark(c, MPM_PROF_GRID);
-        k_g2p<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, c->meta, c->active, c->perm, cur, nxt, (const T*)c->gv,
+        k_g2p<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, b.meta, b.active, b.perm, cur, nxt, (const T*)b.gv,
                                                       c->key, c->count, c->status);
         prof_mark(c, MPM_PROF_G2P);
+    }
+
+    template <int MAT>
+    static void step_views(mpm_ctx* c, const Phys<T>& P, const PView<T>& cur, const PView<T>& nxt)
+    {
+        step_views<MAT>(c, P, cur, nxt, ctx_bufs(c));
     }
 
     template <int MAT>

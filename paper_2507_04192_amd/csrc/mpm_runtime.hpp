@@ -23,6 +23,13 @@ constexpr int kMaxBoxes = MPM_MAX_BOXES;   // Eulerian observation regions
 
 struct Ops;
 
+// Byte offsets inside one record of the grid tape: what one step's adjoint
+// needs from that step's forward pass (nodal velocity after and before the
+// walls, nodal mass, the sort permutation and the active-tile list).
+struct GridRec {
+    size_t gv = 0, gvt = 0, gmass = 0, perm = 0, tile_slot = 0, active = 0, meta = 0, bytes = 0;
+};
+
 }  // namespace mpm
 
 struct mpm_ctx {
@@ -69,7 +76,8 @@ struct mpm_ctx {
     int32_t* tape_pid = nullptr;
     char* adj[2] = {nullptr, nullptr};   // adjoint states (same layout as a state)
     void* mid = nullptr;           // per slot: position, F (or J), G2P velocity and velocity-gradient adjoints
-    void* gvt = nullptr;           // nodal velocity before the walls [dim]
+    char* gtape = nullptr;         // per step of a segment: the grid and sort it used
+    mpm::GridRec grec;
     int32_t* inv = nullptr;        // slot of each pid
     double* amu = nullptr;         // dL/dmu per floor node
     double* loss = nullptr;        // [0] loss of the last forward rollout
