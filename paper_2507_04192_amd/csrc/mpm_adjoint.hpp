@@ -110,40 +110,37 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj_cons(Geo g, Phys<T> P, const
                 int l = b + g.G - tc[a] * TE;
                 lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
             }
-            // forward G2P of this particle: velocity and velocity gradient
+            // forward G2P of this particle: velocity and velocity gradient,
+            // line by line along x as in the forward kernel (per-axis weight
+            // factors; a scheduling barrier per line bounds register use)
             T vn[D], Lm[D][D];
+            {
+                constexpr int NL = (D == 3) ? 9 : 3;
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                vn[a] = T(0);
+                for (int a = 0; a < D; ++a) {
+                    vn[a] = T(0);
 #pragma unroll
-                for (int b = 0; b < D; ++b) Lm[a][b] = T(0);
-            }
-            constexpr int KZ = (D == 3) ? 3 : 1;
+                    for (int b = 0; b < D; ++b) Lm[a][b] = T(0);
+                }
 #pragma unroll
-            for (int kz = 0; kz < KZ; ++kz)
+                for (int l = 0; l < NL; ++l) {
+                    const int ky = l % 3, kz = l / 3;
+                    const T lw = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
+                    const T ldw1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
+                    const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
 #pragma unroll
-                for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) {
-                        int kk[3] = {kx, ky, kz};
-                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
-                        T phi = T(1);
-#pragma unroll
-                        for (int a = 0; a < D; ++a) phi *= w[a][kk[a]];
-#pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            T vi = s_v[a][n];
-                            vn[a] += phi * vi;
-#pragma unroll
-                            for (int b = 0; b < D; ++b) {
-                                T gg = dw[b][kk[b]];
-#pragma unroll
-                                for (int c = 0; c < D; ++c)
-                                    if (c != b) gg *= w[c][kk[c]];
-                                Lm[a][b] += vi * gg;
-                            }
-                        }
+                    for (int a = 0; a < D; ++a) {
+                        T v0 = s_v[a][n0], v1 = s_v[a][n0 + 1], v2 = s_v[a][n0 + 2];
+                        T A0 = w[0][0] * v0 + w[0][1] * v1 + w[0][2] * v2;
+                        T A2 = dw[0][0] * v0 + dw[0][1] * v1 + dw[0][2] * v2;
+                        vn[a] += lw * A0;
+                        Lm[a][0] += lw * A2;
+                        Lm[a][1] += ldw1 * A0;
+                        if constexpr (D == 3) Lm[a][2] += (w[1][ky] * dw[2][kz]) * A0;
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
             // reverse of the constitutive update
             T Lb[D][D];
             if constexpr (MAT == MAT_FLUID) {
@@ -279,6 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const
                             for (int b = 0; b < D; ++b) t += gbar[b] * H[b][c];
                             xbar[c] += t;
                         }
+                        // one node at a time: bounds the registers in flight
+                        __builtin_amdgcn_sched_barrier(0);
                     }
 #pragma unroll
             for (int a = 0; a < D; ++a) mid[(ML::X + a) * cap + s] = xbar[a];

@@ -280,43 +280,47 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const PView<T>& c
             fs[0][1] = fs[1][0] = -P.dt * s2;
         }
     }
+    // Every weight factors over the axes: per node line along x the terms
+    // that do not depend on x are formed once.  With wyz = w_y w_z (2-D:
+    // w_y), momentum component a at node (kx, line) is
+    //   w_x U_a + w_x dd_x V_a + dw_x W_a,
+    //   U_a = wyz (m v_a + sum_{b>0} mC_ab dd_b) + sum_{b>0} fs_ab (grad phi_b / w_x),
+    //   V_a = wyz mC_a0,  W_a = wyz fs_a0.
+    T wdx[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) wdx[q] = w[0][q] * dd[0][q];
     constexpr int KZ = (D == 3) ? 3 : 1;
 #pragma unroll
     for (int kz = 0; kz < KZ; ++kz)
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
+        for (int ky = 0; ky < 3; ++ky) {
+            T wyz = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
+            T g1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
+            T g2 = (D == 3) ? w[1][ky] * dw[2][kz] : T(0);
+            T U[D], V[D], Wf[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                T aff = mv[a] + mC[a][1] * dd[1][ky];
+                if constexpr (D == 3) aff += mC[a][2] * dd[2][kz];
+                T u = wyz * aff + fs[a][1] * g1;
+                if constexpr (D == 3) u += fs[a][2] * g2;
+                U[a] = u;
+                V[a] = wyz * mC[a][0];
+                Wf[a] = wyz * fs[a][0];
+            }
+            T mw = P.mass * wyz;
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                int k[3] = {kx, ky, kz};
-                T phi = T(1);
-                T gr[D];
-#pragma unroll
-                for (int a = 0; a < D; ++a) phi *= w[a][k[a]];
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    T gg = dw[a][k[a]];
-#pragma unroll
-                    for (int b = 0; b < D; ++b)
-                        if (b != a) gg *= w[b][k[b]];
-                    gr[a] = gg;
-                }
                 int n;
                 if constexpr (D == 3) n = ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
                 else n = (lb[1] + ky) * BE + lb[0] + kx;
                 T add[D + 1];
-                add[0] = phi * P.mass;
+                add[0] = w[0][kx] * mw;
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    T aff = mv[a];
-#pragma unroll
-                    for (int b = 0; b < D; ++b) aff += mC[a][b] * dd[b][k[b]];
-                    T frc = T(0);
-#pragma unroll
-                    for (int b = 0; b < D; ++b) frc += fs[a][b] * gr[b];
-                    add[1 + a] = phi * aff + frc;
-                }
+                for (int a = 0; a < D; ++a) add[1 + a] = w[0][kx] * U[a] + wdx[kx] * V[a] + dw[0][kx] * Wf[a];
                 sink((kz * 3 + ky) * 3 + kx, n, add);
             }
+        }
 }
 
 // Node index in the tile's LDS block of stencil offset k for a lane whose
@@ -675,47 +679,51 @@ __global__ __launch_bounds__(kBlock) void k_g2p(Geo g, Phys<T> P, const int* __r
 #pragma unroll
                     for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
                 }
+                // Gather over the 3^D stencil nodes of the LDS block:
+                //   vn = sum phi v,  Bm = sum phi v (x_i - x_p)^T,  Lm = sum v (grad phi)^T.
+                // Each weight is a product of per-axis factors: every node
+                // line along x is reduced with the x factors (w, w dd, dw),
+                // then combined with the line's y/z factors.  The scheduling
+                // barrier after each line keeps the compiler from hoisting
+                // all LDS reads of the stencil (registers, occupancy).
                 T vn[D], Bm[D][D], Lm[D][D];
+                {
+                    constexpr int NL = (D == 3) ? 9 : 3;
+                    T wdx[3];
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    vn[a] = T(0);
+                    for (int q = 0; q < 3; ++q) wdx[q] = w[0][q] * dd[0][q];
 #pragma unroll
-                    for (int b = 0; b < D; ++b) { Bm[a][b] = T(0); Lm[a][b] = T(0); }
-                }
-                constexpr int KZ = (D == 3) ? 3 : 1;
+                    for (int a = 0; a < D; ++a) {
+                        vn[a] = T(0);
 #pragma unroll
-                for (int kz = 0; kz < KZ; ++kz)
+                        for (int b = 0; b < D; ++b) { Bm[a][b] = T(0); Lm[a][b] = T(0); }
+                    }
 #pragma unroll
-                    for (int ky = 0; ky < 3; ++ky)
+                    for (int l = 0; l < NL; ++l) {
+                        const int ky = l % 3, kz = l / 3;
+                        const T lw = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
+                        const T ld1 = lw * dd[1][ky];
+                        const T ldw1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
+                        const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
 #pragma unroll
-                        for (int kx = 0; kx < 3; ++kx) {
-                            int kk[3] = {kx, ky, kz};
-                            int n;
-                            if constexpr (D == 3) n = ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
-                            else n = (lb[1] + ky) * BE + lb[0] + kx;
-                            T phi = T(1), gr[D];
-#pragma unroll
-                            for (int a = 0; a < D; ++a) phi *= w[a][kk[a]];
-#pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                T gg = dw[a][kk[a]];
-#pragma unroll
-                                for (int b = 0; b < D; ++b)
-                                    if (b != a) gg *= w[b][kk[b]];
-                                gr[a] = gg;
-                            }
-#pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                T vi = s_v[a][n];
-                                T pv = phi * vi;
-                                vn[a] += pv;
-#pragma unroll
-                                for (int b = 0; b < D; ++b) {
-                                    Bm[a][b] += pv * dd[b][kk[b]];
-                                    Lm[a][b] += vi * gr[b];
-                                }
+                        for (int a = 0; a < D; ++a) {
+                            T v0 = s_v[a][n0], v1 = s_v[a][n0 + 1], v2 = s_v[a][n0 + 2];
+                            T A0 = w[0][0] * v0 + w[0][1] * v1 + w[0][2] * v2;
+                            T A1 = wdx[0] * v0 + wdx[1] * v1 + wdx[2] * v2;
+                            T A2 = dw[0][0] * v0 + dw[0][1] * v1 + dw[0][2] * v2;
+                            vn[a] += lw * A0;
+                            Bm[a][0] += lw * A1;
+                            Bm[a][1] += ld1 * A0;
+                            Lm[a][0] += lw * A2;
+                            Lm[a][1] += ldw1 * A0;
+                            if constexpr (D == 3) {
+                                Bm[a][2] += (lw * dd[2][kz]) * A0;
+                                Lm[a][2] += (w[1][ky] * dw[2][kz]) * A0;
                             }
                         }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
                 bool bad = false;
                 T xn[D];
 #pragma unroll
