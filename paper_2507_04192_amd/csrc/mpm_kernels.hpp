@@ -33,7 +33,9 @@ template <int D> struct TileShape;
 template <> struct TileShape<3> { static constexpr int TE = 4, BE = 6, NB = 216; };
 template <> struct TileShape<2> { static constexpr int TE = 8, BE = 10, NB = 100; };
 
-constexpr int kSortCap = 2048;   // particles per tile sorted in LDS (larger: in perm)
+constexpr int kSortCap = 1024;   // particles per tile sorted in LDS (larger: in perm)
+constexpr int kP2GBlock = 64;    // threads of a P2G workgroup (one wave per tile)
+constexpr int kP2GWGs = kTileWGs * kBlock / kP2GBlock;
 
 // Active-list entry handled by this workgroup on iteration `it`.  Workgroup b
 // runs on XCD b % 8; each XCD gets one contiguous chunk of the active list so
@@ -360,13 +362,13 @@ __device__ __forceinline__ int rank_major_pos(int c, int q, const unsigned long 
 // the sum of the waves' node blocks (mass, momentum), in wave order, to the
 // tile's partial block.
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, int* __restrict__ tmp,
                                                 const int* __restrict__ tmpk, PView<T> cur, int* __restrict__ perm,
                                                 T* __restrict__ part)
 {
     constexpr int TE = TileShape<D>::TE, NB = TileShape<D>::NB;
-    constexpr int NW = kBlock / 64;
+    constexpr int NW = kP2GBlock / 64;
     constexpr bool kRegAcc = sizeof(T) == 4;            // binary32: sums in registers
     constexpr int NBLK = NW;                             // one LDS node block per wave
     constexpr int NK = (D == 3) ? 27 : 9;
@@ -382,12 +384,12 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
         int e = tile_entry(it, n_active);
         if (e < 0) break;
         const ActiveTile at = active[e];
-        for (int i = tid; i < NBLK * (D + 1) * NB; i += kBlock) (&s_node[0][0][0])[i] = T(0);
+        for (int i = tid; i < NBLK * (D + 1) * NB; i += kP2GBlock) (&s_node[0][0][0])[i] = T(0);
         if (tid < 64) { s_cnt[tid] = 0; s_cur[tid] = 0; }
         __syncthreads();
         const bool in_lds = at.cnt <= kSortCap;
         // cell histogram; the cell of a particle is the low 6 bits of its key
-        for (int k = tid; k < at.cnt; k += kBlock) atomicAdd(&s_cnt[tmpk[at.off + k] & 63], 1);
+        for (int k = tid; k < at.cnt; k += kP2GBlock) atomicAdd(&s_cnt[tmpk[at.off + k] & 63], 1);
         __syncthreads();
         if (tid < 64) {
             int v = s_cnt[lane], inc = v, mx = v;
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
         __syncthreads();
         // place each particle in its cell's range (arbitrary order inside)
         int* unord = in_lds ? s_unord : (perm + at.off);
-        for (int k = tid; k < at.cnt; k += kBlock) {
+        for (int k = tid; k < at.cnt; k += kP2GBlock) {
             int c = tmpk[at.off + k] & 63;
             int pos = atomicAdd(&s_cur[c], 1);
             unord[s_off[c] + pos] = tmp[at.off + k];
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
         __syncthreads();
         if (in_lds) {
             // rank inside the cell by previous slot: a stable order
-            for (int k = tid; k < at.cnt; k += kBlock) {
+            for (int k = tid; k < at.cnt; k += kP2GBlock) {
                 int c = tmpk[at.off + k] & 63;
                 int j = tmp[at.off + k];
                 int o = s_off[c], n = s_cnt[c], rank = 0;
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
                 s_sorted[rank_major_pos(c, rank, s_rmask, s_roff, s_cnt)] = j;
             }
             __syncthreads();
-            for (int k = tid; k < at.cnt; k += kBlock) perm[at.off + k] = s_sorted[k];
+            for (int k = tid; k < at.cnt; k += kP2GBlock) perm[at.off + k] = s_sorted[k];
         } else {
             // crowded tile: insertion sort of each cell's range in perm
             if (tid < 64) {
@@ -448,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
             // cell-major -> rank-major, through this tile's range of tmp
             // (its bucketed input is no longer needed); the cell of position
             // p is the last cell whose range starts at or before p
-            for (int p = tid; p < at.cnt; p += kBlock) {
+            for (int p = tid; p < at.cnt; p += kP2GBlock) {
                 int lo = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1)
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
             __threadfence_block();
             __syncthreads();
             const volatile int* rm = tmp + at.off;
-            for (int k = tid; k < at.cnt; k += kBlock) unord[k] = rm[k];
+            for (int k = tid; k < at.cnt; k += kP2GBlock) unord[k] = rm[k];
             __threadfence_block();
             __syncthreads();
         }
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g(Geo g, Phys<T> P, const int* __r
         }
         __syncthreads();
         T* dst = part + (long long)e * (D + 1) * NB;
-        for (int i = tid; i < (D + 1) * NB; i += kBlock) {
+        for (int i = tid; i < (D + 1) * NB; i += kP2GBlock) {
             T v = (&s_node[0][0][0])[i];
 #pragma unroll
             for (int b = 1; b < NBLK; ++b) v += (&s_node[b][0][0])[i];
@@ -1016,7 +1018,7 @@ struct Solver {
         prof_mark(c, MPM_PROF_SCAN);
         k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
         prof_mark(c, MPM_PROF_BUCKET);
-        k_p2g<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
+        k_p2g<T, D, MAT><<<kP2GWGs, kP2GBlock, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
                                                       (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
         k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,

@@ -165,16 +165,19 @@ def test_floor_friction_field(orc):
     assert rel_l2(g["x"], r["x"]) <= 1e-10
 
 
-def test_crowded_tile_uses_global_sort(orc):
-    """More particles in one tile than the in-LDS sort holds (2048)."""
+@pytest.mark.parametrize("N,cells", [(3000, 8), (900, 2)])
+def test_crowded_tile_uses_global_sort(orc, N, cells):
+    """One tile holding more particles than the in-LDS sort takes (1024:
+    the sort runs in global memory), or fewer but with more than 64 per
+    cell (ranks past the 64-entry rank table)."""
     cfg = W.SimConfig(dim=2, n=(32, 32, 1), dx=0.01, dt=1e-5, material=W.FLUID, ppc=4,
                       gravity=(0, -9.81, 0))
     rng = np.random.default_rng(35)
-    N = 3000
-    # all inside cells [10, 18) x [10, 18): one tile (base + ghost in [8, 16))
-    lo, hi = (8 - 2 + 0.5) * cfg.dx + 1e-6, (16 - 2 + 0.5) * cfg.dx - 1e-6
+    # inside cells [10, 10 + cells) of the tile whose base + ghost is in [8, 16)
+    lo = (8 - 2 + 0.5) * cfg.dx + 1e-6
+    hi = (8 + cells - 2 + 0.5) * cfg.dx - 1e-6
     x = rng.uniform(lo, hi, size=(2, N))
-    print(f"[case] crowded tile N={N}", flush=True)
+    print(f"[case] crowded tile N={N} over {cells}x{cells} cells", flush=True)
     o = orc.Oracle(cfg)
     st = oracle_state(orc, cfg, x)
     s = gpu_solver(cfg, "f64", x)
