@@ -353,10 +353,11 @@ def frame_loss_and_seed(st, obs, fi):
     return loss, gx, gv
 
 
-def rollout(cfg, x0, v0, steps, dt, floor_mu=None, obs=None, keep_states=False):
-    """Forward rollout; returns (loss, states S^0..S^steps if kept, observed Q per frame)."""
+def rollout(cfg, x0, v0, steps, dt, floor_mu=None, obs=None, keep_states=False, state0=None):
+    """Forward rollout; returns (loss, states S^0..S^steps if kept, observed Q per frame).
+    state0, when given, is the starting state (x0 and v0 are then ignored)."""
     o = Oracle(cfg)
-    st = State(cfg, x0, v=v0)
+    st = State(cfg, x0, v=v0) if state0 is None else state0.copy()
     states = [st.copy()] if keep_states else None
     loss = 0.0
     frames = {} if obs is None else {f: i for i, f in enumerate(obs.frames)}
@@ -394,11 +395,11 @@ def adjoint_step(cfg, st_in, adj_out, dt, floor_mu=None, amu=None):
     return out
 
 
-def rollout_grad(cfg, x0, v0, steps, dt, floor_mu=None, obs=None):
+def rollout_grad(cfg, x0, v0, steps, dt, floor_mu=None, obs=None, state0=None):
     """Loss and its gradient with respect to the initial velocity (pid order)
     and the per-node floor friction, by a reverse sweep over the stored
     states (Sec. 3.1, eq:dzda)."""
-    loss, states, _ = rollout(cfg, x0, v0, steps, dt, floor_mu, obs, keep_states=True)
+    loss, states, _ = rollout(cfg, x0, v0, steps, dt, floor_mu, obs, keep_states=True, state0=state0)
     frames = {} if obs is None else {f: i for i, f in enumerate(obs.frames)}
     d = cfg.dim
     N = states[0].N

@@ -21,6 +21,8 @@
 
 namespace mpm {
 
+constexpr int kAdjBlock = 128;   // threads of the reverse per-tile kernels
+
 // Second derivative of the quadratic B-spline weights (per unit length^2):
 // +1, -2, +1 for the three nodes.
 template <class T>
@@ -71,7 +73,7 @@ template <int D> struct MidLayout {
 // from the tile's node block, applies the constitutive VJP, and stores the
 // adjoints that the reverse G2P needs.
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kBlock) void k_g2p_adj_cons(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kAdjBlock) void k_g2p_adj_cons(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                          const ActiveTile* __restrict__ active,
                                                          const int* __restrict__ perm, PView<T> st, PView<T> aout,
                                                          const T* __restrict__ gv, T* __restrict__ mid)
@@ -89,14 +91,14 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj_cons(Geo g, Phys<T> P, const
         ActiveTile at = active[e];
         int tc[3];
         tile_coords(g, at.tile, tc);
-        for (int i = tid; i < NB; i += kBlock) {
+        for (int i = tid; i < NB; i += kAdjBlock) {
             int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
             long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
 #pragma unroll
             for (int a = 0; a < D; ++a) s_v[a][i] = gv[a * g.NN + node];
         }
         __syncthreads();
-        for (int k = tid; k < at.cnt; k += kBlock) {
+        for (int k = tid; k < at.cnt; k += kAdjBlock) {
             long long s = at.off + k;
             int j = perm[s];
             T xp[D], w[D][3], dw[D][3];
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj_cons(Geo g, Phys<T> P, const
 // (accumulated in binary64 in LDS, then written as the tile's partial
 // block) and the position adjoint through the weights and x_i - x_p.
 template <class T, int D>
-__global__ __launch_bounds__(kBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kAdjBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                          const ActiveTile* __restrict__ active,
                                                          const int* __restrict__ perm, PView<T> st, PView<T> aout,
                                                          const T* __restrict__ gv, T* __restrict__ part,
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const
         ActiveTile at = active[e];
         int tc[3];
         tile_coords(g, at.tile, tc);
-        for (int i = tid; i < NB; i += kBlock) {
+        for (int i = tid; i < NB; i += kAdjBlock) {
             int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
             long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
 #pragma unroll
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const
             }
         }
         __syncthreads();
-        for (int k = tid; k < at.cnt; k += kBlock) {
+        for (int k = tid; k < at.cnt; k += kAdjBlock) {
             long long s = at.off + k;
             int j = perm[s];
             T w[D][3], dw[D][3], dd[D][3];
@@ -284,13 +286,13 @@ __global__ __launch_bounds__(kBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const
         }
         __syncthreads();
         T* dst = part + (long long)e * (D + 1) * NB;
-        for (int i = tid; i < D * NB; i += kBlock) dst[i] = (T)(&s_b[0][0])[i];
+        for (int i = tid; i < D * NB; i += kAdjBlock) dst[i] = (T)(&s_b[0][0])[i];
         __syncthreads();
     }
 }
 
 template <class T, int D>
-__global__ __launch_bounds__(kBlock) void k_grid_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kAdjBlock) void k_grid_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                      const ActiveTile* __restrict__ active,
                                                      const int* __restrict__ tile_slot, const T* __restrict__ part,
                                                      T* __restrict__ gmass, const T* __restrict__ gvt,
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(Geo g, Phys<T> P, const int
         int tile = active[e].tile;
         int tc[3];
         tile_coords(g, tile, tc);
-        for (int i = threadIdx.x; i < NB; i += kBlock) {
+        for (int i = threadIdx.x; i < NB; i += kAdjBlock) {
             int l[3] = {i % BE, (i / BE) % BE, (D == 3) ? i / (BE * BE) : 0};
             int I[3], own[3];
             bool down[3];
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_adj(Geo g, Phys<T> P, const int
 }
 
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kBlock) void k_p2g_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kAdjBlock) void k_p2g_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                     const ActiveTile* __restrict__ active,
                                                     const int* __restrict__ perm, PView<T> st,
                                                     const T* __restrict__ gpb, const T* __restrict__ gmb,
@@ -421,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g_adj(Geo g, Phys<T> P, const int*
         ActiveTile at = active[e];
         int tc[3];
         tile_coords(g, at.tile, tc);
-        for (int i = tid; i < NB; i += kBlock) {
+        for (int i = tid; i < NB; i += kAdjBlock) {
             int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
             long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
             s_m[i] = gmb[node];
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_p2g_adj(Geo g, Phys<T> P, const int*
             for (int a = 0; a < D; ++a) s_p[a][i] = gpb[a * g.NN + node];
         }
         __syncthreads();
-        for (int k = tid; k < at.cnt; k += kBlock) {
+        for (int k = tid; k < at.cnt; k += kAdjBlock) {
             long long s = at.off + k;
             int j = perm[s];
             T w[D][3], dw[D][3], dd[D][3], vp[D], Cp[D][D], Sp[D][D];
@@ -817,16 +819,16 @@ struct Adjoint {
         hipStream_t st = c->stream;
         const Geo& g = c->geo;
         prof_mark(c, -1);
-        k_g2p_adj_cons<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
+        k_g2p_adj_cons<T, D, MAT><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
                                                                (const T*)rb.gv, (T*)c->mid);
-        k_g2p_adj_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
+        k_g2p_adj_grid<T, D><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
                                                           (const T*)rb.gv, (T*)c->part_grid, (T*)c->mid);
         prof_mark(c, MPM_PROF_G2P_ADJ);
-        k_grid_adj<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.tile_slot,
+        k_grid_adj<T, D><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.tile_slot,
                                                       (const T*)c->part_grid, rb.gmass, (const T*)rb.gvt, rb.gv,
                                                       c->floor_mu ? c->amu : nullptr);
         prof_mark(c, MPM_PROF_GRID_ADJ);
-        k_p2g_adj<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in,
+        k_p2g_adj<T, D, MAT><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in,
                                                           (const T*)rb.gv, (const T*)rb.gmass, (const T*)c->mid,
                                                           ain);
         prof_mark(c, MPM_PROF_P2G_ADJ);

@@ -84,13 +84,14 @@ __device__ __forceinline__ void from_eig(const T U[D][D], const T A[D][D], T R[D
         }
 }
 
-// Reverse of hencky_update.  Inputs: the velocity gradient L and stored
-// G = F_e - I of the step, the adjoints of the outputs (Gb_out for F_e',
-// sb_out for the stored symmetric stress).  Outputs: Lb and Gb_in.
+// Reverse of hencky_update through the eigen-decomposition of b (any
+// strain).  Inputs: the velocity gradient L and stored G = F_e - I of the
+// step, the adjoints of the outputs (Gb_out for F_e', sb_out for the stored
+// symmetric stress).  Outputs: Lb and Gb_in.
 template <class T, int D>
-__device__ __forceinline__ void hencky_vjp(const Phys<T>& P, bool plastic, const T L[D][D], const T G[D][D],
-                                           const T Gb_out[D][D], const T sb_out[D * (D + 1) / 2], T Lb[D][D],
-                                           T Gb_in[D][D])
+__device__ __forceinline__ void hencky_vjp_eig(const Phys<T>& P, bool plastic, const T L[D][D], const T G[D][D],
+                                               const T Gb_out[D][D], const T sb_out[D * (D + 1) / 2], T Lb[D][D],
+                                               T Gb_in[D][D])
 {
     const T dt = P.dt;
     T Gt[D][D], Ft[D][D];
@@ -288,6 +289,300 @@ __device__ __forceinline__ void hencky_vjp(const Phys<T>& P, bool plastic, const
             Lb[i][j] = dt * l;
             Gb_in[i][j] = g;
         }
+}
+
+// General D x D matrix (the adjoints are not symmetric in general).
+template <class T, int D> struct Gen {
+    T a[D][D];
+};
+
+template <class T, int D>
+__device__ __forceinline__ Gen<T, D> sym_gen(const Sym<T, D>& X, const Gen<T, D>& A)   // X A
+{
+    Gen<T, D> R;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += X.at(i, k) * A.a[k][j];
+            R.a[i][j] = s;
+        }
+    return R;
+}
+
+template <class T, int D>
+__device__ __forceinline__ Gen<T, D> gen_sym(const Gen<T, D>& A, const Sym<T, D>& X)   // A X
+{
+    Gen<T, D> R;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += A.a[i][k] * X.at(k, j);
+            R.a[i][j] = s;
+        }
+    return R;
+}
+
+template <class T, int D>
+__device__ __forceinline__ Sym<T, D> sym_part(const Gen<T, D>& A, T scale)   // scale (A + A^T) / 2
+{
+    Sym<T, D> R;
+#pragma unroll
+    for (int i = 0; i < D; ++i) R.a[i] = scale * A.a[i][i];
+    if constexpr (D == 3) {
+        R.a[3] = T(0.5) * scale * (A.a[0][1] + A.a[1][0]);
+        R.a[4] = T(0.5) * scale * (A.a[0][2] + A.a[2][0]);
+        R.a[5] = T(0.5) * scale * (A.a[1][2] + A.a[2][1]);
+    } else {
+        R.a[2] = T(0.5) * scale * (A.a[0][1] + A.a[1][0]);
+    }
+    return R;
+}
+
+// Frechet derivatives of the truncated series of hencky_series, applied to
+// a direction A: D f(X)[A] = sum_k c_k sum_{j<k} X^j A X^(k-1-j).  For
+// symmetric X this map is its own adjoint in the Frobenius product, so it
+// is also the vector-Jacobian product.  Evaluated by carrying the derivative
+// through the same Horner recurrence (the upper-right block of f applied to
+// [[X, A], [0, X]]).
+template <class T, int D>
+__device__ __forceinline__ Gen<T, D> dlog1p_sym(const Sym<T, D>& X, const Gen<T, D>& A)
+{
+    constexpr int K = Series<T>::kLog;
+    constexpr int NS = D * (D + 1) / 2;
+    Sym<T, D> P1;
+    Gen<T, D> P2;
+    T cK = ((K & 1) ? T(1) : T(-1)) / T(K);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) P1.a[q] = (q < D) ? cK : T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) P2.a[i][j] = T(0);
+#pragma unroll
+    for (int k = K - 1; k >= 1; --k) {
+        Gen<T, D> t1 = sym_gen(X, P2), t2 = gen_sym(A, P1);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) P2.a[i][j] = t1.a[i][j] + t2.a[i][j];
+        P1 = cI_plus_AB(((k & 1) ? T(1) : T(-1)) / T(k), X, P1);
+    }
+    Gen<T, D> t1 = sym_gen(X, P2), t2 = gen_sym(A, P1);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) t1.a[i][j] += t2.a[i][j];
+    return t1;
+}
+
+template <class T, int D>
+__device__ __forceinline__ Gen<T, D> dexpm1_sym(const Sym<T, D>& Y, const Gen<T, D>& A)
+{
+    constexpr int K = Series<T>::kExp;
+    constexpr int NS = D * (D + 1) / 2;
+    Sym<T, D> P1;
+    Gen<T, D> P2;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) P1.a[q] = (q < D) ? T(1) : T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) P2.a[i][j] = T(0);
+#pragma unroll
+    for (int k = K; k >= 2; --k) {
+        const T ik = T(1) / T(k);
+        Gen<T, D> t1 = sym_gen(Y, P2), t2 = gen_sym(A, P1);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) P2.a[i][j] = ik * (t1.a[i][j] + t2.a[i][j]);
+        Sym<T, D> Z = Y;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Z.a[q] *= ik;
+        P1 = cI_plus_AB(T(1), Z, P1);
+    }
+    Gen<T, D> t1 = sym_gen(Y, P2), t2 = gen_sym(A, P1);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) t1.a[i][j] += t2.a[i][j];
+    return t1;
+}
+
+// Reverse of the series form of the Hencky return (hencky_series), valid
+// where that form was taken; returns false otherwise (then the caller takes
+// hencky_vjp_eig).  With Hb the adjoint of H from the stress and Gb_out that
+// of F_e' = exp(Y) F_tr (Y = H - E):
+//   F_tr bar = Gb_out + (exp(Y) - I) Gb_out,   exp(Y) bar = Gb_out F_tr^T,
+//   Y bar = D expm1(Y)[exp(Y) bar],
+//   E bar = Hb (elastic), -Y bar (apex), or, on the cone (Y = -r dev E,
+//   r = 1 + c tr E / |dev E|):  Hb + dev(W) - (c z / n) I with Z = Hb + Y bar,
+//   z = <Z, dev E>, n = |dev E|, W = (c z tr E / n^3) dev E - r Z;
+//   X bar = D log1p(X)[E bar] / 2,  F_tr bar += 2 X bar F_tr.
+template <class T, int D>
+__device__ __forceinline__ bool hencky_vjp_series(const Phys<T>& P, bool plastic, const T L[D][D], const T G[D][D],
+                                                  const T Gb_out[D][D], const T sb_out[D * (D + 1) / 2],
+                                                  T Lb[D][D], T Gb_in[D][D])
+{
+    constexpr int NS = D * (D + 1) / 2;
+    const T dt = P.dt;
+    T Gt[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T lg = L[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) lg += L[i][k] * G[k][j];
+            Gt[i][j] = G[i][j] + dt * lg;
+        }
+    // forward, as hencky_series
+    Sym<T, D> X;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            T s = Gt[i][j] + Gt[j][i];
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += Gt[i][k] * Gt[j][k];
+            int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            X.a[q] = s;
+        }
+    const T lim2 = Series<T>::kMax * Series<T>::kMax;
+    if (!(X.norm2() < lim2)) return false;
+    Sym<T, D> E = log1p_sym(X);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) E.a[q] *= T(0.5);
+    T trE = E.tr();
+    Sym<T, D> Eh = E;
+#pragma unroll
+    for (int i = 0; i < D; ++i) Eh.a[i] -= trE / T(D);
+    T n = sqrt(Eh.norm2());
+    int cas = 1;
+    T r = T(0);
+    if (plastic) {
+        if (trE > T(0)) cas = 0;
+        else {
+            T dg = n + P.cone_coef * trE;
+            if (dg > T(0)) {
+                cas = 2;
+                r = dg / n;
+            }
+        }
+    }
+    Sym<T, D> Y;
+    if (cas == 0) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Y.a[q] = -E.a[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) Y.a[q] = -r * Eh.a[q];
+    }
+    if (cas != 1 && !(Y.norm2() < lim2)) return false;
+    // adjoint of H from the stored stress S = V0 (2 mu H + lam tr(H) I)
+    Sym<T, D> tb;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) tb.a[q] = P.vol0 * ((q < D) ? sb_out[q] : T(0.5) * sb_out[q]);
+    T trt = tb.tr();
+    Sym<T, D> Hb;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) Hb.a[q] = T(2) * P.mu * tb.a[q] + ((q < D) ? P.lam * trt : T(0));
+    Gen<T, D> Ftb;   // adjoint of F_tr (equivalently of G_tr)
+    Sym<T, D> Eb;
+    if (cas == 1) {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) Ftb.a[i][j] = Gb_out[i][j];
+        Eb = Hb;
+    } else {
+        Sym<T, D> M = expm1_sym(Y);
+        Gen<T, D> Mb;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                T f = Gb_out[i][j], mb = Gb_out[i][j];   // F_tr^T = I + Gt^T
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    f += M.at(i, k) * Gb_out[k][j];
+                    mb += Gb_out[i][k] * Gt[j][k];
+                }
+                Ftb.a[i][j] = f;
+                Mb.a[i][j] = mb;
+            }
+        Sym<T, D> Yb = sym_part(dexpm1_sym(Y, Mb), T(1));
+        if (cas == 0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) Eb.a[q] = -Yb.a[q];
+        } else {
+            const T c = P.cone_coef;
+            Sym<T, D> Z;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) Z.a[q] = Hb.a[q] + Yb.a[q];
+            // <Z, dev E> in the full-matrix Frobenius product
+            T z = T(0);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) z += ((q < D) ? T(1) : T(2)) * Z.a[q] * Eh.a[q];
+            const T cw = c * z * trE / (n * n * n);
+            Sym<T, D> Wm;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) Wm.a[q] = cw * Eh.a[q] - r * Z.a[q];
+            T trW = Wm.tr();
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                Eb.a[q] = Hb.a[q] + Wm.a[q] + ((q < D) ? -trW / T(D) - c * z / n : T(0));
+        }
+    }
+    // E = log1p(X) / 2
+    Gen<T, D> Ebg;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) Ebg.a[i][j] = Eb.at(i, j);
+    Sym<T, D> Xb = sym_part(dlog1p_sym(X, Ebg), T(0.5));
+    // X = Gt + Gt^T + Gt Gt^T:  Gt bar += 2 Xb (I + Gt)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T s = Xb.at(i, j);
+#pragma unroll
+            for (int k = 0; k < D; ++k) s += Xb.at(i, k) * Gt[k][j];
+            Ftb.a[i][j] += T(2) * s;
+        }
+    // Gt = G + dt L (I + G)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T l = T(0), g = Ftb.a[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                l += Ftb.a[i][k] * (G[j][k] + ((j == k) ? T(1) : T(0)));
+                g += dt * L[k][i] * Ftb.a[k][j];
+            }
+            Lb[i][j] = dt * l;
+            Gb_in[i][j] = g;
+        }
+    return true;
+}
+
+// Reverse of hencky_update: the series form where the forward took it, the
+// eigen form otherwise.
+template <class T, int D>
+__device__ __forceinline__ void hencky_vjp(const Phys<T>& P, bool plastic, const T L[D][D], const T G[D][D],
+                                           const T Gb_out[D][D], const T sb_out[D * (D + 1) / 2], T Lb[D][D],
+                                           T Gb_in[D][D])
+{
+    if (!hencky_vjp_series<T, D>(P, plastic, L, G, Gb_out, sb_out, Lb, Gb_in))
+        hencky_vjp_eig<T, D>(P, plastic, L, G, Gb_out, sb_out, Lb, Gb_in);
 }
 
 // Reverse of fluid_update: Jb_out and sb_out are the adjoints of J' - 1 and

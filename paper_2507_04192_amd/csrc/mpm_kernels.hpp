@@ -36,6 +36,9 @@ template <> struct TileShape<2> { static constexpr int TE = 8, BE = 10, NB = 100
 constexpr int kSortCap = 1024;   // particles per tile sorted in LDS (larger: in perm)
 constexpr int kP2GBlock = 64;    // threads of a P2G workgroup (one wave per tile)
 constexpr int kP2GWGs = kTileWGs * kBlock / kP2GBlock;
+// threads of a G2P workgroup (binary64: smaller groups, measured faster)
+template <class T> constexpr int kG2PBlock = sizeof(T) == 8 ? 128 : 256;
+constexpr int kGridBlock = 128;  // threads of a grid-update workgroup
 
 // Active-list entry handled by this workgroup on iteration `it`.  Workgroup b
 // runs on XCD b % 8; each XCD gets one contiguous chunk of the active list so
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
 // ---------------------------------------------------------------------------
 
 template <class T, int D>
-__global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                  const ActiveTile* __restrict__ active,
                                                  const int* __restrict__ tile_slot, const T* __restrict__ part,
                                                  T* __restrict__ gv, T* __restrict__ gmass, T* __restrict__ gvt)
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __
         int tile = active[e].tile;
         int tc[3];
         tile_coords(g, tile, tc);
-        for (int i = threadIdx.x; i < NB; i += kBlock) {
+        for (int i = threadIdx.x; i < NB; i += kGridBlock) {
             int l[3] = {i % BE, (i / BE) % BE, (D == 3) ? i / (BE * BE) : 0};
             int I[3], own[3];
             bool down[3];
@@ -636,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_grid(Geo g, Phys<T> P, const int* __
 // ---------------------------------------------------------------------------
 
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kBlock) void k_g2p(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, const int* __restrict__ perm,
                                                 PView<T> cur, PView<T> nxt, const T* __restrict__ gv,
                                                 int* __restrict__ key_out, int* __restrict__ count,
@@ -654,14 +657,14 @@ __global__ __launch_bounds__(kBlock) void k_g2p(Geo g, Phys<T> P, const int* __r
         ActiveTile at = active[e];
         int tc[3];
         tile_coords(g, at.tile, tc);
-        for (int i = tid; i < NB; i += kBlock) {
+        for (int i = tid; i < NB; i += kG2PBlock<T>) {
             int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
             long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
 #pragma unroll
             for (int a = 0; a < D; ++a) s_v[a][i] = gv[a * g.NN + node];
         }
         __syncthreads();
-        for (int k0 = 0; k0 < at.cnt; k0 += kBlock) {
+        for (int k0 = 0; k0 < at.cnt; k0 += kG2PBlock<T>) {
             int k = k0 + tid;
             bool valid = k < at.cnt;
             int newkey = 0;
@@ -1021,10 +1024,10 @@ struct Solver {
         k_p2g<T, D, MAT><<<kP2GWGs, kP2GBlock, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
                                                       (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
-        k_grid<T, D><<<kTileWGs, kBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,
+        k_grid<T, D><<<kTileWGs * kBlock / kGridBlock, kGridBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,
                                                   b.gv, b.gmass, b.gvt);
         prof_mark(c, MPM_PROF_GRID);
-        k_g2p<T, D, MAT><<<kTileWGs, kBlock, 0, st>>>(g, P, b.meta, b.active, b.perm, cur, nxt, (const T*)b.gv,
+        k_g2p<T, D, MAT><<<kTileWGs * kBlock / kG2PBlock<T>, kG2PBlock<T>, 0, st>>>(g, P, b.meta, b.active, b.perm, cur, nxt, (const T*)b.gv,
                                                       c->key, c->count, c->status);
         prof_mark(c, MPM_PROF_G2P);
     }
