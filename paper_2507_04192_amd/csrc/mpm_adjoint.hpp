@@ -891,19 +891,50 @@ struct Adjoint {
     {
         hipStream_t st = c->stream;
         Phys<T> P = make_phys<T>(c, dt);
+        Phys<T> Pk = P;
+        Pk.keep_grid = 1;
         int k = c->ckpt_every;
+        // the last segment runs directly on the tape (states and grid
+        // records), so the backward sweep starts without recomputing it
+        const int tl = ((n + k - 1) / k - 1) * k;
+        c->tail_taped = false;
         k_fill<double><<<1, kBlock, 0, st>>>(c->loss, 2, 0.0);
         for (int t = 0; t < n; ++t) {
             if (t % k == 0) {
                 int rc = copy_state(c, ckpt(c, t / k), view<T>(c, c->cur));
                 if (rc) return rc;
             }
-            PView<T> cur = view<T>(c, c->cur), nxt = view<T>(c, 1 - c->cur);
-            S::template step_views<MAT>(c, P, cur, nxt);
-            c->cur = 1 - c->cur;
+            PView<T> obs_state;
+            if (t < tl) {
+                PView<T> cur = view<T>(c, c->cur), nxt = view<T>(c, 1 - c->cur);
+                S::template step_views<MAT>(c, P, cur, nxt);
+                c->cur = 1 - c->cur;
+                obs_state = view<T>(c, c->cur);
+            } else {
+                if (t == tl) {
+                    int rc = copy_state(c, tape(c, 0), view<T>(c, c->cur));
+                    if (rc) return rc;
+                }
+                S::template step_views<MAT>(c, Pk, tape(c, t - tl), tape(c, t - tl + 1), rec_bufs(c, t - tl));
+                obs_state = tape(c, t + 1 - tl);
+            }
             int fi = frame_index(c, t + 1);
-            if (fi >= 0) observe(c, view<T>(c, c->cur), fi, nullptr);
+            if (fi >= 0) observe(c, obs_state, fi, nullptr);
         }
+        // the context's state, sort and grid again describe the last step
+        {
+            int rc = copy_state(c, view<T>(c, c->cur), tape(c, n - tl));
+            if (rc) return rc;
+            typename S::StepBufs last = rec_bufs(c, n - 1 - tl);
+            const size_t nn = (size_t)c->geo.NN * sizeof(T);
+            rc = hip_check(c, hipMemcpyAsync(c->perm, last.perm, (size_t)c->cap * 4, hipMemcpyDeviceToDevice, st),
+                           "sort copy");
+            if (!rc) rc = hip_check(c, hipMemcpyAsync(c->gv, last.gv, D * nn, hipMemcpyDeviceToDevice, st), "grid copy");
+            if (!rc && c->cfg.keep_grid)
+                rc = hip_check(c, hipMemcpyAsync(c->gmass, last.gmass, nn, hipMemcpyDeviceToDevice, st), "grid copy");
+            if (rc) return rc;
+        }
+        c->tail_taped = true;
         int rc = S::launch_err(c, "forward loss");
         if (rc) return rc;
         double h[2];
@@ -928,13 +959,19 @@ struct Adjoint {
         long long nfl = c->geo.dim == 3 ? (long long)c->geo.box[0] * c->geo.box[1] : c->geo.box[0];
         k_fill<double><<<std::min<long long>(nblocks(nfl), 4096), kBlock, 0, st>>>(c->amu, nfl, 0.0);
         int nseg = (n + k - 1) / k;
+        // the forward pass left the last segment on the tape (once: the
+        // reverse steps overwrite the grid records with adjoints)
+        const bool tail = c->tail_taped;
+        c->tail_taped = false;
         for (int seg = nseg - 1; seg >= 0; --seg) {
             int t0 = seg * k, t1 = std::min(t0 + k, n);
-            int rc = copy_state(c, tape(c, 0), ckpt(c, seg));
-            if (rc) return rc;
-            keys_of(c, tape(c, 0));
-            for (int t = t0; t < t1; ++t)
-                S::template step_views<MAT>(c, Pk, tape(c, t - t0), tape(c, t - t0 + 1), rec_bufs(c, t - t0));
+            if (!(tail && seg == nseg - 1)) {
+                int rc = copy_state(c, tape(c, 0), ckpt(c, seg));
+                if (rc) return rc;
+                keys_of(c, tape(c, 0));
+                for (int t = t0; t < t1; ++t)
+                    S::template step_views<MAT>(c, Pk, tape(c, t - t0), tape(c, t - t0 + 1), rec_bufs(c, t - t0));
+            }
             for (int t = t1 - 1; t >= t0; --t) {
                 int fi = frame_index(c, t + 1);
                 PView<T> aout = adj(c, a), ain = adj(c, 1 - a);

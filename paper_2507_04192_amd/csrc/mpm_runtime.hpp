@@ -88,6 +88,7 @@ struct mpm_ctx {
     int fwd_steps = 0;
     double fwd_dt = 0.0;
     bool has_tape = false;
+    bool tail_taped = false;       // the tape holds the last segment of the forward rollout
 
     // observations (mpm_set_observations)
     std::vector<int> obs_frames;
