@@ -240,14 +240,16 @@ __device__ __forceinline__ void hencky_vjp_eig(const Phys<T>& P, bool plastic, c
                 kb -= Yt[i][i] * dev[i];
                 sTd += Tt[i][i] * dev[i];
             }
+            // ratios first: tr/dn is bounded on the cone, dn^2 may underflow
+            const T td = tr / dn;
 #pragma unroll
             for (int i = 0; i < D; ++i)
 #pragma unroll
-                for (int j = 0; j < D; ++j) Eht[i][j] = -kappa * Yt[i][j] - b1 * tr * Tt[i][j] / dn;
+                for (int j = 0; j < D; ++j) Eht[i][j] = -kappa * Yt[i][j] - b1 * td * Tt[i][j];
             T trb = a1 * trT - b1 * sTd / dn + kb * c / dn;
-            T nb = b1 * tr * sTd / (dn * dn) - kb * c * tr / (dn * dn);
+            T nb = (b1 * td * sTd - kb * c * td) / dn;
 #pragma unroll
-            for (int i = 0; i < D; ++i) Eht[i][i] += nb * dev[i] / dn;
+            for (int i = 0; i < D; ++i) Eht[i][i] += nb * (dev[i] / dn);
             T trE = T(0);
 #pragma unroll
             for (int i = 0; i < D; ++i) trE += Eht[i][i];
@@ -526,18 +528,21 @@ __device__ __forceinline__ bool hencky_vjp_series(const Phys<T>& P, bool plastic
             Sym<T, D> Z;
 #pragma unroll
             for (int q = 0; q < NS; ++q) Z.a[q] = Hb.a[q] + Yb.a[q];
-            // <Z, dev E> in the full-matrix Frobenius product
+            // <Z, dev E> in the full-matrix Frobenius product, divided by
+            // n; the factors are formed so that nothing underflows when the
+            // strain is tiny (n^3 would)
             T z = T(0);
 #pragma unroll
             for (int q = 0; q < NS; ++q) z += ((q < D) ? T(1) : T(2)) * Z.a[q] * Eh.a[q];
-            const T cw = c * z * trE / (n * n * n);
+            const T zn = z / n, tn = trE / n;
+            const T cw = c * zn * tn / n;
             Sym<T, D> Wm;
 #pragma unroll
             for (int q = 0; q < NS; ++q) Wm.a[q] = cw * Eh.a[q] - r * Z.a[q];
             T trW = Wm.tr();
 #pragma unroll
             for (int q = 0; q < NS; ++q)
-                Eb.a[q] = Hb.a[q] + Wm.a[q] + ((q < D) ? -trW / T(D) - c * z / n : T(0));
+                Eb.a[q] = Hb.a[q] + Wm.a[q] + ((q < D) ? -trW / T(D) - c * zn : T(0));
         }
     }
     // E = log1p(X) / 2

@@ -438,27 +438,19 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
             __syncthreads();
             for (int k = tid; k < at.cnt; k += kP2GBlock) perm[at.off + k] = s_sorted[k];
         } else {
-            // crowded tile: insertion sort of each cell's range in perm
-            if (tid < 64) {
-                int* a = unord + s_off[tid];
-                int n = s_cnt[tid];
-                for (int i = 1; i < n; ++i) {
-                    int v = a[i], q = i - 1;
-                    while (q >= 0 && a[q] > v) { a[q + 1] = a[q]; --q; }
-                    a[q + 1] = v;
-                }
-            }
-            __threadfence_block();
-            __syncthreads();
-            // cell-major -> rank-major, through this tile's range of tmp
-            // (its bucketed input is no longer needed); the cell of position
-            // p is the last cell whose range starts at or before p
-            for (int p = tid; p < at.cnt; p += kP2GBlock) {
-                int lo = 0;
+            // crowded tile: the same rank-by-counting, with the cell-major
+            // placement in perm and the rank-major result staged in this
+            // tile's range of tmp (its bucketed input is no longer needed),
+            // then copied back to perm
+            for (int k = tid; k < at.cnt; k += kP2GBlock) {
+                int p = k, lo = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1)
                     if (lo + step < 64 && s_off[lo + step] <= p) lo += step;
-                tmp[at.off + rank_major_pos(lo, p - s_off[lo], s_rmask, s_roff, s_cnt)] = unord[p];
+                const int j = unord[p], o = s_off[lo], n = s_cnt[lo];
+                int rank = 0;
+                for (int q = 0; q < n; ++q) rank += unord[o + q] < j;
+                tmp[at.off + rank_major_pos(lo, rank, s_rmask, s_roff, s_cnt)] = j;
             }
             __threadfence_block();
             __syncthreads();

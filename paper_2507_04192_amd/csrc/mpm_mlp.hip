@@ -2,10 +2,12 @@
 // whose layers run on the matrix cores of gfx950.
 //
 // Each wave owns 16 samples.  A layer h' = act(h W^T + b) is a 16 x out
-// product computed as 16 x 16 output tiles with v_mfma_f32_16x16x16_bf16
-// (BF16 operands, FP32 accumulation) or v_mfma_f32_16x16x4_f32 (FP32
-// operands); activations stay in the wave's LDS rows between layers.  Widths
-// are padded to multiples of 16 with zeros.  The weight gradient
+// product computed as 16 x 16 output tiles with gfx950's
+// v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation, 32-deep K
+// steps) or v_mfma_f32_16x16x4_f32 (FP32 operands); activations stay in the
+// wave's LDS rows between layers.  Widths are padded to multiples of 16 with
+// zeros (the operand functions return zero past the true widths, so a
+// 32-deep step may run past the padding).  The weight gradient
 // dW = dZ^T H (a reduction over samples) is a split-K MFMA product whose
 // partial tiles are added with global atomics.
 #include <hip/hip_runtime.h>
@@ -19,7 +21,7 @@ namespace {
 constexpr int kMaxW = 128;
 constexpr int kRowsPerWave = 16;
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 
 struct MlpDesc {
     int L;
@@ -49,7 +51,10 @@ __device__ __forceinline__ void wave_sync()
 
 // One 16 x 16 tile: C[r][c] = sum_k A(r, k) * B(k, c), k < K (a multiple of
 // 16).  fa(r, k) and fb(k, c) return zero outside the operands.  Lane l
-// holds C[4*(l/16) + i][l%16], i = 0..3.
+// holds C[4*(l/16) + i][l%16], i = 0..3.  BF16: lane l supplies A(l%16, k)
+// and B(k, l%16) for the eight k = k0 + 8*(l/16) + i of each 32-deep step
+// (the same k for both operands, so the pairing is exact whatever order the
+// unit sums in).
 template <int BF16, class FA, class FB>
 __device__ __forceinline__ f4 mfma_tile(int K, FA fa, FB fb)
 {
@@ -57,14 +62,14 @@ __device__ __forceinline__ f4 mfma_tile(int K, FA fa, FB fb)
     const int r = lane & 15, q = lane >> 4;
     f4 c = {0.f, 0.f, 0.f, 0.f};
     if constexpr (BF16) {
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            s4 a, b;
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            b8 a, b;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = to_bf16(fa(r, k0 + 4 * q + i));
-                b[i] = to_bf16(fb(k0 + 4 * q + i, r));
+            for (int i = 0; i < 8; ++i) {
+                a[i] = __builtin_bit_cast(__bf16, to_bf16(fa(r, k0 + 8 * q + i)));
+                b[i] = __builtin_bit_cast(__bf16, to_bf16(fb(k0 + 8 * q + i, r)));
             }
-            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
         }
     } else {
         for (int k0 = 0; k0 < K; k0 += 4) c = __builtin_amdgcn_mfma_f32_16x16x4f32(fa(r, k0 + q), fb(k0 + q, r), c, 0, 0, 0);

@@ -358,3 +358,36 @@ def test_return_mapping_gradient_from_random_state(orc, precision, fscale):
     assert el <= (1e-10 if precision == "f64" else 1e-4)
     assert ev <= (1e-8 if precision == "f64" else 5e-3)
 
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_gradient_from_rest(orc, precision):
+    """A sand block released from rest (v0 = 0).  Away from the floor the
+    first steps leave E at rounding level, i.e. at the apex of the cone,
+    where the return is not differentiable: which branch (apex, cone,
+    elastic) a particle takes there is decided by rounding, so the two
+    implementations legitimately pick different one-sided derivatives.
+    What must hold: no overflow in the reverse of the return (it has terms
+    like tr E / |dev E|^2), the same loss, and a gradient of the same size."""
+    cfg = W.SimConfig(dim=2, n=(48, 24, 1), dx=1 / 80, dt=2e-5, material=W.SAND, ppc=4,
+                      gravity=(0, -9.81, 0), rho0=2000.0, youngs=1e7, poisson=0.3, phi_deg=35.0,
+                      wall_mode=(W.SLIP, W.SLIP, W.COULOMB, W.SLIP, W.SLIP, W.SLIP),
+                      wall_mu=(0, 0, 0.5, 0, 0, 0))
+    x0 = W.lattice_particles(cfg, W.box_inside((0.1, 0), (0.4, 0.1)), (0.1, 0), (0.4, 0.1), seed=120)
+    x0 = x0.astype(np.float32).astype(np.float64)
+    N = x0.shape[1]
+    v0 = np.zeros((2, N))
+    steps, frames = 20, [5, 10, 15, 20]
+    tr = W.pick_tracers(N, 40, 121)
+    tgt = np.random.default_rng(122).normal(0, 0.05, size=(4, 2, 40)).astype(np.float32).astype(np.float64)
+    print(f"[case] gradient from rest {precision} N={N}", flush=True)
+    obs_o = orc.Observations(frames, tr, "v", tgt)
+    loss_o, gv_o, _ = orc.rollout_grad(cfg, x0, v0, steps, cfg.dt, None, obs_o)
+    loss, gv, _, _ = run_gpu(cfg, precision, x0, v0, None, steps, 8,
+                             dict(frames=frames, tracer_pid=tr, lag_field="v", lag_target=tgt))
+    assert np.all(np.isfinite(gv))
+    el, ev = abs(loss - loss_o) / loss_o, rel_l2(gv, gv_o)
+    ratio = np.linalg.norm(gv) / np.linalg.norm(gv_o)
+    print(f"  loss {el:.2e}; dL/dv0 {ev:.2e}; norm ratio {ratio:.3f}", flush=True)
+    assert el <= (1e-10 if precision == "f64" else 1e-4)
+    assert 0.5 <= ratio <= 2.0
