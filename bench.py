@@ -11,7 +11,8 @@ G2P with the constitutive update.  Inputs are resident in HBM before the
 timed region starts.  Prints one JSON line.
 
 The forward+adjoint leg times a checkpointed rollout with a tracer loss and
-its backward sweep on the same cylinder (FP32 and FP64).
+its backward sweep on the same cylinder (FP32 and FP64; 1000 steps with a
+checkpoint every 100 by default).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -217,8 +218,8 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5)
-    ap.add_argument("--adj-steps", type=int, default=200, help="rollout length of the forward+adjoint leg")
-    ap.add_argument("--adj-ckpt", type=int, default=50, help="checkpoint interval of the forward+adjoint leg")
+    ap.add_argument("--adj-steps", type=int, default=1000, help="rollout length of the forward+adjoint leg")
+    ap.add_argument("--adj-ckpt", type=int, default=100, help="checkpoint interval of the forward+adjoint leg")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
@@ -267,9 +268,10 @@ def main():
     adj = None
     if not args.no_adjoint:
         adj = {}
-        for prec, elem, T in (("f32", 4, args.adj_steps), ("f64", 8, max(args.adj_ckpt, args.adj_steps // 2))):
+        for prec, elem, T in (("f32", 4, args.adj_steps), ("f64", 8, args.adj_steps)):
             if prec == "f64" and args.no_f64:
                 continue
+            torch.cuda.empty_cache()
             torch.cuda.reset_peak_memory_stats()
             r, prof = run_adjoint(cfg, x, prec, T, args.adj_ckpt)
             _, kern, roof_a = roofline({k: prof[k] for k in ("g2p_adj", "p2g_adj") if k in prof}, n, elem)

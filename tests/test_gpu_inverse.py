@@ -45,7 +45,7 @@ def test_learned_friction_small_dam_break():
     the floor under the initial column."""
     from paper_2507_04192_amd import inverse as I
     print("[case] learned friction, 3-D dam-break / 4", flush=True)
-    r = I.learned_friction_3d(scale_div=4, steps=1000, epochs=20)
+    r = I.learned_friction_3d(scale_div=4, steps=1000, epochs=20, cells=(24, 12))
     m, c = r["mlp"], r["cells"]
     print(f"  network: field error {m['start_err']:.3f} -> {m['field_err']:.3f}, loss {m['loss'][0]:.3e} -> "
           f"{m['loss'][-1]:.3e}", flush=True)
