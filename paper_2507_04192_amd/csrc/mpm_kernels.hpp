@@ -242,16 +242,35 @@ __device__ __forceinline__ int wave_tile_entry(int it, int n_active, int w)
 // for each of the 3^D stencil nodes, sink(k, n, add) receives the offset
 // index k, the node's index n in the tile's LDS block and the D+1 values
 // (mass, momentum) to add there.
+// The state of one particle that P2G reads.
+template <class T, int D, int MAT>
+struct P2GIn {
+    static constexpr int NS = (MAT == MAT_FLUID) ? 1 : D * (D + 1) / 2;
+    T x[D], v[D], C[D * D], S[NS];
+    __device__ __forceinline__ void load(const PView<T>& cur, int j)
+    {
+        const long long cap = cur.cap;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            x[a] = cur.x[a * cap + j];
+            v[a] = cur.v[a * cap + j];
+        }
+#pragma unroll
+        for (int q = 0; q < D * D; ++q) C[q] = cur.C[q * cap + j];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) S[q] = cur.S[q * cap + j];
+    }
+};
+
 template <class T, int D, int MAT, class Sink>
-__device__ __forceinline__ void p2g_particle(const Phys<T>& P, const PView<T>& cur, int j, const int lb[3],
+__device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D, MAT>& in, const int lb[3],
                                              const int gb[3], Sink&& sink)
 {
     constexpr int BE = TileShape<D>::BE;
-    const long long cap = cur.cap;
     T w[D][3], dw[D][3], dd[D][3];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        T x = cur.x[a * cap + j];
+        T x = in.x[a];
         T t = mul_exact(x, P.inv);
         T f = t - T(gb[a]);
         weights_from_f(f, P.inv, w[a], dw[a]);
@@ -261,26 +280,26 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const PView<T>& c
     T mv[D], mC[D][D], fs[D][D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        mv[a] = P.mass * cur.v[a * cap + j];
+        mv[a] = P.mass * in.v[a];
 #pragma unroll
-        for (int b = 0; b < D; ++b) mC[a][b] = P.mass * cur.C[(a * D + b) * cap + j];
+        for (int b = 0; b < D; ++b) mC[a][b] = P.mass * in.C[a * D + b];
     }
     if constexpr (MAT == MAT_FLUID) {
-        T s = -P.dt * cur.S[j];
+        T s = -P.dt * in.S[0];
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int b = 0; b < D; ++b) fs[a][b] = (a == b) ? s : T(0);
     } else {
         if constexpr (D == 3) {
-            T s0 = cur.S[0 * cap + j], s1 = cur.S[1 * cap + j], s2 = cur.S[2 * cap + j];
-            T s3 = cur.S[3 * cap + j], s4 = cur.S[4 * cap + j], s5 = cur.S[5 * cap + j];
+            T s0 = in.S[0], s1 = in.S[1], s2 = in.S[2];
+            T s3 = in.S[3], s4 = in.S[4], s5 = in.S[5];
             fs[0][0] = -P.dt * s0; fs[1][1] = -P.dt * s1; fs[2][2] = -P.dt * s2;
             fs[0][1] = fs[1][0] = -P.dt * s3;
             fs[0][2] = fs[2][0] = -P.dt * s4;
             fs[1][2] = fs[2][1] = -P.dt * s5;
         } else {
-            T s0 = cur.S[0 * cap + j], s1 = cur.S[1 * cap + j], s2 = cur.S[2 * cap + j];
+            T s0 = in.S[0], s1 = in.S[1], s2 = in.S[2];
             fs[0][0] = -P.dt * s0; fs[1][1] = -P.dt * s1;
             fs[0][1] = fs[1][0] = -P.dt * s2;
         }
@@ -478,9 +497,13 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
             for (int k = 0; k < NK; ++k)
 #pragma unroll
                 for (int q = 0; q <= D; ++q) acc[k][q] = T(0);
+            // the next particle's state is loaded while this one is spread
+            P2GIn<T, D, MAT> nx;
+            if (w < mycnt) nx.load(cur, sorted[rank_major_pos(lane, w, s_rmask, s_roff, s_cnt)]);
             for (int r = w; r < mycnt; r += NW) {
-                int j = sorted[rank_major_pos(lane, r, s_rmask, s_roff, s_cnt)];
-                p2g_particle<T, D, MAT>(P, cur, j, lb, gb, [&](int k, int, const T* add) {
+                const P2GIn<T, D, MAT> in = nx;
+                if (r + NW < mycnt) nx.load(cur, sorted[rank_major_pos(lane, r + NW, s_rmask, s_roff, s_cnt)]);
+                p2g_particle<T, D, MAT>(P, in, lb, gb, [&](int k, int, const T* add) {
 #pragma unroll
                     for (int q = 0; q <= D; ++q) acc[k][q] += add[q];
                 });
@@ -508,8 +531,9 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
             T (*node)[NB] = s_node[w];
             for (int r = w; r < maxc; r += NW) {
                 if (r < mycnt) {
-                    int j = sorted[rank_major_pos(lane, r, s_rmask, s_roff, s_cnt)];
-                    p2g_particle<T, D, MAT>(P, cur, j, lb, gb, [&](int, int n, const T* add) {
+                    P2GIn<T, D, MAT> in;
+                    in.load(cur, sorted[rank_major_pos(lane, r, s_rmask, s_roff, s_cnt)]);
+                    p2g_particle<T, D, MAT>(P, in, lb, gb, [&](int, int n, const T* add) {
 #pragma unroll
                         for (int q = 0; q <= D; ++q) atomicAdd(&node[q][n], add[q]);
                     });
