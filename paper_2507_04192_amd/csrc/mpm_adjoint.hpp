@@ -479,76 +479,100 @@ __global__ __launch_bounds__(kAdjBlock) void k_p2g_adj(Geo g, Phys<T> P, const i
 #pragma unroll
                 for (int b = 0; b < D; ++b) { Bp[a][b] = T(0); Lp[a][b] = T(0); }
             }
-            constexpr int KZ = (D == 3) ? 3 : 1;
+            // Both passes run line by line along x: every weight, gradient and
+            // Hessian entry of phi is a product of per-axis factors, so each
+            // line is first reduced with the x factors, then combined with
+            // the line's y/z factors.  ddw, the second derivative of the
+            // quadratic B-spline, is (1, -2, 1)/h^2 along each axis.
+            constexpr int NL = (D == 3) ? 9 : 3;
+            const T ddw[3] = {inv2, T(-2) * inv2, inv2};
+            T wdx[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) wdx[q] = w[0][q] * dd[0][q];
             // pass 1: the G2P-like gathers of p
 #pragma unroll
-            for (int kz = 0; kz < KZ; ++kz)
+            for (int l = 0; l < NL; ++l) {
+                const int ky = l % 3, kz = l / 3;
+                const T lw = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
+                const T ld1 = lw * dd[1][ky];
+                const T ldw1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
+                const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
 #pragma unroll
-                for (int ky = 0; ky < 3; ++ky)
+                for (int a = 0; a < D; ++a) {
+                    T p0 = s_p[a][n0], p1 = s_p[a][n0 + 1], p2 = s_p[a][n0 + 2];
+                    T A0 = w[0][0] * p0 + w[0][1] * p1 + w[0][2] * p2;
+                    T A1 = wdx[0] * p0 + wdx[1] * p1 + wdx[2] * p2;
+                    T A2 = dw[0][0] * p0 + dw[0][1] * p1 + dw[0][2] * p2;
+                    V[a] += lw * A0;
+                    Bp[a][0] += lw * A1;
+                    Bp[a][1] += ld1 * A0;
+                    Lp[a][0] += lw * A2;
+                    Lp[a][1] += ldw1 * A0;
+                    if constexpr (D == 3) {
+                        Bp[a][2] += (lw * dd[2][kz]) * A0;
+                        Lp[a][2] += (w[1][ky] * dw[2][kz]) * A0;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // pass 2: X1 = sum grad phi (m_i + (x_i - x_p).(Cp^T p_i)) and
+            // X2 = sum Hess(phi) (S_p p_i); per node s_i and sp_i = S_p p_i,
+            // per line the x-reductions
+            //   A = sum s dw_x, B = sum s w_x, C1 = sum sp_x ddw_x,
+            //   C2 = sum sp_y dw_x, C3 = sum sp_z dw_x, C4 = sum sp_x dw_x,
+            //   C5 = sum sp_y w_x, C6 = sum sp_z w_x
 #pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) {
-                        int kk[3] = {kx, ky, kz};
-                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
-                        T phi = T(1), gr[D];
+            for (int l = 0; l < NL; ++l) {
+                const int ky = l % 3, kz = l / 3;
+                const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
+                T A = T(0), B = T(0), Cx[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
-                        for (int a = 0; a < D; ++a) phi *= w[a][kk[a]];
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int n = n0 + kx;
+                    T pb[D];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) pb[a] = s_p[a][n];
+                    T sc = s_m[n], sp[D];
+                    const T ddn[3] = {dd[0][kx], dd[1][ky], (D == 3) ? dd[D - 1][kz] : T(0)};
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        T ub = T(0), sb = T(0);
 #pragma unroll
                         for (int a = 0; a < D; ++a) {
-                            T gg = dw[a][kk[a]];
-#pragma unroll
-                            for (int b = 0; b < D; ++b)
-                                if (b != a) gg *= w[b][kk[b]];
-                            gr[a] = gg;
+                            ub += Cp[a][b] * pb[a];
+                            sb += Sp[b][a] * pb[a];
                         }
-#pragma unroll
-                        for (int a = 0; a < D; ++a) {
-                            T pa = s_p[a][n];
-                            T fp = phi * pa;
-                            V[a] += fp;
-#pragma unroll
-                            for (int b = 0; b < D; ++b) {
-                                Bp[a][b] += fp * dd[b][kk[b]];
-                                Lp[a][b] += pa * gr[b];
-                            }
-                        }
+                        sp[b] = sb;
+                        sc += ddn[b] * ub;
                     }
-            // keep the two passes apart so that their live ranges do not overlap
-            __builtin_amdgcn_sched_barrier(0);
-            // pass 2: terms through the weights' derivatives
-#pragma unroll
-            for (int kz = 0; kz < KZ; ++kz)
-#pragma unroll
-                for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) {
-                        int kk[3] = {kx, ky, kz};
-                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
-                        T phi, gr[D], H[D][D];
-                        node_grad_hess<T, D>(w, dw, kk, inv2, phi, gr, H);
-                        T pb[D];
-#pragma unroll
-                        for (int a = 0; a < D; ++a) pb[a] = s_p[a][n];
-                        T sc = s_m[n], sp[D];
-#pragma unroll
-                        for (int b = 0; b < D; ++b) {
-                            T ub = T(0), sb = T(0);
-#pragma unroll
-                            for (int a = 0; a < D; ++a) {
-                                ub += Cp[a][b] * pb[a];
-                                sb += Sp[b][a] * pb[a];
-                            }
-                            sp[b] = sb;
-                            sc += dd[b][kk[b]] * ub;
-                        }
-#pragma unroll
-                        for (int c = 0; c < D; ++c) {
-                            X1[c] += sc * gr[c];
-                            T h = T(0);
-#pragma unroll
-                            for (int b = 0; b < D; ++b) h += sp[b] * H[b][c];
-                            X2[c] += h;
-                        }
+                    A += sc * dw[0][kx];
+                    B += sc * w[0][kx];
+                    Cx[0] += sp[0] * ddw[kx];
+                    Cx[1] += sp[1] * dw[0][kx];
+                    Cx[3] += sp[0] * dw[0][kx];
+                    Cx[4] += sp[1] * w[0][kx];
+                    if constexpr (D == 3) {
+                        Cx[2] += sp[D - 1] * dw[0][kx];
+                        Cx[5] += sp[D - 1] * w[0][kx];
                     }
+                }
+                if constexpr (D == 3) {
+                    const T wy = w[1][ky], dwy = dw[1][ky], wz = w[2][kz], dwz = dw[2][kz];
+                    X1[0] += wy * wz * A;
+                    X1[1] += dwy * wz * B;
+                    X1[2] += wy * dwz * B;
+                    X2[0] += wy * wz * Cx[0] + dwy * wz * Cx[1] + wy * dwz * Cx[2];
+                    X2[1] += dwy * wz * Cx[3] + ddw[ky] * wz * Cx[4] + dwy * dwz * Cx[5];
+                    X2[2] += wy * dwz * Cx[3] + dwy * dwz * Cx[4] + wy * ddw[kz] * Cx[5];
+                } else {
+                    const T wy = w[1][ky], dwy = dw[1][ky];
+                    X1[0] += wy * A;
+                    X1[1] += dwy * B;
+                    X2[0] += wy * Cx[0] + dwy * Cx[1];
+                    X2[1] += dwy * Cx[3] + ddw[ky] * Cx[4];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
             T xbar[D], vbar[D], Cbar[D][D], Sbar[D][D];
 #pragma unroll
             for (int c = 0; c < D; ++c) {
