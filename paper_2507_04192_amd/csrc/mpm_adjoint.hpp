@@ -23,40 +23,6 @@ namespace mpm {
 
 constexpr int kAdjBlock = 128;   // threads of the reverse per-tile kernels
 
-// Second derivative of the quadratic B-spline weights (per unit length^2):
-// +1, -2, +1 for the three nodes.
-template <class T>
-__device__ __forceinline__ T ddw_of(int k, T inv2) { return (k == 1) ? T(-2) * inv2 : inv2; }
-
-// Stencil terms of one node: phi, grad phi and d(grad phi)/dx.
-template <class T, int D>
-__device__ __forceinline__ void node_grad_hess(const T w[D][3], const T dw[D][3], const int k[3], T inv2, T& phi,
-                                               T gr[D], T H[D][D])
-{
-    phi = T(1);
-#pragma unroll
-    for (int a = 0; a < D; ++a) phi *= w[a][k[a]];
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            T h = T(1);
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                if (b == a && b == c) h *= ddw_of<T>(k[b], inv2);
-                else if (b == a || b == c) h *= dw[b][k[b]];
-                else h *= w[b][k[b]];
-            }
-            H[a][c] = h;
-        }
-        T gg = dw[a][k[a]];
-#pragma unroll
-        for (int b = 0; b < D; ++b)
-            if (b != a) gg *= w[b][k[b]];
-        gr[a] = gg;
-    }
-}
-
 // Per-slot intermediate of the reverse sweep (mid), component-major with
 // stride cap:
 //   [0, D)              position adjoint (partial after k_g2p_adj_cons,
@@ -242,45 +208,100 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, co
                     Lb[a][b] = mid[(ML::LB + a * D + b) * cap + s];
                 }
             }
-            constexpr int KZ = (D == 3) ? 3 : 1;
+            // Line by line along x (per-axis weight factors).  Node adjoint of
+            // the velocity, scattered:
+            //   phi (vt + Dinv Cb dd) + Lb grad phi = w_x U + w_x dd_x V + dw_x W.
+            // Position adjoint, gathered with u = Cb^T v_i, g = Lb^T v_i,
+            // wbar = v_i.vt + Dinv dd.u:
+            //   xbar += sum wbar grad phi + sum Hess(phi) g - Dinv Cb^T vn,
+            // vn = sum phi v_i (the forward G2P velocity).
+            constexpr int NL = (D == 3) ? 9 : 3;
+            const T ddw[3] = {inv2, T(-2) * inv2, inv2};
+            T X1[D], X2[D], vn[D];
 #pragma unroll
-            for (int kz = 0; kz < KZ; ++kz)
+            for (int a = 0; a < D; ++a) { X1[a] = T(0); X2[a] = T(0); vn[a] = T(0); }
 #pragma unroll
-                for (int ky = 0; ky < 3; ++ky)
+            for (int l = 0; l < NL; ++l) {
+                const int ky = l % 3, kz = l / 3;
+                const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
+                const T wy = w[1][ky], dwy = dw[1][ky];
+                const T wz = (D == 3) ? w[D - 1][kz] : T(1), dwz = (D == 3) ? dw[D - 1][kz] : T(0);
+                const T ddz = (D == 3) ? dd[D - 1][kz] : T(0);
+                const T wyz = wy * wz;
+                T U[D], V[D], Wl[D];
 #pragma unroll
-                    for (int kx = 0; kx < 3; ++kx) {
-                        int kk[3] = {kx, ky, kz};
-                        int n = block_node<D>(lb, (kz * 3 + ky) * 3 + kx);
-                        T phi, gr[D], H[D][D];
-                        node_grad_hess<T, D>(w, dw, kk, inv2, phi, gr, H);
-                        T wbar = T(0), dbar[D], gbar[D];
+                for (int a = 0; a < D; ++a) {
+                    T u = vt[a] + P.Dinv * Cb[a][1] * dd[1][ky];
+                    if constexpr (D == 3) u += P.Dinv * Cb[a][D - 1] * ddz;
+                    u = wyz * u + Lb[a][1] * dwy * wz;
+                    if constexpr (D == 3) u += Lb[a][D - 1] * wy * dwz;
+                    U[a] = u;
+                    V[a] = wyz * P.Dinv * Cb[a][0];
+                    Wl[a] = wyz * Lb[a][0];
+                }
+                T A = T(0), B = T(0), VN[D], Cx[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
-                        for (int b = 0; b < D; ++b) { dbar[b] = T(0); gbar[b] = T(0); }
+                for (int a = 0; a < D; ++a) VN[a] = T(0);
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int n = n0 + kx;
+                    const T ddn[3] = {dd[0][kx], dd[1][ky], ddz};
+                    T vi[D];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        vi[a] = s_v[a][n];
+                        T nbv = w[0][kx] * U[a] + w[0][kx] * dd[0][kx] * V[a] + dw[0][kx] * Wl[a];
+                        atomicAdd(&s_b[a][n], (double)nbv);
+                    }
+                    T wbar = T(0), gq[D];
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        T ub = T(0), gb = T(0);
 #pragma unroll
                         for (int a = 0; a < D; ++a) {
-                            T vi = s_v[a][n];
-                            T cd = T(0), lg = T(0);
-#pragma unroll
-                            for (int b = 0; b < D; ++b) {
-                                cd += Cb[a][b] * dd[b][kk[b]];
-                                lg += Lb[a][b] * gr[b];
-                                dbar[b] += P.Dinv * phi * Cb[a][b] * vi;
-                                gbar[b] += Lb[a][b] * vi;
-                            }
-                            T nbv = phi * (vt[a] + P.Dinv * cd) + lg;
-                            atomicAdd(&s_b[a][n], (double)nbv);
-                            wbar += vi * (vt[a] + P.Dinv * cd);
+                            ub += Cb[a][b] * vi[a];
+                            gb += Lb[a][b] * vi[a];
                         }
-#pragma unroll
-                        for (int c = 0; c < D; ++c) {
-                            T t = wbar * gr[c] - dbar[c];
-#pragma unroll
-                            for (int b = 0; b < D; ++b) t += gbar[b] * H[b][c];
-                            xbar[c] += t;
-                        }
-                        // one node at a time: bounds the registers in flight
-                        __builtin_amdgcn_sched_barrier(0);
+                        gq[b] = gb;
+                        wbar += vi[b] * vt[b] + P.Dinv * ddn[b] * ub;
                     }
+                    A += wbar * dw[0][kx];
+                    B += wbar * w[0][kx];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) VN[a] += vi[a] * w[0][kx];
+                    Cx[0] += gq[0] * ddw[kx];
+                    Cx[1] += gq[1] * dw[0][kx];
+                    Cx[3] += gq[0] * dw[0][kx];
+                    Cx[4] += gq[1] * w[0][kx];
+                    if constexpr (D == 3) {
+                        Cx[2] += gq[D - 1] * dw[0][kx];
+                        Cx[5] += gq[D - 1] * w[0][kx];
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < D; ++a) vn[a] += wyz * VN[a];
+                if constexpr (D == 3) {
+                    X1[0] += wyz * A;
+                    X1[1] += dwy * wz * B;
+                    X1[2] += wy * dwz * B;
+                    X2[0] += wyz * Cx[0] + dwy * wz * Cx[1] + wy * dwz * Cx[2];
+                    X2[1] += dwy * wz * Cx[3] + ddw[ky] * wz * Cx[4] + dwy * dwz * Cx[5];
+                    X2[2] += wy * dwz * Cx[3] + dwy * dwz * Cx[4] + wy * ddw[kz] * Cx[5];
+                } else {
+                    X1[0] += wy * A;
+                    X1[1] += dwy * B;
+                    X2[0] += wy * Cx[0] + dwy * Cx[1];
+                    X2[1] += dwy * Cx[3] + ddw[ky] * Cx[4];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T t = X1[c] + X2[c];
+#pragma unroll
+                for (int a = 0; a < D; ++a) t -= P.Dinv * Cb[a][c] * vn[a];
+                xbar[c] += t;
+            }
 #pragma unroll
             for (int a = 0; a < D; ++a) mid[(ML::X + a) * cap + s] = xbar[a];
         }
