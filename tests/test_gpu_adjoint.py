@@ -319,35 +319,48 @@ def test_friction_inverse_full_size_finite_differences():
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("fscale", [2e-3, 3e-2])
-def test_return_mapping_gradient_from_random_state(orc, precision, fscale):
-    """Three steps of 3-D sand from a random state (F, C and stress random):
-    the gradient flows through every case of the return (apex, elastic,
-    cone).  At the small strain scale the kernels take the series form of
-    the return and of its reverse, at the large one the eigen form."""
+@pytest.mark.parametrize("material,fscale", [(W.SAND, 2e-3), (W.SAND, 3e-2), (W.ELASTIC, 2e-3),
+                                             (W.ELASTIC, 3e-2), (W.FLUID, 0.0)])
+def test_return_mapping_gradient_from_random_state(orc, precision, material, fscale):
+    """Three steps from a random state (F or J, C and stress random): for
+    sand the gradient flows through every case of the return (apex,
+    elastic, cone), for the elastic material through the plain Hencky
+    stress, for the fluid through the equation of state.  At the small
+    strain scale the kernels take the series form of the return and of its
+    reverse, at the large one the eigen form."""
     from paper_2507_04192_amd.native import Solver
-    cfg = W.SimConfig(dim=3, n=(20, 16, 12), dx=0.01, dt=1e-5, material=W.SAND, ppc=8,
+    cfg = W.SimConfig(dim=3, n=(20, 16, 12), dx=0.01, dt=1e-5, material=material, ppc=8,
                       gravity=(0, 0, -9.81), youngs=1e6, rho0=1500.0,
                       wall_mode=(W.SLIP, W.STICK, W.SLIP, W.SLIP, W.COULOMB, W.SLIP),
                       wall_mu=(0, 0, 0, 0, 0.4, 0))
     N = 3001
-    x, v, C, G = W.random_state(cfg, N, 52, vscale=0.5, cscale=5.0, fscale=fscale, margin=2.0)
+    x, v, C, G = W.random_state(cfg, N, 52, vscale=0.5, cscale=5.0, fscale=max(fscale, 1e-3), margin=2.0)
     rng = np.random.default_rng(53)
     S = rng.normal(0, 1e-3, size=(3, 3, N))
     S = (S + S.transpose(1, 0, 2)).reshape(9, N)
+    Jm1 = None
+    if material == W.FLUID:
+        S = np.repeat(np.eye(3).reshape(9, 1), N, axis=1) * rng.normal(0, 1e-3, size=N)
+        Jm1 = rng.normal(0, 1e-3, size=N)
+        G = None
     if precision == "f32":
-        x, v, C, G, S = (a.astype(np.float32).astype(np.float64) for a in (x, v, C, G, S))
+        x, v, C, S = (a.astype(np.float32).astype(np.float64) for a in (x, v, C, S))
+        G = None if G is None else G.astype(np.float32).astype(np.float64)
+        Jm1 = None if Jm1 is None else Jm1.astype(np.float32).astype(np.float64)
     steps, frames = 3, [1, 2, 3]
     tr = W.pick_tracers(N, 300, 54)
     tgt = rng.normal(0, 0.3, size=(3, 3, 300)).astype(np.float32).astype(np.float64)
-    print(f"[case] return-mapping gradient {precision} fscale={fscale} N={N}", flush=True)
-    st0 = oracle_state(orc, cfg, x, v=v, C=C, G=G, S=S)
+    print(f"[case] return-mapping gradient {material} {precision} fscale={fscale} N={N}", flush=True)
+    st0 = oracle_state(orc, cfg, x, v=v, C=C, G=G, S=S, Jm1=Jm1)
     obs_o = orc.Observations(frames, tr, "v", tgt)
     loss_o, gv_o, _ = orc.rollout_grad(cfg, x, v, steps, cfg.dt, None, obs_o, state0=st0)
     s = Solver(cfg, precision, capacity=N, tape_steps=steps, ckpt_every=2)
     s.mpm_init_particles(x, v)
     s.mpm_write_state("C", C, "pid")
-    s.mpm_write_state("FmI", G, "pid")
+    if G is not None:
+        s.mpm_write_state("FmI", G, "pid")
+    if Jm1 is not None:
+        s.mpm_write_state("Jm1", np.asarray(Jm1).reshape(1, -1), "pid")
     s.mpm_write_state("stress", S, "pid")
     s.mpm_set_observations(frames=frames, tracer_pid=tr, lag_field="v", lag_target=tgt)
     loss = s.mpm_forward_loss(steps)
