@@ -107,7 +107,9 @@ int mpm_create(const mpm_config* cfg, void* hip_stream, mpm_ctx** out);
 
 /* Device bytes needed for n_particles and, if tape_steps > 0, for a
  * forward-plus-adjoint rollout of tape_steps steps checkpointed every
- * ckpt_every steps (Sec. 3.3: memory O(N_t / n) per segment). */
+ * ckpt_every steps (Sec. 3.3: memory O(N_t / n) per segment): one state per
+ * checkpoint, a tape of ckpt_every + 1 states, and a grid tape holding each
+ * step of a segment's sort and nodal mass and velocities. */
 int mpm_workspace_bytes(const mpm_config* cfg, int64_t n_particles, int32_t tape_steps,
                         int32_t ckpt_every, size_t* bytes);
 
@@ -188,13 +190,18 @@ int mpm_set_observations(mpm_ctx* ctx, const mpm_obs* obs);
  * current particle velocities and the floor friction set by
  * mpm_set_floor_mu), storing a checkpoint every ckpt_every steps (the values
  * given to mpm_bind_workspace; n_steps <= its tape_steps) and accumulating
- * the loss of the observations in binary64.  Synchronizes; *host_loss gets
- * the loss.  The state afterwards is the state after n_steps. */
+ * the loss of the observations in binary64.  The last segment runs directly
+ * on the tape, so that the first mpm_backward after it need not recompute
+ * it.  Synchronizes; *host_loss gets the loss.  The state, sort and grid
+ * afterwards are those after n_steps, as after mpm_step(n_steps). */
 int mpm_forward_loss(mpm_ctx* ctx, int32_t n_steps, double dt, double* host_loss);
 
 /* Gradient of the last mpm_forward_loss by the hand-written reverse sweep:
- * each segment between checkpoints is recomputed, then every step is
- * reversed (constitutive update, G2P, walls, grid, P2G, sort).  grad_v0
+ * each segment between checkpoints is recomputed (the grid of each step is
+ * kept on the grid tape), then every step is reversed (constitutive update,
+ * G2P, walls, grid, P2G, sort).  May be called again for the same rollout:
+ * node adjoints are summed with atomics, so repeated calls agree to rounding,
+ * not bit for bit.  grad_v0
  * (device [dim][n], pid order) receives dL/dv of the rollout's initial
  * state, grad_mu (device, floor layout of mpm_set_floor_mu) dL/dmu per floor
  * node (zero without a friction field).  Either may be NULL.  Synchronizes.
