@@ -43,7 +43,7 @@ typedef enum mpm_status {
     MPM_ENOMEM = -2,      /* workspace missing or too small */
     MPM_EHIP = -3,        /* a HIP runtime call or launch failed */
     MPM_ENONFINITE = -4,  /* a particle's state became NaN or Inf */
-    MPM_EDOMAIN = -5,     /* reserved: particle outside the padded grid */
+    MPM_EDOMAIN = -5,     /* a particle moved more than one cell in a step (CFL) */
     MPM_ESTATE = -6       /* call made in the wrong order */
 } mpm_status;
 
@@ -135,12 +135,14 @@ int mpm_set_floor_mu(mpm_ctx* ctx, const void* mu, int64_t count);
 /* Advances n steps of size dt (Sec. 2.2, USL): per step the particles are
  * sorted by cell key, P2G, grid update with gravity and walls, G2P with the
  * velocity gradient, then the constitutive update.  Asynchronous; data errors
- * (non-finite state) are latched and reported by mpm_sync_status. */
+ * (non-finite state, a particle moving more than one cell in a step) are
+ * latched and reported by mpm_sync_status. */
 int mpm_step(mpm_ctx* ctx, int32_t n, double dt);
 
-/* Synchronizes the stream and returns the latched data status (MPM_OK or
- * MPM_ENONFINITE); *bad_pid (may be NULL) gets the smallest offending pid or
- * -1.  Clears the latch. */
+/* Synchronizes the stream and returns the latched data status: MPM_OK,
+ * MPM_ENONFINITE (checked first) or MPM_EDOMAIN (|v| dt > dx on an axis:
+ * the step violates the CFL condition); *bad_pid (may be NULL) gets the
+ * smallest offending pid or -1.  Clears the latch. */
 int mpm_sync_status(mpm_ctx* ctx, int64_t* bad_pid);
 
 /* Copies a particle field to dst (device; int32 for PID), in memory order or

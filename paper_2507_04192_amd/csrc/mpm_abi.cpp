@@ -350,15 +350,20 @@ int mpm_sync_status(mpm_ctx* c, int64_t* bad_pid)
     if (bad_pid) *bad_pid = -1;
     rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     if (rc) return rc;
-    int32_t h[2];
+    int32_t h[3];
     rc = hip_check(c, hipMemcpy(h, c->status, sizeof(h), hipMemcpyDeviceToHost), "status read");
     if (rc) return rc;
-    int32_t clear[2] = {0, 0x7fffffff};
+    int32_t clear[3] = {0, 0x7fffffff, 0x7fffffff};
     rc = hip_check(c, hipMemcpy(c->status, clear, sizeof(clear), hipMemcpyHostToDevice), "status clear");
     if (rc) return rc;
     if (h[0] & 1) {
         if (bad_pid) *bad_pid = h[1];
         return set_err(c, MPM_ENONFINITE, "non-finite particle state (pid " + std::to_string(h[1]) + ")");
+    }
+    if (h[0] & 2) {
+        if (bad_pid) *bad_pid = h[2];
+        return set_err(c, MPM_EDOMAIN, "a particle moved more than one cell in a step (pid " + std::to_string(h[2]) +
+                                           "): the time step violates the CFL condition");
     }
     return MPM_OK;
 }

@@ -745,12 +745,13 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
-                bool bad = false;
+                bool bad = false, fast = false;
                 T xn[D];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     T xv = xp[a] + P.dt * vn[a];
                     bad |= !finite(xv) || !finite(vn[a]);
+                    fast |= fabs(P.dt * vn[a]) > P.h;   // moved more than a cell: CFL violated
                     xv = fmin(fmax(xv, T(0)), P.ext[a]);
                     xn[a] = xv;
                     nxt.x[a * cap + s] = xv;
@@ -786,6 +787,10 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                 if (bad) {
                     atomicOr(&status[0], 1);
                     atomicMin(&status[1], pid);
+                }
+                if (fast) {
+                    atomicOr(&status[0], 2);
+                    atomicMin(&status[2], pid);
                 }
                 newkey = cell_key<T, D>(g, xn, P.inv);
                 key_out[s] = newkey;
@@ -1002,7 +1007,7 @@ struct Solver {
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gv, D * NN, T(0));
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gmass, NN, T(0));
         k_fill<int><<<1, kBlock, 0, st>>>(c->status, 16, 0);
-        k_fill<int><<<1, kBlock, 0, st>>>(c->status + 1, 1, 0x7fffffff);
+        k_fill<int><<<1, kBlock, 0, st>>>(c->status + 1, 2, 0x7fffffff);
         return launch_err(c, "clear grid");
     }
 

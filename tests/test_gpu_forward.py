@@ -244,6 +244,25 @@ def test_empty_and_nan(orc):
     assert s.mpm_sync_status()[0] == 0      # latch cleared
 
 
+def test_cfl_violation_is_reported():
+    """A step in which particles move more than one cell is latched as
+    EDOMAIN with the smallest such particle id; a normal step is not."""
+    cfg, x = W.dam_break_2d()
+    s = gpu_solver(cfg, "f64", x)
+    s.mpm_step(2)
+    assert s.mpm_sync_status()[0] == 0
+    v = s.mpm_read_state("v", "pid")
+    v[0, :] = 2.5 * cfg.dx / cfg.dt
+    s.mpm_write_state("v", v, "pid")
+    s.mpm_step(1)
+    rc, bad = s.mpm_sync_status()
+    assert rc == -5
+    vn = _np(s.mpm_read_state("v", "pid"))
+    fast = np.where((np.abs(vn) * cfg.dt > cfg.dx).any(axis=0))[0]
+    assert len(fast) > 0 and bad == fast.min()
+    assert s.mpm_sync_status()[0] == 0      # latch cleared
+
+
 def test_read_write_round_trip(orc):
     cfg, x = _small_3d()
     s = gpu_solver(cfg, "f64", x)
