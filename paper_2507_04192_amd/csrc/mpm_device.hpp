@@ -429,11 +429,12 @@ __device__ __forceinline__ Sym<T, 2> cI_plus_AB(T c, const Sym<T, 2>& A, const S
 
 // Truncated series for the matrix functions of a small symmetric argument:
 // log(I + X) = sum_k (-1)^(k+1) X^k / k and exp(Y) - I = sum_k Y^k / k!, by
-// Horner's rule.  Used when |X|_F, |Y|_F < kMax: the remainder is then below
-// the working precision relative to the result (float: 0.02^6/6 and
-// 0.02^5/5!; double: 0.01^10/10 and 0.01^8/8!).
+// Horner's rule.  Used when |X|_F, |Y|_F < kMax: the first omitted term,
+// relative to the result, is then at or below the unit roundoff (float:
+// 0.02^4/5 = 3.2e-8 for log with kLog = 4, 0.02^4/5! = 1.3e-9 for exp;
+// double: 0.01^9/10 = 1e-19 and 0.01^7/8! = 2.5e-19).
 template <class T> struct Series;
-template <> struct Series<float> { static constexpr float kMax = 0.02f; static constexpr int kLog = 5, kExp = 4; };
+template <> struct Series<float> { static constexpr float kMax = 0.02f; static constexpr int kLog = 4, kExp = 4; };
 template <> struct Series<double> { static constexpr double kMax = 0.01; static constexpr int kLog = 9, kExp = 7; };
 
 template <class T, int D>
