@@ -293,3 +293,34 @@ def test_step_is_deterministic(orc, precision):
         out.append({f: _np(s.mpm_read_state(f, "memory")) for f in ("x", "v", "C", "FmI", "stress", "pid")})
     for f in out[0]:
         assert np.array_equal(out[0][f], out[1][f]), f
+
+
+@pytest.mark.parametrize("case", ["cylinder", "dambreak3d"])
+def test_full_size_steps_match_oracle(orc, case):
+    """Full-size workloads in the launch configuration the bench times: the
+    3-D cylinder collapse (2,780,928 particles, Drucker-Prager sand) and the
+    3-D dam-break of the friction problem (1,843,200 particles, fluid).
+    Three steps in binary64 and binary32 against one oracle run from the
+    same binary32-rounded input, whole arrays compared."""
+    from paper_2507_04192_amd.native import Solver
+    cfg, x = (W.cylinder_collapse_3d(scale_div=1, seed=0) if case == "cylinder" else W.dam_break_3d())
+    x = x.astype(np.float32).astype(np.float64)
+    N = x.shape[1]
+    steps = 3
+    print(f"[case] full size {case} N={N}, {steps} steps (oracle first)", flush=True)
+    o = orc.Oracle(cfg)
+    st = orc.State(cfg, x)
+    o.run(st, steps, cfg.dt)
+    xr, vr = st.by_pid("x"), st.by_pid("v")
+    for precision in ("f64", "f32"):
+        s = Solver(cfg, precision, capacity=N)
+        s.mpm_init_particles(x)
+        s.mpm_step(steps)
+        rc, bad = s.mpm_sync_status()
+        assert rc == 0, bad
+        xg = s.mpm_read_state("x", "pid").cpu().numpy()
+        vg = s.mpm_read_state("v", "pid").cpu().numpy()
+        s.close()
+        ex, ev = rel_l2(xg, xr), rel_l2(vg, vr)
+        print(f"  {precision}: rel L2 x={ex:.3e} v={ev:.3e}", flush=True)
+        assert ex <= TOL[precision] and ev <= TOL[precision]
