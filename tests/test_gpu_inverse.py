@@ -2,9 +2,9 @@
 solver's adjoint on observations that a ground-truth run of the solver
 generates (Sec. 3.2 parameter forms; Sec. 5 inverse problems).
 
-Both forms are fitted by Adam to the same loss from the same data; the
-forward solver is the judge of neither, the hidden field is: the tests
-compare each estimate with the seeded ground-truth field.  The network's
+Both forms are fitted by Adam to the same loss from the same data, and
+each estimate is scored against the seeded ground-truth field, not
+against the loss.  The network's
 gain is its smoothness: the table fits the observations more tightly (lower
 loss) but is piecewise constant, the network recovers the field better."""
 import pytest
