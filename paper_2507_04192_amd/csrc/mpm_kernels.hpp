@@ -38,6 +38,9 @@ constexpr int kP2GBlock = 64;    // threads of a P2G workgroup (one wave per til
 constexpr int kP2GWGs = kTileWGs * kBlock / kP2GBlock;
 // threads of a G2P workgroup (binary64: smaller groups, measured faster)
 template <class T> constexpr int kG2PBlock = sizeof(T) == 8 ? 128 : 256;
+// G2P loads the next tile's node block while it works on the current one
+// (binary64: measured faster; binary32: slower)
+template <class T> constexpr bool kG2PPrefetch = sizeof(T) == 8;
 constexpr int kGridBlock = 128;  // threads of a grid-update workgroup
 
 // Active-list entry handled by this workgroup on iteration `it`.  Workgroup b
@@ -237,11 +240,6 @@ __device__ __forceinline__ int wave_tile_entry(int it, int n_active, int w)
     return e < end ? e : -1;
 }
 
-// One particle's P2G contribution (eq:update_m, the momentum with the APIC
-// affine term of App. B, and the internal force -dt V_p sigma_p grad phi):
-// for each of the 3^D stencil nodes, sink(k, n, add) receives the offset
-// index k, the node's index n in the tile's LDS block and the D+1 values
-// (mass, momentum) to add there.
 // The state of one particle that P2G reads.
 template <class T, int D, int MAT>
 struct P2GIn {
@@ -262,6 +260,19 @@ struct P2GIn {
     }
 };
 
+// One particle's P2G contribution (eq:update_m, the momentum with the APIC
+// affine term of App. B, and the internal force -dt V_p sigma_p grad phi).
+// Every weight factors over the axes, so per node line along x the terms
+// that do not depend on x are formed once.  With wyz = w_y w_z (2-D: w_y),
+// the values at node (kx, line) are
+//   mass  w_x mw,                              mw  = m_p wyz,
+//   P_a   w_x U_a + (w_x dd_x) V_a + dw_x W_a,
+//   U_a = wyz (m v_a + sum_{b>0} mC_ab dd_b) + sum_{b>0} fs_ab (grad phi_b / w_x),
+//   V_a = wyz mC_a0,  W_a = wyz fs_a0.
+// For each of the 3^D stencil nodes, sink(k, n, fx, mw, U, V, W) receives
+// the offset index k, the node's index n in the tile's LDS block, the x
+// factors fx = (w_x, w_x dd_x, dw_x) and the line terms; p2g_node_values
+// forms the D+1 values from them.
 template <class T, int D, int MAT, class Sink>
 __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D, MAT>& in, const int lb[3],
                                              const int gb[3], Sink&& sink)
@@ -304,18 +315,19 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
             fs[0][1] = fs[1][0] = -P.dt * s2;
         }
     }
-    // Every weight factors over the axes: per node line along x the terms
-    // that do not depend on x are formed once.  With wyz = w_y w_z (2-D:
-    // w_y), momentum component a at node (kx, line) is
-    //   w_x U_a + w_x dd_x V_a + dw_x W_a,
-    //   U_a = wyz (m v_a + sum_{b>0} mC_ab dd_b) + sum_{b>0} fs_ab (grad phi_b / w_x),
-    //   V_a = wyz mC_a0,  W_a = wyz fs_a0.
-    T wdx[3];
+    T fx[3][3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) wdx[q] = w[0][q] * dd[0][q];
+    for (int q = 0; q < 3; ++q) {
+        fx[q][0] = w[0][q];
+        fx[q][1] = w[0][q] * dd[0][q];
+        fx[q][2] = dw[0][q];
+    }
     constexpr int KZ = (D == 3) ? 3 : 1;
 #pragma unroll
-    for (int kz = 0; kz < KZ; ++kz)
+    for (int kz = 0; kz < KZ; ++kz) {
+        T mvz[D];   // m v_a + mC_a2 dd_z: the part of the affine term fixed on a z plane
+#pragma unroll
+        for (int a = 0; a < D; ++a) mvz[a] = (D == 3) ? mv[a] + mC[a][D - 1] * dd[D - 1][kz] : mv[a];
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
             T wyz = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
@@ -324,8 +336,7 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
             T U[D], V[D], Wf[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                T aff = mv[a] + mC[a][1] * dd[1][ky];
-                if constexpr (D == 3) aff += mC[a][2] * dd[2][kz];
+                T aff = mvz[a] + mC[a][1] * dd[1][ky];
                 T u = wyz * aff + fs[a][1] * g1;
                 if constexpr (D == 3) u += fs[a][2] * g2;
                 U[a] = u;
@@ -338,13 +349,21 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
                 int n;
                 if constexpr (D == 3) n = ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
                 else n = (lb[1] + ky) * BE + lb[0] + kx;
-                T add[D + 1];
-                add[0] = w[0][kx] * mw;
-#pragma unroll
-                for (int a = 0; a < D; ++a) add[1 + a] = w[0][kx] * U[a] + wdx[kx] * V[a] + dw[0][kx] * Wf[a];
-                sink((kz * 3 + ky) * 3 + kx, n, add);
+                sink((kz * 3 + ky) * 3 + kx, n, fx[kx], mw, U, V, Wf);
             }
         }
+    }
+}
+
+// The D+1 values (mass, momentum) a particle adds at one node, from the
+// factors p2g_particle hands to its sink.
+template <class T, int D>
+__device__ __forceinline__ void p2g_node_values(const T fx[3], T mw, const T U[D], const T V[D], const T W[D],
+                                                T add[D + 1])
+{
+    add[0] = fx[0] * mw;
+#pragma unroll
+    for (int a = 0; a < D; ++a) add[1 + a] = fx[0] * U[a] + fx[1] * V[a] + fx[2] * W[a];
 }
 
 // Node index in the tile's LDS block of stencil offset k for a lane whose
@@ -383,8 +402,10 @@ __device__ __forceinline__ int rank_major_pos(int c, int q, const unsigned long 
 // for r = w, w+4, ... (the lanes of a round read adjacent slots); (3) writes
 // the sum of the waves' node blocks (mass, momentum), in wave order, to the
 // tile's partial block.
+// Two waves per SIMD (at most 256 registers per lane, binary32 included,
+// whose 27 x 4 register sums sit close to that limit).
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kP2GBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, int* __restrict__ tmp,
                                                 const int* __restrict__ tmpk, PView<T> cur, int* __restrict__ perm,
                                                 T* __restrict__ part)
@@ -397,6 +418,7 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
     __shared__ T s_node[NBLK][D + 1][NB];
     __shared__ int s_cnt[64], s_off[64], s_cur[64];
     __shared__ int s_unord[kSortCap], s_sorted[kSortCap];
+    __shared__ unsigned char s_ucell[kSortCap];
     __shared__ int s_max;
     __shared__ unsigned long long s_rmask[64];
     __shared__ int s_roff[64];
@@ -410,8 +432,27 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
         if (tid < 64) { s_cnt[tid] = 0; s_cur[tid] = 0; }
         __syncthreads();
         const bool in_lds = at.cnt <= kSortCap;
-        // cell histogram; the cell of a particle is the low 6 bits of its key
-        for (int k = tid; k < at.cnt; k += kP2GBlock) atomicAdd(&s_cnt[tmpk[at.off + k] & 63], 1);
+        // A tile that fits in LDS keeps its particles' cells and slots in
+        // registers (lane l holds entries l, l + 64, ...): one batch of global
+        // loads instead of one round trip per pass below.
+        constexpr int KPL = kSortCap / kP2GBlock;
+        const int nk = at.cnt - tid;                 // entry i * 64 of this lane exists if below
+        const int* tk = tmpk + at.off + tid;
+        const int* tj = tmp + at.off + tid;
+        int rc[KPL], rj[KPL];
+        if (in_lds) {
+#pragma unroll
+            for (int i = 0; i < KPL; ++i)
+                if (i * kP2GBlock < nk) {
+                    rc[i] = tk[i * kP2GBlock] & 63;   // the cell is the low 6 bits of the key
+                    rj[i] = tj[i * kP2GBlock];
+                }
+#pragma unroll
+            for (int i = 0; i < KPL; ++i)
+                if (i * kP2GBlock < nk) atomicAdd(&s_cnt[rc[i]], 1);
+        } else {
+            for (int k = tid; k < at.cnt; k += kP2GBlock) atomicAdd(&s_cnt[tmpk[at.off + k] & 63], 1);
+        }
         __syncthreads();
         if (tid < 64) {
             int v = s_cnt[lane], inc = v, mx = v;
@@ -436,31 +477,48 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
             }
         }
         __syncthreads();
-        // place each particle in its cell's range (arbitrary order inside)
-        int* unord = in_lds ? s_unord : (perm + at.off);
-        for (int k = tid; k < at.cnt; k += kP2GBlock) {
-            int c = tmpk[at.off + k] & 63;
-            int pos = atomicAdd(&s_cur[c], 1);
-            unord[s_off[c] + pos] = tmp[at.off + k];
-        }
-        if (!in_lds) __threadfence_block();
-        __syncthreads();
         if (in_lds) {
-            // rank inside the cell by previous slot: a stable order
-            for (int k = tid; k < at.cnt; k += kP2GBlock) {
-                int c = tmpk[at.off + k] & 63;
-                int j = tmp[at.off + k];
-                int o = s_off[c], n = s_cnt[c], rank = 0;
-                for (int q = 0; q < n; ++q) rank += unord[o + q] < j;
+            // place each particle in its cell's range (arbitrary order inside)
+            // and note the cell of each position; then rank every particle
+            // inside its cell by previous slot: a stable order
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                if (i * kP2GBlock >= nk) continue;
+                const int u = s_off[rc[i]] + atomicAdd(&s_cur[rc[i]], 1);
+                s_unord[u] = rj[i];
+                s_ucell[u] = (unsigned char)rc[i];
+            }
+            __syncthreads();
+            for (int u = tid; u < at.cnt; u += kP2GBlock) {
+                const int c = s_ucell[u], j = s_unord[u];
+                const int o = s_off[c], n = s_cnt[c], last = o + n - 1;
+                int rank = 0;
+                // four independent LDS reads per pass; reads past the cell's
+                // range repeat its last entry and are not counted
+                for (int q = 0; q < n; q += 4) {
+                    int e[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) e[i] = s_unord[min(o + q + i, last)];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) rank += (q + i < n && e[i] < j) ? 1 : 0;
+                }
                 s_sorted[rank_major_pos(c, rank, s_rmask, s_roff, s_cnt)] = j;
             }
             __syncthreads();
             for (int k = tid; k < at.cnt; k += kP2GBlock) perm[at.off + k] = s_sorted[k];
         } else {
-            // crowded tile: the same rank-by-counting, with the cell-major
-            // placement in perm and the rank-major result staged in this
-            // tile's range of tmp (its bucketed input is no longer needed),
-            // then copied back to perm
+            // crowded tile: the same placement and rank-by-counting, with the
+            // cell-major placement in perm and the rank-major result staged in
+            // this tile's range of tmp (its bucketed input is no longer
+            // needed), then copied back to perm
+            int* unord = perm + at.off;
+            for (int k = tid; k < at.cnt; k += kP2GBlock) {
+                int c = tmpk[at.off + k] & 63;
+                int pos = atomicAdd(&s_cur[c], 1);
+                unord[s_off[c] + pos] = tmp[at.off + k];
+            }
+            __threadfence_block();
+            __syncthreads();
             for (int k = tid; k < at.cnt; k += kP2GBlock) {
                 int p = k, lo = 0;
 #pragma unroll
@@ -503,9 +561,13 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
             for (int r = w; r < mycnt; r += NW) {
                 const P2GIn<T, D, MAT> in = nx;
                 if (r + NW < mycnt) nx.load(cur, sorted[rank_major_pos(lane, r + NW, s_rmask, s_roff, s_cnt)]);
-                p2g_particle<T, D, MAT>(P, in, lb, gb, [&](int k, int, const T* add) {
+                // the products go straight into the sums (one FMA each)
+                p2g_particle<T, D, MAT>(P, in, lb, gb,
+                                        [&](int k, int, const T* fx, T mw, const T* U, const T* V, const T* W) {
+                    acc[k][0] = fma(fx[0], mw, acc[k][0]);
 #pragma unroll
-                    for (int q = 0; q <= D; ++q) acc[k][q] += add[q];
+                    for (int a = 0; a < D; ++a)
+                        acc[k][1 + a] = fma(fx[2], W[a], fma(fx[1], V[a], fma(fx[0], U[a], acc[k][1 + a])));
                 });
             }
             T (*node)[NB] = s_node[w];
@@ -533,7 +595,10 @@ __global__ __launch_bounds__(kP2GBlock) void k_p2g(Geo g, Phys<T> P, const int* 
                 if (r < mycnt) {
                     P2GIn<T, D, MAT> in;
                     in.load(cur, sorted[rank_major_pos(lane, r, s_rmask, s_roff, s_cnt)]);
-                    p2g_particle<T, D, MAT>(P, in, lb, gb, [&](int, int n, const T* add) {
+                    p2g_particle<T, D, MAT>(P, in, lb, gb,
+                                            [&](int, int n, const T* fx, T mw, const T* U, const T* V, const T* W) {
+                        T add[D + 1];
+                        p2g_node_values<T, D>(fx, mw, U, V, W, add);
 #pragma unroll
                         for (int q = 0; q <= D; ++q) atomicAdd(&node[q][n], add[q]);
                     });
@@ -654,6 +719,27 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int
 // G2P + kinematics + constitutive
 // ---------------------------------------------------------------------------
 
+// Nodal velocities of a tile's LDS block (the tile's nodes and its halo), NPT
+// block nodes per thread: thread t takes nodes t, t + NT, ...
+template <class T, int D, int NPT, int NT>
+__device__ __forceinline__ void g2p_block_load(const Geo& g, const T* __restrict__ gv, int tile, int tid,
+                                               T r[D][NPT])
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    int tc[3];
+    tile_coords(g, tile, tc);
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+        const int i = tid + p * NT;
+        if (i < NB) {
+            int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
+            long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a][p] = gv[a * g.NN + node];
+        }
+    }
+}
+
 template <class T, int D, int MAT>
 __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, const int* __restrict__ perm,
@@ -663,23 +749,43 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     constexpr int NS = D * (D + 1) / 2;
+    constexpr int NPT = (NB + kG2PBlock<T> - 1) / kG2PBlock<T>;   // block nodes per thread
     __shared__ T s_v[D][NB];
     const int n_active = meta[0];
     const int tid = threadIdx.x;
     const long long cap = cur.cap;
-    for (int it = 0;; ++it) {
-        int e = tile_entry(it, n_active);
-        if (e < 0) break;
-        ActiveTile at = active[e];
-        int tc[3];
-        tile_coords(g, at.tile, tc);
-        for (int i = tid; i < NB; i += kG2PBlock<T>) {
-            int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
-            long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
+    // With kG2PPrefetch, the next tile's node velocities are loaded into
+    // registers while this tile's particles are processed (and its
+    // active-list entry one tile earlier still); otherwise each tile loads its
+    // own block at its top.
+    constexpr bool PF = kG2PPrefetch<T>;
+    int e = __builtin_amdgcn_readfirstlane(tile_entry(0, n_active));
+    if (e < 0) return;
+    ActiveTile at = active[e];
+    T pre[D][NPT];
+    if (PF) g2p_block_load<T, D, NPT, kG2PBlock<T>>(g, gv, at.tile, tid, pre);
+    int en = __builtin_amdgcn_readfirstlane(tile_entry(1, n_active));
+    int next_tile = (PF && en >= 0) ? active[en].tile : 0;
+    for (int it = 0; e >= 0; ++it) {
+        if (!PF) g2p_block_load<T, D, NPT, kG2PBlock<T>>(g, gv, at.tile, tid, pre);
 #pragma unroll
-            for (int a = 0; a < D; ++a) s_v[a][i] = gv[a * g.NN + node];
+        for (int p = 0; p < NPT; ++p) {
+            const int i = tid + p * kG2PBlock<T>;
+            if (i < NB)
+#pragma unroll
+                for (int a = 0; a < D; ++a) s_v[a][i] = pre[a][p];
         }
         __syncthreads();
+        int enn = -1, next2_tile = 0;
+        if (!PF) {
+            enn = __builtin_amdgcn_readfirstlane(tile_entry(it + 2, n_active));
+        } else if (en >= 0) {
+            g2p_block_load<T, D, NPT, kG2PBlock<T>>(g, gv, next_tile, tid, pre);
+            enn = __builtin_amdgcn_readfirstlane(tile_entry(it + 2, n_active));
+            if (enn >= 0) next2_tile = active[enn].tile;
+        }
+        int tc[3];
+        tile_coords(g, at.tile, tc);
         for (int k0 = 0; k0 < at.cnt; k0 += kG2PBlock<T>) {
             int k = k0 + tid;
             bool valid = k < at.cnt;
@@ -800,6 +906,10 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
             if (valid && rank == 0) atomicAdd(&count[newkey >> 6], len);
         }
         __syncthreads();
+        e = en;
+        if (e >= 0) at = active[e];
+        en = enn;
+        next_tile = next2_tile;
     }
 }
 
