@@ -337,35 +337,20 @@ __global__ __launch_bounds__(kAdjBlock) void k_grid_adj(Geo g, Phys<T> P, const 
                 own[a] = I[a] / TE;
                 down[a] = (a < D) && (I[a] % TE < 2) && own[a] >= 1;
             }
-            int des = -1;
+            constexpr int NC = 1 << D;
+            int slot[NC], li[NC];
+            const int des = node_blocks<D>(g, I, own, down, tile_slot, slot, li);
             T vb[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) vb[a] = T(0);
-            for (int msk = 0; msk < (1 << D); ++msk) {
-                bool ok = true;
-                int ct[3] = {own[0], own[1], own[2]};
+            if (des == tile) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    if ((msk >> a) & 1) {
-                        if (!down[a]) ok = false;
-                        ct[a] -= 1;
-                    }
-                    if (ct[a] >= g.ntile[a]) ok = false;
-                }
-                if (!ok) continue;
-                int tl = (ct[2] * g.ntile[1] + ct[1]) * g.ntile[0] + ct[0];
-                int slot = tile_slot[tl];
-                if (slot < 0) continue;
-                if (des < 0) {
-                    des = tl;
-                    if (des != tile) break;
-                }
-                int li;
-                if constexpr (D == 3) li = ((I[2] - ct[2] * TE) * BE + I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
-                else li = (I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
-                const T* src = part + (long long)slot * (D + 1) * NB;
+                for (int msk = 0; msk < NC; ++msk) {
+                    if (slot[msk] < 0) continue;
+                    const T* src = part + (long long)slot[msk] * (D + 1) * NB;
 #pragma unroll
-                for (int a = 0; a < D; ++a) vb[a] += src[a * NB + li];
+                    for (int a = 0; a < D; ++a) vb[a] += src[a * NB + li[msk]];
+                }
             }
             if (des != tile) continue;
             long long node = node_index(g, I[0], I[1], I[2]);

@@ -160,24 +160,39 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int* __restrict__ co
 }
 
 // Scatter every particle into its tile's range (order inside a tile is
-// arbitrary here; the P2G kernel sorts it).  Leaves count[] at zero.
+// arbitrary here; the P2G kernel sorts it).  Leaves count[] at zero.  A
+// thread takes kBucketPer particles, kBlock apart, whose loads, range
+// reservations and stores are each issued together.
+constexpr int kBucketPer = 4;
+
 template <int Unused = 0>
 __global__ __launch_bounds__(kBlock) void k_bucket(long long N, const int* __restrict__ key,
                                                    int* __restrict__ count, const int* __restrict__ tile_off,
                                                    int* __restrict__ tmp, int* __restrict__ tmpk)
 {
-    long long j = (long long)blockIdx.x * kBlock + threadIdx.x;
-    bool valid = j < N;
-    int t = valid ? (key[j] >> 6) : -1;
-    int head, len, rank;
-    wave_runs(t, valid, head, len, rank);
-    int base = 0;
-    if (valid && rank == 0) base = atomicSub(&count[t], len) - len;
-    base = __shfl(base, head);
-    if (valid) {
-        int slot = tile_off[t] + base + rank;
-        tmp[slot] = (int)j;
-        tmpk[slot] = key[j];
+    const long long j0 = (long long)blockIdx.x * (kBlock * kBucketPer) + threadIdx.x;
+    int k[kBucketPer], head[kBucketPer], len[kBucketPer], rank[kBucketPer], base[kBucketPer];
+#pragma unroll
+    for (int q = 0; q < kBucketPer; ++q) {
+        const long long j = j0 + q * kBlock;
+        k[q] = j < N ? key[j] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kBucketPer; ++q) {
+        const bool valid = j0 + q * kBlock < N;
+        wave_runs(valid ? (k[q] >> 6) : -1, valid, head[q], len[q], rank[q]);
+        base[q] = 0;
+        if (valid && rank[q] == 0) base[q] = atomicSub(&count[k[q] >> 6], len[q]) - len[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kBucketPer; ++q) {
+        const long long j = j0 + q * kBlock;
+        const int b = __shfl(base[q], head[q]);
+        if (j < N) {
+            const int slot = tile_off[k[q] >> 6] + b + rank[q];
+            tmp[slot] = (int)j;
+            tmpk[slot] = k[q];
+        }
     }
 }
 
@@ -624,6 +639,42 @@ __global__ __launch_bounds__(kP2GBlock) __attribute__((amdgpu_waves_per_eu(2))) 
 // the partial blocks that cover it, in that same fixed order.
 // ---------------------------------------------------------------------------
 
+// The partial blocks that cover block node I (global node coordinates):
+// candidate msk takes its own tile minus one along every axis whose bit is
+// set, own tile first.  Writes each candidate's active slot (-1: none) and
+// the node's index in that block, and returns the node's owner tile: the
+// first active candidate (-1 if none).  All slots are loaded before any is
+// used.
+template <int D>
+__device__ __forceinline__ int node_blocks(const Geo& g, const int I[3], const int own[3], const bool down[3],
+                                           const int* __restrict__ tile_slot, int slot[1 << D], int li[1 << D])
+{
+    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NC = 1 << D;
+    int tl[NC];
+#pragma unroll
+    for (int msk = 0; msk < NC; ++msk) {
+        bool ok = true;
+        int ct[3] = {own[0], own[1], own[2]};
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if ((msk >> a) & 1) {
+                if (!down[a]) ok = false;
+                ct[a] -= 1;
+            }
+            if (ct[a] >= g.ntile[a]) ok = false;
+        }
+        tl[msk] = (ct[2] * g.ntile[1] + ct[1]) * g.ntile[0] + ct[0];
+        if constexpr (D == 3) li[msk] = ((I[2] - ct[2] * TE) * BE + I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
+        else li[msk] = (I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
+        slot[msk] = ok ? tile_slot[tl[msk]] : -1;
+    }
+    int des = -1;
+#pragma unroll
+    for (int msk = NC - 1; msk >= 0; --msk)
+        if (slot[msk] >= 0) des = tl[msk];
+    return des;
+}
+
 template <class T, int D>
 __global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                  const ActiveTile* __restrict__ active,
@@ -648,36 +699,21 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int
                 own[a] = I[a] / TE;
                 down[a] = (a < D) && (I[a] % TE < 2) && own[a] >= 1;
             }
-            int des = -1;
+            constexpr int NC = 1 << D;
+            int slot[NC], li[NC];
+            const int des = node_blocks<D>(g, I, own, down, tile_slot, slot, li);
             T m = T(0), p[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) p[a] = T(0);
-            for (int msk = 0; msk < (1 << D); ++msk) {
-                bool ok = true;
-                int ct[3] = {own[0], own[1], own[2]};
+            if (des == tile) {
 #pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    if ((msk >> a) & 1) {
-                        if (!down[a]) ok = false;
-                        ct[a] -= 1;
-                    }
-                    if (ct[a] >= g.ntile[a]) ok = false;
-                }
-                if (!ok) continue;
-                int tl = (ct[2] * g.ntile[1] + ct[1]) * g.ntile[0] + ct[0];
-                int slot = tile_slot[tl];
-                if (slot < 0) continue;
-                if (des < 0) {
-                    des = tl;
-                    if (des != tile) break;
-                }
-                int li;
-                if constexpr (D == 3) li = ((I[2] - ct[2] * TE) * BE + I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
-                else li = (I[1] - ct[1] * TE) * BE + I[0] - ct[0] * TE;
-                const T* src = part + (long long)slot * (D + 1) * NB;
-                m += src[li];
+                for (int msk = 0; msk < NC; ++msk) {
+                    if (slot[msk] < 0) continue;
+                    const T* src = part + (long long)slot[msk] * (D + 1) * NB;
+                    m += src[li[msk]];
 #pragma unroll
-                for (int a = 0; a < D; ++a) p[a] += src[(1 + a) * NB + li];
+                    for (int a = 0; a < D; ++a) p[a] += src[(1 + a) * NB + li[msk]];
+                }
             }
             if (des != tile) continue;
             long long node = node_index(g, I[0], I[1], I[2]);
@@ -1150,7 +1186,8 @@ struct Solver {
         k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
         k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, b.tile_slot, b.active, b.meta);
         prof_mark(c, MPM_PROF_SCAN);
-        k_bucket<0><<<nblocks(c->N), kBlock, 0, st>>>(c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
+        k_bucket<0><<<(unsigned)((c->N + kBlock * kBucketPer - 1) / (kBlock * kBucketPer)), kBlock, 0, st>>>(
+            c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
         prof_mark(c, MPM_PROF_BUCKET);
         k_p2g<T, D, MAT><<<kP2GWGs, kP2GBlock, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
                                                       (T*)c->part_grid);
