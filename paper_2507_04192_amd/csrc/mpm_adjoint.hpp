@@ -409,8 +409,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_grid_adj(Geo g, Phys<T> P, const 
     }
 }
 
+// At least two waves per SIMD: binary64 needs a few more than 256 registers
+// per lane and would otherwise run one wave (measured faster with the spills).
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kAdjBlock) void k_p2g_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_p2g_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                     const ActiveTile* __restrict__ active,
                                                     const int* __restrict__ perm, PView<T> st,
                                                     const T* __restrict__ gpb, const T* __restrict__ gmb,
