@@ -192,6 +192,40 @@ def test_crowded_tile_uses_global_sort(orc, N, cells):
     assert rel_l2(g["v"], r["v"]) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("N", [1023, 1024, 1025])
+def test_tile_at_sort_capacity(orc, precision, N):
+    """A tile with one particle fewer than, exactly as many as, and one more
+    than the in-LDS sort takes (1024: 16 entries per lane of the one-wave
+    sort; above it the sort runs in global memory), 16 particles per cell
+    over the 64 cells of a 2-D tile: the GPU's order must equal the oracle's
+    ordering of the GPU's own keys, and the step must match the oracle."""
+    cfg = W.SimConfig(dim=2, n=(32, 32, 1), dx=0.01, dt=1e-5, material=W.FLUID, ppc=4,
+                      gravity=(0, -9.81, 0))
+    rng = np.random.default_rng(36 + N)
+    lo = (8 - 2 + 0.5) * cfg.dx + 1e-6
+    hi = (8 + 8 - 2 + 0.5) * cfg.dx - 1e-6
+    x = rng.uniform(lo, hi, size=(2, N))
+    if precision == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    print(f"[case] tile at sort capacity N={N} {precision}", flush=True)
+    o = orc.Oracle(cfg, key_f32=(precision == "f32"))
+    s = gpu_solver(cfg, precision, x)
+    kb = _np(s.read_keys())
+    assert len(np.unique(kb >> 6)) == 1
+    assert np.array_equal(kb, o.keys(_np(s.mpm_read_state("x")).astype(np.float64)))
+    st = oracle_state(orc, cfg, x)
+    o.step(st, cfg.dt)
+    s.mpm_step(1)
+    assert s.mpm_sync_status()[0] == 0
+    perm, _ = s.mpm_read_sort()
+    assert np.array_equal(_np(perm), o.sort_perm(kb))
+    g, r = gpu_fields(s), oracle_fields(cfg, st)
+    tol = 1e-12 if precision == "f64" else 2e-5
+    assert rel_l2(g["x"], r["x"]) <= tol
+    assert rel_l2(g["v"], r["v"]) <= (1e-10 if precision == "f64" else 1e-4)
+
+
 def test_walls_and_clamping(orc):
     """Particles on the walls and moving out of the box are clamped the same
     way on both sides."""
