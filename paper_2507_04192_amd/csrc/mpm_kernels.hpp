@@ -3,10 +3,10 @@
 // One step (Sec. 2.2, update-stress-last):
 //   1. scan_reduce / scan_down  tile histogram -> tile offsets, active tiles
 //   2. bucket                   particles scattered into their tile's range
-//   3. p2g                      one tile per wave: cell-level stable sort in
-//                               LDS, then P2G (eq:update_m, momentum with the
+//   3. p2g                      one tile per workgroup: cell-level stable sort
+//                               in LDS, then P2G (eq:update_m, momentum with the
 //                               APIC affine term of App. B, internal force from
-//                               the stress cache) into the wave's LDS node
+//                               the stress cache) into the tile's LDS node
 //                               block, written out as the tile's partial block
 //   4. grid                     sums the partial blocks covering each node in
 //                               a fixed order; v = P/m + dt g, walls (Sec. 5.3
@@ -34,8 +34,11 @@ template <> struct TileShape<3> { static constexpr int TE = 4, BE = 6, NB = 216;
 template <> struct TileShape<2> { static constexpr int TE = 8, BE = 10, NB = 100; };
 
 constexpr int kSortCap = 1024;   // particles per tile sorted in LDS (larger: in perm)
-constexpr int kP2GBlock = 64;    // threads of a P2G workgroup (one wave per tile)
-constexpr int kP2GWGs = kTileWGs * kBlock / kP2GBlock;
+// threads of a P2G workgroup, one tile each: binary64 one wave; binary32 two
+// waves that share the tile's particles and split the node values between
+// them (mass and momentum x | the other momentum components)
+template <class T> constexpr int kP2GBlock = sizeof(T) == 4 ? 128 : 64;
+template <class T> constexpr int kP2GWGs = kTileWGs * kBlock / kP2GBlock<T>;
 // threads of a G2P workgroup (binary64: smaller groups, measured faster)
 template <class T> constexpr int kG2PBlock = sizeof(T) == 8 ? 128 : 256;
 // G2P loads the next tile's node block while it works on the current one
@@ -240,40 +243,35 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Active-list entry handled by wave w of this workgroup on iteration `it`
-// (one tile per wave; XCD chunking as in tile_entry).
-__device__ __forceinline__ int wave_tile_entry(int it, int n_active, int w)
-{
-    constexpr int NW = kBlock / 64;
-    int nx = 8;
-    int per = (gridDim.x / nx) * NW;
-    int xcd = blockIdx.x % nx;
-    int lw = (blockIdx.x / nx) * NW + w;
-    int chunk = (n_active + nx - 1) / nx;
-    int e = xcd * chunk + lw + it * per;
-    int end = min((xcd + 1) * chunk, n_active);
-    return e < end ? e : -1;
-}
-
-// The state of one particle that P2G reads.
-template <class T, int D, int MAT>
+// The state of one particle that P2G reads for the momentum components
+// [A0, A1): the position, those components of v, those rows of C and the
+// stress cache.
+template <class T, int D, int MAT, int A0 = 0, int A1 = D>
 struct P2GIn {
     static constexpr int NS = (MAT == MAT_FLUID) ? 1 : D * (D + 1) / 2;
-    T x[D], v[D], C[D * D], S[NS];
+    static constexpr int NA = A1 - A0;
+    T x[D], v[NA], C[NA * D], S[NS];
     __device__ __forceinline__ void load(const PView<T>& cur, int j)
     {
         const long long cap = cur.cap;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            x[a] = cur.x[a * cap + j];
-            v[a] = cur.v[a * cap + j];
-        }
+        for (int a = 0; a < D; ++a) x[a] = cur.x[a * cap + j];
 #pragma unroll
-        for (int q = 0; q < D * D; ++q) C[q] = cur.C[q * cap + j];
+        for (int a = 0; a < NA; ++a) v[a] = cur.v[(A0 + a) * cap + j];
+#pragma unroll
+        for (int q = 0; q < NA * D; ++q) C[q] = cur.C[(A0 * D + q) * cap + j];
 #pragma unroll
         for (int q = 0; q < NS; ++q) S[q] = cur.S[q * cap + j];
     }
 };
+
+// Index of entry (a, b) in the packed symmetric storage of the stress cache
+// (3-D: 00 11 22 01 02 12; 2-D: 00 11 01).
+template <int D>
+__host__ __device__ constexpr int sym_index(int a, int b)
+{
+    return a == b ? a : (D == 2 ? 2 : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5)));
+}
 
 // One particle's P2G contribution (eq:update_m, the momentum with the APIC
 // affine term of App. B, and the internal force -dt V_p sigma_p grad phi).
@@ -286,13 +284,14 @@ struct P2GIn {
 //   V_a = wyz mC_a0,  W_a = wyz fs_a0.
 // For each of the 3^D stencil nodes, sink(k, n, fx, mw, U, V, W) receives
 // the offset index k, the node's index n in the tile's LDS block, the x
-// factors fx = (w_x, w_x dd_x, dw_x) and the line terms; p2g_node_values
-// forms the D+1 values from them.
-template <class T, int D, int MAT, class Sink>
-__device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D, MAT>& in, const int lb[3],
+// factors fx = (w_x, w_x dd_x, dw_x) and the line terms of the momentum
+// components [A0, A1); p2g_node_values forms the D+1 values from them when
+// the range is all of them.
+template <class T, int D, int MAT, int A0, int A1, class Sink>
+__device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D, MAT, A0, A1>& in, const int lb[3],
                                              const int gb[3], Sink&& sink)
 {
-    constexpr int BE = TileShape<D>::BE;
+    constexpr int BE = TileShape<D>::BE, NA = A1 - A0;
     T w[D][3], dw[D][3], dd[D][3];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -303,31 +302,16 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
 #pragma unroll
         for (int k = 0; k < 3; ++k) dd[a][k] = (T(k) - f) * P.h;
     }
-    T mv[D], mC[D][D], fs[D][D];
+    // rows A0..A1-1 of m v, m C and fs = -dt V sigma
+    T mv[NA], mC[NA][D], fs[NA][D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
+    for (int a = 0; a < NA; ++a) {
         mv[a] = P.mass * in.v[a];
 #pragma unroll
-        for (int b = 0; b < D; ++b) mC[a][b] = P.mass * in.C[a * D + b];
-    }
-    if constexpr (MAT == MAT_FLUID) {
-        T s = -P.dt * in.S[0];
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int b = 0; b < D; ++b) fs[a][b] = (a == b) ? s : T(0);
-    } else {
-        if constexpr (D == 3) {
-            T s0 = in.S[0], s1 = in.S[1], s2 = in.S[2];
-            T s3 = in.S[3], s4 = in.S[4], s5 = in.S[5];
-            fs[0][0] = -P.dt * s0; fs[1][1] = -P.dt * s1; fs[2][2] = -P.dt * s2;
-            fs[0][1] = fs[1][0] = -P.dt * s3;
-            fs[0][2] = fs[2][0] = -P.dt * s4;
-            fs[1][2] = fs[2][1] = -P.dt * s5;
-        } else {
-            T s0 = in.S[0], s1 = in.S[1], s2 = in.S[2];
-            fs[0][0] = -P.dt * s0; fs[1][1] = -P.dt * s1;
-            fs[0][1] = fs[1][0] = -P.dt * s2;
+        for (int b = 0; b < D; ++b) {
+            mC[a][b] = P.mass * in.C[a * D + b];
+            if constexpr (MAT == MAT_FLUID) fs[a][b] = (A0 + a == b) ? -P.dt * in.S[0] : T(0);
+            else fs[a][b] = -P.dt * in.S[sym_index<D>(A0 + a, b)];
         }
     }
     T fx[3][3];
@@ -340,17 +324,17 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
     constexpr int KZ = (D == 3) ? 3 : 1;
 #pragma unroll
     for (int kz = 0; kz < KZ; ++kz) {
-        T mvz[D];   // m v_a + mC_a2 dd_z: the part of the affine term fixed on a z plane
+        T mvz[NA];   // m v_a + mC_a2 dd_z: the part of the affine term fixed on a z plane
 #pragma unroll
-        for (int a = 0; a < D; ++a) mvz[a] = (D == 3) ? mv[a] + mC[a][D - 1] * dd[D - 1][kz] : mv[a];
+        for (int a = 0; a < NA; ++a) mvz[a] = (D == 3) ? mv[a] + mC[a][D - 1] * dd[D - 1][kz] : mv[a];
 #pragma unroll
         for (int ky = 0; ky < 3; ++ky) {
             T wyz = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
             T g1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
             T g2 = (D == 3) ? w[1][ky] * dw[2][kz] : T(0);
-            T U[D], V[D], Wf[D];
+            T U[NA], V[NA], Wf[NA];
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
+            for (int a = 0; a < NA; ++a) {
                 T aff = mvz[a] + mC[a][1] * dd[1][ky];
                 T u = wyz * aff + fs[a][1] * g1;
                 if constexpr (D == 3) u += fs[a][2] * g2;
@@ -402,35 +386,88 @@ __device__ __forceinline__ int rank_major_pos(int c, int q, const unsigned long 
                                               const int* cnt)
 {
     if (q < 64) return roff[q] + __popcll(rmask[q] & ((1ull << c) - 1ull));
+    // read through volatile: keeps the compiler from hoisting the 64 counts
+    // into registers out of the callers' particle loops
+    const volatile int* vc = cnt;
     int r = 0;
+#pragma unroll 1
     for (int c2 = 0; c2 < 64; ++c2) {
-        int n = cnt[c2];
+        int n = vc[c2];
         r += min(n, q) + ((c2 < c && n > q) ? 1 : 0);
     }
     return r;
 }
 
+// Binary32 P2G of one lane (cell) for the momentum components [A0, A1)
+// (and the mass when A0 = 0): the lane sums the particles of its cell in
+// registers (they all hit the same 3^D nodes), the next particle's state
+// loaded while this one is spread, then adds its sums to node arrays
+// [Q0, Q0 + NQ) of the tile's LDS block.  The lanes of a wave write distinct
+// nodes per offset and wave_sync orders the offsets.
+template <class T, int D, int MAT, int A0, int A1>
+__device__ __forceinline__ void p2g_lane_sums(const Phys<T>& P, const PView<T>& cur, const int* sorted, int lane,
+                                              int mycnt, const int lb[3], const int gb[3],
+                                              const unsigned long long* s_rmask, const int* s_roff,
+                                              const int* s_cnt, T (*node)[TileShape<D>::NB])
+{
+    constexpr int NK = (D == 3) ? 27 : 9;
+    constexpr int M = A0 == 0 ? 1 : 0;          // this wave carries the mass
+    constexpr int NQ = M + A1 - A0;             // node values of this wave
+    constexpr int Q0 = M ? 0 : 1 + A0;          // its first node array
+    T acc[NK][NQ];
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[k][q] = T(0);
+    P2GIn<T, D, MAT, A0, A1> nx;
+    if (mycnt > 0) nx.load(cur, sorted[rank_major_pos(lane, 0, s_rmask, s_roff, s_cnt)]);
+    for (int r = 0; r < mycnt; ++r) {
+        const P2GIn<T, D, MAT, A0, A1> in = nx;
+        if (r + 1 < mycnt) nx.load(cur, sorted[rank_major_pos(lane, r + 1, s_rmask, s_roff, s_cnt)]);
+        // the products go straight into the sums (one FMA each)
+        p2g_particle<T, D, MAT, A0, A1>(P, in, lb, gb,
+                                        [&](int k, int, const T* fx, T mw, const T* U, const T* V, const T* W) {
+            if constexpr (M) acc[k][0] = fma(fx[0], mw, acc[k][0]);
+#pragma unroll
+            for (int a = 0; a < A1 - A0; ++a)
+                acc[k][M + a] = fma(fx[2], W[a], fma(fx[1], V[a], fma(fx[0], U[a], acc[k][M + a])));
+        });
+    }
+    if (mycnt > 0) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            int n = block_node<D>(lb, k);
+            T cv[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) cv[q] = node[Q0 + q][n];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) node[Q0 + q][n] = cv[q] + acc[k][q];
+            wave_sync();
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) wave_sync();
+    }
+}
+
 // P2G, one tile per workgroup.  The workgroup (1) sorts the tile's particles
 // into perm: by rank within their cell (previous slot order), then by cell,
 // so that the r-th particles of the 64 cells are adjacent in memory; (2)
-// takes them in rounds, lane c of wave w holding the r-th particle of cell c
-// for r = w, w+4, ... (the lanes of a round read adjacent slots); (3) writes
-// the sum of the waves' node blocks (mass, momentum), in wave order, to the
-// tile's partial block.
-// Two waves per SIMD (at most 256 registers per lane, binary32 included,
-// whose 27 x 4 register sums sit close to that limit).
+// takes them in rounds, lane c holding the r-th particle of cell c for
+// r = 0, 1, ... (the lanes of a round read adjacent slots), binary32 with
+// two waves that split the node values; (3) writes the tile's node block
+// (mass, momentum) to its partial block.  Register budget: three waves per
+// SIMD in binary32 (168 registers), two in binary64.
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kP2GBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
+__global__ __launch_bounds__(kP2GBlock<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, int* __restrict__ tmp,
                                                 const int* __restrict__ tmpk, PView<T> cur, int* __restrict__ perm,
                                                 T* __restrict__ part)
 {
     constexpr int TE = TileShape<D>::TE, NB = TileShape<D>::NB;
-    constexpr int NW = kP2GBlock / 64;
+    constexpr int NT = kP2GBlock<T>;
     constexpr bool kRegAcc = sizeof(T) == 4;            // binary32: sums in registers
-    constexpr int NBLK = NW;                             // one LDS node block per wave
-    constexpr int NK = (D == 3) ? 27 : 9;
-    __shared__ T s_node[NBLK][D + 1][NB];
+    __shared__ T s_node[D + 1][NB];
     __shared__ int s_cnt[64], s_off[64], s_cur[64];
     __shared__ int s_unord[kSortCap], s_sorted[kSortCap];
     __shared__ unsigned char s_ucell[kSortCap];
@@ -443,30 +480,30 @@ __global__ __launch_bounds__(kP2GBlock) __attribute__((amdgpu_waves_per_eu(2))) 
         int e = tile_entry(it, n_active);
         if (e < 0) break;
         const ActiveTile at = active[e];
-        for (int i = tid; i < NBLK * (D + 1) * NB; i += kP2GBlock) (&s_node[0][0][0])[i] = T(0);
+        for (int i = tid; i < (D + 1) * NB; i += NT) (&s_node[0][0])[i] = T(0);
         if (tid < 64) { s_cnt[tid] = 0; s_cur[tid] = 0; }
         __syncthreads();
         const bool in_lds = at.cnt <= kSortCap;
         // A tile that fits in LDS keeps its particles' cells and slots in
-        // registers (lane l holds entries l, l + 64, ...): one batch of global
+        // registers (thread t holds entries t, t + NT, ...): one batch of global
         // loads instead of one round trip per pass below.
-        constexpr int KPL = kSortCap / kP2GBlock;
-        const int nk = at.cnt - tid;                 // entry i * 64 of this lane exists if below
+        constexpr int KPL = kSortCap / NT;
+        const int nk = at.cnt - tid;                 // entry i * NT of this thread exists if below
         const int* tk = tmpk + at.off + tid;
         const int* tj = tmp + at.off + tid;
         int rc[KPL], rj[KPL];
         if (in_lds) {
 #pragma unroll
             for (int i = 0; i < KPL; ++i)
-                if (i * kP2GBlock < nk) {
-                    rc[i] = tk[i * kP2GBlock] & 63;   // the cell is the low 6 bits of the key
-                    rj[i] = tj[i * kP2GBlock];
+                if (i * NT < nk) {
+                    rc[i] = tk[i * NT] & 63;   // the cell is the low 6 bits of the key
+                    rj[i] = tj[i * NT];
                 }
 #pragma unroll
             for (int i = 0; i < KPL; ++i)
-                if (i * kP2GBlock < nk) atomicAdd(&s_cnt[rc[i]], 1);
+                if (i * NT < nk) atomicAdd(&s_cnt[rc[i]], 1);
         } else {
-            for (int k = tid; k < at.cnt; k += kP2GBlock) atomicAdd(&s_cnt[tmpk[at.off + k] & 63], 1);
+            for (int k = tid; k < at.cnt; k += NT) atomicAdd(&s_cnt[tmpk[at.off + k] & 63], 1);
         }
         __syncthreads();
         if (tid < 64) {
@@ -498,13 +535,13 @@ __global__ __launch_bounds__(kP2GBlock) __attribute__((amdgpu_waves_per_eu(2))) 
             // inside its cell by previous slot: a stable order
 #pragma unroll
             for (int i = 0; i < KPL; ++i) {
-                if (i * kP2GBlock >= nk) continue;
+                if (i * NT >= nk) continue;
                 const int u = s_off[rc[i]] + atomicAdd(&s_cur[rc[i]], 1);
                 s_unord[u] = rj[i];
                 s_ucell[u] = (unsigned char)rc[i];
             }
             __syncthreads();
-            for (int u = tid; u < at.cnt; u += kP2GBlock) {
+            for (int u = tid; u < at.cnt; u += NT) {
                 const int c = s_ucell[u], j = s_unord[u];
                 const int o = s_off[c], n = s_cnt[c], last = o + n - 1;
                 int rank = 0;
@@ -520,21 +557,21 @@ __global__ __launch_bounds__(kP2GBlock) __attribute__((amdgpu_waves_per_eu(2))) 
                 s_sorted[rank_major_pos(c, rank, s_rmask, s_roff, s_cnt)] = j;
             }
             __syncthreads();
-            for (int k = tid; k < at.cnt; k += kP2GBlock) perm[at.off + k] = s_sorted[k];
+            for (int k = tid; k < at.cnt; k += NT) perm[at.off + k] = s_sorted[k];
         } else {
             // crowded tile: the same placement and rank-by-counting, with the
             // cell-major placement in perm and the rank-major result staged in
             // this tile's range of tmp (its bucketed input is no longer
             // needed), then copied back to perm
             int* unord = perm + at.off;
-            for (int k = tid; k < at.cnt; k += kP2GBlock) {
+            for (int k = tid; k < at.cnt; k += NT) {
                 int c = tmpk[at.off + k] & 63;
                 int pos = atomicAdd(&s_cur[c], 1);
                 unord[s_off[c] + pos] = tmp[at.off + k];
             }
             __threadfence_block();
             __syncthreads();
-            for (int k = tid; k < at.cnt; k += kP2GBlock) {
+            for (int k = tid; k < at.cnt; k += NT) {
                 int p = k, lo = 0;
 #pragma unroll
                 for (int step = 32; step >= 1; step >>= 1)
@@ -547,87 +584,59 @@ __global__ __launch_bounds__(kP2GBlock) __attribute__((amdgpu_waves_per_eu(2))) 
             __threadfence_block();
             __syncthreads();
             const volatile int* rm = tmp + at.off;
-            for (int k = tid; k < at.cnt; k += kP2GBlock) unord[k] = rm[k];
+            for (int k = tid; k < at.cnt; k += NT) unord[k] = rm[k];
             __threadfence_block();
             __syncthreads();
         }
         const int* sorted = in_lds ? s_sorted : (perm + at.off);
         int tc[3];
         tile_coords(g, at.tile, tc);
+        // The lane's cell, made opaque to the compiler for this tile: what is
+        // derived from it (node offsets, LDS addresses) is then formed per
+        // tile instead of being hoisted out of the tile loop, where it would
+        // hold registers through the particle loop.
+        int cl = lane;
+        asm volatile("" : "+v"(cl));
         int lb[3], gb[3];
-        lb[0] = lane % TE;
-        lb[1] = (lane / TE) % TE;
-        lb[2] = (D == 3) ? lane / (TE * TE) : 0;
+        lb[0] = cl % TE;
+        lb[1] = (cl / TE) % TE;
+        lb[2] = (D == 3) ? cl / (TE * TE) : 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) gb[a] = tc[a] * TE + lb[a] - g.G;
-        const int mycnt = s_cnt[lane], maxc = s_max;
+        const int mycnt = s_cnt[cl], maxc = s_max;
         if constexpr (kRegAcc) {
-            // a lane sums its cell's particles in registers (they all hit the
-            // same 3^D nodes), then adds the sums to its wave's block; lanes
-            // write distinct nodes per offset and wave_sync orders the offsets
-            T acc[NK][D + 1];
-#pragma unroll
-            for (int k = 0; k < NK; ++k)
-#pragma unroll
-                for (int q = 0; q <= D; ++q) acc[k][q] = T(0);
-            // the next particle's state is loaded while this one is spread
-            P2GIn<T, D, MAT> nx;
-            if (w < mycnt) nx.load(cur, sorted[rank_major_pos(lane, w, s_rmask, s_roff, s_cnt)]);
-            for (int r = w; r < mycnt; r += NW) {
-                const P2GIn<T, D, MAT> in = nx;
-                if (r + NW < mycnt) nx.load(cur, sorted[rank_major_pos(lane, r + NW, s_rmask, s_roff, s_cnt)]);
-                // the products go straight into the sums (one FMA each)
-                p2g_particle<T, D, MAT>(P, in, lb, gb,
-                                        [&](int k, int, const T* fx, T mw, const T* U, const T* V, const T* W) {
-                    acc[k][0] = fma(fx[0], mw, acc[k][0]);
-#pragma unroll
-                    for (int a = 0; a < D; ++a)
-                        acc[k][1 + a] = fma(fx[2], W[a], fma(fx[1], V[a], fma(fx[0], U[a], acc[k][1 + a])));
-                });
-            }
-            T (*node)[NB] = s_node[w];
-            if (w < mycnt) {
-#pragma unroll
-                for (int k = 0; k < NK; ++k) {
-                    int n = block_node<D>(lb, k);
-                    T cv[D + 1];
-#pragma unroll
-                    for (int q = 0; q <= D; ++q) cv[q] = node[q][n];
-#pragma unroll
-                    for (int q = 0; q <= D; ++q) node[q][n] = cv[q] + acc[k][q];
-                    wave_sync();
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < NK; ++k) wave_sync();
-            }
+            // binary32: lane c of each wave sums the particles of cell c in
+            // registers (they all hit the same 3^D nodes), wave 0 the mass and
+            // momentum x, wave 1 the other momentum components, then adds its
+            // sums to the tile's LDS block; the waves write different node
+            // arrays, the lanes of a wave distinct nodes per offset, and
+            // wave_sync orders the offsets
+            T (*node)[NB] = s_node;
+            if (w == 0)
+                p2g_lane_sums<T, D, MAT, 0, 1>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
+            else
+                p2g_lane_sums<T, D, MAT, 1, D>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
         } else {
-            // binary64: hardware LDS atomics (ds_add_f64) into the wave's own
-            // block, issued without waiting; lanes hit distinct nodes per
-            // offset, so the summation order is fixed
-            T (*node)[NB] = s_node[w];
-            for (int r = w; r < maxc; r += NW) {
+            // binary64 (one wave): hardware LDS atomics (ds_add_f64) into the
+            // tile's block, issued without waiting; lanes hit distinct nodes
+            // per offset, so the summation order is fixed
+            for (int r = 0; r < maxc; ++r) {
                 if (r < mycnt) {
                     P2GIn<T, D, MAT> in;
-                    in.load(cur, sorted[rank_major_pos(lane, r, s_rmask, s_roff, s_cnt)]);
+                    in.load(cur, sorted[rank_major_pos(cl, r, s_rmask, s_roff, s_cnt)]);
                     p2g_particle<T, D, MAT>(P, in, lb, gb,
                                             [&](int, int n, const T* fx, T mw, const T* U, const T* V, const T* W) {
                         T add[D + 1];
                         p2g_node_values<T, D>(fx, mw, U, V, W, add);
 #pragma unroll
-                        for (int q = 0; q <= D; ++q) atomicAdd(&node[q][n], add[q]);
+                        for (int q = 0; q <= D; ++q) atomicAdd(&s_node[q][n], add[q]);
                     });
                 }
             }
         }
         __syncthreads();
         T* dst = part + (long long)e * (D + 1) * NB;
-        for (int i = tid; i < (D + 1) * NB; i += kP2GBlock) {
-            T v = (&s_node[0][0][0])[i];
-#pragma unroll
-            for (int b = 1; b < NBLK; ++b) v += (&s_node[b][0][0])[i];
-            dst[i] = v;
-        }
+        for (int i = tid; i < (D + 1) * NB; i += NT) dst[i] = (&s_node[0][0])[i];
         __syncthreads();
     }
 }
@@ -1189,7 +1198,7 @@ struct Solver {
         k_bucket<0><<<(unsigned)((c->N + kBlock * kBucketPer - 1) / (kBlock * kBucketPer)), kBlock, 0, st>>>(
             c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
         prof_mark(c, MPM_PROF_BUCKET);
-        k_p2g<T, D, MAT><<<kP2GWGs, kP2GBlock, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
+        k_p2g<T, D, MAT><<<kP2GWGs<T>, kP2GBlock<T>, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
                                                       (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
         k_grid<T, D><<<kTileWGs * kBlock / kGridBlock, kGridBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,
