@@ -130,18 +130,31 @@ def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cylinder_f32.txt")
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of a kernel from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when there is
-    none or the kernel sources changed since it was taken."""
+# The binary32 3-D sand kernels behind each timed class (the reverse G2P is
+# two launches).
+TRAFFIC_KERNELS = {"p2g": ["k_p2g<float, 3, 1>"], "g2p": ["k_g2p<float, 3, 1>"],
+                   "g2p_adj": ["k_g2p_adj_cons<float, 3, 1>", "k_g2p_adj_grid<float, 3>"],
+                   "p2g_adj": ["k_p2g_adj<float, 3, 1>"]}
+
+
+def measured_traffic(kernels):
+    """HBM bytes per launch of a kernel (or the sum over a list of kernels)
+    from the committed counter summary (FETCH_SIZE + WRITE_SIZE scaled by a
+    plain copy), or None when there is none or the kernel sources changed
+    since it was taken."""
+    if isinstance(kernels, str):
+        kernels = [kernels]
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
         from paper_2507_04192_amd.rocprof_summary import kernel_sources_hash
         if t.get("csrc_sha256") != kernel_sources_hash():
             return None
-        v = t["kernels"][kernel]
-        return v["fetch_bytes"] + v["write_bytes"]
+        total = 0.0
+        for k in kernels:
+            v = t["kernels"][k]
+            total += v["fetch_bytes"] + v["write_bytes"]
+        return total
     except (OSError, KeyError, TypeError, ValueError):
         return None
 
@@ -248,7 +261,7 @@ def main():
         f"(no events: {t32_noev / args.steps * 1e3:.4f} ms/step)")
     dom, kernels, roof = roofline(prof32, n, 4)
     if args.scale_div == 1:
-        roof["traffic"] = measured_traffic({"p2g": "k_p2g<float, 3, 1>", "g2p": "k_g2p<float, 3, 1>"}.get(dom, dom))
+        roof["traffic"] = measured_traffic(TRAFFIC_KERNELS.get(dom, dom))
     for k, v in kernels.items():
         log(f"[bench]   {k:7s} {v['avg_ms'] * 1e3:9.2f} us/launch" +
             (f"  {v['gbs']:8.1f} GB/s algorithmic" if "gbs" in v else ""))
@@ -274,7 +287,9 @@ def main():
             torch.cuda.empty_cache()
             torch.cuda.reset_peak_memory_stats()
             r, prof = run_adjoint(cfg, x, prec, T, args.adj_ckpt)
-            _, kern, roof_a = roofline({k: prof[k] for k in ("g2p_adj", "p2g_adj") if k in prof}, n, elem)
+            dom_a, kern, roof_a = roofline({k: prof[k] for k in ("g2p_adj", "p2g_adj") if k in prof}, n, elem)
+            if prec == "f32" and args.scale_div == 1:
+                roof_a["traffic"] = measured_traffic(TRAFFIC_KERNELS.get(dom_a, dom_a))
             r["roofline"] = roof_a
             r["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1] > 0}
             adj[prec] = r
