@@ -130,10 +130,9 @@ def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cylinder_f32.txt")
 
 
-# The binary32 3-D sand kernels behind each timed class (the reverse G2P is
-# two launches).
+# The binary32 3-D sand kernels behind each timed class.
 TRAFFIC_KERNELS = {"p2g": ["k_p2g<float, 3, 1>"], "g2p": ["k_g2p<float, 3, 1>"],
-                   "g2p_adj": ["k_g2p_adj_cons<float, 3, 1>", "k_g2p_adj_grid<float, 3>"],
+                   "g2p_adj": ["k_g2p_adj<float, 3, 1>"],
                    "p2g_adj": ["k_p2g_adj<float, 3, 1>"]}
 
 

@@ -133,7 +133,7 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
         L.tape_pid = take((size_t)(ckpt_every + 1) * ucap * 4);
         L.adj[0] = take(sb);
         L.adj[1] = take(sb);
-        L.mid = take((size_t)(2 * c.dim + 2 * c.dim * c.dim) * ucap * elem);
+        L.mid = take((size_t)(c.dim + c.dim * c.dim) * ucap * elem);   // position and F adjoints
         // grid tape: one record per step of a segment
         GridRec& r = L.grec;
         size_t ro = 0;

@@ -24,141 +24,30 @@ namespace mpm {
 constexpr int kAdjBlock = 128;   // threads of the reverse per-tile kernels
 
 // Per-slot intermediate of the reverse sweep (mid), component-major with
-// stride cap:
-//   [0, D)              position adjoint (partial after k_g2p_adj_cons,
-//                       complete after k_g2p_adj_grid)
+// stride cap, written by k_g2p_adj and read by k_p2g_adj:
+//   [0, D)              position adjoint
 //   [D, D + D^2)        adjoint of the stored F_e - I (fluid: [D] holds J)
-//   [D + D^2, 2D + D^2) adjoint of the G2P velocity (vt)
-//   [2D + D^2, 2D + 2D^2)  adjoint of the velocity gradient (Lb)
 template <int D> struct MidLayout {
-    static constexpr int X = 0, G = D, VT = D + D * D, LB = 2 * D + D * D, N = 2 * D + 2 * D * D;
+    static constexpr int X = 0, G = D, N = D + D * D;
 };
 
-// Reverse of the constitutive update and of the kinematics x' = x + dt v,
-// per particle of a tile: recomputes the G2P velocity and velocity gradient
-// from the tile's node block, applies the constitutive VJP, and stores the
-// adjoints that the reverse G2P needs.
+// Reverse of the constitutive update, the kinematics x' = x + dt v and G2P,
+// per particle of a tile.  First part: recomputes the G2P velocity and
+// velocity gradient from the tile's node block and applies the constitutive
+// VJP.  Second part, line by line: node adjoints of the velocity
+// (accumulated in binary64 in LDS, then written as the tile's partial block)
+// and the position adjoint through the weights and x_i - x_p.  The velocity,
+// velocity-gradient and partial position adjoints pass between the parts in
+// registers; the F (or J) adjoint and the position adjoint go to mid.
 template <class T, int D, int MAT>
-__global__ __launch_bounds__(kAdjBlock) void k_g2p_adj_cons(Geo g, Phys<T> P, const int* __restrict__ meta,
-                                                         const ActiveTile* __restrict__ active,
-                                                         const int* __restrict__ perm, PView<T> st, PView<T> aout,
-                                                         const T* __restrict__ gv, T* __restrict__ mid)
+__global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
+                                                    const ActiveTile* __restrict__ active,
+                                                    const int* __restrict__ perm, PView<T> st, PView<T> aout,
+                                                    const T* __restrict__ gv, T* __restrict__ part,
+                                                    T* __restrict__ mid)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     constexpr int NS = D * (D + 1) / 2;
-    using ML = MidLayout<D>;
-    __shared__ T s_v[D][NB];
-    const int n_active = meta[0];
-    const int tid = threadIdx.x;
-    const long long cap = st.cap;
-    for (int it = 0;; ++it) {
-        int e = tile_entry(it, n_active);
-        if (e < 0) break;
-        ActiveTile at = active[e];
-        int tc[3];
-        tile_coords(g, at.tile, tc);
-        for (int i = tid; i < NB; i += kAdjBlock) {
-            int l0 = i % BE, l1 = (i / BE) % BE, l2 = (D == 3) ? i / (BE * BE) : 0;
-            long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
-#pragma unroll
-            for (int a = 0; a < D; ++a) s_v[a][i] = gv[a * g.NN + node];
-        }
-        __syncthreads();
-        for (int k = tid; k < at.cnt; k += kAdjBlock) {
-            long long s = at.off + k;
-            int j = perm[s];
-            T xp[D], w[D][3], dw[D][3];
-            int lb[3] = {0, 0, 0};
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                xp[a] = st.x[a * cap + j];
-                int b;
-                T f;
-                stencil_axis(xp[a], P.inv, b, f, w[a], dw[a]);
-                int l = b + g.G - tc[a] * TE;
-                lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
-            }
-            // forward G2P of this particle: velocity and velocity gradient,
-            // line by line along x as in the forward kernel (per-axis weight
-            // factors; a scheduling barrier per line bounds register use)
-            T vn[D], Lm[D][D];
-            {
-                constexpr int NL = (D == 3) ? 9 : 3;
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    vn[a] = T(0);
-#pragma unroll
-                    for (int b = 0; b < D; ++b) Lm[a][b] = T(0);
-                }
-#pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    const int ky = l % 3, kz = l / 3;
-                    const T lw = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
-                    const T ldw1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
-                    const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
-#pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        T v0 = s_v[a][n0], v1 = s_v[a][n0 + 1], v2 = s_v[a][n0 + 2];
-                        T A0 = w[0][0] * v0 + w[0][1] * v1 + w[0][2] * v2;
-                        T A2 = dw[0][0] * v0 + dw[0][1] * v1 + dw[0][2] * v2;
-                        vn[a] += lw * A0;
-                        Lm[a][0] += lw * A2;
-                        Lm[a][1] += ldw1 * A0;
-                        if constexpr (D == 3) Lm[a][2] += (w[1][ky] * dw[2][kz]) * A0;
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            // reverse of the constitutive update
-            T Lb[D][D];
-            if constexpr (MAT == MAT_FLUID) {
-                T Jb_in;
-                fluid_vjp<T, D>(P, Lm, st.G[j], aout.G[s], aout.S[s], Lb, Jb_in);
-                mid[ML::G * cap + s] = Jb_in;
-            } else {
-                T G[D][D], Gb[D][D], Gb_in[D][D], sb[NS];
-#pragma unroll
-                for (int a = 0; a < D; ++a)
-#pragma unroll
-                    for (int b = 0; b < D; ++b) {
-                        G[a][b] = st.G[(a * D + b) * cap + j];
-                        Gb[a][b] = aout.G[(a * D + b) * cap + s];
-                    }
-#pragma unroll
-                for (int q = 0; q < NS; ++q) sb[q] = aout.S[q * cap + s];
-                hencky_vjp<T, D>(P, MAT == MAT_SAND, Lm, G, Gb, sb, Lb, Gb_in);
-#pragma unroll
-                for (int a = 0; a < D; ++a)
-#pragma unroll
-                    for (int b = 0; b < D; ++b) mid[(ML::G + a * D + b) * cap + s] = Gb_in[a][b];
-            }
-            // x' = clamp(x + dt v'): no gradient through a clamped component
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                T xb = aout.x[a * cap + s];
-                T xn = xp[a] + P.dt * vn[a];
-                bool free_ = (xn >= T(0)) && (xn <= P.ext[a]);
-                mid[(ML::X + a) * cap + s] = free_ ? xb : T(0);
-                mid[(ML::VT + a) * cap + s] = aout.v[a * cap + s] + (free_ ? P.dt * xb : T(0));
-#pragma unroll
-                for (int b = 0; b < D; ++b) mid[(ML::LB + a * D + b) * cap + s] = Lb[a][b];
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// Reverse of G2P per particle of a tile: node adjoints of the velocity
-// (accumulated in binary64 in LDS, then written as the tile's partial
-// block) and the position adjoint through the weights and x_i - x_p.
-template <class T, int D>
-__global__ __launch_bounds__(kAdjBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
-                                                         const ActiveTile* __restrict__ active,
-                                                         const int* __restrict__ perm, PView<T> st, PView<T> aout,
-                                                         const T* __restrict__ gv, T* __restrict__ part,
-                                                         T* __restrict__ mid)
-{
-    constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     using ML = MidLayout<D>;
     __shared__ T s_v[D][NB];
     __shared__ double s_b[D][NB];
@@ -185,125 +74,206 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj_grid(Geo g, Phys<T> P, co
         for (int k = tid; k < at.cnt; k += kAdjBlock) {
             long long s = at.off + k;
             int j = perm[s];
-            T w[D][3], dw[D][3], dd[D][3];
-            int lb[3] = {0, 0, 0};
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                int b;
-                T f;
-                stencil_axis(st.x[a * cap + j], P.inv, b, f, w[a], dw[a]);
-                int l = b + g.G - tc[a] * TE;
-                lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
-            }
-            T xbar[D], vt[D], Cb[D][D], Lb[D][D];
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                xbar[a] = mid[(ML::X + a) * cap + s];
-                vt[a] = mid[(ML::VT + a) * cap + s];
-#pragma unroll
-                for (int b = 0; b < D; ++b) {
-                    Cb[a][b] = aout.C[(a * D + b) * cap + s];
-                    Lb[a][b] = mid[(ML::LB + a * D + b) * cap + s];
-                }
-            }
-            // Line by line along x (per-axis weight factors).  Node adjoint of
-            // the velocity, scattered:
-            //   phi (vt + Dinv Cb dd) + Lb grad phi = w_x U + w_x dd_x V + dw_x W.
-            // Position adjoint, gathered with u = Cb^T v_i, g = Lb^T v_i,
-            // wbar = v_i.vt + Dinv dd.u:
-            //   xbar += sum wbar grad phi + sum Hess(phi) g - Dinv Cb^T vn,
-            // vn = sum phi v_i (the forward G2P velocity).
-            constexpr int NL = (D == 3) ? 9 : 3;
-            const T ddw[3] = {inv2, T(-2) * inv2, inv2};
-            T X1[D], X2[D], vn[D];
-#pragma unroll
-            for (int a = 0; a < D; ++a) { X1[a] = T(0); X2[a] = T(0); vn[a] = T(0); }
-#pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                const int ky = l % 3, kz = l / 3;
-                const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
-                const T wy = w[1][ky], dwy = dw[1][ky];
-                const T wz = (D == 3) ? w[D - 1][kz] : T(1), dwz = (D == 3) ? dw[D - 1][kz] : T(0);
-                const T ddz = (D == 3) ? dd[D - 1][kz] : T(0);
-                const T wyz = wy * wz;
-                T U[D], V[D], Wl[D];
-#pragma unroll
+            T xbar_c[D], vt_c[D], Lb_c[D][D];
+            {
+                T xp[D], w[D][3], dw[D][3];
+                int lb[3] = {0, 0, 0};
+    #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    T u = vt[a] + P.Dinv * Cb[a][1] * dd[1][ky];
-                    if constexpr (D == 3) u += P.Dinv * Cb[a][D - 1] * ddz;
-                    u = wyz * u + Lb[a][1] * dwy * wz;
-                    if constexpr (D == 3) u += Lb[a][D - 1] * wy * dwz;
-                    U[a] = u;
-                    V[a] = wyz * P.Dinv * Cb[a][0];
-                    Wl[a] = wyz * Lb[a][0];
+                    xp[a] = st.x[a * cap + j];
+                    int b;
+                    T f;
+                    stencil_axis(xp[a], P.inv, b, f, w[a], dw[a]);
+                    int l = b + g.G - tc[a] * TE;
+                    lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
                 }
-                T A = T(0), B = T(0), VN[D], Cx[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-                for (int a = 0; a < D; ++a) VN[a] = T(0);
-#pragma unroll
-                for (int kx = 0; kx < 3; ++kx) {
-                    const int n = n0 + kx;
-                    const T ddn[3] = {dd[0][kx], dd[1][ky], ddz};
-                    T vi[D];
-#pragma unroll
+                // forward G2P of this particle: velocity and velocity gradient,
+                // line by line along x as in the forward kernel (per-axis weight
+                // factors; a scheduling barrier per line bounds register use)
+                T vn[D], Lm[D][D];
+                {
+                    constexpr int NL = (D == 3) ? 9 : 3;
+    #pragma unroll
                     for (int a = 0; a < D; ++a) {
-                        vi[a] = s_v[a][n];
-                        T nbv = w[0][kx] * U[a] + w[0][kx] * dd[0][kx] * V[a] + dw[0][kx] * Wl[a];
-                        atomicAdd(&s_b[a][n], (double)nbv);
+                        vn[a] = T(0);
+    #pragma unroll
+                        for (int b = 0; b < D; ++b) Lm[a][b] = T(0);
                     }
-                    T wbar = T(0), gq[D];
-#pragma unroll
-                    for (int b = 0; b < D; ++b) {
-                        T ub = T(0), gb = T(0);
-#pragma unroll
+    #pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        const int ky = l % 3, kz = l / 3;
+                        const T lw = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
+                        const T ldw1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
+                        const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
+    #pragma unroll
                         for (int a = 0; a < D; ++a) {
-                            ub += Cb[a][b] * vi[a];
-                            gb += Lb[a][b] * vi[a];
+                            T v0 = s_v[a][n0], v1 = s_v[a][n0 + 1], v2 = s_v[a][n0 + 2];
+                            T A0 = w[0][0] * v0 + w[0][1] * v1 + w[0][2] * v2;
+                            T A2 = dw[0][0] * v0 + dw[0][1] * v1 + dw[0][2] * v2;
+                            vn[a] += lw * A0;
+                            Lm[a][0] += lw * A2;
+                            Lm[a][1] += ldw1 * A0;
+                            if constexpr (D == 3) Lm[a][2] += (w[1][ky] * dw[2][kz]) * A0;
                         }
-                        gq[b] = gb;
-                        wbar += vi[b] * vt[b] + P.Dinv * ddn[b] * ub;
-                    }
-                    A += wbar * dw[0][kx];
-                    B += wbar * w[0][kx];
-#pragma unroll
-                    for (int a = 0; a < D; ++a) VN[a] += vi[a] * w[0][kx];
-                    Cx[0] += gq[0] * ddw[kx];
-                    Cx[1] += gq[1] * dw[0][kx];
-                    Cx[3] += gq[0] * dw[0][kx];
-                    Cx[4] += gq[1] * w[0][kx];
-                    if constexpr (D == 3) {
-                        Cx[2] += gq[D - 1] * dw[0][kx];
-                        Cx[5] += gq[D - 1] * w[0][kx];
+                        __builtin_amdgcn_sched_barrier(0);
                     }
                 }
-#pragma unroll
-                for (int a = 0; a < D; ++a) vn[a] += wyz * VN[a];
-                if constexpr (D == 3) {
-                    X1[0] += wyz * A;
-                    X1[1] += dwy * wz * B;
-                    X1[2] += wy * dwz * B;
-                    X2[0] += wyz * Cx[0] + dwy * wz * Cx[1] + wy * dwz * Cx[2];
-                    X2[1] += dwy * wz * Cx[3] + ddw[ky] * wz * Cx[4] + dwy * dwz * Cx[5];
-                    X2[2] += wy * dwz * Cx[3] + dwy * dwz * Cx[4] + wy * ddw[kz] * Cx[5];
+                // reverse of the constitutive update
+                T Lb[D][D];
+                if constexpr (MAT == MAT_FLUID) {
+                    T Jb_in;
+                    fluid_vjp<T, D>(P, Lm, st.G[j], aout.G[s], aout.S[s], Lb, Jb_in);
+                    mid[ML::G * cap + s] = Jb_in;
                 } else {
-                    X1[0] += wy * A;
-                    X1[1] += dwy * B;
-                    X2[0] += wy * Cx[0] + dwy * Cx[1];
-                    X2[1] += dwy * Cx[3] + ddw[ky] * Cx[4];
+                    T G[D][D], Gb[D][D], Gb_in[D][D], sb[NS];
+    #pragma unroll
+                    for (int a = 0; a < D; ++a)
+    #pragma unroll
+                        for (int b = 0; b < D; ++b) {
+                            G[a][b] = st.G[(a * D + b) * cap + j];
+                            Gb[a][b] = aout.G[(a * D + b) * cap + s];
+                        }
+    #pragma unroll
+                    for (int q = 0; q < NS; ++q) sb[q] = aout.S[q * cap + s];
+                    hencky_vjp<T, D>(P, MAT == MAT_SAND, Lm, G, Gb, sb, Lb, Gb_in);
+    #pragma unroll
+                    for (int a = 0; a < D; ++a)
+    #pragma unroll
+                        for (int b = 0; b < D; ++b) mid[(ML::G + a * D + b) * cap + s] = Gb_in[a][b];
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                // x' = clamp(x + dt v'): no gradient through a clamped component
+    #pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    T xb = aout.x[a * cap + s];
+                    T xn = xp[a] + P.dt * vn[a];
+                    bool free_ = (xn >= T(0)) && (xn <= P.ext[a]);
+                    xbar_c[a] = free_ ? xb : T(0);
+                    vt_c[a] = aout.v[a * cap + s] + (free_ ? P.dt * xb : T(0));
+    #pragma unroll
+                    for (int b = 0; b < D; ++b) Lb_c[a][b] = Lb[a][b];
+                }
             }
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                T t = X1[c] + X2[c];
-#pragma unroll
-                for (int a = 0; a < D; ++a) t -= P.Dinv * Cb[a][c] * vn[a];
-                xbar[c] += t;
+            {
+                T w[D][3], dw[D][3], dd[D][3];
+                int lb[3] = {0, 0, 0};
+    #pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    int b;
+                    T f;
+                    stencil_axis(st.x[a * cap + j], P.inv, b, f, w[a], dw[a]);
+                    int l = b + g.G - tc[a] * TE;
+                    lb[a] = l < 0 ? 0 : (l > TE - 1 ? TE - 1 : l);
+    #pragma unroll
+                    for (int q = 0; q < 3; ++q) dd[a][q] = (T(q) - f) * P.h;
+                }
+                T xbar[D], vt[D], Cb[D][D], Lb[D][D];
+    #pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    xbar[a] = xbar_c[a];
+                    vt[a] = vt_c[a];
+    #pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        Cb[a][b] = aout.C[(a * D + b) * cap + s];
+                        Lb[a][b] = Lb_c[a][b];
+                    }
+                }
+                // Line by line along x (per-axis weight factors).  Node adjoint of
+                // the velocity, scattered:
+                //   phi (vt + Dinv Cb dd) + Lb grad phi = w_x U + w_x dd_x V + dw_x W.
+                // Position adjoint, gathered with u = Cb^T v_i, g = Lb^T v_i,
+                // wbar = v_i.vt + Dinv dd.u:
+                //   xbar += sum wbar grad phi + sum Hess(phi) g - Dinv Cb^T vn,
+                // vn = sum phi v_i (the forward G2P velocity).
+                constexpr int NL = (D == 3) ? 9 : 3;
+                const T ddw[3] = {inv2, T(-2) * inv2, inv2};
+                T X1[D], X2[D], vn[D];
+    #pragma unroll
+                for (int a = 0; a < D; ++a) { X1[a] = T(0); X2[a] = T(0); vn[a] = T(0); }
+    #pragma unroll
+                for (int l = 0; l < NL; ++l) {
+                    const int ky = l % 3, kz = l / 3;
+                    const int n0 = (D == 3) ? ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] : (lb[1] + ky) * BE + lb[0];
+                    const T wy = w[1][ky], dwy = dw[1][ky];
+                    const T wz = (D == 3) ? w[D - 1][kz] : T(1), dwz = (D == 3) ? dw[D - 1][kz] : T(0);
+                    const T ddz = (D == 3) ? dd[D - 1][kz] : T(0);
+                    const T wyz = wy * wz;
+                    T U[D], V[D], Wl[D];
+    #pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        T u = vt[a] + P.Dinv * Cb[a][1] * dd[1][ky];
+                        if constexpr (D == 3) u += P.Dinv * Cb[a][D - 1] * ddz;
+                        u = wyz * u + Lb[a][1] * dwy * wz;
+                        if constexpr (D == 3) u += Lb[a][D - 1] * wy * dwz;
+                        U[a] = u;
+                        V[a] = wyz * P.Dinv * Cb[a][0];
+                        Wl[a] = wyz * Lb[a][0];
+                    }
+                    T A = T(0), B = T(0), VN[D], Cx[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    #pragma unroll
+                    for (int a = 0; a < D; ++a) VN[a] = T(0);
+    #pragma unroll
+                    for (int kx = 0; kx < 3; ++kx) {
+                        const int n = n0 + kx;
+                        const T ddn[3] = {dd[0][kx], dd[1][ky], ddz};
+                        T vi[D];
+    #pragma unroll
+                        for (int a = 0; a < D; ++a) {
+                            vi[a] = s_v[a][n];
+                            T nbv = w[0][kx] * U[a] + w[0][kx] * dd[0][kx] * V[a] + dw[0][kx] * Wl[a];
+                            atomicAdd(&s_b[a][n], (double)nbv);
+                        }
+                        T wbar = T(0), gq[D];
+    #pragma unroll
+                        for (int b = 0; b < D; ++b) {
+                            T ub = T(0), gb = T(0);
+    #pragma unroll
+                            for (int a = 0; a < D; ++a) {
+                                ub += Cb[a][b] * vi[a];
+                                gb += Lb[a][b] * vi[a];
+                            }
+                            gq[b] = gb;
+                            wbar += vi[b] * vt[b] + P.Dinv * ddn[b] * ub;
+                        }
+                        A += wbar * dw[0][kx];
+                        B += wbar * w[0][kx];
+    #pragma unroll
+                        for (int a = 0; a < D; ++a) VN[a] += vi[a] * w[0][kx];
+                        Cx[0] += gq[0] * ddw[kx];
+                        Cx[1] += gq[1] * dw[0][kx];
+                        Cx[3] += gq[0] * dw[0][kx];
+                        Cx[4] += gq[1] * w[0][kx];
+                        if constexpr (D == 3) {
+                            Cx[2] += gq[D - 1] * dw[0][kx];
+                            Cx[5] += gq[D - 1] * w[0][kx];
+                        }
+                    }
+    #pragma unroll
+                    for (int a = 0; a < D; ++a) vn[a] += wyz * VN[a];
+                    if constexpr (D == 3) {
+                        X1[0] += wyz * A;
+                        X1[1] += dwy * wz * B;
+                        X1[2] += wy * dwz * B;
+                        X2[0] += wyz * Cx[0] + dwy * wz * Cx[1] + wy * dwz * Cx[2];
+                        X2[1] += dwy * wz * Cx[3] + ddw[ky] * wz * Cx[4] + dwy * dwz * Cx[5];
+                        X2[2] += wy * dwz * Cx[3] + dwy * dwz * Cx[4] + wy * ddw[kz] * Cx[5];
+                    } else {
+                        X1[0] += wy * A;
+                        X1[1] += dwy * B;
+                        X2[0] += wy * Cx[0] + dwy * Cx[1];
+                        X2[1] += dwy * Cx[3] + ddw[ky] * Cx[4];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+    #pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    T t = X1[c] + X2[c];
+    #pragma unroll
+                    for (int a = 0; a < D; ++a) t -= P.Dinv * Cb[a][c] * vn[a];
+                    xbar[c] += t;
+                }
+    #pragma unroll
+                for (int a = 0; a < D; ++a) mid[(ML::X + a) * cap + s] = xbar[a];
             }
-#pragma unroll
-            for (int a = 0; a < D; ++a) mid[(ML::X + a) * cap + s] = xbar[a];
         }
         __syncthreads();
         T* dst = part + (long long)e * (D + 1) * NB;
@@ -851,10 +821,8 @@ struct Adjoint {
         hipStream_t st = c->stream;
         const Geo& g = c->geo;
         prof_mark(c, -1);
-        k_g2p_adj_cons<T, D, MAT><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
-                                                               (const T*)rb.gv, (T*)c->mid);
-        k_g2p_adj_grid<T, D><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in, aout,
-                                                          (const T*)rb.gv, (T*)c->part_grid, (T*)c->mid);
+        k_g2p_adj<T, D, MAT><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in,
+                                                              aout, (const T*)rb.gv, (T*)c->part_grid, (T*)c->mid);
         prof_mark(c, MPM_PROF_G2P_ADJ);
         k_grid_adj<T, D><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.tile_slot,
                                                       (const T*)c->part_grid, rb.gmass, (const T*)rb.gvt, rb.gv,

@@ -75,7 +75,7 @@ struct mpm_ctx {
     char* tape = nullptr;          // a segment's recomputed states (ckpt_every + 1)
     int32_t* tape_pid = nullptr;
     char* adj[2] = {nullptr, nullptr};   // adjoint states (same layout as a state)
-    void* mid = nullptr;           // per slot: position, F (or J), G2P velocity and velocity-gradient adjoints
+    void* mid = nullptr;           // per slot: position and F (or J) adjoints between the reverse kernels
     char* gtape = nullptr;         // per step of a segment: the grid and sort it used
     mpm::GridRec grec;
     int32_t* inv = nullptr;        // slot of each pid
