@@ -165,8 +165,9 @@ def test_floor_friction_field(orc):
     assert rel_l2(g["x"], r["x"]) <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("N,cells", [(3000, 8), (900, 2)])
-def test_crowded_tile_uses_global_sort(orc, N, cells):
+def test_crowded_tile_uses_global_sort(orc, N, cells, precision):
     """One tile holding more particles than the in-LDS sort takes (1024:
     the sort runs in global memory), or fewer but with more than 64 per
     cell (ranks past the 64-entry rank table)."""
@@ -177,19 +178,22 @@ def test_crowded_tile_uses_global_sort(orc, N, cells):
     lo = (8 - 2 + 0.5) * cfg.dx + 1e-6
     hi = (8 + cells - 2 + 0.5) * cfg.dx - 1e-6
     x = rng.uniform(lo, hi, size=(2, N))
-    print(f"[case] crowded tile N={N} over {cells}x{cells} cells", flush=True)
-    o = orc.Oracle(cfg)
+    if precision == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    print(f"[case] crowded tile N={N} over {cells}x{cells} cells {precision}", flush=True)
+    o = orc.Oracle(cfg, key_f32=(precision == "f32"))
     st = oracle_state(orc, cfg, x)
-    s = gpu_solver(cfg, "f64", x)
+    s = gpu_solver(cfg, precision, x)
     kb = _np(s.read_keys())
     assert len(np.unique(kb >> 6)) == 1
-    perm_o, _ = o.step(st, cfg.dt)
+    o.step(st, cfg.dt)
     s.mpm_step(1)
+    assert s.mpm_sync_status()[0] == 0
     perm, _ = s.mpm_read_sort()
-    assert np.array_equal(_np(perm), perm_o)
+    assert np.array_equal(_np(perm), o.sort_perm(kb))
     g, r = gpu_fields(s), oracle_fields(cfg, st)
-    assert rel_l2(g["x"], r["x"]) <= 1e-12
-    assert rel_l2(g["v"], r["v"]) <= 1e-10
+    assert rel_l2(g["x"], r["x"]) <= (1e-12 if precision == "f64" else 2e-5)
+    assert rel_l2(g["v"], r["v"]) <= (1e-10 if precision == "f64" else 1e-4)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
