@@ -487,7 +487,8 @@ __global__ __launch_bounds__(kP2GBlock<T>) __attribute__((amdgpu_waves_per_eu(si
         // A tile that fits in LDS keeps its particles' cells and slots in
         // registers (thread t holds entries t, t + NT, ...): one batch of global
         // loads instead of one round trip per pass below.
-        constexpr int KPL = kSortCap / NT;
+        constexpr int KPL = (kSortCap + NT - 1) / NT;   // register slots per thread: KPL * NT >= kSortCap
+        static_assert(KPL * NT >= kSortCap, "the register batch must cover an in-LDS tile");
         const int nk = at.cnt - tid;                 // entry i * NT of this thread exists if below
         const int* tk = tmpk + at.off + tid;
         const int* tj = tmp + at.off + tid;
