@@ -238,7 +238,7 @@ def main():
     ap.add_argument("--scale-div", type=int, default=1, help="shrink the cylinder (tests only)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               f"(multi-GPU sharding is designed but not built)", file=sys.stderr)
         sys.exit(2)
 

@@ -33,3 +33,30 @@ def test_traffic_scales_by_the_copy(tmp_path):
     assert g["fetch_bytes"] == 200.0 * 2048 and g["write_bytes"] == 50.0 * 1024
     json.dumps(t)
     assert len(t["csrc_sha256"]) == 64
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_measured_traffic_sums_kernels_and_checks_the_sources(tmp_path, monkeypatch):
+    import bench
+    t = {"csrc_sha256": R.kernel_sources_hash(),
+         "kernels": {"a": {"fetch_bytes": 10.0, "write_bytes": 5.0},
+                     "b": {"fetch_bytes": 1.0, "write_bytes": 2.0}}}
+    f = tmp_path / "traffic.txt"
+    f.write_text(json.dumps(t))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("a") == 15.0
+    assert bench.measured_traffic(["a", "b"]) == 18.0
+    assert bench.measured_traffic(["a", "missing"]) is None
+    t["csrc_sha256"] = "0" * 64            # counters taken on other sources
+    f.write_text(json.dumps(t))
+    assert bench.measured_traffic("a") is None
