@@ -73,7 +73,9 @@ def _declare(L):
     L.orc_num_keys.restype = i64
     L.orc_num_keys.argtypes = [P]
     L.orc_cell_keys.argtypes = [P, i64, P, P]
-    L.orc_sort_perm.argtypes = [i64, P, P]
+    L.orc_cells_per_tile.restype = ct.c_int32
+    L.orc_cells_per_tile.argtypes = [P]
+    L.orc_sort_perm.argtypes = [i64, P, ct.c_int32, P]
     L.orc_p2g.argtypes = [P, i64, f64, P, P, P, P, P, P]
     L.orc_grid_update.argtypes = [P, f64, P, P, P, P]
     L.orc_g2p.argtypes = [P, i64, f64, P, P, P, P, P]
@@ -186,11 +188,16 @@ class Oracle:
     def num_keys(self):
         return int(self.L.orc_num_keys(ct.byref(self.c)))
 
+    def cells_per_tile(self):
+        return int(self.L.orc_cells_per_tile(ct.byref(self.c)))
+
     @staticmethod
-    def sort_perm(key):
+    def sort_perm(key, cells_per_tile=64):
+        """The step's order of particles with cell keys `key` (tile =
+        key // cells_per_tile; every workload here has 64 cells per tile)."""
         key = np.ascontiguousarray(key, dtype=np.int32)
         perm = np.empty_like(key)
-        lib().orc_sort_perm(key.shape[0], _ptr(key), _ptr(perm))
+        lib().orc_sort_perm(key.shape[0], _ptr(key), int(cells_per_tile), _ptr(perm))
         return perm
 
     def p2g(self, st: State, dt):

@@ -172,12 +172,13 @@ static int cmp_keyslot(const void* pa, const void* pb)
     return 0;
 }
 
-/* Sort order of a step.  Particles are grouped by tile (key >> 6); inside a
- * tile they are ordered by their rank within their cell (the number of
- * particles of the same key at smaller current slots), then by the cell
- * (key & 63).  So the r-th particles of all cells of a tile sit next to each
- * other.  Computed in two plain passes: a sort by (key, slot) gives the
- * ranks, a sort by (tile, rank, cell) the order. */
+/* Sort order of a step.  Particles are grouped by tile (key / cpt, with
+ * cpt = cells per tile = T^d); inside a tile they are ordered by their rank
+ * within their cell (the number of particles of the same key at smaller
+ * current slots), then by the cell (key % cpt).  So the r-th particles of
+ * all cells of a tile sit next to each other.  Computed in two plain
+ * passes: a sort by (key, slot) gives the ranks, a sort by (tile, rank,
+ * cell) the order. */
 typedef struct {
     int32_t tile, rank, cell, slot;
 } trc;
@@ -192,7 +193,14 @@ static int cmp_trc(const void* a, const void* b)
     return 0;
 }
 
-void orc_sort_perm(int64_t N, const int32_t* key, int32_t* perm)
+int32_t orc_cells_per_tile(const orc_config* c)
+{
+    int32_t k = 1;
+    for (int a = 0; a < c->dim; ++a) k *= c->tile;
+    return k;
+}
+
+void orc_sort_perm(int64_t N, const int32_t* key, int32_t cpt, int32_t* perm)
 {
     size_t n1 = (size_t)(N > 0 ? N : 1);
     keyslot* ks = (keyslot*)malloc(sizeof(keyslot) * n1);
@@ -205,8 +213,8 @@ void orc_sort_perm(int64_t N, const int32_t* key, int32_t* perm)
     int32_t rank = 0;
     for (int64_t s = 0; s < N; ++s) {
         rank = (s > 0 && ks[s].key == ks[s - 1].key) ? rank + 1 : 0;
-        t[s].tile = ks[s].key >> 6;
-        t[s].cell = ks[s].key & 63;
+        t[s].tile = ks[s].key / cpt;
+        t[s].cell = ks[s].key % cpt;
         t[s].rank = rank;
         t[s].slot = ks[s].slot;
     }
@@ -585,7 +593,12 @@ int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9]
     double H[3] = {0, 0, 0};
     int cas;
     double dg = 0.0;
-    if (elastic_only) {
+    double en2 = 0.0;
+    for (int i = 0; i < d; ++i) en2 += eps[i] * eps[i];
+    if (elastic_only || en2 <= ORC_EPS_ELASTIC * ORC_EPS_ELASTIC) {
+        /* elastic material, or a strain below the elastic band (reading:
+         * the return is not differentiable at zero strain, so the case is
+         * fixed there instead of being left to rounding) */
         cas = 1;
         for (int i = 0; i < d; ++i) H[i] = eps[i];
     } else if (tr > 0.0) {
@@ -705,7 +718,7 @@ int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
     }
 
     orc_cell_keys(c, N, x, key);
-    orc_sort_perm(N, key, perm);
+    orc_sort_perm(N, key, orc_cells_per_tile(c), perm);
     gather_d(N, d, x, perm, tmp);
     gather_d(N, d, v, perm, tmp);
     gather_d(N, d * d, C, perm, tmp);

@@ -10,6 +10,12 @@
 enum { ORC_FLUID = 0, ORC_DP_HENCKY = 1, ORC_HENCKY_ELASTIC = 2 };
 enum { ORC_WALL_SLIP = 0, ORC_WALL_STICK = 1, ORC_WALL_COULOMB = 2 };
 
+/* Hencky strain magnitude |eps|_F at or below which the Drucker-Prager
+ * return takes the elastic case whatever the sign of tr(eps) (a reading:
+ * the apex is not differentiable, so at rounding-level strain the case is
+ * fixed by this rule rather than by the rounding of tr(eps)). */
+#define ORC_EPS_ELASTIC 1e-6
+
 typedef struct orc_config {
     int32_t dim;          /* 2 or 3 */
     int32_t n[3];         /* cells per axis */
@@ -33,7 +39,8 @@ int64_t orc_node_dims(const orc_config* c, int32_t dims[3]);
 int64_t orc_num_keys(const orc_config* c);
 int64_t orc_key_of_base(const orc_config* c, const int32_t B[3]);
 void orc_cell_keys(const orc_config* c, int64_t N, const double* x, int32_t* key);
-void orc_sort_perm(int64_t N, const int32_t* key, int32_t* perm);
+int32_t orc_cells_per_tile(const orc_config* c);
+void orc_sort_perm(int64_t N, const int32_t* key, int32_t cpt, int32_t* perm);
 void orc_p2g(const orc_config* c, int64_t N, double dt, const double* x, const double* v,
              const double* C, const double* S, double* gm, double* gp);
 void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,

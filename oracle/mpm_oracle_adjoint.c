@@ -255,7 +255,9 @@ static void hencky_tangent(const orc_config* c, int elastic_only, const double F
     dn = sqrt(dn);
     int cas;
     double alpha = orc_cone_alpha(c), cc = (d * lam + 2.0 * mu) / (2.0 * mu) * alpha;
-    if (elastic_only) cas = 1;
+    double en2 = 0.0;
+    for (int i = 0; i < d; ++i) en2 += eps[i] * eps[i];
+    if (elastic_only || en2 <= ORC_EPS_ELASTIC * ORC_EPS_ELASTIC) cas = 1;
     else if (tr > 0.0) cas = 0;
     else cas = (dn + cc * tr <= 0.0) ? 1 : 2;
 
@@ -364,7 +366,7 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
 
     /* the step's sort, applied to a copy of the input state */
     orc_cell_keys(c, N, x0, key);
-    orc_sort_perm(N, key, perm);
+    orc_sort_perm(N, key, orc_cells_per_tile(c), perm);
     for (int64_t s = 0; s < N; ++s) {
         int64_t j = perm[s];
         for (int a = 0; a < d; ++a) {

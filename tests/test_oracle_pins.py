@@ -108,29 +108,38 @@ def test_keys_match_base_cells(orc):
         assert k[p] == o.L.orc_key_of_base(ct.byref(o.c), arr)
 
 
-def _tile_rank_cell_order(key):
+def _tile_rank_cell_order(key, cpt=64):
     """The step's sort order written with numpy: group by key (stable, ties
     by slot) to get each particle's rank inside its cell, then order by
-    (tile, rank, cell)."""
+    (tile, rank, cell) with tile = key // cpt and cell = key % cpt."""
     st = np.argsort(key, kind="stable")
     ks = key[st]
     idx = np.arange(len(ks))
     first = np.r_[True, ks[1:] != ks[:-1]] if len(ks) else np.zeros(0, bool)
     rank = idx - np.maximum.accumulate(np.where(first, idx, 0))
-    return st[np.lexsort((ks & 63, rank, ks >> 6))].astype(np.int32)
+    return st[np.lexsort((ks % cpt, rank, ks // cpt))].astype(np.int32)
 
 
-def test_sort_order_brute_force(orc):
+@pytest.mark.parametrize("cpt", [64, 16])
+def test_sort_order_brute_force(orc, cpt):
     """Tiny case by counting: a particle's rank is the number of particles
-    with its key at smaller slots; the order is by (tile, rank, cell)."""
+    with its key at smaller slots; the order is by (tile, rank, cell), with
+    cpt cells per tile (64 in every workload: 4^3 in 3-D, 8^2 in 2-D; 16
+    for a 2-D tile of 4 x 4 cells)."""
     rng = np.random.default_rng(41)
     key = rng.integers(0, 200, size=300).astype(np.int32)
     t = []
     for p in range(len(key)):
         rank = sum(1 for q in range(p) if key[q] == key[p])
-        t.append((int(key[p]) >> 6, rank, int(key[p]) & 63, p))
+        t.append((int(key[p]) // cpt, rank, int(key[p]) % cpt, p))
     ref = np.array([e[3] for e in sorted(t)], dtype=np.int32)
-    assert np.array_equal(orc.Oracle.sort_perm(key), ref)
+    assert np.array_equal(orc.Oracle.sort_perm(key, cpt), ref)
+
+
+def test_cells_per_tile_follows_the_tile(orc):
+    assert orc.Oracle(small_cfg(2)).cells_per_tile() == 64
+    assert orc.Oracle(small_cfg(3)).cells_per_tile() == 64
+    assert orc.Oracle(small_cfg(2, tile=4)).cells_per_tile() == 16
 
 
 def test_sort_order_matches_definition(orc):
@@ -493,6 +502,33 @@ def test_hencky_return_invariants(orc):
             # stress is symmetric
             assert np.allclose(tau, tau.T, atol=1e-8)
         assert min(counts.values()) > 0, counts
+
+
+def test_hencky_elastic_band_at_rounding_strain(orc):
+    """Below a Hencky strain of 1e-6 (Frobenius) the return is elastic
+    whatever the sign of tr(eps) (the reading that fixes the case where the
+    return is not differentiable: a body at rest has rounding-level strain);
+    just above it the usual cases apply.  The band changes the stress by at
+    most (2 mu + d lam) times the strain, i.e. nothing at the gravity loads
+    of the workloads (1e-5 .. 1e-3 strain)."""
+    for dim in (2, 3):
+        cfg = small_cfg(dim, material=W.SAND)
+        o = orc.Oracle(cfg)
+        lam, mu = _lame(cfg)
+        for sc, want in ((0.5e-6, 1), (2e-6, 0)):
+            e = np.full(dim, sc / math.sqrt(dim))          # pure dilation: apex outside the band
+            Fe, tau, cas, _ = o.hencky_return(np.diag(np.exp(e)))
+            assert cas == want, (dim, sc, cas)
+            if cas == 1:
+                assert np.allclose(np.diag(tau), 2 * mu * e + lam * e.sum(), rtol=1e-7)
+                assert np.abs(tau).max() <= (2 * mu + dim * lam) * sc
+            else:
+                assert np.abs(tau).max() == 0.0
+        # a deviatoric strain inside the band stays elastic (outside it: the cone)
+        e = np.zeros(dim)
+        e[0], e[1] = 0.4e-6, -0.4e-6
+        assert o.hencky_return(np.diag(np.exp(e)))[2] == 1
+        assert o.hencky_return(np.diag(np.exp(10 * e)))[2] == 2
 
 
 def test_hencky_rotation_equivariance(orc):
