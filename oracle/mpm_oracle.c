@@ -486,7 +486,10 @@ static double det(int d, const double A[3][3])
 }
 
 /* Cyclic Jacobi eigen-decomposition of a symmetric d x d matrix A:
- * A = V diag(ev) V^T, iterated until the off-diagonal part is negligible. */
+ * A = V diag(ev) V^T, iterated until the off-diagonal part is negligible:
+ * below 1e-15 of the matrix norm (a few units of rounding of the diagonal;
+ * a smaller bound is below what rounding lets the rotations reach, and then
+ * every call runs out its sweep budget). */
 void orc_sym_eig(int d, const double Ain[9], double ev[3], double Vout[9])
 {
     double A[3][3], V[3][3];
@@ -502,7 +505,7 @@ void orc_sym_eig(int d, const double Ain[9], double ev[3], double Vout[9])
                 tot += A[i][j] * A[i][j];
                 if (i != j) off += A[i][j] * A[i][j];
             }
-        if (off <= 1e-36 * tot || off == 0.0)
+        if (off <= 1e-30 * tot || off == 0.0)
             break;
         for (int p = 0; p < d - 1; ++p)
             for (int q = p + 1; q < d; ++q) {
