@@ -44,7 +44,8 @@ typedef enum mpm_status {
     MPM_EHIP = -3,        /* a HIP runtime call or launch failed */
     MPM_ENONFINITE = -4,  /* a particle's state became NaN or Inf */
     MPM_EDOMAIN = -5,     /* a particle moved more than one cell in a step (CFL) */
-    MPM_ESTATE = -6       /* call made in the wrong order */
+    MPM_ESTATE = -6,      /* call made in the wrong order */
+    MPM_ECONVERGE = -7    /* binary64: a particle's eigen-solve (Hencky return) did not converge */
 } mpm_status;
 
 enum { MPM_F32 = 0, MPM_F64 = 1 };
@@ -54,7 +55,8 @@ enum { MPM_F32 = 0, MPM_F64 = 1 };
  *                 gamma = 1 with K = rho0 c^2 is eq:eos
  *  DP_HENCKY      Drucker-Prager sand: Hencky strain of F_e, radial return onto
  *                 the cone with slope (sqrt2/3) q_phi (q_phi of App. A),
- *                 stress-free apex for tr(eps) > 0
+ *                 stress-free apex for tr(eps) > 0; elastic whenever
+ *                 |eps|_F <= 1e-6 (the case at rounding-level strain)
  *  HENCKY_ELASTIC the same elastic law without the return (checks only) */
 enum { MPM_FLUID_TAIT = 0, MPM_DP_HENCKY = 1, MPM_HENCKY_ELASTIC = 2 };
 
@@ -102,7 +104,9 @@ typedef struct mpm_ctx mpm_ctx;
 
 /* Validates cfg and creates a context on the current device, bound to
  * hip_stream (a hipStream_t; NULL = default stream).  Allocates no device
- * memory.  *out receives the context; EINVAL on a bad configuration. */
+ * memory.  *out receives the context; EINVAL on a bad configuration,
+ * including a grid whose tile count times 64 reaches 2^31 (cell keys are
+ * int32). */
 int mpm_create(const mpm_config* cfg, void* hip_stream, mpm_ctx** out);
 
 /* Device bytes needed for n_particles and, if tape_steps > 0, for a
@@ -140,9 +144,11 @@ int mpm_set_floor_mu(mpm_ctx* ctx, const void* mu, int64_t count);
 int mpm_step(mpm_ctx* ctx, int32_t n, double dt);
 
 /* Synchronizes the stream and returns the latched data status: MPM_OK,
- * MPM_ENONFINITE (checked first) or MPM_EDOMAIN (|v| dt > dx on an axis:
- * the step violates the CFL condition); *bad_pid (may be NULL) gets the
- * smallest offending pid or -1.  Clears the latch. */
+ * MPM_ENONFINITE (checked first), MPM_EDOMAIN (|v| dt > dx on an axis:
+ * the step violates the CFL condition) or MPM_ECONVERGE (binary64 only: the
+ * Jacobi eigen-solve that the Hencky return falls back to for large strains
+ * ran out of sweeps before its off-diagonal part was negligible); *bad_pid
+ * (may be NULL) gets the smallest offending pid or -1.  Clears the latch. */
 int mpm_sync_status(mpm_ctx* ctx, int64_t* bad_pid);
 
 /* Copies a particle field to dst (device; int32 for PID), in memory order or
@@ -154,7 +160,8 @@ int mpm_read_state(mpm_ctx* ctx, int32_t field, int32_t order, void* dst);
 int mpm_write_state(mpm_ctx* ctx, int32_t field, int32_t order, const void* src);
 
 /* Last step's grid field (see MPM_GRID_*), dense node box, device dst.
- * MASS needs keep_grid = 1. */
+ * Nodes outside the last step's active tiles (no particle near them) read
+ * as zero.  MASS needs keep_grid = 1. */
 int mpm_read_grid(mpm_ctx* ctx, int32_t which, void* dst);
 
 /* Last step's sort: perm[s] = memory slot, before the step, of the particle

@@ -31,6 +31,13 @@ int check_config(const mpm_config* c, std::string& why)
     for (int a = 0; a < c->dim; ++a)
         if (c->n[a] < 1 || c->n[a] > 8192) { why = "cells per axis must be in [1, 8192]"; return MPM_EINVAL; }
     if (c->ghost < 1 || c->ghost > 8) { why = "ghost must be in [1, 8]"; return MPM_EINVAL; }
+    {
+        // cell keys are int32: tile count * 64 cells must stay below 2^31
+        long long tiles = 1;
+        int T = c->dim == 3 ? 4 : 8;
+        for (int a = 0; a < c->dim; ++a) tiles *= ((long long)c->n[a] + 2 * c->ghost + 1 + T - 1) / T;
+        if (tiles * 64 >= (1ll << 31)) { why = "grid too large for 32-bit cell keys (tiles * 64 >= 2^31)"; return MPM_EINVAL; }
+    }
     int want_tile = c->dim == 3 ? 4 : 8;
     if (c->tile != 0 && c->tile != want_tile) { why = "tile must be 4 in 3D and 8 in 2D (64 cells per tile)"; return MPM_EINVAL; }
     if (!(c->dx > 0.0) || !isfinite(c->dx)) { why = "dx must be positive"; return MPM_EINVAL; }
@@ -210,11 +217,6 @@ int mpm_create(const mpm_config* cfg, void* hip_stream, mpm_ctx** out)
         return MPM_EHIP;
     }
     c->geo = make_geo(c->cfg);
-    if ((long long)c->geo.ntiles * 64 >= (1ll << 31)) {
-        g_create_error = "grid too large for 32-bit cell keys";
-        delete c;
-        return MPM_EINVAL;
-    }
     c->elem = cfg->precision == MPM_F64 ? 8 : 4;
     c->nsc = nsc_of(c->cfg);
     c->nsym = nsym_of(cfg->dim);
@@ -350,10 +352,10 @@ int mpm_sync_status(mpm_ctx* c, int64_t* bad_pid)
     if (bad_pid) *bad_pid = -1;
     rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     if (rc) return rc;
-    int32_t h[3];
+    int32_t h[4];
     rc = hip_check(c, hipMemcpy(h, c->status, sizeof(h), hipMemcpyDeviceToHost), "status read");
     if (rc) return rc;
-    int32_t clear[3] = {0, 0x7fffffff, 0x7fffffff};
+    int32_t clear[4] = {0, 0x7fffffff, 0x7fffffff, 0x7fffffff};
     rc = hip_check(c, hipMemcpy(c->status, clear, sizeof(clear), hipMemcpyHostToDevice), "status clear");
     if (rc) return rc;
     if (h[0] & 1) {
@@ -364,6 +366,11 @@ int mpm_sync_status(mpm_ctx* c, int64_t* bad_pid)
         if (bad_pid) *bad_pid = h[2];
         return set_err(c, MPM_EDOMAIN, "a particle moved more than one cell in a step (pid " + std::to_string(h[2]) +
                                            "): the time step violates the CFL condition");
+    }
+    if (h[0] & 4) {
+        if (bad_pid) *bad_pid = h[3];
+        return set_err(c, MPM_ECONVERGE, "the binary64 eigen-solve of the Hencky return did not converge (pid " +
+                                             std::to_string(h[3]) + ")");
     }
     return MPM_OK;
 }

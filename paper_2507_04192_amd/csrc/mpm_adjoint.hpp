@@ -930,6 +930,9 @@ struct Adjoint {
             rc = hip_check(c, hipMemcpyAsync(c->perm, last.perm, (size_t)c->cap * 4, hipMemcpyDeviceToDevice, st),
                            "sort copy");
             if (!rc) rc = hip_check(c, hipMemcpyAsync(c->gv, last.gv, D * nn, hipMemcpyDeviceToDevice, st), "grid copy");
+            if (!rc)
+                rc = hip_check(c, hipMemcpyAsync(c->tile_slot, last.tile_slot, (size_t)c->geo.ntiles * 4,
+                                                 hipMemcpyDeviceToDevice, st), "grid copy");
             if (!rc && c->cfg.keep_grid)
                 rc = hip_check(c, hipMemcpyAsync(c->gmass, last.gmass, nn, hipMemcpyDeviceToDevice, st), "grid copy");
             if (rc) return rc;

@@ -148,7 +148,10 @@ __device__ __forceinline__ void hencky_vjp_eig(const Phys<T>& P, bool plastic, c
     }
     T dn = sqrt(dn2);
     int cas = 1;
-    if (plastic) {
+    T en2 = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) en2 += eps[i] * eps[i];
+    if (plastic && en2 > eps_elastic2<T>()) {
         if (tr > T(0)) cas = 0;
         else if (dn + P.cone_coef * tr > T(0)) cas = 2;
     }
@@ -468,7 +471,7 @@ __device__ __forceinline__ bool hencky_vjp_series(const Phys<T>& P, bool plastic
     T n = sqrt(Eh.norm2());
     int cas = 1;
     T r = T(0);
-    if (plastic) {
+    if (plastic && E.norm2() > eps_elastic2<T>()) {
         if (trE > T(0)) cas = 0;
         else {
             T dg = n + P.cone_coef * trE;

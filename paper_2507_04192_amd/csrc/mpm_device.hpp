@@ -122,7 +122,8 @@ __device__ __forceinline__ void wave_runs(int v, bool valid, int& head_lane, int
 // Symmetric eigen-decomposition by cyclic Jacobi rotations, in registers.
 // A = V diag(ev) V^T.  Packed input: 3D (a00,a11,a22,a01,a02,a12);
 // 2D (a00,a11,a01).  Float stops after a fixed sweep budget; double iterates
-// until the off-diagonal part is negligible.
+// until the off-diagonal part is negligible and returns false if the sweep
+// budget ran out first (float always returns true).
 // ---------------------------------------------------------------------------
 
 template <class T> struct JacobiTol;
@@ -144,7 +145,7 @@ __device__ __forceinline__ void jacobi_rot(T& app, T& aqq, T& apq, T& c, T& s)
 }
 
 template <class T>
-__device__ __forceinline__ void sym_eig3(const T a_in[6], T ev[3], T V[3][3])
+__device__ __forceinline__ bool sym_eig3(const T a_in[6], T ev[3], T V[3][3])
 {
     T a00 = a_in[0], a11 = a_in[1], a22 = a_in[2], a01 = a_in[3], a02 = a_in[4], a12 = a_in[5];
 #pragma unroll
@@ -199,6 +200,9 @@ __device__ __forceinline__ void sym_eig3(const T a_in[6], T ev[3], T V[3][3])
     ev[0] = a00;
     ev[1] = a11;
     ev[2] = a22;
+    if constexpr (sizeof(T) == 4) return true;
+    T off = a01 * a01 + a02 * a02 + a12 * a12;
+    return off <= JacobiTol<T>::rel * (a00 * a00 + a11 * a11 + a22 * a22);
 }
 
 template <class T>
@@ -212,6 +216,13 @@ __device__ __forceinline__ void sym_eig2(const T a_in[3], T ev[2], T V[2][2])
     ev[0] = a00;
     ev[1] = a11;
 }
+
+// Hencky strain magnitude |eps|_F at or below which the Drucker-Prager
+// return takes the elastic case whatever the sign of tr(eps).  The return is
+// not differentiable at zero strain; this fixes the case there (a body at
+// rest, whose strain is rounding noise) instead of leaving it to rounding.
+// The resulting stress is at most E times this strain.
+template <class T> __device__ __forceinline__ constexpr T eps_elastic2() { return T(1e-12); }
 
 // ---------------------------------------------------------------------------
 // Constitutive updates.  S is V0 * Kirchhoff stress (= V_p sigma_p), stored
@@ -259,9 +270,10 @@ __device__ __forceinline__ void fluid_update(const Phys<T>& P, const T L[D][D], 
 // with dgamma = |dev| + (d lam + 2 mu)/(2 mu) alpha tr(eps).  Then
 // F_e' = U diag(exp(H - eps)) U^T F_tr and tau = U diag(2 mu H + lam tr H) U^T.
 template <class T, int D>
-__device__ __forceinline__ void hencky_eig(const Phys<T>& P, bool plastic, const T Gt[D][D], T G[D][D],
+__device__ __forceinline__ bool hencky_eig(const Phys<T>& P, bool plastic, const T Gt[D][D], T G[D][D],
                                        T S[D * (D + 1) / 2])
 {
+    bool conv = true;
     // b - I
     T B[D][D];
 #pragma unroll
@@ -278,7 +290,7 @@ __device__ __forceinline__ void hencky_eig(const Phys<T>& P, bool plastic, const
     if constexpr (D == 3) {
         T pk[6] = {B[0][0], B[1][1], B[2][2], B[0][1], B[0][2], B[1][2]};
         T V[3][3];
-        sym_eig3(pk, ev, V);
+        conv = sym_eig3(pk, ev, V);
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -300,7 +312,10 @@ __device__ __forceinline__ void hencky_eig(const Phys<T>& P, bool plastic, const
     }
     T H[D];
     int cas = 1;   // 0 apex, 1 elastic, 2 cone
-    if (!plastic) {
+    T en2 = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) en2 += eps[i] * eps[i];
+    if (!plastic || en2 <= eps_elastic2<T>()) {
 #pragma unroll
         for (int i = 0; i < D; ++i) H[i] = eps[i];
     } else if (tr > T(0)) {
@@ -354,7 +369,7 @@ __device__ __forceinline__ void hencky_eig(const Phys<T>& P, bool plastic, const
         for (int i = 0; i < D; ++i)
 #pragma unroll
             for (int j = 0; j < D; ++j) G[i][j] = Gt[i][j];
-        return;
+        return conv;
     }
     // G' = U diag(expm1(H - eps)) U^T (I + G_tr) + G_tr
     T e1[D];
@@ -379,6 +394,7 @@ __device__ __forceinline__ void hencky_eig(const Phys<T>& P, bool plastic, const
             for (int k = 0; k < D; ++k) s += M[i][k] * Gt[k][j];
             G[i][j] = Gt[i][j] + s;
         }
+    return conv;
 }
 
 // Small symmetric matrices, packed: 3-D (xx,yy,zz,xy,xz,yz), 2-D (xx,yy,xy).
@@ -500,7 +516,7 @@ __device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, co
     T n = sqrt(Eh.norm2());
     int cas = 1;
     T r = T(0);   // H = E - r * Ehat (cone), 0 (apex), E (elastic)
-    if (plastic) {
+    if (plastic && E.norm2() > eps_elastic2<T>()) {
         if (trE > T(0)) cas = 0;
         else {
             T dg = n + P.cone_coef * trE;
@@ -547,8 +563,10 @@ __device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, co
     return true;
 }
 
+// Returns false when the binary64 eigen-solve of the fallback did not
+// converge within its sweep budget (the caller latches it).
 template <class T, int D>
-__device__ __forceinline__ void hencky_update(const Phys<T>& P, bool plastic, const T L[D][D],
+__device__ __forceinline__ bool hencky_update(const Phys<T>& P, bool plastic, const T L[D][D],
                                               T G[D][D], T S[D * (D + 1) / 2])
 {
     T dt = P.dt;
@@ -562,7 +580,8 @@ __device__ __forceinline__ void hencky_update(const Phys<T>& P, bool plastic, co
             for (int k = 0; k < D; ++k) lg += L[i][k] * G[k][j];
             Gt[i][j] = G[i][j] + dt * lg;
         }
-    if (!hencky_series<T, D>(P, plastic, Gt, G, S)) hencky_eig<T, D>(P, plastic, Gt, G, S);
+    if (hencky_series<T, D>(P, plastic, Gt, G, S)) return true;
+    return hencky_eig<T, D>(P, plastic, Gt, G, S);
 }
 
 // ---------------------------------------------------------------------------

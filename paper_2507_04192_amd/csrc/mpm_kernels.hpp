@@ -897,7 +897,7 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
-                bool bad = false, fast = false;
+                bool bad = false, fast = false, noconv = false;
                 T xn[D];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
@@ -923,7 +923,7 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                     for (int a = 0; a < D; ++a)
 #pragma unroll
                         for (int b = 0; b < D; ++b) Gm[a][b] = cur.G[(a * D + b) * cap + j];
-                    hencky_update<T, D>(P, MAT == MAT_SAND, Lm, Gm, Sv);
+                    noconv = !hencky_update<T, D>(P, MAT == MAT_SAND, Lm, Gm, Sv);
 #pragma unroll
                     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -943,6 +943,10 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                 if (fast) {
                     atomicOr(&status[0], 2);
                     atomicMin(&status[2], pid);
+                }
+                if (noconv) {
+                    atomicOr(&status[0], 4);
+                    atomicMin(&status[3], pid);
                 }
                 newkey = cell_key<T, D>(g, xn, P.inv);
                 key_out[s] = newkey;
@@ -1047,19 +1051,38 @@ __global__ void k_iota(int32_t* p, long long n)
     if (i < n) p[i] = (int32_t)i;
 }
 
-// Dense node box (n + 1 + 2G per axis) from the tile-padded grid.
+// Dense node box (n + 1 + 2G per axis) from the tile-padded grid.  The grid
+// kernel writes only the node blocks of the step's active tiles, so a node
+// that no active tile's block covers holds a value of an earlier step; it is
+// read as zero (no mass, no velocity), which is what the step's grid holds
+// there.  tile_slot[t] >= 0 marks the active tiles of the step.
 template <class T>
-__global__ void k_read_grid(Geo g, const T* __restrict__ src, int ncomp, T* __restrict__ dst)
+__global__ void k_read_grid(Geo g, const T* __restrict__ src, int ncomp, const int* __restrict__ tile_slot,
+                            T* __restrict__ dst)
 {
     long long nbox = (long long)g.box[0] * g.box[1] * g.box[2];
     long long i = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (i >= nbox) return;
-    int I0 = (int)(i % g.box[0]);
+    int I[3];
+    I[0] = (int)(i % g.box[0]);
     long long r = i / g.box[0];
-    int I1 = (int)(r % g.box[1]);
-    int I2 = (int)(r / g.box[1]);
-    long long node = node_index(g, I0, I1, I2);
-    for (int c = 0; c < ncomp; ++c) dst[c * nbox + i] = src[c * g.NN + node];
+    I[1] = (int)(r % g.box[1]);
+    I[2] = (int)(r / g.box[1]);
+    // tiles whose (T+2)-node block holds the node: own = I / T, and own - 1
+    // where I lies in the first two nodes of its tile
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        int own = (a < g.dim) ? I[a] / g.T : 0;
+        hi[a] = own;
+        lo[a] = (a < g.dim && I[a] % g.T < 2 && own >= 1) ? own - 1 : own;
+    }
+    bool live = false;
+    for (int tz = lo[2]; tz <= hi[2]; ++tz)
+        for (int ty = lo[1]; ty <= hi[1]; ++ty)
+            for (int tx = lo[0]; tx <= hi[0]; ++tx)
+                live |= tile_slot[((long long)tz * g.ntile[1] + ty) * g.ntile[0] + tx] >= 0;
+    long long node = node_index(g, I[0], I[1], I[2]);
+    for (int c = 0; c < ncomp; ++c) dst[c * nbox + i] = live ? src[c * g.NN + node] : T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1163,7 +1186,9 @@ struct Solver {
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gv, D * NN, T(0));
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gmass, NN, T(0));
         k_fill<int><<<1, kBlock, 0, st>>>(c->status, 16, 0);
-        k_fill<int><<<1, kBlock, 0, st>>>(c->status + 1, 2, 0x7fffffff);
+        k_fill<int><<<1, kBlock, 0, st>>>(c->status + 1, 3, 0x7fffffff);
+        if (c->geo.ntiles > 0)
+            k_fill<int><<<std::min<long long>(nblocks(c->geo.ntiles), 4096), kBlock, 0, st>>>(c->tile_slot, c->geo.ntiles, -1);
         return launch_err(c, "clear grid");
     }
 
@@ -1310,9 +1335,9 @@ struct Solver {
         long long nbox = (long long)g.box[0] * g.box[1] * g.box[2];
         if (which == MPM_GRID_MASS) {
             if (!c->cfg.keep_grid) return set_err(c, MPM_EINVAL, "grid mass needs keep_grid = 1");
-            k_read_grid<T><<<nblocks(nbox), kBlock, 0, c->stream>>>(g, (const T*)c->gmass, 1, (T*)dst);
+            k_read_grid<T><<<nblocks(nbox), kBlock, 0, c->stream>>>(g, (const T*)c->gmass, 1, c->tile_slot, (T*)dst);
         } else if (which == MPM_GRID_VEL) {
-            k_read_grid<T><<<nblocks(nbox), kBlock, 0, c->stream>>>(g, (const T*)c->gv, D, (T*)dst);
+            k_read_grid<T><<<nblocks(nbox), kBlock, 0, c->stream>>>(g, (const T*)c->gv, D, c->tile_slot, (T*)dst);
         } else {
             return set_err(c, MPM_EINVAL, "unknown grid field");
         }

@@ -16,9 +16,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpm.so")
 
-MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EHIP, MPM_ENONFINITE, MPM_EDOMAIN, MPM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EHIP, MPM_ENONFINITE, MPM_EDOMAIN, MPM_ESTATE, MPM_ECONVERGE = \
+    0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "EDOMAIN",
-                -6: "ESTATE"}
+                -6: "ESTATE", -7: "ECONVERGE"}
 MPM_F32, MPM_F64 = 0, 1
 MATERIAL = {"fluid": 0, "sand": 1, "elastic": 2}
 WALL = {"slip": 0, "stick": 1, "coulomb": 2}

@@ -14,10 +14,6 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))
 
 
-def sym_to_full(S):
-    return S
-
-
 def oracle_state(orc, cfg, x, v=None, C=None, G=None, S=None, Jm1=None):
     d = cfg.dim
     N = x.shape[1]
@@ -65,3 +61,23 @@ def oracle_fields(cfg, st):
             F[a * d + a] -= 1.0
         out["FmI"] = F
     return out
+
+
+def displacement_error(x_gpu, x_ref, x0, steps, precision):
+    """Relative L2 error of the displacement x - x0 and the bound it is held
+    to: the stated tolerance (1e-10 binary64, 1e-4 binary32) plus the
+    rounding floor of storing positions in the working precision, two units
+    of rounding of the largest coordinate per step accumulated as a random
+    walk over the steps, relative to the rms displacement.  Positions alone
+    (rel-L2 of x) cannot test a short run: its displacement is far below
+    the positions' size."""
+    x_gpu = np.asarray(x_gpu, dtype=np.float64)
+    x_ref = np.asarray(x_ref, dtype=np.float64)
+    x0 = np.asarray(x0, dtype=np.float64)
+    d_ref = x_ref - x0
+    err = rel_l2(x_gpu - x0, d_ref)
+    eps = np.finfo(np.float32 if precision == "f32" else np.float64).eps
+    rms = np.sqrt(np.mean(d_ref ** 2))
+    floor = 2.0 * eps * np.abs(x0).max() * np.sqrt(steps) / max(rms, 1e-300)
+    tol = (1e-4 if precision == "f32" else 1e-10) + floor
+    return err, tol

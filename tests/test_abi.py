@@ -54,3 +54,27 @@ def test_config_validation_without_gpu():
     # a null context is rejected, not dereferenced
     assert L.mpm_step(None, 1, 1e-4) == native.MPM_EINVAL
     assert L.mpm_destroy(None) == 0
+
+
+def test_grid_beyond_int32_keys_is_rejected():
+    """Cell keys are int32 (tile * 64 + cell): a grid whose tile count times
+    64 reaches 2^31 is an EINVAL from both mpm_workspace_bytes and
+    mpm_create, computed without overflow; the largest grid below the
+    limit is accepted."""
+    from paper_2507_04192_amd import native
+    from paper_2507_04192_amd import workloads as W
+    L = native.lib()
+    nb = ct.c_size_t()
+    cfg = W.SimConfig(dim=3, n=(8192, 8192, 8192), dx=1e-3, dt=1e-5, material=W.SAND, ppc=8)
+    c = native.make_config(cfg, "f32")
+    assert L.mpm_workspace_bytes(ct.byref(c), 10, 0, 0, ct.byref(nb)) == native.MPM_EINVAL
+    assert b"32-bit cell keys" in L.mpm_last_error(None)
+    ctx = ct.c_void_p()
+    assert L.mpm_create(ct.byref(c), None, ct.byref(ctx)) == native.MPM_EINVAL
+    # 2^31 / 64 = 2^25 tiles.  With 4^3-cell tiles, 8192 x 8192 cells take
+    # ceil(8197 / 4)^2 = 2050^2 tile columns: 7 tiles deep (n_z = 23) is
+    # below the limit, 8 (n_z = 24) above it
+    below = W.SimConfig(dim=3, n=(8192, 8192, 23), dx=1e-3, dt=1e-5, material=W.SAND, ppc=8)
+    above = below.replace(n=(8192, 8192, 24))
+    assert L.mpm_workspace_bytes(ct.byref(native.make_config(below, "f32")), 10, 0, 0, ct.byref(nb)) == 0
+    assert L.mpm_workspace_bytes(ct.byref(native.make_config(above, "f32")), 10, 0, 0, ct.byref(nb)) == native.MPM_EINVAL

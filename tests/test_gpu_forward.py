@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2507_04192_amd import workloads as W
-from tests.helpers import gpu_fields, gpu_solver, oracle_fields, oracle_state, rel_l2
+from tests.helpers import displacement_error, gpu_fields, gpu_solver, oracle_fields, oracle_state, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -54,15 +54,35 @@ def test_keys_and_sort_bit_exact(orc, precision, case):
     assert rc == 0
 
 
+def _moving_velocity(cfg, x):
+    """A smooth sheared and rotating field whose speed is about 5 % of a cell
+    per step (7 m/s in the dam-break, 12 m/s in the small cylinder), so that
+    ten steps move particles by ~0.5 cells: the displacement is then far
+    above the rounding of binary32 positions."""
+    a = 0.05 * cfg.dx / cfg.dt
+    L = cfg.n[0] * cfg.dx
+    v = np.empty_like(x)
+    v[0] = a * (0.8 + 0.4 * np.sin(2 * np.pi * x[1] / L))
+    v[1] = a * 0.5 * np.cos(2 * np.pi * x[0] / L)
+    if x.shape[0] == 3:
+        v[2] = a * 0.3 * np.sin(2 * np.pi * (x[0] + x[1]) / L)
+    return v
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("case", ["dam2d", "sand3d"])
+@pytest.mark.parametrize("case", ["dam2d", "sand3d", "dam2d_moving", "sand3d_moving"])
 def test_ten_steps_match_oracle(orc, precision, case):
-    cfg, x = W.dam_break_2d() if case == "dam2d" else _small_3d()
+    cfg, x = W.dam_break_2d() if case.startswith("dam2d") else _small_3d()
     print(f"[case] 10 steps {case} {precision} N={x.shape[1]}", flush=True)
     o = orc.Oracle(cfg)
     xin = x.astype(np.float32).astype(np.float64) if precision == "f32" else x
-    st = oracle_state(orc, cfg, xin)
-    s = gpu_solver(cfg, precision, xin)
+    v0 = None
+    if case.endswith("moving"):
+        v0 = _moving_velocity(cfg, xin)
+        if precision == "f32":
+            v0 = v0.astype(np.float32).astype(np.float64)
+    st = oracle_state(orc, cfg, xin, v=v0)
+    s = gpu_solver(cfg, precision, xin, v=v0)
     o.run(st, 10, cfg.dt)
     s.mpm_step(10)
     rc, bad = s.mpm_sync_status()
@@ -70,9 +90,13 @@ def test_ten_steps_match_oracle(orc, precision, case):
     g = gpu_fields(s)
     r = oracle_fields(cfg, st)
     ex, ev = rel_l2(g["x"], r["x"]), rel_l2(g["v"], r["v"])
-    print(f"  rel L2 x={ex:.3e} v={ev:.3e}", flush=True)
+    ed, tol_d = displacement_error(g["x"], r["x"], xin, 10, precision)
+    print(f"  rel L2 x={ex:.3e} v={ev:.3e} displacement={ed:.3e} (bound {tol_d:.2e})", flush=True)
     assert ex <= TOL[precision]
     assert ev <= TOL[precision]
+    assert ed <= tol_d
+    if case.endswith("moving"):
+        assert tol_d < 3 * TOL[precision]      # the rounding floor is small here
     # the other state fields to the same order of accuracy
     tolf = 1e-8 if precision == "f64" else 5e-3
     for f in ("C", "stress", "Jm1" if cfg.material == W.FLUID else "FmI"):
@@ -102,6 +126,36 @@ def test_grid_fields_after_one_step(orc, precision):
     assert rel_l2(v_gpu, gv) <= (1e-11 if precision == "f64" else 1e-5)
     # nodes the particles never reach stay exactly empty on both sides
     assert np.array_equal(m_gpu == 0, gm == 0)
+
+
+def test_grid_read_after_many_steps(orc):
+    """The grid read back after 60 steps of the dam-break (the column has
+    collapsed, so tiles that held particles earlier are empty now): nodal
+    mass and velocity equal the oracle's, and nodes without mass read as
+    exactly empty on both sides (the grid kernel writes only the active
+    tiles' nodes; the read masks the rest)."""
+    cfg, x = W.dam_break_2d()
+    print("[case] grid read after 60 steps", flush=True)
+    rng = np.random.default_rng(37)
+    v = np.stack([rng.uniform(2.0, 3.0, x.shape[1]), rng.uniform(-0.5, 0.5, x.shape[1])])
+    o = orc.Oracle(cfg)
+    st = oracle_state(orc, cfg, x, v=v)
+    o.run(st, 59, cfg.dt)
+    _, _, gm, gv = o.step(st, cfg.dt, want_grid=True)
+    s = gpu_solver(cfg, "f64", x, v=v, keep_grid=True)
+    s.mpm_step(60)
+    assert s.mpm_sync_status()[0] == 0
+    m_gpu = _np(s.mpm_read_grid("mass"))[0]
+    v_gpu = _np(s.mpm_read_grid("vel"))
+    assert rel_l2(m_gpu, gm) <= 1e-10
+    assert rel_l2(v_gpu, gv) <= 1e-10
+    assert np.array_equal(m_gpu == 0, gm == 0)
+    assert not v_gpu[:, m_gpu == 0].any()
+    # the run moved the column: nodes it covered at the start are empty now
+    m0 = np.zeros_like(gm)
+    o0 = orc.Oracle(cfg)
+    _, _, m0, _ = o0.step(oracle_state(orc, cfg, x, v=v), cfg.dt, want_grid=True)
+    assert ((m0 > 0) & (gm == 0)).sum() > 100
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -338,13 +392,14 @@ def test_full_size_steps_match_oracle(orc, case):
     """Full-size workloads in the launch configuration the bench times: the
     3-D cylinder collapse (2,780,928 particles, Drucker-Prager sand) and the
     3-D dam-break of the friction problem (1,843,200 particles, fluid).
-    Three steps in binary64 and binary32 against one oracle run from the
-    same binary32-rounded input, whole arrays compared."""
+    Ten steps in binary64 and binary32 against one oracle run from the
+    same binary32-rounded input, whole arrays compared (positions,
+    displacements, velocities)."""
     from paper_2507_04192_amd.native import Solver
     cfg, x = (W.cylinder_collapse_3d(scale_div=1, seed=0) if case == "cylinder" else W.dam_break_3d())
     x = x.astype(np.float32).astype(np.float64)
     N = x.shape[1]
-    steps = 3
+    steps = 10
     print(f"[case] full size {case} N={N}, {steps} steps (oracle first)", flush=True)
     o = orc.Oracle(cfg)
     st = orc.State(cfg, x)
@@ -360,5 +415,7 @@ def test_full_size_steps_match_oracle(orc, case):
         vg = s.mpm_read_state("v", "pid").cpu().numpy()
         s.close()
         ex, ev = rel_l2(xg, xr), rel_l2(vg, vr)
-        print(f"  {precision}: rel L2 x={ex:.3e} v={ev:.3e}", flush=True)
+        ed, tol_d = displacement_error(xg, xr, x, steps, precision)
+        print(f"  {precision}: rel L2 x={ex:.3e} v={ev:.3e} displacement={ed:.3e} (bound {tol_d:.2e})", flush=True)
         assert ex <= TOL[precision] and ev <= TOL[precision]
+        assert ed <= tol_d

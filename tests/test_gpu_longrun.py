@@ -1,0 +1,174 @@
+"""Long runs: front position and runout, GPU against the oracle, binary32
+against binary64, and the shallow-water solution of the dam-break.
+
+- Dam-break (2-D water column 0.5 x 1.0 m, 8,192 particles): 2000 steps
+  (t = 0.2 s, before the front reaches the far wall), front = max x and the
+  99.9th percentile of x; GPU (binary64 and binary32) within 2h of the
+  oracle.
+- Shallow dam-break of Sec. 4.1.1 (H0 = 0.1 m, L0 = 1.0 m, dh = 0.004 m,
+  4 particles per cell, linear EOS with c_n = 35 m/s, dt = 1e-5 s, slip
+  walls): the free surface against eq:shallow, the position where the
+  depth is y being x = L0 + (2 sqrt(g H0) - 3 sqrt(g y)) t, within 10 % of
+  the travelled distance at t = 0.3, 0.4 and 0.5 s (the paper reports
+  agreement from t = 0.3 s on).
+- Cylinder collapse (2.78 M particles): runout (largest distance from the
+  axis of the particles within 2h of the floor, and its 99.9th percentile)
+  binary32 against binary64 within h after 1000 steps and within 2h after
+  10,000 steps (t = 0.2 s); the 1/8-scale cylinder against the oracle for
+  1000 steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2507_04192_amd import workloads as W
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _front(x):
+    return float(x[0].max()), float(np.percentile(x[0], 99.9))
+
+
+def _runout(cfg, x, axis_xy):
+    low = x[2] < 2 * cfg.dx
+    r = np.hypot(x[0][low] - axis_xy[0], x[1][low] - axis_xy[1])
+    return float(r.max()), float(np.percentile(r, 99.9))
+
+
+def _gpu_run(cfg, precision, x, steps, v=None, chunk=500):
+    from paper_2507_04192_amd.native import Solver
+    s = Solver(cfg, precision, capacity=x.shape[1])
+    s.mpm_init_particles(x, v)
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        s.mpm_step(n)
+        rc, bad = s.mpm_sync_status()
+        assert rc == 0, (rc, bad, done)
+        done += n
+    out = s.mpm_read_state("x", "pid").cpu().numpy().astype(np.float64)
+    s.close()
+    return out
+
+
+def test_dam_break_front_long_run(orc):
+    cfg, x = W.dam_break_2d()
+    steps = 2000
+    print(f"[case] dam-break front, {steps} steps, N={x.shape[1]} (oracle first)", flush=True)
+    xs = x.astype(np.float32).astype(np.float64)
+    st = orc.State(cfg, xs)
+    orc.Oracle(cfg).run(st, steps, cfg.dt)
+    xr = st.by_pid("x")
+    fr = _front(xr)
+    h = cfg.dx
+    assert fr[0] > 1.2          # the front has travelled well past the column
+    for precision in ("f64", "f32"):
+        xg = _gpu_run(cfg, precision, xs, steps)
+        fg = _front(xg)
+        e = rel_l2(xg, xr)
+        print(f"  {precision}: front max {fg[0]:.4f} vs {fr[0]:.4f}, p99.9 {fg[1]:.4f} vs {fr[1]:.4f}; "
+              f"rel L2 x {e:.2e}", flush=True)
+        assert abs(fg[0] - fr[0]) <= 2 * h and abs(fg[1] - fr[1]) <= 2 * h
+        if precision == "f64":
+            assert e <= 1e-6
+
+
+def _shallow_setup():
+    h = 0.004
+    H0, L0 = 0.1, 1.0
+    c_n = 35.0
+    n = (600, 30, 1)                                  # 2.4 x 0.12 m
+    cfg = W.SimConfig(dim=2, n=n, dx=h, dt=1e-5, material=W.FLUID, ppc=4, gravity=(0.0, -9.8, 0.0),
+                      rho0=1000.0, bulk=1000.0 * c_n ** 2, gamma=1.0)
+    x = W.lattice_particles(cfg, W.box_inside((0.0, 0.0), (L0, H0)), (0.0, 0.0), (L0, H0), seed=0)
+    return cfg, x, H0, L0
+
+
+def _surface_reach(cfg, x, y):
+    """Largest x of a particle column (cell-wide bins) whose free surface
+    stands at height >= y."""
+    nb = cfg.n[0]
+    b = np.clip((x[0] / cfg.dx).astype(np.int64), 0, nb - 1)
+    top = np.full(nb, -1.0)
+    np.maximum.at(top, b, x[1])
+    ok = np.where(top >= y)[0]
+    return (ok.max() + 0.5) * cfg.dx if len(ok) else 0.0
+
+
+@pytest.mark.parametrize("precision", ["f32"])
+def test_shallow_dam_break_against_eq_shallow(precision):
+    cfg, x, H0, L0 = _shallow_setup()
+    g = 9.8
+    print(f"[case] shallow dam-break, N={x.shape[1]}, {precision}", flush=True)
+    from paper_2507_04192_amd.native import Solver
+    s = Solver(cfg, precision, capacity=x.shape[1])
+    s.mpm_init_particles(x)
+    t_done = 0
+    worst = 0.0
+    for t_obs in (0.3, 0.4, 0.5):
+        n = int(round(t_obs / cfg.dt)) - t_done
+        while n > 0:
+            k = min(n, 5000)
+            s.mpm_step(k)
+            rc, bad = s.mpm_sync_status()
+            assert rc == 0, (rc, bad)
+            n -= k
+            t_done += k
+        xs = s.mpm_read_state("x", "pid").cpu().numpy().astype(np.float64)
+        for y in (0.01, 0.02, 0.04, 0.06):
+            xa = L0 + (2 * np.sqrt(g * H0) - 3 * np.sqrt(g * y)) * t_obs
+            xm = _surface_reach(cfg, xs, y)
+            rel = abs(xm - xa) / (xa - L0)
+            worst = max(worst, rel)
+            print(f"  t={t_obs:.1f} depth {y:.2f}: simulated {xm:.3f} m, eq:shallow {xa:.3f} m ({rel:.1%})",
+                  flush=True)
+            assert rel <= 0.10
+        print(f"  t={t_obs:.1f} front (max x) {xs[0].max():.3f} m", flush=True)
+    s.close()
+    print(f"  worst {worst:.1%}", flush=True)
+
+
+def test_cylinder_runout_binary32_vs_binary64():
+    cfg, x = W.cylinder_collapse_3d()
+    axis = (cfg.n[0] * cfg.dx / 2, cfg.n[1] * cfg.dx / 2)
+    h = cfg.dx
+    print(f"[case] cylinder runout, N={x.shape[1]}", flush=True)
+    xs = x.astype(np.float32).astype(np.float64)
+    for steps, tol in ((1000, h), (10000, 2 * h)):
+        r = {}
+        for precision in ("f64", "f32"):
+            r[precision] = _runout(cfg, _gpu_run(cfg, precision, xs, steps, chunk=1000), axis)
+        print(f"  {steps} steps: runout max {r['f32'][0]:.4f} (f32) vs {r['f64'][0]:.4f} (f64), "
+              f"p99.9 {r['f32'][1]:.4f} vs {r['f64'][1]:.4f}", flush=True)
+        assert abs(r["f32"][0] - r["f64"][0]) <= tol
+        assert abs(r["f32"][1] - r["f64"][1]) <= tol
+    # the collapse has spread the base by then
+    assert r["f64"][0] > 48 * h
+
+
+def test_small_cylinder_long_run_vs_oracle(orc):
+    cfg, x = W.cylinder_collapse_3d(scale_div=8)
+    steps = 1000
+    axis = (cfg.n[0] * cfg.dx / 2, cfg.n[1] * cfg.dx / 2)
+    print(f"[case] 1/8 cylinder, {steps} steps, N={x.shape[1]} (oracle first)", flush=True)
+    xs = x.astype(np.float32).astype(np.float64)
+    st = orc.State(cfg, xs)
+    orc.Oracle(cfg).run(st, steps, cfg.dt)
+    xr = st.by_pid("x")
+    rr = _runout(cfg, xr, axis)
+    for precision in ("f64", "f32"):
+        xg = _gpu_run(cfg, precision, xs, steps)
+        rg = _runout(cfg, xg, axis)
+        e = rel_l2(xg - xs, xr - xs)
+        print(f"  {precision}: runout {rg[0]:.5f} vs {rr[0]:.5f}, p99.9 {rg[1]:.5f} vs {rr[1]:.5f}; "
+              f"rel L2 displacement {e:.2e}", flush=True)
+        assert abs(rg[0] - rr[0]) <= cfg.dx and abs(rg[1] - rr[1]) <= cfg.dx
+        assert e <= (1e-8 if precision == "f64" else 1e-2)
