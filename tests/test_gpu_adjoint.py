@@ -441,6 +441,10 @@ def test_cylinder_from_rest_gradient(orc, precision):
     el, ev, em = abs(loss - loss_o) / loss_o, rel_l2(gv, gv_o), rel_l2(gmu, gmu_o)
     print(f"  loss {loss:.4e} vs {loss_o:.4e} ({el:.2e}); dL/dv0 {ev:.2e}; dL/dmu {em:.2e} "
           f"(|dL/dmu|max {np.abs(gmu_o).max():.2e})", flush=True)
-    assert el <= (1e-10 if precision == "f64" else 1e-4)
+    # binary32: the loss is a sum of squared displacements of ~8e-5 m (200
+    # steps of free settling) read from positions stored to half an ulp of
+    # 0.64 m (3e-8 m), so each term carries ~4e-4 relative rounding; the
+    # stated binary32 adjoint tolerance (5e-3) covers loss and gradients
+    assert el <= (1e-10 if precision == "f64" else 2e-3)
     assert ev <= (1e-8 if precision == "f64" else 5e-3)
     assert em <= (1e-8 if precision == "f64" else 5e-3)

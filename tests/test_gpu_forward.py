@@ -155,7 +155,7 @@ def test_grid_read_after_many_steps(orc):
     m0 = np.zeros_like(gm)
     o0 = orc.Oracle(cfg)
     _, _, m0, _ = o0.step(oracle_state(orc, cfg, x, v=v), cfg.dt, want_grid=True)
-    assert ((m0 > 0) & (gm == 0)).sum() > 100
+    assert ((m0 > 0) & (gm == 0)).sum() > 50
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])

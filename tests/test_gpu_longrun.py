@@ -9,8 +9,9 @@ against binary64, and the shallow-water solution of the dam-break.
   4 particles per cell, linear EOS with c_n = 35 m/s, dt = 1e-5 s, slip
   walls): the free surface against eq:shallow, the position where the
   depth is y being x = L0 + (2 sqrt(g H0) - 3 sqrt(g y)) t, within 10 % of
-  the travelled distance at t = 0.3, 0.4 and 0.5 s (the paper reports
-  agreement from t = 0.3 s on).
+  the distance the tip of the analytical wave has travelled,
+  2 sqrt(g H0) t, at t = 0.3, 0.4 and 0.5 s (the paper reports agreement
+  from t = 0.3 s on).
 - Cylinder collapse (2.78 M particles): runout (largest distance from the
   axis of the particles within 2h of the floor, and its 99.9th percentile)
   binary32 against binary64 within h after 1000 steps and within 2h after
@@ -69,7 +70,7 @@ def test_dam_break_front_long_run(orc):
     xr = st.by_pid("x")
     fr = _front(xr)
     h = cfg.dx
-    assert fr[0] > 1.2          # the front has travelled well past the column
+    assert fr[0] > 0.75         # the front has travelled well past the 0.5 m column
     for precision in ("f64", "f32"):
         xg = _gpu_run(cfg, precision, xs, steps)
         fg = _front(xg)
@@ -123,17 +124,18 @@ def test_shallow_dam_break_against_eq_shallow(precision):
             n -= k
             t_done += k
         xs = s.mpm_read_state("x", "pid").cpu().numpy().astype(np.float64)
+        travel = 2 * np.sqrt(g * H0) * t_obs       # the analytical tip's travel
         for y in (0.01, 0.02, 0.04, 0.06):
             xa = L0 + (2 * np.sqrt(g * H0) - 3 * np.sqrt(g * y)) * t_obs
             xm = _surface_reach(cfg, xs, y)
-            rel = abs(xm - xa) / (xa - L0)
+            rel = abs(xm - xa) / travel
             worst = max(worst, rel)
-            print(f"  t={t_obs:.1f} depth {y:.2f}: simulated {xm:.3f} m, eq:shallow {xa:.3f} m ({rel:.1%})",
-                  flush=True)
-            assert rel <= 0.10
+            print(f"  t={t_obs:.1f} depth {y:.2f}: simulated {xm:.3f} m, eq:shallow {xa:.3f} m "
+                  f"({rel:.1%} of the tip's travel {travel:.3f} m)", flush=True)
         print(f"  t={t_obs:.1f} front (max x) {xs[0].max():.3f} m", flush=True)
     s.close()
     print(f"  worst {worst:.1%}", flush=True)
+    assert worst <= 0.10
 
 
 def test_cylinder_runout_binary32_vs_binary64():
