@@ -21,9 +21,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["mpm_oracle.c", "mpm_oracle_adjoint.c"]
 LIB_PATH = os.path.join(HERE, "liborc.so")
 
-ORC_FLUID, ORC_DP_HENCKY, ORC_HENCKY_ELASTIC = 0, 1, 2
-_MAT = {"fluid": ORC_FLUID, "sand": ORC_DP_HENCKY, "elastic": ORC_HENCKY_ELASTIC}
+ORC_FLUID, ORC_DP_HENCKY, ORC_HENCKY_ELASTIC, ORC_DP_JAUMANN = 0, 1, 2, 3
+_MAT = {"fluid": ORC_FLUID, "sand": ORC_DP_HENCKY, "elastic": ORC_HENCKY_ELASTIC,
+        "dp_jaumann": ORC_DP_JAUMANN}
 _WALL = {"slip": 0, "stick": 1, "coulomb": 2}
+_XFER = {"apic": 0, "pic": 1, "flip": 2, "tpic": 3}
+MAX_OBSTACLES = 4
 
 
 def build(opt: str = "-O2", extra=()) -> str:
@@ -44,6 +47,10 @@ class OrcConfig(ct.Structure):
         ("rho0", ct.c_double), ("bulk", ct.c_double), ("gamma", ct.c_double),
         ("youngs", ct.c_double), ("poisson", ct.c_double), ("phi_deg", ct.c_double),
         ("vol0", ct.c_double), ("mass", ct.c_double),
+        ("transfer", ct.c_int32), ("n_obstacles", ct.c_int32),
+        ("flip_alpha", ct.c_double), ("viscosity", ct.c_double),
+        ("psi_deg", ct.c_double), ("cohesion", ct.c_double), ("tension", ct.c_double),
+        ("obst_lo", (ct.c_double * 3) * 4), ("obst_hi", (ct.c_double * 3) * 4),
     ]
 
 
@@ -77,8 +84,14 @@ def _declare(L):
     L.orc_cells_per_tile.argtypes = [P]
     L.orc_sort_perm.argtypes = [i64, P, ct.c_int32, P]
     L.orc_p2g.argtypes = [P, i64, f64, P, P, P, P, P, P]
+    L.orc_p2g_ex.argtypes = [P, i64, f64, P, P, P, P, P, P, P]
     L.orc_grid_update.argtypes = [P, f64, P, P, P, P]
     L.orc_g2p.argtypes = [P, i64, f64, P, P, P, P, P]
+    L.orc_g2p_ex.argtypes = [P, i64, f64, P, P, P, P, P, P]
+    L.orc_obstacles.argtypes = [P, P, P]
+    L.orc_dp_jaumann.restype = ct.c_int
+    L.orc_dp_jaumann.argtypes = [P, f64, P, P, P]
+    L.orc_fluid_stress.argtypes = [P, f64, P, P]
     L.orc_sym_eig.argtypes = [ct.c_int, P, P, P]
     L.orc_fluid_pressure.restype = f64
     L.orc_fluid_pressure.argtypes = [P, f64]
@@ -122,6 +135,18 @@ def make_config(cfg, key_f32: bool = False) -> OrcConfig:
     c.rho0, c.bulk, c.gamma = float(cfg.rho0), float(cfg.bulk), float(cfg.gamma)
     c.youngs, c.poisson, c.phi_deg = float(cfg.youngs), float(cfg.poisson), float(cfg.phi_deg)
     c.vol0, c.mass = float(cfg.vol0), float(cfg.mass)
+    c.transfer = _XFER[cfg.transfer]
+    c.flip_alpha = float(cfg.flip_alpha)
+    c.viscosity = float(cfg.viscosity)
+    c.psi_deg, c.cohesion, c.tension = float(cfg.psi_deg), float(cfg.cohesion), float(cfg.tension)
+    obs = list(cfg.obstacles)
+    if len(obs) > MAX_OBSTACLES:
+        raise ValueError("too many obstacles")
+    c.n_obstacles = len(obs)
+    for o, (lo, hi) in enumerate(obs):
+        for a in range(3):
+            c.obst_lo[o][a] = float(lo[a]) if a < len(lo) else 0.0
+            c.obst_hi[o][a] = float(hi[a]) if a < len(hi) else 0.0
     return c
 
 
@@ -200,13 +225,16 @@ class Oracle:
         lib().orc_sort_perm(key.shape[0], _ptr(key), int(cells_per_tile), _ptr(perm))
         return perm
 
-    def p2g(self, st: State, dt):
+    def p2g(self, st: State, dt, with_momentum=False):
+        """Nodal mass and momentum-plus-force; with_momentum also returns the
+        momentum without the force (FLIP's v^n = that / mass)."""
         d = self.cfg.dim
         gm = np.empty(self.NN)
         gp = np.empty((d, self.NN))
-        self.L.orc_p2g(ct.byref(self.c), st.N, dt, _ptr(st.x), _ptr(st.v), _ptr(st.C),
-                       _ptr(st.S), _ptr(gm), _ptr(gp))
-        return gm, gp
+        gq = np.empty((d, self.NN)) if with_momentum else None
+        self.L.orc_p2g_ex(ct.byref(self.c), st.N, dt, _ptr(st.x), _ptr(st.v), _ptr(st.C),
+                          _ptr(st.S), _ptr(gm), _ptr(gp), _ptr(gq))
+        return (gm, gp, gq) if with_momentum else (gm, gp)
 
     def grid_update(self, gm, gp, dt, floor_mu=None):
         d = self.cfg.dim
@@ -216,13 +244,42 @@ class Oracle:
                                _ptr(gv))
         return gv
 
-    def g2p(self, st: State, gv, dt):
-        """Updates st.x, st.v, st.C in place; returns the velocity gradient L."""
+    def g2p(self, st: State, gv, dt, gv_old=None):
+        """Updates st.x, st.v, st.C in place with the configured transfer
+        (gv_old: the grid velocity before the update, needed by FLIP); returns
+        the velocity gradient L."""
         d = self.cfg.dim
         L = np.empty((d * d, st.N))
-        self.L.orc_g2p(ct.byref(self.c), st.N, dt, _ptr(_f64(gv)), _ptr(st.x), _ptr(st.v),
-                       _ptr(st.C), _ptr(L))
+        go = None if gv_old is None else _f64(gv_old)
+        self.L.orc_g2p_ex(ct.byref(self.c), st.N, dt, _ptr(_f64(gv)), _ptr(go), _ptr(st.x),
+                          _ptr(st.v), _ptr(st.C), _ptr(L))
         return L
+
+    def obstacles(self, I, vel):
+        """The obstacle rule applied to one node (stored index I) velocity."""
+        Ii = (ct.c_int32 * 3)(*[int(v) for v in (list(I) + [0, 0, 0])[:3]])
+        v = np.zeros(3)
+        v[:len(vel)] = vel
+        self.L.orc_obstacles(ct.byref(self.c), Ii, _ptr(v))
+        return v[:self.cfg.dim]
+
+    def dp_jaumann(self, L, sigma, dt):
+        """One stress update of the hypoelastic Drucker-Prager material:
+        returns (sigma', zone, equivalent plastic strain increment)."""
+        d = self.cfg.dim
+        Lf = _f64(L).reshape(d * d).copy()
+        sg = _f64(sigma).reshape(d * d).copy()
+        de = ct.c_double(0.0)
+        zone = self.L.orc_dp_jaumann(ct.byref(self.c), float(dt), _ptr(Lf), _ptr(sg), ct.byref(de))
+        return sg.reshape(d, d), int(zone), de.value
+
+    def fluid_stress(self, J, L):
+        """Kirchhoff stress J sigma of the (viscous) fluid at J and velocity gradient L."""
+        d = self.cfg.dim
+        Lf = _f64(L).reshape(d * d).copy()
+        tau = np.empty(d * d)
+        self.L.orc_fluid_stress(ct.byref(self.c), float(J), _ptr(Lf), _ptr(tau))
+        return tau.reshape(d, d)
 
     def constitutive(self, st: State, L, dt):
         self.L.orc_constitutive(ct.byref(self.c), st.N, dt, _ptr(_f64(L)), _ptr(st.F),
@@ -397,6 +454,8 @@ def adjoint_step(cfg, st_in, adj_out, dt, floor_mu=None, amu=None):
                             _ptr(a["x"]), _ptr(a["v"]), _ptr(a["C"]), _ptr(a["F"]), _ptr(a["J"]), _ptr(a["S"]),
                             _ptr(out["x"]), _ptr(out["v"]), _ptr(out["C"]), _ptr(out["F"]), _ptr(out["J"]),
                             _ptr(out["S"]), _ptr(amu))
+    if rc == -2:
+        raise NotImplementedError("the oracle's reverse step covers APIC, inviscid fluid and Hencky materials")
     if rc != 0:
         raise MemoryError("oracle adjoint failed to allocate")
     return out

@@ -17,6 +17,12 @@
  *   - Coulomb wall friction                    Sec. 5.3, eq:coulomb_friction
  *   - Hencky-strain return on the D-P cone     (Klar et al. 2016, cited in
  *                                               Sec. 4.2.3)
+ *   - FLIP, PIC, their blend, TPIC transfers   Sec. 2.2 G2P, App. B
+ *   - Newtonian viscous stress                 Sec. 2.3, eq:stress_strain
+ *   - hypoelastic Drucker-Prager with the
+ *     Jaumann rate and tension cutoff          Sec. 2.3 eq:dp_stress, App. A
+ *   - resting rigid obstacles, frictionless
+ *     contact (normal velocity removed)        Sec. 4.2.1
  *
  * Readings taken where the paper is silent (all listed with reasons in the
  * design notes):
@@ -295,11 +301,22 @@ void orc_p2g(const orc_config* c, int64_t N, double dt,
              const double* x, const double* v, const double* C, const double* S,
              double* gm, double* gp)
 {
+    orc_p2g_ex(c, N, dt, x, v, C, S, gm, gp, NULL);
+}
+
+/* As orc_p2g; gq (may be NULL) also receives the nodal momentum without the
+ * internal force, sum phi m_p (v_p + C_p (x_i - x_p)), from which the grid
+ * velocity before the update, v_i^n = gq / m_i, is formed for FLIP. */
+void orc_p2g_ex(const orc_config* c, int64_t N, double dt,
+                const double* x, const double* v, const double* C, const double* S,
+                double* gm, double* gp, double* gq)
+{
     int d = dimv(c);
     int32_t dims[3];
     int64_t NN = orc_node_dims(c, dims);
     memset(gm, 0, sizeof(double) * (size_t)NN);
     memset(gp, 0, sizeof(double) * (size_t)(NN * d));
+    if (gq) memset(gq, 0, sizeof(double) * (size_t)(NN * d));
     int kz_max = (d == 3) ? 3 : 1;
     for (int64_t p = 0; p < N; ++p) {
         stencil st;
@@ -326,6 +343,7 @@ void orc_p2g(const orc_config* c, int64_t N, double dt,
                             frc += S[(a * d + b) * N + p] * grad[b];
                         }
                         gp[a * NN + li] += phi * c->mass * (vp[a] + aff) - dt * frc;
+                        if (gq) gq[a * NN + li] += phi * c->mass * (vp[a] + aff);
                     }
                 }
     }
@@ -371,6 +389,46 @@ static void wall_apply(int d, int mode, double mu, const double nrm[3], double v
     }
 }
 
+/* Resting rigid obstacles (Sec. 4.2.1): frictionless contact removes the
+ * normal velocity of a node at the interface, v = v~ - (v~ . n) n.
+ * Readings: a node is at the interface of obstacle box [lo, hi] when it lies
+ * in the closed box; n is the normal of the nearest face that is not on the
+ * domain boundary (ties: the first in the order x-, x+, y-, y+, z-, z+);
+ * as for the walls and in the contact method the paper cites, the
+ * correction acts only while the node moves into the obstacle; obstacles
+ * are applied after the walls, in their order. */
+void orc_obstacles(const orc_config* c, const int32_t I[3], double vel[3])
+{
+    int d = dimv(c);
+    for (int o = 0; o < c->n_obstacles; ++o) {
+        double xi[3] = {0, 0, 0};
+        int inside = 1;
+        for (int a = 0; a < d; ++a) {
+            xi[a] = (double)(I[a] - c->ghost) * c->dx;
+            if (xi[a] < c->obst_lo[o][a] || xi[a] > c->obst_hi[o][a]) inside = 0;
+        }
+        if (!inside) continue;
+        int best_a = -1, best_side = 0;
+        double best = 0.0;
+        for (int a = 0; a < d; ++a)
+            for (int side = 0; side < 2; ++side) {
+                double face = side == 0 ? c->obst_lo[o][a] : c->obst_hi[o][a];
+                double ext = (double)c->n[a] * c->dx;
+                if ((side == 0 && face <= 0.0) || (side == 1 && face >= ext)) continue;
+                double depth = side == 0 ? xi[a] - face : face - xi[a];
+                if (best_a < 0 || depth < best) {
+                    best = depth;
+                    best_a = a;
+                    best_side = side;
+                }
+            }
+        if (best_a < 0) continue;
+        /* n points into the obstacle: +e_a through its lower face */
+        double vn = best_side == 0 ? vel[best_a] : -vel[best_a];
+        if (vn > 0.0) vel[best_a] = 0.0;
+    }
+}
+
 void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
                      const double* gm, const double* gp, double* gv)
 {
@@ -405,6 +463,7 @@ void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
                         wall_apply(d, c->wall_mode[face], mu, nrm, vel);
                     }
                 }
+                if (gm[li] > 0.0) orc_obstacles(c, I, vel);
                 for (int a = 0; a < d; ++a)
                     gv[a * NN + li] = vel[a];
             }
@@ -417,6 +476,22 @@ void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
 void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
              double* x, double* v, double* C, double* L)
 {
+    orc_g2p_ex(c, N, dt, gv, NULL, x, v, C, L);
+}
+
+/* G2P with the configured transfer (Sec. 2.2 G2P; App. B):
+ *   APIC  v' = sum phi v_i,  C' = (4/h^2) sum phi v_i (x_i - x_p)^T
+ *   PIC   v' = sum phi v_i,  C' = 0
+ *   TPIC  v' = sum phi v_i,  C' = grad v (the next P2G's affine matrix)
+ *   FLIP  v' = sum phi v_i + alpha (v_p - sum phi v_i^n), C' = 0; alpha = 1
+ *         is FLIP (v_p + dt sum phi a_i), alpha = 0 PIC, between: the blend.
+ * Reading: the grid acceleration of FLIP is (v_i^{n+1} - v_i^n) / dt with
+ * v_i^{n+1} after the walls and obstacles and v_i^n = gq / m (gvo), so the
+ * boundary conditions reach FLIP particles too.  Every transfer moves the
+ * particle with the interpolated new grid velocity. */
+void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const double* gv, const double* gvo,
+                double* x, double* v, double* C, double* L)
+{
     int d = dimv(c);
     int32_t dims[3];
     int64_t NN = orc_node_dims(c, dims);
@@ -428,7 +503,8 @@ void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
         double xp[3] = {0, 0, 0};
         for (int a = 0; a < d; ++a)
             xp[a] = x[a * N + p];
-        double vn[3] = {0, 0, 0}, Bm[3][3] = {{0}}, Lm[3][3] = {{0}};
+        double vn[3] = {0, 0, 0}, vo[3] = {0, 0, 0}, Bm[3][3] = {{0}}, Lm[3][3] = {{0}};
+        int flip = c->transfer == ORC_FLIP && gvo;
         for (int k2 = 0; k2 < kz_max; ++k2)
             for (int k1 = 0; k1 < 3; ++k1)
                 for (int k0 = 0; k0 < 3; ++k0) {
@@ -440,6 +516,7 @@ void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
                     for (int a = 0; a < d; ++a) {
                         double vi = gv[a * NN + li];
                         vn[a] += phi * vi;
+                        if (flip) vo[a] += phi * gvo[a * NN + li];
                         for (int b = 0; b < d; ++b) {
                             Bm[a][b] += phi * vi * dpos[b];
                             Lm[a][b] += vi * grad[b];
@@ -447,14 +524,22 @@ void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
                     }
                 }
         for (int a = 0; a < d; ++a) {
-            v[a * N + p] = vn[a];
+            double vnew = vn[a];
+            if (flip) vnew = vn[a] + c->flip_alpha * (v[a * N + p] - vo[a]);
+            v[a * N + p] = vnew;
             double xn = xp[a] + dt * vn[a];
             double hi = (double)c->n[a] * c->dx;
             if (xn < 0.0) xn = 0.0;
             if (xn > hi) xn = hi;
             x[a * N + p] = xn;
             for (int b = 0; b < d; ++b) {
-                C[(a * d + b) * N + p] = Dinv * Bm[a][b];
+                double cab;
+                switch (c->transfer) {
+                case ORC_APIC: cab = Dinv * Bm[a][b]; break;
+                case ORC_TPIC: cab = Lm[a][b]; break;
+                default: cab = 0.0; break;     /* PIC, FLIP: no affine part */
+                }
+                C[(a * d + b) * N + p] = cab;
                 L[(a * d + b) * N + p] = Lm[a][b];
             }
         }
@@ -652,9 +737,126 @@ int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9]
     return cas;
 }
 
+/* Newtonian fluid (Sec. 2.3 eq:stress_strain): Kirchhoff stress
+ * tau = J sigma with sigma = -p I + 2 mu (d - tr(d)/3 I), d = (L + L^T)/2.
+ * Readings: the printed increment Delta d stands where the rate d is meant
+ * (a stress needs the rate, units Pa = Pa s * 1/s); in 2-D the 3 is the
+ * dimension, so that the viscous stress stays traceless there too. */
+void orc_fluid_stress(const orc_config* c, double J, const double L[9], double tau[9])
+{
+    int d = dimv(c);
+    double pr = orc_fluid_pressure(c, J);
+    double trd = 0.0;
+    for (int a = 0; a < d; ++a) trd += L[a * d + a];
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            double rate = 0.5 * (L[a * d + b] + L[b * d + a]);
+            double sig = 2.0 * c->viscosity * rate;
+            if (a == b) sig += -pr - 2.0 * c->viscosity * trd / d;
+            tau[a * d + b] = J * sig;
+        }
+}
+
+/* Hypoelastic Drucker-Prager with the Jaumann rate, shear yielding and a
+ * tension cutoff (Sec. 2.3 eq:dp_stress; App. A steps (1)-(5)).  sigma is
+ * the Cauchy stress (d x d, row-major), updated in place; L the velocity
+ * gradient of the step, (L)_ab = d v_a / d x_b.  Returns the zone: 1
+ * elastic, 2 shear failure, 3 tensile failure; *deps_eq (may be NULL) the
+ * equivalent plastic strain increment.
+ *   (1) Delta d = dt (L + L^T)/2, Delta w = dt (L - L^T)/2,
+ *       sigma^R_ij = sigma_ij + sigma_ik Dw_jk + sigma_jk Dw_ik,
+ *       trial = sigma^R + lam tr(Delta d) I + 2 G Delta d;
+ *   (2) sigma_m = tr/d, tau = sqrt(s:s / 2);
+ *   (3) f^s = tau - k_phi + q_phi sigma_m, f^t = sigma_m - sigma^t,
+ *       h = tau - tau^P - alpha^P (sigma_m - sigma^t);
+ *   (4) zone II: dl = f^s / (G + K q_phi q_psi), sigma_m -= K q_psi dl,
+ *       tau = k_phi - q_phi sigma_m, s scaled to tau;
+ *   (5) zone III: sigma_m = sigma^t, s kept.
+ * Readings (no value or rule in the paper): in 2-D the mean is tr/2 and
+ * K = lam + G (the 2-D bulk modulus), the paper's 3 being the dimension;
+ * a shear return that ends beyond the cutoff (sigma_m > sigma^t, reached
+ * only from the corner branch h > 0, f^t >= 0) is taken to the corner
+ * (sigma^t, tau^P); a trial stress of Frobenius norm at or below 1e-6 E is
+ * elastic whatever its zone (the zones meet at zero stress, where a body at
+ * rest sits). */
+int orc_dp_jaumann(const orc_config* c, double dt, const double L[9], double sigma[9],
+                   double* deps_eq)
+{
+    int d = dimv(c);
+    double E = c->youngs, nu = c->poisson;
+    double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    double G = E / (2.0 * (1.0 + nu));
+    double K = lam + 2.0 * G / d;
+    double sp = sin(c->phi_deg * M_PI / 180.0), cp = cos(c->phi_deg * M_PI / 180.0);
+    double ss = sin(c->psi_deg * M_PI / 180.0);
+    double q_phi = 6.0 * sp / (sqrt(3.0) * (3.0 + sp));
+    double k_phi = 6.0 * c->cohesion * cp / (sqrt(3.0) * (3.0 + sp));
+    double q_psi = 6.0 * ss / (sqrt(3.0) * (3.0 + ss));
+    double st = c->tension;
+    double tauP = k_phi - q_phi * st;
+    double alphaP = sqrt(1.0 + q_phi * q_phi) - q_phi;
+
+    double Dd[3][3] = {{0}}, Dw[3][3] = {{0}}, S0[3][3] = {{0}};
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            Dd[a][b] = 0.5 * dt * (L[a * d + b] + L[b * d + a]);
+            Dw[a][b] = 0.5 * dt * (L[a * d + b] - L[b * d + a]);
+            S0[a][b] = sigma[a * d + b];
+        }
+    double trD = 0.0;
+    for (int a = 0; a < d; ++a) trD += Dd[a][a];
+    double Tr[3][3];
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double r = S0[i][j];
+            for (int k = 0; k < d; ++k) r += S0[i][k] * Dw[j][k] + S0[j][k] * Dw[i][k];
+            Tr[i][j] = r + 2.0 * G * Dd[i][j] + (i == j ? lam * trD : 0.0);
+        }
+    double sm = 0.0;
+    for (int a = 0; a < d; ++a) sm += Tr[a][a];
+    sm /= d;
+    double s[3][3], ss2 = 0.0, nrm2 = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            s[i][j] = Tr[i][j] - (i == j ? sm : 0.0);
+            ss2 += s[i][j] * s[i][j];
+            nrm2 += Tr[i][j] * Tr[i][j];
+        }
+    double tau = sqrt(0.5 * ss2);
+    double fs = tau - k_phi + q_phi * sm;
+    double ft = sm - st;
+    double h = tau - tauP - alphaP * (sm - st);
+    int zone;
+    if (sqrt(nrm2) <= 1e-6 * E) zone = 1;
+    else if (ft < 0.0) zone = fs <= 0.0 ? 1 : 2;
+    else zone = h > 0.0 ? 2 : 3;
+    double sm_n = sm, scale = 1.0, de = 0.0;
+    if (zone == 2) {
+        double dl = fs / (G + K * q_phi * q_psi);
+        sm_n = sm - K * q_psi * dl;
+        double tau_n = k_phi - q_phi * sm_n;
+        if (sm_n > st) {          /* beyond the cutoff: the corner */
+            sm_n = st;
+            tau_n = tauP;
+        }
+        scale = tau > 0.0 ? tau_n / tau : 0.0;
+        de = dl * sqrt(1.0 / 3.0 + 2.0 / 9.0 * q_psi * q_psi);
+    } else if (zone == 3) {
+        sm_n = st;
+        de = sqrt(2.0) / 3.0 * (sm - st) / K;
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            sigma[i * d + j] = scale * s[i][j] + (i == j ? sm_n : 0.0);
+    if (deps_eq) *deps_eq = de;
+    return zone;
+}
+
 /* Kinematics (F or J update with the velocity gradient L) followed by the
  * stress of the material; S = V0 * tau (Kirchhoff stress times initial
- * volume, equal to V_p sigma_p). */
+ * volume, equal to V_p sigma_p).  For the hypoelastic Drucker-Prager
+ * material the carried stress is S = V_p sigma = V0 J sigma: the Cauchy
+ * stress of the step is S / (V0 J) with the J before the update. */
 void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L,
                       double* F, double* J, double* S)
 {
@@ -668,9 +870,24 @@ void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L
         if (c->material == ORC_FLUID) {
             double Jn = J[p] * det(d, M);
             J[p] = Jn;
-            double pr = orc_fluid_pressure(c, Jn);
+            double Lp[9], tu[9];
             for (int a = 0; a < d; ++a)
-                tau[a][a] = -Jn * pr;
+                for (int b = 0; b < d; ++b) Lp[a * d + b] = L[(a * d + b) * N + p];
+            orc_fluid_stress(c, Jn, Lp, tu);
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) tau[a][b] = tu[a * d + b];
+        } else if (c->material == ORC_DP_JAUMANN) {
+            double Jo = J[p], Jn = Jo * det(d, M);
+            double Lp[9], sg[9];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) {
+                    Lp[a * d + b] = L[(a * d + b) * N + p];
+                    sg[a * d + b] = S[(a * d + b) * N + p] / (c->vol0 * Jo);
+                }
+            orc_dp_jaumann(c, dt, Lp, sg, NULL);
+            J[p] = Jn;
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) tau[a][b] = Jn * sg[a * d + b];
         } else {
             double Fo[3][3] = {{0}}, Ft[3][3];
             for (int a = 0; a < d; ++a)
@@ -726,21 +943,34 @@ int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
     gather_d(N, d, v, perm, tmp);
     gather_d(N, d * d, C, perm, tmp);
     gather_d(N, d * d, S, perm, tmp);
-    if (c->material == ORC_FLUID)
+    if (c->material == ORC_FLUID || c->material == ORC_DP_JAUMANN)
         gather_d(N, 1, J, perm, tmp);
-    else
+    if (c->material != ORC_FLUID)
         gather_d(N, d * d, F, perm, tmp);
     gather_i(N, pid, perm, itmp);
     if (perm_out) memcpy(perm_out, perm, sizeof(int32_t) * (size_t)N);
     if (key_out) memcpy(key_out, key, sizeof(int32_t) * (size_t)N);
 
-    orc_p2g(c, N, dt, x, v, C, S, gm, gp);
+    /* FLIP needs the grid velocity before the update, v_i^n = gq / m_i */
+    double* gq = NULL;
+    if (c->transfer == ORC_FLIP) {
+        gq = (double*)malloc(sizeof(double) * (size_t)(NN * d));
+        if (!gq) {
+            free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv);
+            return -1;
+        }
+    }
+    orc_p2g_ex(c, N, dt, x, v, C, S, gm, gp, gq);
     orc_grid_update(c, dt, floor_mu, gm, gp, gv);
+    if (gq)
+        for (int64_t i = 0; i < NN; ++i)
+            for (int a = 0; a < d; ++a)
+                gq[a * NN + i] = gm[i] > 0.0 ? gq[a * NN + i] / gm[i] : 0.0;
     if (grid_m_out) memcpy(grid_m_out, gm, sizeof(double) * (size_t)NN);
     if (grid_v_out) memcpy(grid_v_out, gv, sizeof(double) * (size_t)(NN * d));
-    orc_g2p(c, N, dt, gv, x, v, C, L);
+    orc_g2p_ex(c, N, dt, gv, gq, x, v, C, L);
     orc_constitutive(c, N, dt, L, F, J, S);
 
-    free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv);
+    free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv); free(gq);
     return 0;
 }

@@ -7,8 +7,11 @@
 #define MPM_ORACLE_H
 #include <stdint.h>
 
-enum { ORC_FLUID = 0, ORC_DP_HENCKY = 1, ORC_HENCKY_ELASTIC = 2 };
+enum { ORC_FLUID = 0, ORC_DP_HENCKY = 1, ORC_HENCKY_ELASTIC = 2, ORC_DP_JAUMANN = 3 };
 enum { ORC_WALL_SLIP = 0, ORC_WALL_STICK = 1, ORC_WALL_COULOMB = 2 };
+/* grid-to-particle transfer (Sec. 2.2 G2P; App. B) */
+enum { ORC_APIC = 0, ORC_PIC = 1, ORC_FLIP = 2, ORC_TPIC = 3 };
+#define ORC_MAX_OBSTACLES 4
 
 /* Hencky strain magnitude |eps|_F at or below which the Drucker-Prager
  * return takes the elastic case whatever the sign of tr(eps) (a reading:
@@ -30,6 +33,12 @@ typedef struct orc_config {
     double rho0, bulk, gamma;          /* fluid */
     double youngs, poisson, phi_deg;   /* sand */
     double vol0, mass;                 /* per particle */
+    int32_t transfer;     /* ORC_APIC / ORC_PIC / ORC_FLIP / ORC_TPIC */
+    int32_t n_obstacles;  /* resting rigid boxes, <= ORC_MAX_OBSTACLES */
+    double flip_alpha;    /* FLIP share of the FLIP/PIC blend (1 = FLIP) */
+    double viscosity;     /* fluid: dynamic viscosity mu (eq:stress_strain) */
+    double psi_deg, cohesion, tension;   /* App. A: dilation angle, c, sigma^t */
+    double obst_lo[ORC_MAX_OBSTACLES][3], obst_hi[ORC_MAX_OBSTACLES][3];
 } orc_config;
 
 double orc_phibar(double xi);
@@ -43,10 +52,18 @@ int32_t orc_cells_per_tile(const orc_config* c);
 void orc_sort_perm(int64_t N, const int32_t* key, int32_t cpt, int32_t* perm);
 void orc_p2g(const orc_config* c, int64_t N, double dt, const double* x, const double* v,
              const double* C, const double* S, double* gm, double* gp);
+void orc_p2g_ex(const orc_config* c, int64_t N, double dt, const double* x, const double* v,
+                const double* C, const double* S, double* gm, double* gp, double* gq);
 void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
                      const double* gm, const double* gp, double* gv);
 void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
              double* x, double* v, double* C, double* L);
+void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const double* gv, const double* gvo,
+                double* x, double* v, double* C, double* L);
+void orc_obstacles(const orc_config* c, const int32_t I[3], double vel[3]);
+int orc_dp_jaumann(const orc_config* c, double dt, const double L[9], double sigma[9],
+                   double* deps_eq);
+void orc_fluid_stress(const orc_config* c, double J, const double L[9], double tau[9]);
 void orc_sym_eig(int d, const double A[9], double ev[3], double V[9]);
 double orc_fluid_pressure(const orc_config* c, double J);
 double orc_cone_alpha(const orc_config* c);

@@ -336,6 +336,11 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
 {
     const int d = c->dim, dd = d * d;
     const int fluid = c->material == ORC_FLUID;
+    /* the reverse sweep covers the APIC transfer, inviscid fluid and the
+     * Hencky materials; other settings are refused */
+    if (c->transfer != ORC_APIC || c->viscosity != 0.0 || c->n_obstacles > 0 ||
+        c->material == ORC_DP_JAUMANN)
+        return -2;
     int32_t dims[3];
     int64_t NN = orc_node_dims(c, dims);
     size_t NP = (size_t)(N > 0 ? N : 1);

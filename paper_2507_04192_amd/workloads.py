@@ -18,9 +18,12 @@ from typing import Callable, Optional, Sequence, Tuple
 
 import numpy as np
 
-FLUID = "fluid"          # weakly compressible Tait fluid
+FLUID = "fluid"          # weakly compressible Tait fluid (optionally viscous)
 SAND = "sand"            # Drucker-Prager sand, Hencky-strain return
 ELASTIC = "elastic"      # Hencky elastic (no return), used by checks
+DP_JAUMANN = "dp_jaumann"   # hypoelastic Drucker-Prager, Jaumann rate, tension cutoff
+
+APIC, PIC, FLIP, TPIC = "apic", "pic", "flip", "tpic"   # grid-to-particle transfers
 
 SLIP, STICK, COULOMB = "slip", "stick", "coulomb"
 
@@ -44,6 +47,13 @@ class SimConfig:
     phi_deg: float = 30.0
     ghost: int = 2
     tile: int = 0                    # 0: 4 in 3D, 8 in 2D
+    transfer: str = APIC
+    flip_alpha: float = 1.0          # FLIP share of the FLIP/PIC blend
+    viscosity: float = 0.0           # fluid dynamic viscosity (Pa s)
+    psi_deg: float = 0.0             # dilation angle (DP_JAUMANN)
+    cohesion: float = 0.0            # c (DP_JAUMANN)
+    tension: float = 0.0             # tensile cutoff sigma^t (DP_JAUMANN)
+    obstacles: Tuple = ()            # resting rigid boxes: ((lo...), (hi...)) each
 
     def __post_init__(self):
         n = tuple(int(v) for v in self.n) + (1,) * (3 - len(self.n))
