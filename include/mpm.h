@@ -252,6 +252,20 @@ int mpm_mlp_forward(const mpm_mlp* net, void* hip_stream, const float* params, i
  * buffer is overwritten), using the cache of the matching forward call. */
 int mpm_mlp_backward(const mpm_mlp* net, void* hip_stream, const float* params, int64_t n, const float* x,
                      const float* cache, const float* dy, float* work, float* dparams);
+/* The same backward pass for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight training or serving loops, harnesses
+ * that forbid hipMalloc): the work buffer is a static device array of
+ * MPM_MLP_SCRATCH_FLOATS floats (32 MiB) that every GPU the library runs on
+ * holds until the process ends, looked up on the first call on a device.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  EINVAL (message in mpm_last_error(NULL)) when
+ * mpm_mlp_cache_floats(net, n) exceeds MPM_MLP_SCRATCH_FLOATS.  Every call
+ * on one GPU shares that GPU's array (it keeps the last call's contents;
+ * the kernels write every entry they read): calls that overlap on one GPU,
+ * on different streams or from different threads, race. */
+#define MPM_MLP_SCRATCH_FLOATS (8 * 1024 * 1024)
+int mpm_mlp_backward_noalloc(const mpm_mlp* net, void* hip_stream, const float* params, int64_t n,
+                             const float* x, const float* cache, const float* dy, float* dparams);
 /* One Adam update (Kingma & Ba) of n parameters in place; step >= 1 counts
  * updates; m and v are the moment buffers (start at zero). */
 int mpm_adam_step(void* hip_stream, int64_t n, float* params, const float* grad, float* m, float* v,
@@ -290,8 +304,9 @@ int mpm_profile_read(mpm_ctx* ctx, double* host_ms, int64_t* host_launches);
 /* Number of particles currently set. */
 int64_t mpm_num_particles(const mpm_ctx* ctx);
 
-/* Message of the last failure on ctx (or of the last mpm_create failure when
- * ctx is NULL).  Valid until the next call on ctx. */
+/* Message of the last failure on ctx (or, when ctx is NULL, of the last
+ * failed call without a context on this thread: mpm_create,
+ * mpm_mlp_backward_noalloc).  Valid until the next such call. */
 const char* mpm_last_error(const mpm_ctx* ctx);
 
 /* Frees the context (not the caller's workspace).  Synchronizes the stream. */

@@ -10,9 +10,18 @@
 
 using namespace mpm;
 
-namespace {
+// Message of the last failure of a call without a context (mpm_create,
+// mpm_workspace_bytes, the context-free calls): a fixed buffer, so that
+// recording it allocates nothing.
+static thread_local char g_global_error[256] = "";
 
-thread_local std::string g_create_error;
+void mpm::set_global_error(const char* msg)
+{
+    strncpy(g_global_error, msg ? msg : "", sizeof(g_global_error) - 1);
+    g_global_error[sizeof(g_global_error) - 1] = 0;
+}
+
+namespace {
 
 int nsym_of(int dim) { return dim * (dim + 1) / 2; }
 
@@ -193,26 +202,26 @@ extern "C" {
 int mpm_create(const mpm_config* cfg, void* hip_stream, mpm_ctx** out)
 {
     if (!out) {
-        g_create_error = "out is NULL";
+        set_global_error("out is NULL");
         return MPM_EINVAL;
     }
     *out = nullptr;
     std::string why;
     int rc = check_config(cfg, why);
     if (rc) {
-        g_create_error = why;
+        set_global_error(why.c_str());
         return rc;
     }
     mpm_ctx* c = new (std::nothrow) mpm_ctx();
     if (!c) {
-        g_create_error = "out of host memory";
+        set_global_error("out of host memory");
         return MPM_ENOMEM;
     }
     c->cfg = *cfg;
     c->cfg.tile = cfg->dim == 3 ? 4 : 8;
     c->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
-        g_create_error = "hipGetDevice failed";
+        set_global_error("hipGetDevice failed");
         delete c;
         return MPM_EHIP;
     }
@@ -231,11 +240,11 @@ int mpm_workspace_bytes(const mpm_config* cfg, int64_t n_particles, int32_t tape
     std::string why;
     int rc = check_config(cfg, why);
     if (rc) {
-        g_create_error = why;
+        set_global_error(why.c_str());
         return rc;
     }
     if (!bytes || n_particles < 0 || n_particles >= (1ll << 31) || tape_steps < 0 || ckpt_every < 0) {
-        g_create_error = "bad workspace arguments";
+        set_global_error("bad workspace arguments");
         return MPM_EINVAL;
     }
     mpm_config c = *cfg;
@@ -520,7 +529,7 @@ int64_t mpm_num_particles(const mpm_ctx* c) { return c ? c->N : -1; }
 
 const char* mpm_last_error(const mpm_ctx* c)
 {
-    if (!c) return g_create_error.c_str();
+    if (!c) return g_global_error;
     return c->err.c_str();
 }
 

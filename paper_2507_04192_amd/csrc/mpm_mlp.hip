@@ -14,9 +14,48 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/mpm.h"
 
+namespace mpm {
+void set_global_error(const char* msg);
+}
+
+// Work buffer of mpm_mlp_backward_noalloc (the layer adjoints dZ), a
+// file-scope device array: every GPU the library runs on holds one copy
+// for the life of the process.  Host code never passes this name to a
+// kernel (on the host it is a stand-in, not a device address); it uses the
+// per-device address from hipGetSymbolAddress below.
+static __device__ __align__(256) float scratch[MPM_MLP_SCRATCH_FLOATS];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// (with that device current) and kept.
+int scratch_address(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        mpm::set_global_error("mpm_mlp_backward_noalloc: no usable current device");
+        return MPM_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            mpm::set_global_error("mpm_mlp_backward_noalloc: hipGetSymbolAddress of the scratch array failed");
+            return MPM_EHIP;
+        }
+        g_scratch_ptr[dev] = (float*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPM_OK;
+}
 
 constexpr int kMaxW = 128;
 constexpr int kRowsPerWave = 16;
@@ -401,6 +440,27 @@ int mpm_mlp_backward(const mpm_mlp* net, void* hip_stream, const float* params, 
         }
     }
     return hipGetLastError() == hipSuccess ? MPM_OK : MPM_EHIP;
+}
+
+int mpm_mlp_backward_noalloc(const mpm_mlp* net, void* hip_stream, const float* params, int64_t n,
+                             const float* x, const float* cache, const float* dy, float* dparams)
+{
+    int64_t need = mpm_mlp_cache_floats(net, n);
+    if (need < 0) {
+        mpm::set_global_error("mpm_mlp_backward_noalloc: invalid network description or n");
+        return MPM_EINVAL;
+    }
+    if (need > (int64_t)MPM_MLP_SCRATCH_FLOATS) {
+        mpm::set_global_error("mpm_mlp_backward_noalloc: n too large for the static scratch "
+                              "(mpm_mlp_cache_floats(net, n) > MPM_MLP_SCRATCH_FLOATS)");
+        return MPM_EINVAL;
+    }
+    float* work = nullptr;
+    if (n > 0) {
+        int rc = scratch_address(&work);
+        if (rc) return rc;
+    }
+    return mpm_mlp_backward(net, hip_stream, params, n, x, cache, dy, work, dparams);
 }
 
 int mpm_cell_field_gather(void* hip_stream, int32_t nc, int32_t nx, int32_t ny, const double* host_lo,

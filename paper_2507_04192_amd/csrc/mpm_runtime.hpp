@@ -151,6 +151,10 @@ inline void prof_mark(mpm_ctx* c, int cls)
     c->marks.push_back({cls, e});
 }
 
+// Records the message of a failed call that has no context (read back by
+// mpm_last_error(NULL)); copies into a fixed buffer, allocates nothing.
+void set_global_error(const char* msg);
+
 inline int set_err(mpm_ctx* c, int code, const std::string& msg)
 {
     if (c) c->err = msg;

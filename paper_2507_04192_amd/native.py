@@ -95,6 +95,7 @@ def lib():
             "mpm_mlp_cache_floats": ([P, i64], ct.c_int64),
             "mpm_mlp_forward": ([P, P, P, i64, P, P, P], ct.c_int),
             "mpm_mlp_backward": ([P, P, P, i64, P, P, P, P, P], ct.c_int),
+            "mpm_mlp_backward_noalloc": ([P, P, P, i64, P, P, P, P], ct.c_int),
             "mpm_cell_field_gather": ([P, i32, i32, i32, P, P, i64, P, P, P], ct.c_int),
             "mpm_cell_field_scatter": ([P, i32, i32, i32, P, P, i64, P, P, P], ct.c_int),
             "mpm_extract": ([P, P, P], ct.c_int),
@@ -122,6 +123,7 @@ _HEADER_NAMES = [
     "mpm_read_grid", "mpm_read_sort", "mpm_num_particles", "mpm_last_error", "mpm_destroy",
     "mpm_profile_enable", "mpm_profile_read", "mpm_set_observations", "mpm_forward_loss",
     "mpm_backward", "mpm_mlp_num_params", "mpm_mlp_cache_floats", "mpm_mlp_forward", "mpm_mlp_backward",
+    "mpm_mlp_backward_noalloc",
     "mpm_adam_step", "mpm_cell_field_gather", "mpm_cell_field_scatter", "mpm_extract",
 ]
 PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p", "g2p_adj", "grid_adj", "p2g_adj"]
@@ -441,6 +443,15 @@ class MLP:
                                      _ptr(dy.contiguous()), _ptr(work), _ptr(dp))
         _check(None, rc)
         return dp
+
+    def backward_noalloc_into(self, params, x, cache, dy, dparams):
+        """The backward pass through mpm_mlp_backward_noalloc (the work buffer
+        is the library's static device array; nothing is allocated by the
+        call): writes the parameter gradient into the caller's dparams."""
+        n = x.shape[1]
+        rc = self.L.mpm_mlp_backward_noalloc(ct.byref(self.desc), self._stream(), _ptr(params), n, _ptr(x),
+                                             _ptr(cache), _ptr(dy), _ptr(dparams))
+        _check(None, rc)
 
 
 def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
