@@ -4,8 +4,9 @@ pass and the Adam update used to train it.
 
 Parameter layout (shared convention with the solver's C-ABI, not code): for
 each layer l, the weight W_l (out x in, row-major) then the bias b_l (out),
-all layers concatenated.  Hidden layers use tanh; the output layer applies
-`out_act` ('none' or 'sigmoid') and then y = shift + scale * act(z).
+all layers concatenated.  Hidden layers use `hidden_act` ('tanh', or
+'relu' as in the velocity-profile network of Sec. 5.2); the output layer
+applies `out_act` ('none' or 'sigmoid') and then y = shift + scale * act(z).
 """
 from __future__ import annotations
 
@@ -13,9 +14,10 @@ import numpy as np
 
 
 class Spec:
-    def __init__(self, widths, out_act="none", out_scale=1.0, out_shift=0.0):
+    def __init__(self, widths, out_act="none", out_scale=1.0, out_shift=0.0, hidden_act="tanh"):
         self.widths = list(widths)
         self.out_act = out_act
+        self.hidden_act = hidden_act
         self.out_scale = float(out_scale)
         self.out_shift = float(out_shift)
 
@@ -54,7 +56,7 @@ def forward(spec, params, x):
     for li, (W, b) in enumerate(layers):
         z = h @ W.T + b
         if li < len(layers) - 1:
-            h = np.tanh(z)
+            h = np.tanh(z) if spec.hidden_act == "tanh" else np.maximum(z, 0.0)
         elif spec.out_act == "sigmoid":
             h = 1.0 / (1.0 + np.exp(-z))
         else:
@@ -81,7 +83,10 @@ def backward(spec, params, acts, dy):
         grads[li] = (gW, gb)
         if li > 0:
             dh = dz @ W
-            dz = dh * (1.0 - h_in * h_in)     # tanh'(z) = 1 - tanh(z)^2
+            if spec.hidden_act == "tanh":
+                dz = dh * (1.0 - h_in * h_in)     # tanh'(z) = 1 - tanh(z)^2
+            else:
+                dz = dh * (h_in > 0.0)            # relu'(z) = 1 for z > 0, else 0
     return np.concatenate([np.concatenate([gW.reshape(-1), gb]) for gW, gb in grads])
 
 

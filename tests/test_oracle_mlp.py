@@ -5,11 +5,11 @@ import pytest
 from oracle import mlp as M
 
 
-@pytest.mark.parametrize("widths,act", [([2, 64, 64, 2], "none"), ([2, 128, 128, 1], "sigmoid"),
-                                        ([3, 16, 5], "none")])
-def test_backward_matches_finite_differences(widths, act):
+@pytest.mark.parametrize("widths,act,hidden", [([2, 64, 64, 2], "none", "tanh"), ([2, 128, 128, 1], "sigmoid", "tanh"),
+                                               ([3, 16, 5], "none", "tanh"), ([1, 30, 30, 30, 1], "none", "relu")])
+def test_backward_matches_finite_differences(widths, act, hidden):
     spec = M.Spec(widths, out_act=act, out_scale=0.8 if act == "sigmoid" else 1.0,
-                  out_shift=0.1 if act == "sigmoid" else 0.0)
+                  out_shift=0.1 if act == "sigmoid" else 0.0, hidden_act=hidden)
     p = M.init_params(spec, 1)
     rng = np.random.default_rng(2)
     x = rng.uniform(-1, 1, size=(37, widths[0]))
@@ -68,3 +68,26 @@ def test_adam_first_step_is_sign_step():
     for t in range(1, 6):
         M.adam(q, g, m, v, t, lr=0.01, eps=0.0)
     assert np.allclose(q, p - 5 * 0.01 * np.sign(g), atol=1e-12)
+
+
+def test_relu_layer_closed_form():
+    """A ReLU hidden layer is max(Wx + b, 0) (the velocity-profile network
+    of Sec. 5.2): checked against the definition with weights that make half
+    of the units inactive; the gradient through an inactive unit is zero."""
+    rng = np.random.default_rng(7)
+    W1 = rng.normal(size=(6, 1))
+    b1 = np.array([-5.0, -5.0, -5.0, 5.0, 5.0, 5.0])      # units 0-2 off, 3-5 on for |x| < 1 / max|W|
+    W1 *= 0.1
+    W2 = rng.normal(size=(1, 6))
+    b2 = rng.normal(size=1)
+    p = np.concatenate([W1.reshape(-1), b1, W2.reshape(-1), b2])
+    spec = M.Spec([1, 6, 1], hidden_act="relu")
+    x = rng.uniform(-1, 1, size=(20, 1))
+    y, acts = M.forward(spec, p, x)
+    h = np.maximum(x @ W1.T + b1, 0.0)
+    assert np.allclose(y, h @ W2.T + b2, atol=1e-14)
+    assert not h[:, :3].any() and (h[:, 3:] > 0).all()
+    g = M.backward(spec, p, acts, np.ones((20, 1)))
+    gW1 = g[:6].reshape(6, 1)
+    assert not gW1[:3].any()
+    assert np.allclose(gW1[3:, 0], W2[0, 3:] * x.sum())
