@@ -322,6 +322,141 @@ static void hencky_tangent(const orc_config* c, int elastic_only, const double F
         }
 }
 
+/* Directional derivative of the hypoelastic Drucker-Prager update of one
+ * particle (Sec. 2.3 eq:dp_stress; App. A; the forward map is
+ * orc_constitutive's DP_JAUMANN branch): inputs the stress cache S (V0 J
+ * sigma), J and the velocity gradient L, outputs S' and J', along (dS, dJ,
+ * dL).  The zone (and the corner of a shear return) is the one the forward
+ * map takes at the point, read from orc_dp_jaumann itself. */
+static void jaumann_tangent(const orc_config* c, double dt, const double S[3][3], double J, const double L[3][3],
+                            const double dS[3][3], double dJ, const double dL[3][3], double dSo[3][3],
+                            double* dJo)
+{
+    int d = c->dim;
+    double E = c->youngs, nu = c->poisson;
+    double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    double G = E / (2.0 * (1.0 + nu));
+    double K = lam + 2.0 * G / d;
+    double sp = sin(c->phi_deg * M_PI / 180.0), cp = cos(c->phi_deg * M_PI / 180.0);
+    double ss = sin(c->psi_deg * M_PI / 180.0);
+    double q_phi = 6.0 * sp / (sqrt(3.0) * (3.0 + sp));
+    double k_phi = 6.0 * c->cohesion * cp / (sqrt(3.0) * (3.0 + sp));
+    double q_psi = 6.0 * ss / (sqrt(3.0) * (3.0 + ss));
+    double st = c->tension, tauP = k_phi - q_phi * st;
+
+    /* volume: J' = J det(M), M = I + dt L; d det(M) = cof(M) : dM */
+    double M[3][3] = {{0}}, cof[3][3] = {{0}};
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) M[a][b] = (a == b ? 1.0 : 0.0) + dt * L[a][b];
+    double detM;
+    if (d == 2) {
+        detM = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+        cof[0][0] = M[1][1]; cof[0][1] = -M[1][0];
+        cof[1][0] = -M[0][1]; cof[1][1] = M[0][0];
+    } else {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                cof[i][j] = M[i1][j1] * M[i2][j2] - M[i1][j2] * M[i2][j1];
+            }
+        detM = M[0][0] * cof[0][0] + M[0][1] * cof[0][1] + M[0][2] * cof[0][2];
+    }
+    double ddet = 0.0;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) ddet += cof[a][b] * dt * dL[a][b];
+    double Jn = J * detM, dJn = dJ * detM + J * ddet;
+
+    /* Cauchy stress sigma = S / (V0 J) and its derivative */
+    double sg[3][3] = {{0}}, dsg[3][3] = {{0}};
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            sg[a][b] = S[a][b] / (c->vol0 * J);
+            dsg[a][b] = (dS[a][b] - sg[a][b] * c->vol0 * dJ) / (c->vol0 * J);
+        }
+    /* the zone the forward map takes */
+    double Lf[9], sgf[9];
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            Lf[a * d + b] = L[a][b];
+            sgf[a * d + b] = sg[a][b];
+        }
+    int zone = orc_dp_jaumann(c, dt, Lf, sgf, NULL);
+
+    /* trial stress T and its derivative */
+    double Dd[3][3] = {{0}}, Dw[3][3] = {{0}}, dDd[3][3] = {{0}}, dDw[3][3] = {{0}}, trD = 0.0, dtrD = 0.0;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            Dd[a][b] = 0.5 * dt * (L[a][b] + L[b][a]);
+            Dw[a][b] = 0.5 * dt * (L[a][b] - L[b][a]);
+            dDd[a][b] = 0.5 * dt * (dL[a][b] + dL[b][a]);
+            dDw[a][b] = 0.5 * dt * (dL[a][b] - dL[b][a]);
+        }
+    for (int a = 0; a < d; ++a) {
+        trD += Dd[a][a];
+        dtrD += dDd[a][a];
+    }
+    double T[3][3] = {{0}}, dT[3][3] = {{0}};
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double r = sg[i][j], dr = dsg[i][j];
+            for (int k = 0; k < d; ++k) {
+                r += sg[i][k] * Dw[j][k] + sg[j][k] * Dw[i][k];
+                dr += dsg[i][k] * Dw[j][k] + sg[i][k] * dDw[j][k] + dsg[j][k] * Dw[i][k] + sg[j][k] * dDw[i][k];
+            }
+            T[i][j] = r + 2.0 * G * Dd[i][j] + (i == j ? lam * trD : 0.0);
+            dT[i][j] = dr + 2.0 * G * dDd[i][j] + (i == j ? lam * dtrD : 0.0);
+        }
+    double sm = 0.0, dsm = 0.0;
+    for (int a = 0; a < d; ++a) {
+        sm += T[a][a] / d;
+        dsm += dT[a][a] / d;
+    }
+    double sv[3][3] = {{0}}, dsv[3][3] = {{0}}, ss2 = 0.0, sds = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            sv[i][j] = T[i][j] - (i == j ? sm : 0.0);
+            dsv[i][j] = dT[i][j] - (i == j ? dsm : 0.0);
+            ss2 += sv[i][j] * sv[i][j];
+            sds += sv[i][j] * dsv[i][j];
+        }
+    double tau = sqrt(0.5 * ss2);
+    double dtau = tau > 0.0 ? 0.5 * sds / tau : 0.0;      /* tau^2 = s:s/2 */
+
+    double sm_n = sm, dsm_n = dsm, scale = 1.0, dscale = 0.0;
+    if (zone == 2) {
+        double fs = tau - k_phi + q_phi * sm, dfs = dtau + q_phi * dsm;
+        double den = G + K * q_phi * q_psi;
+        sm_n = sm - K * q_psi * fs / den;
+        dsm_n = dsm - K * q_psi * dfs / den;
+        double tau_n = k_phi - q_phi * sm_n, dtau_n = -q_phi * dsm_n;
+        if (sm_n > st) {           /* the corner */
+            sm_n = st;
+            dsm_n = 0.0;
+            tau_n = tauP;
+            dtau_n = 0.0;
+        }
+        if (tau > 0.0) {
+            scale = tau_n / tau;
+            dscale = (dtau_n * tau - tau_n * dtau) / (tau * tau);
+        } else {
+            scale = 0.0;
+            dscale = 0.0;
+        }
+    } else if (zone == 3) {
+        sm_n = st;
+        dsm_n = 0.0;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dSo[i][j] = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double so = scale * sv[i][j] + (i == j ? sm_n : 0.0);
+            double dso = dscale * sv[i][j] + scale * dsv[i][j] + (i == j ? dsm_n : 0.0);
+            dSo[i][j] = c->vol0 * (dJn * so + Jn * dso);
+        }
+    *dJo = dJn;
+}
+
 /* ------------------------------------------------------------------ */
 /* One step's vector-Jacobian product                                   */
 /* ------------------------------------------------------------------ */
@@ -336,10 +471,12 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
 {
     const int d = c->dim, dd = d * d;
     const int fluid = c->material == ORC_FLUID;
-    /* the reverse sweep covers the APIC transfer, inviscid fluid and the
-     * Hencky materials; other settings are refused */
-    if (c->transfer != ORC_APIC || c->viscosity != 0.0 || c->n_obstacles > 0 ||
-        c->material == ORC_DP_JAUMANN)
+    const int jaumann = c->material == ORC_DP_JAUMANN;
+    const int carries_j = fluid || jaumann;
+    /* the reverse sweep covers the APIC transfer without obstacles, the
+     * inviscid fluid, the Hencky materials and the hypoelastic
+     * Drucker-Prager material; other settings are refused */
+    if (c->transfer != ORC_APIC || c->viscosity != 0.0 || c->n_obstacles > 0)
         return -2;
     int32_t dims[3];
     int64_t NN = orc_node_dims(c, dims);
@@ -380,10 +517,10 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
         }
         for (int q = 0; q < dd; ++q) {
             Cm[q * N + s] = C0[q * N + j];
-            Fm[q * N + s] = fluid ? 0.0 : F0[q * N + j];
+            Fm[q * N + s] = carries_j ? 0.0 : F0[q * N + j];
             Sm[q * N + s] = S0[q * N + j];
         }
-        Jm[s] = fluid ? J0[j] : 1.0;
+        Jm[s] = carries_j ? J0[j] : 1.0;
     }
 
     /* forward recomputation: P2G and grid (velocity before and after walls) */
@@ -450,7 +587,40 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
 
         /* adjoint of the constitutive outputs -> Lbar and the input F/J adjoint */
         double Lb[3][3] = {{0}};
-        if (fluid) {
+        if (jaumann) {
+            /* contract the output adjoints (S', J') with the tangent along
+             * every input direction: S entries, J, L entries */
+            double Sp[3][3] = {{0}}, Lp[3][3] = {{0}}, zero[3][3] = {{0}}, dSo[3][3];
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) {
+                    Sp[a][b] = Sm[(a * d + b) * N + s];
+                    Lp[a][b] = L[a][b];
+                }
+            double dJo;
+            for (int p = 0; p < d; ++p)
+                for (int q = 0; q < d; ++q) {
+                    double e[3][3] = {{0}};
+                    e[p][q] = 1.0;
+                    double sum;
+                    /* along S_pq: the constitutive part of the input stress adjoint */
+                    jaumann_tangent(c, dt, Sp, Jm[s], Lp, e, 0.0, zero, dSo, &dJo);
+                    sum = aJ1[s] * dJo;
+                    for (int a = 0; a < d; ++a)
+                        for (int b = 0; b < d; ++b) sum += aS1[(a * d + b) * N + s] * dSo[a][b];
+                    aSs[(p * d + q) * N + s] += sum;
+                    /* along L_pq */
+                    jaumann_tangent(c, dt, Sp, Jm[s], Lp, zero, 0.0, e, dSo, &dJo);
+                    sum = aJ1[s] * dJo;
+                    for (int a = 0; a < d; ++a)
+                        for (int b = 0; b < d; ++b) sum += aS1[(a * d + b) * N + s] * dSo[a][b];
+                    Lb[p][q] = sum;
+                }
+            jaumann_tangent(c, dt, Sp, Jm[s], Lp, zero, 1.0, zero, dSo, &dJo);
+            double sum = aJ1[s] * dJo;
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) sum += aS1[(a * d + b) * N + s] * dSo[a][b];
+            aJs[s] = sum;
+        } else if (fluid) {
             double detM = (d == 2) ? M[0][0] * M[1][1] - M[0][1] * M[1][0]
                                    : M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1])
                                    - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0])
@@ -655,9 +825,9 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
         for (int q = 0; q < dd; ++q) {
             aC0[q * N + j] = aCs[q * N + s];
             aS0[q * N + j] = aSs[q * N + s];
-            if (!fluid) aF0[q * N + j] = aFs[q * N + s];
+            if (!carries_j) aF0[q * N + j] = aFs[q * N + s];
         }
-        if (fluid) aJ0[j] = aJs[s];
+        if (carries_j) aJ0[j] = aJs[s];
     }
 
     free(key); free(perm); free(X); free(V); free(Cm); free(Fm); free(Jm); free(Sm);

@@ -39,7 +39,7 @@ def _state(orc, cfg, N, seed):
 def _outputs(cfg, st):
     d = cfg.dim
     out = {"x": st.x, "v": st.v, "C": st.C, "S": st.S}
-    if cfg.material == W.FLUID:
+    if cfg.material in (W.FLUID, W.DP_JAUMANN):
         out["J"] = st.J
     else:
         out["F"] = st.F
@@ -193,3 +193,61 @@ def test_eulerian_loss_gradient(orc):
     fd = (Lp - Lm) / (2 * h)
     ad = float((gv0 * dv).sum())
     assert abs(fd - ad) <= 1e-5 * abs(fd), (fd, ad)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_adjoint_step_jaumann_every_zone(orc, dim):
+    """The hypoelastic Drucker-Prager update (Sec. 2.3 eq:dp_stress; App. A)
+    in the reverse step: prestresses spread over the elastic zone, shear
+    failure and the tension cutoff (with cohesion, a negative cutoff and a
+    dilation angle), one step's vector-Jacobian product against central
+    differences of the forward step, for every input field.  Each zone is
+    also checked on its own: the outputs are weighted only on the particles
+    of that zone."""
+    cfg = _cfg(dim, W.DP_JAUMANN, phi_deg=30.0, psi_deg=10.0, cohesion=40.0, tension=-10.0)
+    o = orc.Oracle(cfg)
+    N = 300 if dim == 3 else 400
+    rng = np.random.default_rng(80 + dim)
+    x, v, C, _ = W.random_state(cfg, N, 81 + dim, vscale=0.3, cscale=3.0, margin=0.3)
+    d = dim
+    sig = rng.normal(0, 1, size=(d, d, N))
+    sig = 0.5 * (sig + sig.transpose(1, 0, 2)) * rng.uniform(0, 150, size=N)
+    sig += np.eye(d)[:, :, None] * rng.uniform(-300, 200, size=N)
+    J = 1.0 + rng.normal(0, 1e-3, size=N)
+    S = (sig * (cfg.vol0 * J)).reshape(d * d, N)
+    st0 = orc.State(cfg, x, v=v, C=C, J=J, S=S)
+    # the zone each particle takes, from the oracle's own stages
+    s2 = st0.copy()
+    key = o.keys(s2.x)
+    perm = o.sort_perm(key, o.cells_per_tile())
+    for name in ("x", "v", "C", "S"):
+        setattr(s2, name, np.ascontiguousarray(getattr(s2, name)[:, perm]))
+    s2.J = np.ascontiguousarray(s2.J[perm])
+    gm, gp = o.p2g(s2, cfg.dt)
+    gv = o.grid_update(gm, gp, cfg.dt)
+    Lg = o.g2p(s2, gv, cfg.dt)
+    zones = np.array([o.dp_jaumann(Lg[:, p].reshape(d, d), s2.S[:, p].reshape(d, d) / (cfg.vol0 * s2.J[p]),
+                                   cfg.dt)[1] for p in range(N)])
+    assert all((zones == z).sum() >= 20 for z in (1, 2, 3)), np.bincount(zones)
+    st1 = st0.copy()
+    o.step(st1, cfg.dt)
+    for sel in (None, 1, 2, 3):
+        mask = np.ones(N) if sel is None else (zones == sel).astype(float)   # in the output (sorted) order
+        w = {k: rng.normal(size=v.shape) * mask for k, v in _outputs(cfg, st1).items()}
+
+        def L(st):
+            s = st.copy()
+            o.step(s, cfg.dt)
+            return sum(float((w[k] * v).sum()) for k, v in _outputs(cfg, s).items())
+
+        g = orc.adjoint_step(cfg, st0, w, cfg.dt)
+        scale = {"x": 1e-4 * cfg.dx, "v": 1e-3, "C": 1e-2, "S": 1e-3 * np.abs(S).max(), "J": 1e-5}
+        for f in ("x", "v", "C", "S", "J"):
+            delta = rng.normal(size=getattr(st0, f).shape) * scale[f]
+            sp, sm = st0.copy(), st0.copy()
+            eps = 1e-2
+            setattr(sp, f, getattr(st0, f) + eps * delta)
+            setattr(sm, f, getattr(st0, f) - eps * delta)
+            fd = (L(sp) - L(sm)) / (2 * eps)
+            ad = float((g[f] * delta).sum())
+            assert abs(fd - ad) <= 2e-6 * max(abs(fd), 1e-12) + 1e-12, (sel, f, fd, ad)
