@@ -31,18 +31,34 @@ if ROOT not in sys.path:
 METRIC = "particle-steps/s fwd & fwd+adjoint, 3D 2.7M-particle collapse; % of HBM peak"
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E peak
 
-# Algorithmic scalars per particle moved by each kernel (3-D sand): the state
-# is x3 v3 C9 F9.  G2P reads x, F and writes x, v, C, F and the stress cache
-# (6); P2G reads x, v, C and the stress cache.  Bucket moves a key and an
-# index (int32).  The whole step's figure is the state read once and written
-# once: 48 scalars.
-ALG_SCALARS = {"g2p": 3 + 9 + 3 + 3 + 9 + 9 + 6, "p2g": 3 + 3 + 9 + 6,
-               # reverse kernels: g2p_adj reads x, F, the output adjoint (x v C F
-               # stress: 30) and writes the intermediate (12); p2g_adj reads x v C
-               # stress and the intermediate and writes the input adjoint (30)
-               "g2p_adj": 3 + 9 + 30 + 12, "p2g_adj": 3 + 3 + 9 + 6 + 12 + 30}
+# Algorithmic scalars per particle moved by each kernel (3-D sand).  The
+# state is x3 v3 C9 F9; a forward step must read it once and write it once
+# (48 scalars), and the forward kernels split that as
+#   G2P reads x, F and writes x, v, C, F        36
+#   P2G reads v, C                              12
+# The reverse step must read the state (24) and the output adjoint (24) and
+# write the input adjoint (24):
+#   reverse G2P reads x, F and the output adjoint of x v C F      36
+#   reverse P2G reads v, C and writes the input adjoint of x v C F 36
+# Everything else a kernel moves is design overhead, reported beside it:
+# the stress cache (6 symmetric scalars written by G2P, read by P2G; its
+# adjoint in the reverse kernels), P2G's second read of x, the 12-scalar
+# intermediate between the reverse kernels, and the int32 sort arrays
+# (pid read and written, key written, permutation and bucket indices).
+ALG_SCALARS = {"g2p": 3 + 9 + 3 + 3 + 9 + 9, "p2g": 3 + 9,
+               "g2p_adj": 3 + 9 + 24, "p2g_adj": 3 + 9 + 24}
+OVERHEAD_SCALARS = {"g2p": 6, "p2g": 6 + 3, "g2p_adj": 6 + 12, "p2g_adj": 3 + 6 + 12 + 6}
+OVERHEAD_INT_BYTES = {"g2p": 4 + 4 + 4 + 4, "p2g": 4 + 4 + 4, "g2p_adj": 4, "p2g_adj": 4 + 4}
 ALG_INT_BYTES = {"bucket": 8}
-STEP_SCALARS = 48
+STEP_SCALARS = 48                # forward step: the state read once, written once
+ADJ_STEP_SCALARS = 168           # forward+adjoint: two forward passes (96) + reverse (72)
+# Vector-ALU work of a 3-D sand particle-step with the gradient-form force
+# and velocity gradient (P2G ~0.95k, G2P ~1.25k, constitutive ~1.2k flops,
+# an FMA counted as 2), and the vector peak it is set against: packed FP32
+# is disabled in every build here, so FP32 issues at the FP64 rate,
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s.
+VALU_FLOPS_PER_PSTEP = 3400.0
+VALU_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
@@ -181,6 +197,7 @@ def roofline(prof, n_particles, elem):
     for k, v in kernels.items():
         if k in ALG_SCALARS:
             v["alg_bytes"] = ALG_SCALARS[k] * elem * n_particles
+            v["overhead_bytes"] = (OVERHEAD_SCALARS[k] * elem + OVERHEAD_INT_BYTES[k]) * n_particles
         elif k in ALG_INT_BYTES:
             v["alg_bytes"] = ALG_INT_BYTES[k] * n_particles
         if "alg_bytes" in v:
@@ -190,8 +207,49 @@ def roofline(prof, n_particles, elem):
     return dom, kernels, {
         "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": None,
-        "kernel": dom, "alg_bytes_per_launch": d.get("alg_bytes"), "avg_launch_ms": d["avg_ms"],
+        "kernel": dom, "alg_bytes_per_launch": d.get("alg_bytes"),
+        "overhead_bytes_per_launch": d.get("overhead_bytes"), "avg_launch_ms": d["avg_ms"],
     }
+
+
+def step_roofline(value, scalars, elem):
+    """The whole step against HBM: the algorithmic bytes per particle-step
+    (the state read once and written once; forward+adjoint: two forward
+    passes and the reverse step) times particle-steps/s."""
+    b = scalars * elem
+    ach = value * b / 1e9
+    return {"bound": "hbm", "bytes_per_particle_step": b, "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+
+
+def valu_roofline(value, passes=1.0):
+    """The whole step against the vector ALUs: VALU_FLOPS_PER_PSTEP per
+    particle-step and pass, against the FP32/FP64 vector peak without packed
+    FP32."""
+    ach = value * VALU_FLOPS_PER_PSTEP * passes / 1e12
+    return {"bound": "alu", "flops_per_particle_step": VALU_FLOPS_PER_PSTEP * passes, "achieved": ach,
+            "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / VALU_PEAK_TFLOPS}
+
+
+def copy_probe(mib=1024, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second),
+    timed with events on torch's stream, on which the copy runs."""
+    import torch
+    n = mib * 2**20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    return {"bytes_per_copy": n * 4, "ms": ms, "gbs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
 def cpu_baseline(cfg, x, steps):
@@ -209,6 +267,47 @@ def cpu_baseline(cfg, x, steps):
                   f"1 thread ({t1 - t0:.1f} s)",
         "host_cpu": _cpu_name(), "nproc": os.cpu_count(),
     }
+
+
+def cpu_baseline_adjoint(steps_cyl=20, steps_fric=50):
+    """The oracle's forward rollout with a tracer loss and its reverse sweep
+    (binary64, one thread), on two bounded samples: the 1/8-scale cylinder
+    (the benchmark's forward+adjoint leg shrunk in every length, 500 tracers
+    every 10 steps, gradients wrt v0 and the floor friction) and the 2-D
+    friction dam-break (32,768 particles, 32 friction segments, 64 tracers
+    every 10 steps) for the first steps_fric of its 500 steps."""
+    import numpy as np
+    import oracle
+    from paper_2507_04192_amd import workloads as W
+    out = {}
+    cfg, x = W.cylinder_collapse_3d(scale_div=8, seed=0)
+    n = x.shape[1]
+    tr = W.pick_tracers(n, 500, 7)
+    frames = list(range(10, steps_cyl + 1, 10))
+    obs = oracle.Observations(frames, tracer_pid=tr, lag_field="x",
+                              lag_target=np.repeat(x[:, tr][None], len(frames), axis=0))
+    mu = np.full(cfg.floor_nodes(), 0.5)
+    t0 = time.perf_counter()
+    oracle.rollout_grad(cfg, x, np.zeros_like(x), steps_cyl, cfg.dt, floor_mu=mu, obs=obs)
+    t1 = time.perf_counter()
+    out["cylinder_div8"] = {"value": n * steps_cyl / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
+                            "kind": "oracle", "sample": f"{steps_cyl} steps forward+adjoint of the "
+                            f"{n}-particle cylinder (1/8 scale), binary64, 1 thread ({t1 - t0:.1f} s)"}
+    cfg, x = W.friction_dam_break_2d()
+    n = x.shape[1]
+    tr = W.pick_tracers(n, 64, 4)
+    frames = list(range(10, steps_fric + 1, 10))
+    obs = oracle.Observations(frames, tracer_pid=tr, lag_field="x",
+                              lag_target=np.repeat(x[:, tr][None], len(frames), axis=0))
+    mu = W.segment_mu(cfg, W.uniform_mu_segments(3))
+    t0 = time.perf_counter()
+    oracle.rollout_grad(cfg, x, np.zeros_like(x), steps_fric, cfg.dt, floor_mu=mu, obs=obs)
+    t1 = time.perf_counter()
+    out["friction_dam_break"] = {"value": n * steps_fric / (t1 - t0), "unit": "particle-steps/s",
+                                 "cores": 1, "kind": "oracle",
+                                 "sample": f"{steps_fric} of 500 steps forward+adjoint of the {n}-particle "
+                                           f"friction dam-break, binary64, 1 thread ({t1 - t0:.1f} s)"}
+    return out
 
 
 def _cpu_name():
@@ -274,6 +373,8 @@ def main():
                    "ms_per_step": t64 / k64 * 1e3, "ms_per_step_no_events": t64_noev / k64 * 1e3,
                    "hbm_frac_step": n * k64 / t64 * STEP_SCALARS * 8 / (HBM_PEAK_GBS * 1e9),
                    "roofline": roof64,
+                   "step_roofline": step_roofline(n * k64 / t64, STEP_SCALARS, 8),
+                   "valu_roofline": valu_roofline(n * k64 / t64),
                    "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kern64.items()}}
         log(f"[bench] f64: {out_f64['ms_per_step']:.4f} ms/step, {out_f64['value']:.4e} particle-steps/s")
 
@@ -290,6 +391,10 @@ def main():
             if prec == "f32" and args.scale_div == 1:
                 roof_a["traffic"] = measured_traffic(TRAFFIC_KERNELS.get(dom_a, dom_a))
             r["roofline"] = roof_a
+            r["step_roofline"] = step_roofline(r["value"], ADJ_STEP_SCALARS, elem)
+            # the forward step runs twice (rollout, segment recompute) and the
+            # reverse step costs about two forward steps of VALU work
+            r["valu_roofline"] = valu_roofline(r["value"], passes=4.0)
             r["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1] > 0}
             adj[prec] = r
             log(f"[bench] fwd+adjoint {prec}: {r['ms_per_step']:.4f} ms/step, {r['value']:.4e} particle-steps/s "
@@ -303,6 +408,15 @@ def main():
         log(f"[bench] timing the oracle for {args.cpu_steps} step(s) on the host ...")
         cpu = cpu_baseline(cfg, x, args.cpu_steps)
         log(f"[bench] oracle: {cpu['value']:.4e} particle-steps/s")
+        if adj is not None:
+            log("[bench] timing the oracle's forward+adjoint on bounded samples ...")
+            cpu_adj = cpu_baseline_adjoint()
+            for k, v in cpu_adj.items():
+                log(f"[bench] oracle forward+adjoint {k}: {v['value']:.4e} particle-steps/s")
+            adj["cpu_baseline"] = cpu_adj
+    copy = copy_probe()
+    log(f"[bench] device copy: {copy['gbs']:.1f} GB/s ({copy['frac_of_peak']:.3f} of the HBM peak)")
+    roof["frac_of_copy"] = roof["achieved"] / copy["gbs"] if roof["achieved"] else None
 
     res = {
         "metric": METRIC, "value": val32, "unit": "particle-steps/s", "n_gpus": 1,
@@ -316,6 +430,9 @@ def main():
                    "scale_div": args.scale_div},
         "ms_per_step_no_events": t32_noev / args.steps * 1e3,
         "hbm_frac_step": val32 * STEP_SCALARS * 4 / (HBM_PEAK_GBS * 1e9),
+        "step_roofline": step_roofline(val32, STEP_SCALARS, 4),
+        "valu_roofline": valu_roofline(val32),
+        "copy_probe": copy,
         "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kernels.items()},
         "f64": out_f64,
         "fwd_adjoint": adj,

@@ -57,8 +57,41 @@ enum { MPM_F32 = 0, MPM_F64 = 1 };
  *                 the cone with slope (sqrt2/3) q_phi (q_phi of App. A),
  *                 stress-free apex for tr(eps) > 0; elastic whenever
  *                 |eps|_F <= 1e-6 (the case at rounding-level strain)
- *  HENCKY_ELASTIC the same elastic law without the return (checks only) */
-enum { MPM_FLUID_TAIT = 0, MPM_DP_HENCKY = 1, MPM_HENCKY_ELASTIC = 2 };
+ *  HENCKY_ELASTIC the same elastic law without the return (checks only)
+ *  DP_JAUMANN     the paper's own Drucker-Prager (Sec. 2.3 eq:dp_stress; App. A):
+ *                 hypoelastic Cauchy stress rotated with the Jaumann rate,
+ *                 Delta d = dt (L + L^T)/2, Delta w = dt (L - L^T)/2, trial
+ *                 stress by the isotropic elastic tensor, then zones I (elastic),
+ *                 II (shear return along the plastic potential of dilation
+ *                 angle psi) and III (tension cutoff sigma_m = sigma^t); a shear
+ *                 return that ends beyond the cutoff stops at the corner
+ *                 (sigma^t, tau^P); a trial stress of Frobenius norm <= 1e-6 E is
+ *                 elastic.  Carries J = J det(I + dt L) and the stress cache
+ *                 V0 J sigma.  In 2-D the mean stress is tr/2 and K = lam + G.
+ * A FLUID_TAIT material with viscosity > 0 adds the Newtonian stress of
+ * Sec. 2.3 eq:stress_strain, 2 mu (d - tr(d)/dim I) with the rate
+ * d = (L + L^T)/2, and then carries the full symmetric stress. */
+enum { MPM_FLUID_TAIT = 0, MPM_DP_HENCKY = 1, MPM_HENCKY_ELASTIC = 2, MPM_DP_JAUMANN = 3 };
+
+/* Grid-to-particle transfer (Sec. 2.2 G2P; App. B), v_i the grid velocity
+ * after the update and walls, x_i - x_p the node offset:
+ *  APIC  v' = sum phi v_i,  C' = (4/h^2) sum phi v_i (x_i - x_p)^T
+ *  PIC   v' = sum phi v_i,  C' = 0
+ *  TPIC  v' = sum phi v_i,  C' = sum v_i (grad phi)^T (the velocity gradient)
+ *  FLIP  v' = sum phi v_i + flip_alpha (v_p - sum phi v_i^n), C' = 0, with
+ *        v_i^n = (P2G momentum without the internal force) / m_i: flip_alpha
+ *        = 1 is FLIP, 0 is PIC, between them the FLIP/PIC blend.
+ * Every transfer moves the particle with the interpolated new velocity,
+ * x' = x + dt sum phi v_i, and P2G uses the carried C as the affine term. */
+enum { MPM_XFER_APIC = 0, MPM_XFER_PIC = 1, MPM_XFER_FLIP = 2, MPM_XFER_TPIC = 3 };
+
+/* Resting rigid obstacles (Sec. 4.2.1, frictionless contact): axis-aligned
+ * boxes [lo, hi].  After the walls, a node with mass inside the closed box
+ * whose velocity points into the obstacle through its nearest face (faces
+ * on the domain boundary excluded; ties: the first face in the order x-,
+ * x+, y-, y+, z-, z+) loses that normal component, v = v - (v.n) n.
+ * Obstacles apply in their order. */
+#define MPM_MAX_OBSTACLES 4
 
 /* Wall behaviour on a face (Sec. 2.2 ghost cells; Sec. 5.3 eq:coulomb_friction
  * with a resting wall).  Applies to nodes on or beyond the wall plane and only
@@ -70,10 +103,10 @@ enum {
     MPM_FIELD_X = 0,      /* position, dim comps */
     MPM_FIELD_V = 1,      /* velocity, dim comps */
     MPM_FIELD_C = 2,      /* APIC affine matrix, dim*dim comps */
-    MPM_FIELD_F = 3,      /* elastic deformation gradient, dim*dim (sand) */
-    MPM_FIELD_FMI = 4,    /* F - I, dim*dim (sand); stored form, exact */
-    MPM_FIELD_J = 5,      /* volume ratio J = rho0/rho, 1 comp (fluid) */
-    MPM_FIELD_JM1 = 6,    /* J - 1, 1 comp (fluid); stored form, exact */
+    MPM_FIELD_F = 3,      /* elastic deformation gradient, dim*dim (Hencky materials) */
+    MPM_FIELD_FMI = 4,    /* F - I, dim*dim (Hencky materials); stored form, exact */
+    MPM_FIELD_J = 5,      /* volume ratio J = rho0/rho, 1 comp (fluid, DP_JAUMANN) */
+    MPM_FIELD_JM1 = 6,    /* J - 1, 1 comp (fluid, DP_JAUMANN); stored form, exact */
     MPM_FIELD_STRESS = 7, /* V0 * Kirchhoff stress = V_p sigma_p, dim*dim */
     MPM_FIELD_PID = 8     /* original particle index, int32 */
 };
@@ -90,7 +123,7 @@ typedef struct mpm_config {
     int32_t n[3];          /* cells per axis; domain is [0, n[a]*dx] */
     int32_t ghost;         /* ghost node layers per side, >= 1 */
     int32_t tile;          /* tile edge in cells: 4 (3D) or 8 (2D); 0 = default */
-    int32_t material;      /* MPM_FLUID_TAIT, MPM_DP_HENCKY, MPM_HENCKY_ELASTIC */
+    int32_t material;      /* MPM_FLUID_TAIT, MPM_DP_HENCKY, MPM_HENCKY_ELASTIC, MPM_DP_JAUMANN */
     int32_t wall_mode[6];  /* faces x-, x+, y-, y+, z-, z+ */
     int32_t keep_grid;     /* 1: keep nodal mass for mpm_read_grid */
     double dx;             /* grid spacing */
@@ -98,6 +131,15 @@ typedef struct mpm_config {
     double wall_mu[6];     /* Coulomb coefficient per face */
     double rho0, bulk, gamma;         /* fluid: reference density, K, gamma */
     double youngs, poisson, phi_deg;  /* sand: E, nu, friction angle */
+    /* added physics; the zero defaults keep the APIC step without them */
+    int32_t transfer;      /* MPM_XFER_APIC (0), _PIC, _FLIP or _TPIC */
+    int32_t n_obstacles;   /* resting rigid boxes in obst_lo/hi, 0..MPM_MAX_OBSTACLES */
+    double flip_alpha;     /* FLIP share of the FLIP/PIC blend, in [0, 1] (FLIP only) */
+    double viscosity;      /* FLUID_TAIT: dynamic viscosity mu >= 0 (Pa s) */
+    double psi_deg;        /* DP_JAUMANN: dilation angle, 0 <= psi <= phi */
+    double cohesion;       /* DP_JAUMANN: c >= 0 */
+    double tension;        /* DP_JAUMANN: tensile strength sigma^t, <= k_phi / q_phi (the apex) */
+    double obst_lo[MPM_MAX_OBSTACLES][3], obst_hi[MPM_MAX_OBSTACLES][3];   /* lo < hi per used axis */
 } mpm_config;
 
 typedef struct mpm_ctx mpm_ctx;
@@ -202,7 +244,10 @@ int mpm_set_observations(mpm_ctx* ctx, const mpm_obs* obs);
  * the loss of the observations in binary64.  The last segment runs directly
  * on the tape, so that the first mpm_backward after it need not recompute
  * it.  Synchronizes; *host_loss gets the loss.  The state, sort and grid
- * afterwards are those after n_steps, as after mpm_step(n_steps). */
+ * afterwards are those after n_steps, as after mpm_step(n_steps).  The
+ * reverse sweep covers the APIC transfer without obstacles, for the
+ * inviscid fluid, the Hencky materials and DP_JAUMANN: other configurations
+ * (the other transfers, obstacles, a viscous fluid) return EINVAL. */
 int mpm_forward_loss(mpm_ctx* ctx, int32_t n_steps, double dt, double* host_loss);
 
 /* Gradient of the last mpm_forward_loss by the hand-written reverse sweep:
@@ -219,7 +264,8 @@ int mpm_backward(mpm_ctx* ctx, void* grad_v0, void* grad_mu);
 
 /* Learned parameter field alpha(x) ~ N_theta(x) (Sec. 3.2, eq:nn_apprx): a
  * small MLP on the matrix cores.  Layers l = 0..n_layers-1 map width[l] to
- * width[l+1]; hidden layers use tanh; the output layer applies out_act and
+ * width[l+1]; hidden layers use hidden_act (tanh by default, or ReLU as in
+ * the velocity-profile network of Sec. 5.2); the output layer applies out_act and
  * then y = out_shift + out_scale * act(z).  Inputs are first mapped
  * feature-wise to in_scale[k] * x_k + in_shift[k].  math selects the MFMA
  * operand type: BF16 operands with FP32 accumulation, or FP32 operands.
@@ -231,6 +277,7 @@ int mpm_backward(mpm_ctx* ctx, void* grad_v0, void* grad_mu);
 #define MPM_MLP_MAX_LAYERS 4
 #define MPM_MLP_MAX_IN 4
 enum { MPM_ACT_NONE = 0, MPM_ACT_SIGMOID = 1 };
+enum { MPM_HIDDEN_TANH = 0, MPM_HIDDEN_RELU = 1 };
 enum { MPM_MLP_BF16 = 0, MPM_MLP_F32 = 1 };
 typedef struct mpm_mlp {
     int32_t n_layers;                       /* 1..MPM_MLP_MAX_LAYERS */
@@ -239,6 +286,7 @@ typedef struct mpm_mlp {
     int32_t math;                           /* MPM_MLP_BF16 or MPM_MLP_F32 */
     float out_scale, out_shift;
     float in_scale[MPM_MLP_MAX_IN], in_shift[MPM_MLP_MAX_IN];
+    int32_t hidden_act;                     /* MPM_HIDDEN_TANH (0) or MPM_HIDDEN_RELU */
 } mpm_mlp;
 
 /* Number of parameters, or -1 for an invalid description. */

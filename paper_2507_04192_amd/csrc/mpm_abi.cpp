@@ -25,12 +25,25 @@ namespace {
 
 int nsym_of(int dim) { return dim * (dim + 1) / 2; }
 
+// Kernel material of a configuration: an inviscid fluid carries one
+// isotropic stress value, a viscous one the full symmetric stress.
+int kernel_mat(const mpm_config& c)
+{
+    switch (c.material) {
+    case MPM_FLUID_TAIT: return c.viscosity > 0.0 ? MAT_VFLUID : MAT_FLUID;
+    case MPM_DP_HENCKY: return MAT_SAND;
+    case MPM_HENCKY_ELASTIC: return MAT_ELASTIC;
+    default: return MAT_JAUMANN;
+    }
+}
+
 int nsc_of(const mpm_config& c)
 {
-    int D = c.dim;
-    if (c.material == MPM_FLUID_TAIT) return 2 * D + D * D + 1 + 1;
-    return 2 * D + D * D + D * D + nsym_of(D);
+    int D = c.dim, m = kernel_mat(c);
+    return 2 * D + D * D + (mat_has_F(m) ? D * D : 1) + (mat_iso_stress(m) ? 1 : nsym_of(D));
 }
+
+bool is_flip(const mpm_config& c) { return c.transfer == MPM_XFER_FLIP; }
 
 int check_config(const mpm_config* c, std::string& why)
 {
@@ -50,7 +63,21 @@ int check_config(const mpm_config* c, std::string& why)
     int want_tile = c->dim == 3 ? 4 : 8;
     if (c->tile != 0 && c->tile != want_tile) { why = "tile must be 4 in 3D and 8 in 2D (64 cells per tile)"; return MPM_EINVAL; }
     if (!(c->dx > 0.0) || !isfinite(c->dx)) { why = "dx must be positive"; return MPM_EINVAL; }
-    if (c->material < MPM_FLUID_TAIT || c->material > MPM_HENCKY_ELASTIC) { why = "unknown material"; return MPM_EINVAL; }
+    if (c->material < MPM_FLUID_TAIT || c->material > MPM_DP_JAUMANN) { why = "unknown material"; return MPM_EINVAL; }
+    if (c->transfer < MPM_XFER_APIC || c->transfer > MPM_XFER_TPIC) { why = "unknown transfer"; return MPM_EINVAL; }
+    if (c->transfer == MPM_XFER_FLIP && !(c->flip_alpha >= 0.0 && c->flip_alpha <= 1.0)) {
+        why = "flip_alpha must be in [0, 1]";
+        return MPM_EINVAL;
+    }
+    if (c->n_obstacles < 0 || c->n_obstacles > MPM_MAX_OBSTACLES) { why = "n_obstacles must be in [0, 4]"; return MPM_EINVAL; }
+    for (int o = 0; o < c->n_obstacles; ++o)
+        for (int a = 0; a < c->dim; ++a)
+            if (!isfinite(c->obst_lo[o][a]) || !isfinite(c->obst_hi[o][a]) || !(c->obst_lo[o][a] < c->obst_hi[o][a])) {
+                why = "obstacle boxes need finite lo < hi on every axis";
+                return MPM_EINVAL;
+            }
+    if (!(c->viscosity >= 0.0) || !isfinite(c->viscosity)) { why = "viscosity must be finite and >= 0"; return MPM_EINVAL; }
+    if (c->viscosity > 0.0 && c->material != MPM_FLUID_TAIT) { why = "viscosity applies to the fluid only"; return MPM_EINVAL; }
     for (int f = 0; f < 6; ++f) {
         if (c->wall_mode[f] < MPM_WALL_SLIP || c->wall_mode[f] > MPM_WALL_COULOMB) { why = "unknown wall mode"; return MPM_EINVAL; }
         if (!(c->wall_mu[f] >= 0.0)) { why = "wall friction must be >= 0"; return MPM_EINVAL; }
@@ -62,6 +89,15 @@ int check_config(const mpm_config* c, std::string& why)
     } else {
         if (!(c->youngs > 0.0) || !(c->poisson > -1.0 && c->poisson < 0.5)) { why = "need E > 0 and -1 < nu < 0.5"; return MPM_EINVAL; }
         if (!(c->phi_deg >= 0.0 && c->phi_deg < 90.0)) { why = "friction angle must be in [0, 90)"; return MPM_EINVAL; }
+    }
+    if (c->material == MPM_DP_JAUMANN) {
+        if (!(c->psi_deg >= 0.0 && c->psi_deg <= c->phi_deg)) { why = "dilation angle must be in [0, phi]"; return MPM_EINVAL; }
+        if (!(c->cohesion >= 0.0) || !isfinite(c->cohesion)) { why = "cohesion must be finite and >= 0"; return MPM_EINVAL; }
+        double sp = sin(c->phi_deg * M_PI / 180.0), cp = cos(c->phi_deg * M_PI / 180.0);
+        double q_phi = 6.0 * sp / (sqrt(3.0) * (3.0 + sp)), k_phi = 6.0 * c->cohesion * cp / (sqrt(3.0) * (3.0 + sp));
+        // the cutoff lies at or below the apex of the cone (sigma_m = k_phi / q_phi)
+        bool ok = isfinite(c->tension) && (q_phi > 0.0 ? c->tension * q_phi <= k_phi : true);
+        if (!ok) { why = "tension must be finite and at or below the apex k_phi / q_phi"; return MPM_EINVAL; }
     }
     return MPM_OK;
 }
@@ -97,7 +133,7 @@ Geo make_geo(const mpm_config& c)
 
 struct Layout {
     size_t st[2], pid[2], key, perm, tmp, tmpk, count, tile_off, tile_slot, active, part, meta, status;
-    size_t part_grid, gv, gmass;
+    size_t part_grid, gv, gmass, gvo;
     size_t inv, loss, box_sum, box_cnt, box_coef;
     size_t ckpt, ckpt_pid, tape, tape_pid, adj[2], mid, gtape, amu;
     GridRec grec;
@@ -132,9 +168,13 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
     L.meta = take(64 * 4);
     L.status = take(64 * 4);
     int nb = c.dim == 3 ? 216 : 100;   // node block of a tile
-    L.part_grid = take((size_t)g.ntiles * (c.dim + 1) * nb * elem);
+    // node values per block node: mass and momentum, and for FLIP the
+    // momentum without the internal force
+    int nv = is_flip(c) ? 2 * c.dim + 1 : c.dim + 1;
+    L.part_grid = take((size_t)g.ntiles * nv * nb * elem);
     L.gv = take((size_t)g.NN * c.dim * elem);
     L.gmass = take((size_t)g.NN * elem);
+    L.gvo = is_flip(c) ? take((size_t)g.NN * c.dim * elem) : 0;
     L.inv = take(ucap * 4);
     L.loss = take(4 * 8);
     L.box_sum = take(kMaxBoxes * 3 * 8);
@@ -229,6 +269,8 @@ int mpm_create(const mpm_config* cfg, void* hip_stream, mpm_ctx** out)
     c->elem = cfg->precision == MPM_F64 ? 8 : 4;
     c->nsc = nsc_of(c->cfg);
     c->nsym = nsym_of(cfg->dim);
+    c->mat = kernel_mat(c->cfg);
+    c->xfer = c->cfg.transfer;
     c->ops = pick_ops(c->cfg);
     *out = c;
     return MPM_OK;
@@ -288,6 +330,7 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     c->part_grid = b + L.part_grid;
     c->gv = b + L.gv;
     c->gmass = b + L.gmass;
+    c->gvo = is_flip(c->cfg) ? b + L.gvo : nullptr;
     c->inv = (int32_t*)(b + L.inv);
     c->loss = (double*)(b + L.loss);
     c->loss_scratch = c->loss + 2;
@@ -470,6 +513,9 @@ int mpm_forward_loss(mpm_ctx* c, int32_t n_steps, double dt, double* host_loss)
     if (n_steps < 1 || n_steps > c->tape_steps) return set_err(c, MPM_EINVAL, "n_steps must be in [1, tape_steps]");
     if (c->N < 1) return set_err(c, MPM_EINVAL, "a rollout needs at least one particle");
     if (!(dt >= 0.0) || !isfinite(dt)) return set_err(c, MPM_EINVAL, "dt must be finite and >= 0");
+    if (c->xfer != XF_APIC || c->cfg.n_obstacles > 0 || c->mat == MAT_VFLUID)
+        return set_err(c, MPM_EINVAL, "the reverse sweep covers the APIC transfer without obstacles, for the "
+                                      "inviscid fluid, the Hencky materials and the hypoelastic Drucker-Prager");
     c->has_tape = false;
     rc = c->ops->forward_loss(c, n_steps, dt, host_loss);
     if (rc) return rc;

@@ -26,9 +26,13 @@ constexpr int kAdjBlock = 128;   // threads of the reverse per-tile kernels
 // Per-slot intermediate of the reverse sweep (mid), component-major with
 // stride cap, written by k_g2p_adj and read by k_p2g_adj:
 //   [0, D)              position adjoint
-//   [D, D + D^2)        adjoint of the stored F_e - I (fluid: [D] holds J)
+//   [D, D + D^2)        adjoint of the stored F_e - I (fluid: [D] holds J;
+//                       hypoelastic Drucker-Prager: [D] J, then the
+//                       constitutive part of the packed stress adjoint in
+//                       [D + 1, D + 1 + D(D+1)/2), which fits the same slots)
 template <int D> struct MidLayout {
-    static constexpr int X = 0, G = D, N = D + D * D;
+    static constexpr int X = 0, G = D, S = D + 1, N = D + D * D;
+    static_assert(D + 1 + D * (D + 1) / 2 <= D + D * D, "stress adjoint fits the intermediate");
 };
 
 // Reverse of the constitutive update, the kinematics x' = x + dt v and G2P,
@@ -124,6 +128,17 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
                     T Jb_in;
                     fluid_vjp<T, D>(P, Lm, st.G[j], aout.G[s], aout.S[s], Lb, Jb_in);
                     mid[ML::G * cap + s] = Jb_in;
+                } else if constexpr (MAT == MAT_JAUMANN) {
+                    T Sv[NS], sb[NS], sb_in[NS], Jb_in;
+    #pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        Sv[q] = st.S[q * cap + j];
+                        sb[q] = aout.S[q * cap + s];
+                    }
+                    jaumann_vjp<T, D>(P, Lm, st.G[j], Sv, aout.G[s], sb, Lb, Jb_in, sb_in);
+                    mid[ML::G * cap + s] = Jb_in;
+    #pragma unroll
+                    for (int q = 0; q < NS; ++q) mid[(ML::S + q) * cap + s] = sb_in[q];
                 } else {
                     T G[D][D], Gb[D][D], Gb_in[D][D], sb[NS];
     #pragma unroll
@@ -579,6 +594,22 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
                 for (int a = 0; a < D; ++a) tr += Sbar[a][a];
                 ain.S[j] = tr;
+            } else if constexpr (MAT == MAT_JAUMANN) {
+                // the force's part of the stress adjoint plus the constitutive part
+                constexpr int S0 = MidLayout<D>::S;
+                ain.G[j] = mid[D * cap + s];
+                if constexpr (D == 3) {
+                    ain.S[0 * cap + j] = Sbar[0][0] + mid[(S0 + 0) * cap + s];
+                    ain.S[1 * cap + j] = Sbar[1][1] + mid[(S0 + 1) * cap + s];
+                    ain.S[2 * cap + j] = Sbar[2][2] + mid[(S0 + 2) * cap + s];
+                    ain.S[3 * cap + j] = Sbar[0][1] + Sbar[1][0] + mid[(S0 + 3) * cap + s];
+                    ain.S[4 * cap + j] = Sbar[0][2] + Sbar[2][0] + mid[(S0 + 4) * cap + s];
+                    ain.S[5 * cap + j] = Sbar[1][2] + Sbar[2][1] + mid[(S0 + 5) * cap + s];
+                } else {
+                    ain.S[0 * cap + j] = Sbar[0][0] + mid[(S0 + 0) * cap + s];
+                    ain.S[1 * cap + j] = Sbar[1][1] + mid[(S0 + 1) * cap + s];
+                    ain.S[2 * cap + j] = Sbar[0][1] + Sbar[1][0] + mid[(S0 + 2) * cap + s];
+                }
             } else {
 #pragma unroll
                 for (int a = 0; a < D; ++a)
@@ -769,7 +800,7 @@ struct Adjoint {
         v.v = b + D * cap;
         v.C = b + 2 * D * cap;
         v.G = b + (2 * D + D * D) * cap;
-        v.S = v.G + (c->cfg.material == MAT_FLUID ? 1 : D * D) * cap;
+        v.S = v.G + (mat_has_F(c->mat) ? D * D : 1) * cap;
         v.pid = pid;
         return v;
     }
@@ -1020,16 +1051,18 @@ struct Adjoint {
 
     static int forward_loss(mpm_ctx* c, int n, double dt, double* loss)
     {
-        switch (c->cfg.material) {
+        switch (c->mat) {
         case MAT_FLUID: return forward_loss_mat<MAT_FLUID>(c, n, dt, loss);
+        case MAT_JAUMANN: return forward_loss_mat<MAT_JAUMANN>(c, n, dt, loss);
         case MAT_SAND: return forward_loss_mat<MAT_SAND>(c, n, dt, loss);
         default: return forward_loss_mat<MAT_ELASTIC>(c, n, dt, loss);
         }
     }
     static int backward(mpm_ctx* c, void* gv0, void* gmu)
     {
-        switch (c->cfg.material) {
+        switch (c->mat) {
         case MAT_FLUID: return backward_mat<MAT_FLUID>(c, gv0, gmu);
+        case MAT_JAUMANN: return backward_mat<MAT_JAUMANN>(c, gv0, gmu);
         case MAT_SAND: return backward_mat<MAT_SAND>(c, gv0, gmu);
         default: return backward_mat<MAT_ELASTIC>(c, gv0, gmu);
         }

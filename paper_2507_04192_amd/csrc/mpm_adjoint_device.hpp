@@ -593,6 +593,206 @@ __device__ __forceinline__ void hencky_vjp(const Phys<T>& P, bool plastic, const
         hencky_vjp_eig<T, D>(P, plastic, L, G, Gb_out, sb_out, Lb, Gb_in);
 }
 
+// Reverse of jaumann_update (hypoelastic Drucker-Prager, App. A) with the
+// zone held fixed.  Inputs: the step's velocity gradient L, the stored
+// J - 1 and stress cache S (packed symmetric, V0 J sigma), and the adjoints
+// Jb_out, Sb_out of the outputs J' - 1 and S'.  Outputs: Lb, and the
+// adjoints Jb_in, Sb_in of the inputs.  Written on full matrices: a packed
+// off-diagonal value stands for two entries, so its adjoint is the sum of
+// theirs.
+template <class T, int D>
+__device__ __forceinline__ void jaumann_vjp(const Phys<T>& P, const T L[D][D], T dJ, const T S[D * (D + 1) / 2],
+                                            T Jb_out, const T Sb_out[D * (D + 1) / 2], T Lb[D][D], T& Jb_in,
+                                            T Sb_in[D * (D + 1) / 2])
+{
+    constexpr int NS = D * (D + 1) / 2;
+    const T dt = P.dt;
+    // ---- forward, keeping what the reverse needs
+    T M[D][D], cof[D][D], detM;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) M[i][j] = ((i == j) ? T(1) : T(0)) + dt * L[i][j];
+    if constexpr (D == 3) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                cof[i][j] = M[i1][j1] * M[i2][j2] - M[i1][j2] * M[i2][j1];
+            }
+        detM = M[0][0] * cof[0][0] + M[0][1] * cof[0][1] + M[0][2] * cof[0][2];
+    } else {
+        cof[0][0] = M[1][1]; cof[0][1] = -M[1][0];
+        cof[1][0] = -M[0][1]; cof[1][1] = M[0][0];
+        detM = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    }
+    const T Jo = T(1) + dJ;
+    const T Jn = Jo * detM;
+    const T to_cauchy = T(1) / (P.vol0 * Jo);
+    T sg[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            sg[i][j] = S[q] * to_cauchy;
+            sg[j][i] = sg[i][j];
+        }
+    T Dd[D][D], Dw[D][D], trD = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            Dd[i][j] = T(0.5) * dt * (L[i][j] + L[j][i]);
+            Dw[i][j] = T(0.5) * dt * (L[i][j] - L[j][i]);
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) trD += Dd[i][i];
+    T sv[D][D], sm = T(0), nrm2 = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            T r = sg[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) r += sg[i][k] * Dw[j][k] + sg[j][k] * Dw[i][k];
+            r += T(2) * P.mu * Dd[i][j] + ((i == j) ? P.lam * trD : T(0));
+            sv[i][j] = r;
+            nrm2 += r * r;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) sm += sv[i][i];
+    sm /= T(D);
+    T ss2 = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        sv[i][i] -= sm;
+#pragma unroll
+        for (int j = 0; j < D; ++j) ss2 += sv[i][j] * sv[i][j];
+    }
+    const T tau = sqrt(T(0.5) * ss2);
+    const T fs = tau - P.jk_phi + P.jq_phi * sm;
+    const T ft = sm - P.jst;
+    const T hh = tau - P.jtauP - P.jalphaP * (sm - P.jst);
+    int zone;
+    if (nrm2 <= P.jband2) zone = 1;
+    else if (ft < T(0)) zone = fs <= T(0) ? 1 : 2;
+    else zone = hh > T(0) ? 2 : 3;
+    const T den = P.mu + P.jK * P.jq_phi * P.jq_psi;
+    T sm_n = sm, scale = T(1), tau_n = T(0);
+    bool corner = false;
+    if (zone == 2) {
+        sm_n = sm - P.jK * P.jq_psi * fs / den;
+        tau_n = P.jk_phi - P.jq_phi * sm_n;
+        if (sm_n > P.jst) {
+            corner = true;
+            sm_n = P.jst;
+            tau_n = P.jtauP;
+        }
+        scale = tau > T(0) ? tau_n / tau : T(0);
+    } else if (zone == 3) {
+        sm_n = P.jst;
+    }
+    // ---- reverse
+    // S'_q = V0 J' sigma'_q, J' = Jn
+    T Jnb = Jb_out;
+    T SgB[D][D];   // full-matrix adjoint of sigma'
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            const T so = scale * sv[i][j] + ((i == j) ? sm_n : T(0));
+            Jnb += P.vol0 * Sb_out[q] * so;
+            const T b = P.vol0 * Jn * Sb_out[q] * ((i == j) ? T(1) : T(0.5));
+            SgB[i][j] = b;
+            SgB[j][i] = b;
+        }
+    // sigma' = scale s + sm_n I
+    T sB[D][D], scaleB = T(0), smnB = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        smnB += SgB[i][i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            sB[i][j] = scale * SgB[i][j];
+            scaleB += SgB[i][j] * sv[i][j];
+        }
+    }
+    T smB = T(0), tauB = T(0);
+    if (zone == 1) {
+        smB += smnB;
+    } else if (zone == 2) {
+        // scale = tau_n / tau (0 and constant at tau = 0)
+        const T taunB = tau > T(0) ? scaleB / tau : T(0);
+        if (tau > T(0)) tauB += -scaleB * tau_n / (tau * tau);
+        if (!corner) {
+            const T smnB2 = smnB - P.jq_phi * taunB;   // tau_n = k_phi - q_phi sm_n
+            smB += smnB2;
+            const T fsB = -P.jK * P.jq_psi / den * smnB2;
+            tauB += fsB;
+            smB += P.jq_phi * fsB;
+        }
+    }
+    // tau = sqrt(s:s / 2), s = T - sm I, sm = tr(T)/D
+    if (tau > T(0)) {
+        const T c = tauB / (T(2) * tau);
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int j = 0; j < D; ++j) sB[i][j] += c * sv[i][j];
+    }
+    T trsB = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) trsB += sB[i][i];
+    T TB[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) TB[i][j] = sB[i][j] + ((i == j) ? (smB - trsB) / T(D) : T(0));
+    // T = sigma + sigma Dw^T + Dw sigma^T + 2 G Dd + lam tr(Dd) I
+    T sgB[D][D], DwB[D][D], trTB = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) trTB += TB[i][i];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            T r = TB[a][b], w = T(0);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                r += TB[a][k] * Dw[k][b] + TB[k][a] * Dw[k][b];
+                w += TB[k][a] * sg[k][b] + TB[a][k] * sg[k][b];
+            }
+            sgB[a][b] = r;
+            DwB[a][b] = w;
+        }
+    // Dd = dt sym(L), Dw = dt skew(L); J' = J det(M) with M = I + dt L
+    const T detB = Jnb * Jo;
+    T JoB = Jnb * detM;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            const T DdB_ab = T(2) * P.mu * TB[a][b] + ((a == b) ? P.lam * trTB : T(0));
+            const T DdB_ba = T(2) * P.mu * TB[b][a] + ((a == b) ? P.lam * trTB : T(0));
+            Lb[a][b] = T(0.5) * dt * (DdB_ab + DdB_ba) + T(0.5) * dt * (DwB[a][b] - DwB[b][a]) + detB * dt * cof[a][b];
+        }
+    // sigma = S / (V0 J)
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            const T bq = (i == j) ? sgB[i][i] : sgB[i][j] + sgB[j][i];
+            Sb_in[q] = bq * to_cauchy;
+            JoB -= bq * sg[i][j] / Jo;
+        }
+    Jb_in = JoB;
+    (void)NS;
+}
+
 // Reverse of fluid_update: Jb_out and sb_out are the adjoints of J' - 1 and
 // of the isotropic stress value; dJ is the stored J - 1 of the step.
 template <class T, int D>

@@ -261,6 +261,120 @@ __device__ __forceinline__ void fluid_update(const Phys<T>& P, const T L[D][D], 
     s_iso = -P.vol0 * J * p;
 }
 
+// Viscous fluid (Sec. 2.3 eq:stress_strain with the rate d = (L + L^T)/2 in
+// place of the printed increment): the Tait pressure of fluid_update plus
+// 2 mu (d - tr(d)/D I), both at the updated J; S = V0 J' sigma, stored
+// symmetric.
+template <class T, int D>
+__device__ __forceinline__ void vfluid_update(const Phys<T>& P, const T L[D][D], T& dJ, T S[D * (D + 1) / 2])
+{
+    T s_iso;
+    fluid_update<T, D>(P, L, dJ, s_iso);
+    T trd = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) trd += L[a][a];
+    const T c = T(2) * P.visc * P.vol0 * (T(1) + dJ);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            T r = T(0.5) * (L[i][j] + L[j][i]);
+            if (i == j) r -= trd / T(D);
+            S[q] = c * r + ((i == j) ? s_iso : T(0));
+        }
+}
+
+// Hypoelastic Drucker-Prager with the Jaumann rate and a tension cutoff
+// (Sec. 2.3 eq:dp_stress; App. A).  The carried stress is S = V0 J sigma;
+// the step's Cauchy stress is S / (V0 J) with J before its update
+// J' = J det(I + dt L), and the new S is V0 J' sigma'.
+//   trial = sigma + sigma Dw^T + Dw sigma^T + lam tr(Dd) I + 2 G Dd,
+//     Dd = dt (L + L^T)/2, Dw = dt (L - L^T)/2
+//   sigma_m = tr/D, s = trial - sigma_m I, tau = sqrt(s:s / 2)
+//   f^s = tau - k_phi + q_phi sigma_m, f^t = sigma_m - sigma^t,
+//   h = tau - tau^P - alpha^P (sigma_m - sigma^t)
+//   zone I  (f^t < 0, f^s <= 0; or a trial of norm at the elastic band)
+//   zone II (f^t < 0, f^s > 0; or f^t >= 0, h > 0): dl = f^s / (G + K q_phi q_psi),
+//           sigma_m' = sigma_m - K q_psi dl, tau' = k_phi - q_phi sigma_m', s
+//           scaled to tau'; a return beyond the cutoff ends at (sigma^t, tau^P)
+//   zone III (f^t >= 0, h <= 0): sigma_m' = sigma^t, s kept
+template <class T, int D>
+__device__ __forceinline__ void jaumann_update(const Phys<T>& P, const T L[D][D], T& dJ, T S[D * (D + 1) / 2])
+{
+    constexpr int NS = D * (D + 1) / 2;
+    const T Jo = T(1) + dJ;
+    T s_unused;
+    fluid_update<T, D>(P, L, dJ, s_unused);   // J' = J det(I + dt L) (its pressure is not used)
+    const T Jn = T(1) + dJ;
+    const T to_cauchy = T(1) / (P.vol0 * Jo);
+    T sg[D][D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            sg[i][j] = S[q] * to_cauchy;
+            sg[j][i] = sg[i][j];
+        }
+    T Dd[D][D], Dw[D][D], trD = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            Dd[i][j] = T(0.5) * P.dt * (L[i][j] + L[j][i]);
+            Dw[i][j] = T(0.5) * P.dt * (L[i][j] - L[j][i]);
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) trD += Dd[i][i];
+    T tr[NS], sm = T(0), nrm2 = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            T r = sg[i][j];
+#pragma unroll
+            for (int k = 0; k < D; ++k) r += sg[i][k] * Dw[j][k] + sg[j][k] * Dw[i][k];
+            r += T(2) * P.mu * Dd[i][j] + ((i == j) ? P.lam * trD : T(0));
+            tr[q] = r;
+            nrm2 += (i == j ? T(1) : T(2)) * r * r;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) sm += tr[i];
+    sm /= T(D);
+    T ss2 = T(0);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (q < D) tr[q] -= sm;   // deviator in place
+        ss2 += (q < D ? T(1) : T(2)) * tr[q] * tr[q];
+    }
+    const T tau = sqrt(T(0.5) * ss2);
+    const T fs = tau - P.jk_phi + P.jq_phi * sm;
+    const T ft = sm - P.jst;
+    const T hh = tau - P.jtauP - P.jalphaP * (sm - P.jst);
+    int zone;
+    if (nrm2 <= P.jband2) zone = 1;
+    else if (ft < T(0)) zone = fs <= T(0) ? 1 : 2;
+    else zone = hh > T(0) ? 2 : 3;
+    T sm_n = sm, scale = T(1);
+    if (zone == 2) {
+        const T dl = fs / (P.mu + P.jK * P.jq_phi * P.jq_psi);
+        sm_n = sm - P.jK * P.jq_psi * dl;
+        T tau_n = P.jk_phi - P.jq_phi * sm_n;
+        if (sm_n > P.jst) {
+            sm_n = P.jst;
+            tau_n = P.jtauP;
+        }
+        scale = tau > T(0) ? tau_n / tau : T(0);
+    } else if (zone == 3) {
+        sm_n = P.jst;
+    }
+    const T back = P.vol0 * Jn;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) S[q] = back * (scale * tr[q] + ((q < D) ? sm_n : T(0)));
+}
+
 // Sand / elastic: F_tr = (I + dt L) F_e with F_e = I + G, so
 // G_tr = G + dt (L + L G).  Hencky strain from b - I = G_tr + G_tr^T +
 // G_tr G_tr^T: eps_i = log1p(eig_i)/2.  Return onto the Drucker-Prager cone:
@@ -611,6 +725,39 @@ __device__ __forceinline__ void wall_node(int mode, T mu, int axis, T sign, T v[
         T sc = T(1) - mu * vn / vt;
 #pragma unroll
         for (int a = 0; a < D; ++a) v[a] *= sc;
+    }
+}
+
+// Resting rigid boxes (Sec. 4.2.1, frictionless contact): a node with mass
+// inside the closed box loses the velocity component that points into the
+// box through its nearest face (faces on the domain boundary excluded; ties
+// to the first face in the order x-, x+, y-, y+, z-, z+).  xi: the node's
+// position.
+template <class T, int D>
+__device__ __forceinline__ void obstacle_node(const Phys<T>& P, const T xi[D], T v[D])
+{
+    for (int o = 0; o < P.n_obst; ++o) {
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) inside &= xi[a] >= P.obst_lo[o][a] && xi[a] <= P.obst_hi[o][a];
+        if (!inside) continue;
+        int best = -1;
+        T bd = T(0);
+#pragma unroll
+        for (int f = 0; f < 2 * D; ++f) {
+            if (!((P.obst_face_ok[o] >> f) & 1)) continue;
+            const int a = f >> 1;
+            const T depth = (f & 1) ? P.obst_hi[o][a] - xi[a] : xi[a] - P.obst_lo[o][a];
+            if (best < 0 || depth < bd) {
+                best = f;
+                bd = depth;
+            }
+        }
+        if (best < 0) continue;
+        const int a = best >> 1;
+        // the normal points into the obstacle: +e_a through its lower face
+        const T vn = (best & 1) ? -v[a] : v[a];
+        if (vn > T(0)) v[a] = T(0);
     }
 }
 

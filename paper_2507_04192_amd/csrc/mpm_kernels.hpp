@@ -37,8 +37,10 @@ constexpr int kSortCap = 1024;   // particles per tile sorted in LDS (larger: in
 // threads of a P2G workgroup, one tile each: binary64 one wave; binary32 two
 // waves that share the tile's particles and split the node values between
 // them (mass and momentum x | the other momentum components)
-template <class T> constexpr int kP2GBlock = sizeof(T) == 4 ? 128 : 64;
-template <class T> constexpr int kP2GWGs = kTileWGs * kBlock / kP2GBlock<T>;
+// With FLIP the node values double (momentum with and without the internal
+// force): binary32 then uses four waves per tile.
+template <class T, bool FL = false> constexpr int kP2GBlock = sizeof(T) == 4 ? (FL ? 256 : 128) : 64;
+template <class T, bool FL = false> constexpr int kP2GWGs = kTileWGs * kBlock / kP2GBlock<T, FL>;
 // threads of a G2P workgroup (binary64: smaller groups, measured faster)
 template <class T> constexpr int kG2PBlock = sizeof(T) == 8 ? 128 : 256;
 // G2P loads the next tile's node block while it works on the current one
@@ -248,7 +250,7 @@ __device__ __forceinline__ void wave_sync()
 // stress cache.
 template <class T, int D, int MAT, int A0 = 0, int A1 = D>
 struct P2GIn {
-    static constexpr int NS = (MAT == MAT_FLUID) ? 1 : D * (D + 1) / 2;
+    static constexpr int NS = mat_iso_stress(MAT) ? 1 : D * (D + 1) / 2;
     static constexpr int NA = A1 - A0;
     T x[D], v[NA], C[NA * D], S[NS];
     __device__ __forceinline__ void load(const PView<T>& cur, int j)
@@ -282,11 +284,13 @@ __host__ __device__ constexpr int sym_index(int a, int b)
 //   P_a   w_x U_a + (w_x dd_x) V_a + dw_x W_a,
 //   U_a = wyz (m v_a + sum_{b>0} mC_ab dd_b) + sum_{b>0} fs_ab (grad phi_b / w_x),
 //   V_a = wyz mC_a0,  W_a = wyz fs_a0.
-// For each of the 3^D stencil nodes, sink(k, n, fx, mw, U, V, W) receives
-// the offset index k, the node's index n in the tile's LDS block, the x
-// factors fx = (w_x, w_x dd_x, dw_x) and the line terms of the momentum
-// components [A0, A1); p2g_node_values forms the D+1 values from them when
-// the range is all of them.
+// For each of the 3^D stencil nodes, sink(k, n, fx, mw, U, V, W, Uq)
+// receives the offset index k, the node's index n in the tile's LDS block,
+// the x factors fx = (w_x, w_x dd_x, dw_x) and the line terms of the
+// momentum components [A0, A1); Uq = wyz (m v_a + ...) is U without the
+// force, so the momentum without the internal force is w_x Uq + (w_x dd_x) V
+// (FLIP's v_i^n); p2g_node_values forms the D+1 values from them when the
+// range is all of them.
 template <class T, int D, int MAT, int A0, int A1, class Sink>
 __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D, MAT, A0, A1>& in, const int lb[3],
                                              const int gb[3], Sink&& sink)
@@ -310,7 +314,7 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
 #pragma unroll
         for (int b = 0; b < D; ++b) {
             mC[a][b] = P.mass * in.C[a * D + b];
-            if constexpr (MAT == MAT_FLUID) fs[a][b] = (A0 + a == b) ? -P.dt * in.S[0] : T(0);
+            if constexpr (mat_iso_stress(MAT)) fs[a][b] = (A0 + a == b) ? -P.dt * in.S[0] : T(0);
             else fs[a][b] = -P.dt * in.S[sym_index<D>(A0 + a, b)];
         }
     }
@@ -332,11 +336,12 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
             T wyz = (D == 3) ? w[1][ky] * w[2][kz] : w[1][ky];
             T g1 = (D == 3) ? dw[1][ky] * w[2][kz] : dw[1][ky];
             T g2 = (D == 3) ? w[1][ky] * dw[2][kz] : T(0);
-            T U[NA], V[NA], Wf[NA];
+            T U[NA], V[NA], Wf[NA], Uq[NA];
 #pragma unroll
             for (int a = 0; a < NA; ++a) {
                 T aff = mvz[a] + mC[a][1] * dd[1][ky];
-                T u = wyz * aff + fs[a][1] * g1;
+                Uq[a] = wyz * aff;
+                T u = Uq[a] + fs[a][1] * g1;
                 if constexpr (D == 3) u += fs[a][2] * g2;
                 U[a] = u;
                 V[a] = wyz * mC[a][0];
@@ -348,7 +353,7 @@ __device__ __forceinline__ void p2g_particle(const Phys<T>& P, const P2GIn<T, D,
                 int n;
                 if constexpr (D == 3) n = ((lb[2] + kz) * BE + lb[1] + ky) * BE + lb[0] + kx;
                 else n = (lb[1] + ky) * BE + lb[0] + kx;
-                sink((kz * 3 + ky) * 3 + kx, n, fx[kx], mw, U, V, Wf);
+                sink((kz * 3 + ky) * 3 + kx, n, fx[kx], mw, U, V, Wf, Uq);
             }
         }
     }
@@ -399,21 +404,24 @@ __device__ __forceinline__ int rank_major_pos(int c, int q, const unsigned long 
 }
 
 // Binary32 P2G of one lane (cell) for the momentum components [A0, A1)
-// (and the mass when A0 = 0): the lane sums the particles of its cell in
+// (and the mass when MASS): the lane sums the particles of its cell in
 // registers (they all hit the same 3^D nodes), the next particle's state
 // loaded while this one is spread, then adds its sums to node arrays
-// [Q0, Q0 + NQ) of the tile's LDS block.  The lanes of a wave write distinct
-// nodes per offset and wave_sync orders the offsets.
-template <class T, int D, int MAT, int A0, int A1>
+// [Q0, Q0 + NQ) of the tile's LDS block.  With QV the sums are those of the
+// momentum without the internal force (node arrays 1 + D + a, for FLIP).
+// The lanes of a wave write distinct nodes per offset and wave_sync orders
+// the offsets.
+template <class T, int D, int MAT, int A0, int A1, bool MASS, bool QV>
 __device__ __forceinline__ void p2g_lane_sums(const Phys<T>& P, const PView<T>& cur, const int* sorted, int lane,
                                               int mycnt, const int lb[3], const int gb[3],
                                               const unsigned long long* s_rmask, const int* s_roff,
                                               const int* s_cnt, T (*node)[TileShape<D>::NB])
 {
+    static_assert(!(MASS && QV), "the mass travels with the momentum including the force");
     constexpr int NK = (D == 3) ? 27 : 9;
-    constexpr int M = A0 == 0 ? 1 : 0;          // this wave carries the mass
+    constexpr int M = MASS ? 1 : 0;
     constexpr int NQ = M + A1 - A0;             // node values of this wave
-    constexpr int Q0 = M ? 0 : 1 + A0;          // its first node array
+    constexpr int Q0 = M ? 0 : (QV ? 1 + D + A0 : 1 + A0);   // its first node array
     T acc[NK][NQ];
 #pragma unroll
     for (int k = 0; k < NK; ++k)
@@ -426,11 +434,14 @@ __device__ __forceinline__ void p2g_lane_sums(const Phys<T>& P, const PView<T>& 
         if (r + 1 < mycnt) nx.load(cur, sorted[rank_major_pos(lane, r + 1, s_rmask, s_roff, s_cnt)]);
         // the products go straight into the sums (one FMA each)
         p2g_particle<T, D, MAT, A0, A1>(P, in, lb, gb,
-                                        [&](int k, int, const T* fx, T mw, const T* U, const T* V, const T* W) {
-            if constexpr (M) acc[k][0] = fma(fx[0], mw, acc[k][0]);
+                                        [&](int k, int, const T* fx, T mw, const T* U, const T* V, const T* W,
+                                            const T* Uq) {
+            if constexpr (MASS) acc[k][0] = fma(fx[0], mw, acc[k][0]);
 #pragma unroll
-            for (int a = 0; a < A1 - A0; ++a)
-                acc[k][M + a] = fma(fx[2], W[a], fma(fx[1], V[a], fma(fx[0], U[a], acc[k][M + a])));
+            for (int a = 0; a < A1 - A0; ++a) {
+                if constexpr (QV) acc[k][M + a] = fma(fx[1], V[a], fma(fx[0], Uq[a], acc[k][M + a]));
+                else acc[k][M + a] = fma(fx[2], W[a], fma(fx[1], V[a], fma(fx[0], U[a], acc[k][M + a])));
+            }
         });
     }
     if (mycnt > 0) {
@@ -456,18 +467,20 @@ __device__ __forceinline__ void p2g_lane_sums(const Phys<T>& P, const PView<T>& 
 // takes them in rounds, lane c holding the r-th particle of cell c for
 // r = 0, 1, ... (the lanes of a round read adjacent slots), binary32 with
 // two waves that split the node values; (3) writes the tile's node block
-// (mass, momentum) to its partial block.  Register budget: three waves per
-// SIMD in binary32 (168 registers), two in binary64.
-template <class T, int D, int MAT>
-__global__ __launch_bounds__(kP2GBlock<T>) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
+// (mass, momentum; with FLIP also the momentum without the internal force)
+// to its partial block.  Register budget: three waves per SIMD in binary32
+// (168 registers), two in binary64.
+template <class T, int D, int MAT, bool FL>
+__global__ __launch_bounds__((kP2GBlock<T, FL>)) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) void k_p2g(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, int* __restrict__ tmp,
                                                 const int* __restrict__ tmpk, PView<T> cur, int* __restrict__ perm,
                                                 T* __restrict__ part)
 {
     constexpr int TE = TileShape<D>::TE, NB = TileShape<D>::NB;
-    constexpr int NT = kP2GBlock<T>;
+    constexpr int NT = kP2GBlock<T, FL>;
+    constexpr int NV = FL ? 2 * D + 1 : D + 1;          // node values per block node
     constexpr bool kRegAcc = sizeof(T) == 4;            // binary32: sums in registers
-    __shared__ T s_node[D + 1][NB];
+    __shared__ T s_node[NV][NB];
     __shared__ int s_cnt[64], s_off[64], s_cur[64];
     __shared__ int s_unord[kSortCap], s_sorted[kSortCap];
     __shared__ unsigned char s_ucell[kSortCap];
@@ -480,7 +493,7 @@ __global__ __launch_bounds__(kP2GBlock<T>) __attribute__((amdgpu_waves_per_eu(si
         int e = tile_entry(it, n_active);
         if (e < 0) break;
         const ActiveTile at = active[e];
-        for (int i = tid; i < (D + 1) * NB; i += NT) (&s_node[0][0])[i] = T(0);
+        for (int i = tid; i < NV * NB; i += NT) (&s_node[0][0])[i] = T(0);
         if (tid < 64) { s_cnt[tid] = 0; s_cur[tid] = 0; }
         __syncthreads();
         const bool in_lds = at.cnt <= kSortCap;
@@ -612,11 +625,19 @@ __global__ __launch_bounds__(kP2GBlock<T>) __attribute__((amdgpu_waves_per_eu(si
             // sums to the tile's LDS block; the waves write different node
             // arrays, the lanes of a wave distinct nodes per offset, and
             // wave_sync orders the offsets
+            // (with FLIP, waves 2 and 3 the same for the momentum without the
+            // internal force)
             T (*node)[NB] = s_node;
             if (w == 0)
-                p2g_lane_sums<T, D, MAT, 0, 1>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
-            else
-                p2g_lane_sums<T, D, MAT, 1, D>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
+                p2g_lane_sums<T, D, MAT, 0, 1, true, false>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
+            else if (w == 1)
+                p2g_lane_sums<T, D, MAT, 1, D, false, false>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
+            else if constexpr (FL) {
+                if (w == 2)
+                    p2g_lane_sums<T, D, MAT, 0, 1, false, true>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
+                else
+                    p2g_lane_sums<T, D, MAT, 1, D, false, true>(P, cur, sorted, cl, mycnt, lb, gb, s_rmask, s_roff, s_cnt, node);
+            }
         } else {
             // binary64 (one wave): hardware LDS atomics (ds_add_f64) into the
             // tile's block, issued without waiting; lanes hit distinct nodes
@@ -626,18 +647,22 @@ __global__ __launch_bounds__(kP2GBlock<T>) __attribute__((amdgpu_waves_per_eu(si
                     P2GIn<T, D, MAT> in;
                     in.load(cur, sorted[rank_major_pos(cl, r, s_rmask, s_roff, s_cnt)]);
                     p2g_particle<T, D, MAT>(P, in, lb, gb,
-                                            [&](int, int n, const T* fx, T mw, const T* U, const T* V, const T* W) {
+                                            [&](int, int n, const T* fx, T mw, const T* U, const T* V, const T* W,
+                                                const T* Uq) {
                         T add[D + 1];
                         p2g_node_values<T, D>(fx, mw, U, V, W, add);
 #pragma unroll
                         for (int q = 0; q <= D; ++q) atomicAdd(&s_node[q][n], add[q]);
+                        if constexpr (FL)
+#pragma unroll
+                            for (int a = 0; a < D; ++a) atomicAdd(&s_node[1 + D + a][n], fma(fx[1], V[a], fx[0] * Uq[a]));
                     });
                 }
             }
         }
         __syncthreads();
-        T* dst = part + (long long)e * (D + 1) * NB;
-        for (int i = tid; i < (D + 1) * NB; i += NT) dst[i] = (&s_node[0][0])[i];
+        T* dst = part + (long long)e * NV * NB;
+        for (int i = tid; i < NV * NB; i += NT) dst[i] = (&s_node[0][0])[i];
         __syncthreads();
     }
 }
@@ -685,13 +710,19 @@ __device__ __forceinline__ int node_blocks(const Geo& g, const int I[3], const i
     return des;
 }
 
-template <class T, int D>
+// With FL (FLIP) the partial blocks also hold the momentum without the
+// internal force, and gvo receives the velocity before the update,
+// v_i^n = that / m_i (0 where m_i = 0).  Resting obstacles (Sec. 4.2.1) act
+// after the walls.
+template <class T, int D, bool FL>
 __global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                  const ActiveTile* __restrict__ active,
                                                  const int* __restrict__ tile_slot, const T* __restrict__ part,
-                                                 T* __restrict__ gv, T* __restrict__ gmass, T* __restrict__ gvt)
+                                                 T* __restrict__ gv, T* __restrict__ gmass, T* __restrict__ gvt,
+                                                 T* __restrict__ gvo)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
+    constexpr int NV = FL ? 2 * D + 1 : D + 1;
     const int n_active = meta[0];
     for (int it = 0;; ++it) {
         int e = tile_entry(it, n_active);
@@ -712,17 +743,23 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int
             constexpr int NC = 1 << D;
             int slot[NC], li[NC];
             const int des = node_blocks<D>(g, I, own, down, tile_slot, slot, li);
-            T m = T(0), p[D];
+            T m = T(0), p[D], pq[FL ? D : 1];
 #pragma unroll
             for (int a = 0; a < D; ++a) p[a] = T(0);
+            if constexpr (FL)
+#pragma unroll
+                for (int a = 0; a < D; ++a) pq[a] = T(0);
             if (des == tile) {
 #pragma unroll
                 for (int msk = 0; msk < NC; ++msk) {
                     if (slot[msk] < 0) continue;
-                    const T* src = part + (long long)slot[msk] * (D + 1) * NB;
+                    const T* src = part + (long long)slot[msk] * NV * NB;
                     m += src[li[msk]];
 #pragma unroll
                     for (int a = 0; a < D; ++a) p[a] += src[(1 + a) * NB + li[msk]];
+                    if constexpr (FL)
+#pragma unroll
+                        for (int a = 0; a < D; ++a) pq[a] += src[(1 + D + a) * NB + li[msk]];
                 }
             }
             if (des != tile) continue;
@@ -750,12 +787,21 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int
                     }
                     if (ip >= g.n[a]) wall_node<T, D>(P.wall_mode[2 * a + 1], P.wall_mu[2 * a + 1], a, T(1), v);
                 }
+                if (P.n_obst > 0) {
+                    T xi[D];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) xi[a] = T(I[a] - g.G) * P.h;
+                    obstacle_node<T, D>(P, xi, v);
+                }
             } else if (gvt) {
 #pragma unroll
                 for (int a = 0; a < D; ++a) gvt[a * g.NN + node] = T(0);
             }
 #pragma unroll
             for (int a = 0; a < D; ++a) gv[a * g.NN + node] = v[a];
+            if constexpr (FL)
+#pragma unroll
+                for (int a = 0; a < D; ++a) gvo[a * g.NN + node] = m > T(0) ? pq[a] / m : T(0);
             if (P.keep_grid) gmass[node] = m;
         }
     }
@@ -786,17 +832,24 @@ __device__ __forceinline__ void g2p_block_load(const Geo& g, const T* __restrict
     }
 }
 
-template <class T, int D, int MAT>
+// The transfer (App. B) sets the new velocity and the carried matrix C:
+// APIC C = (4/h^2) sum phi v_i (x_i - x_p)^T, TPIC C = the velocity gradient,
+// PIC and FLIP C = 0; FLIP (FL) also gathers the grid velocity before the
+// update, gvo, and blends: v' = sum phi v_i + alpha (v_p - sum phi v_i^n).
+template <class T, int D, int MAT, int XF>
 __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                 const ActiveTile* __restrict__ active, const int* __restrict__ perm,
                                                 PView<T> cur, PView<T> nxt, const T* __restrict__ gv,
+                                                const T* __restrict__ gvo,
                                                 int* __restrict__ key_out, int* __restrict__ count,
                                                 int* __restrict__ status)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     constexpr int NS = D * (D + 1) / 2;
     constexpr int NPT = (NB + kG2PBlock<T> - 1) / kG2PBlock<T>;   // block nodes per thread
+    constexpr bool FL = XF == XF_FLIP;
     __shared__ T s_v[D][NB];
+    __shared__ T s_vo[FL ? D : 1][FL ? NB : 1];
     const int n_active = meta[0];
     const int tid = threadIdx.x;
     const long long cap = cur.cap;
@@ -804,7 +857,7 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
     // registers while this tile's particles are processed (and its
     // active-list entry one tile earlier still); otherwise each tile loads its
     // own block at its top.
-    constexpr bool PF = kG2PPrefetch<T>;
+    constexpr bool PF = kG2PPrefetch<T> && !FL;
     int e = __builtin_amdgcn_readfirstlane(tile_entry(0, n_active));
     if (e < 0) return;
     ActiveTile at = active[e];
@@ -814,6 +867,17 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
     int next_tile = (PF && en >= 0) ? active[en].tile : 0;
     for (int it = 0; e >= 0; ++it) {
         if (!PF) g2p_block_load<T, D, NPT, kG2PBlock<T>>(g, gv, at.tile, tid, pre);
+        if constexpr (FL) {
+            T preo[D][NPT];
+            g2p_block_load<T, D, NPT, kG2PBlock<T>>(g, gvo, at.tile, tid, preo);
+#pragma unroll
+            for (int p = 0; p < NPT; ++p) {
+                const int i = tid + p * kG2PBlock<T>;
+                if (i < NB)
+#pragma unroll
+                    for (int a = 0; a < D; ++a) s_vo[a][i] = preo[a][p];
+            }
+        }
 #pragma unroll
         for (int p = 0; p < NPT; ++p) {
             const int i = tid + p * kG2PBlock<T>;
@@ -859,7 +923,7 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                 // then combined with the line's y/z factors.  The scheduling
                 // barrier after each line keeps the compiler from hoisting
                 // all LDS reads of the stencil (registers, occupancy).
-                T vn[D], Bm[D][D], Lm[D][D];
+                T vn[D], Bm[D][D], Lm[D][D], vo[FL ? D : 1];
                 {
                     constexpr int NL = (D == 3) ? 9 : 3;
                     T wdx[3];
@@ -868,6 +932,7 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
 #pragma unroll
                     for (int a = 0; a < D; ++a) {
                         vn[a] = T(0);
+                        if constexpr (FL) vo[a] = T(0);
 #pragma unroll
                         for (int b = 0; b < D; ++b) { Bm[a][b] = T(0); Lm[a][b] = T(0); }
                     }
@@ -893,6 +958,9 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                                 Bm[a][2] += (lw * dd[2][kz]) * A0;
                                 Lm[a][2] += (w[1][ky] * dw[2][kz]) * A0;
                             }
+                            if constexpr (FL)
+                                vo[a] += lw * (w[0][0] * s_vo[a][n0] + w[0][1] * s_vo[a][n0 + 1] +
+                                               w[0][2] * s_vo[a][n0 + 2]);
                         }
                         __builtin_amdgcn_sched_barrier(0);
                     }
@@ -907,9 +975,23 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                     xv = fmin(fmax(xv, T(0)), P.ext[a]);
                     xn[a] = xv;
                     nxt.x[a * cap + s] = xv;
-                    nxt.v[a * cap + s] = vn[a];
+                    if constexpr (FL) {
+                        const T vf = vn[a] + P.flip_alpha * (cur.v[a * cap + j] - vo[a]);
+                        bad |= !finite(vf);
+                        nxt.v[a * cap + s] = vf;
 #pragma unroll
-                    for (int b = 0; b < D; ++b) nxt.C[(a * D + b) * cap + s] = P.Dinv * Bm[a][b];
+                        for (int b = 0; b < D; ++b) nxt.C[(a * D + b) * cap + s] = T(0);
+                    } else {
+                        nxt.v[a * cap + s] = vn[a];
+#pragma unroll
+                        for (int b = 0; b < D; ++b) {
+                            T cab;
+                            if constexpr (XF == XF_APIC) cab = P.Dinv * Bm[a][b];
+                            else if constexpr (XF == XF_TPIC) cab = Lm[a][b];
+                            else cab = T(0);
+                            nxt.C[(a * D + b) * cap + s] = cab;
+                        }
+                    }
                 }
                 if constexpr (MAT == MAT_FLUID) {
                     T dJ = cur.G[j], si;
@@ -917,6 +999,20 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                     bad |= !finite(si) || !finite(dJ);
                     nxt.G[s] = dJ;
                     nxt.S[s] = si;
+                } else if constexpr (MAT == MAT_VFLUID || MAT == MAT_JAUMANN) {
+                    T dJ = cur.G[j], Sv[NS];
+                    if constexpr (MAT == MAT_JAUMANN)   // the viscous fluid's stress is a function of J and L
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) Sv[q] = cur.S[q * cap + j];
+                    if constexpr (MAT == MAT_VFLUID) vfluid_update<T, D>(P, Lm, dJ, Sv);
+                    else jaumann_update<T, D>(P, Lm, dJ, Sv);
+                    bad |= !finite(dJ);
+                    nxt.G[s] = dJ;
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        bad |= !finite(Sv[q]);
+                        nxt.S[q * cap + s] = Sv[q];
+                    }
                 } else {
                     T Gm[D][D], Sv[NS];
 #pragma unroll
@@ -1118,7 +1214,7 @@ Phys<T> make_phys(const mpm_ctx* c, double dt)
     P.cone_coef = (T)((D * lam + 2.0 * mu) / (2.0 * mu) * alpha);
     P.k_over_gamma = (T)(k.bulk / k.gamma);
     P.gamma = (T)k.gamma;
-    P.material = k.material;
+    P.material = c->mat;
     for (int f = 0; f < 6; ++f) {
         P.wall_mode[f] = k.wall_mode[f];
         P.wall_mu[f] = (T)k.wall_mu[f];
@@ -1126,6 +1222,39 @@ Phys<T> make_phys(const mpm_ctx* c, double dt)
     P.floor_mu = (const T*)c->floor_mu;
     P.floor_stride = c->geo.box[0];
     P.keep_grid = k.keep_grid;
+    P.xfer = c->xfer;
+    P.flip_alpha = (T)k.flip_alpha;
+    P.visc = (T)k.viscosity;
+    {
+        // hypoelastic Drucker-Prager constants (App. A)
+        double sp = sin(k.phi_deg * M_PI / 180.0), cp = cos(k.phi_deg * M_PI / 180.0);
+        double ss = sin(k.psi_deg * M_PI / 180.0);
+        double q_phi = 6.0 * sp / (sqrt(3.0) * (3.0 + sp));
+        double k_phi = 6.0 * k.cohesion * cp / (sqrt(3.0) * (3.0 + sp));
+        double q_psi = 6.0 * ss / (sqrt(3.0) * (3.0 + ss));
+        P.jK = (T)(lam + 2.0 * mu / D);
+        P.jq_phi = (T)q_phi;
+        P.jk_phi = (T)k_phi;
+        P.jq_psi = (T)q_psi;
+        P.jst = (T)k.tension;
+        P.jtauP = (T)(k_phi - q_phi * k.tension);
+        P.jalphaP = (T)(sqrt(1.0 + q_phi * q_phi) - q_phi);
+        P.jband2 = (T)(1e-6 * E * 1e-6 * E);
+    }
+    P.n_obst = k.n_obstacles;
+    for (int o = 0; o < kMaxObstacles; ++o) {
+        int ok = 0;
+        for (int a = 0; a < 3; ++a) {
+            P.obst_lo[o][a] = (T)k.obst_lo[o][a];
+            P.obst_hi[o][a] = (T)k.obst_hi[o][a];
+            if (a < D) {
+                double ext = (double)k.n[a] * k.dx;
+                if (k.obst_lo[o][a] > 0.0) ok |= 1 << (2 * a);        // lower face inside the domain
+                if (k.obst_hi[o][a] < ext) ok |= 1 << (2 * a + 1);    // upper face inside the domain
+            }
+        }
+        P.obst_face_ok[o] = ok;
+    }
     return P;
 }
 
@@ -1141,8 +1270,7 @@ PView<T> view(const mpm_ctx* c, int which)
     v.v = base + D * cap;
     v.C = base + 2 * D * cap;
     v.G = base + (2 * D + D * D) * cap;
-    bool fluid = c->cfg.material == MAT_FLUID;
-    v.S = v.G + (fluid ? 1 : D * D) * cap;
+    v.S = v.G + (mat_has_F(c->mat) ? D * D : 1) * cap;
     v.pid = c->pid[which];
     return v;
 }
@@ -1185,6 +1313,7 @@ struct Solver {
         long long NN = c->geo.NN;
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gv, D * NN, T(0));
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gmass, NN, T(0));
+        if (c->gvo) k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->gvo, D * NN, T(0));
         k_fill<int><<<1, kBlock, 0, st>>>(c->status, 16, 0);
         k_fill<int><<<1, kBlock, 0, st>>>(c->status + 1, 3, 0x7fffffff);
         if (c->geo.ntiles > 0)
@@ -1209,11 +1338,18 @@ struct Solver {
         return {c->perm, c->tile_slot, c->active, c->meta, (T*)c->gv, (T*)c->gmass, nullptr};
     }
 
-    // One step from state view cur into state view nxt.
-    template <int MAT>
+    // One step from state view cur into state view nxt with the transfer XF
+    // (FLIP: P2G and the grid update also form the velocity before the
+    // update).  The transfer is a template parameter: as a run-time choice it
+    // kept both affine candidates live in G2P and cost it half its waves.
+    template <int MAT, int XF = XF_APIC>
     static void step_views(mpm_ctx* c, const Phys<T>& P, const PView<T>& cur, const PView<T>& nxt,
                            const StepBufs& b)
     {
+        constexpr bool FL = XF == XF_FLIP;
+        // P2G depends on the material only through the stored stress: one
+        // isotropic value or the symmetric tensor
+        constexpr int PM = mat_iso_stress(MAT) ? MAT_FLUID : MAT_SAND;
         hipStream_t st = c->stream;
         const Geo& g = c->geo;
         unsigned nsb = (unsigned)((g.ntiles + kScanChunk - 1) / kScanChunk);
@@ -1224,38 +1360,51 @@ struct Solver {
         k_bucket<0><<<(unsigned)((c->N + kBlock * kBucketPer - 1) / (kBlock * kBucketPer)), kBlock, 0, st>>>(
             c->N, c->key, c->count, c->tile_off, c->tmp, c->tmpk);
         prof_mark(c, MPM_PROF_BUCKET);
-        k_p2g<T, D, MAT><<<kP2GWGs<T>, kP2GBlock<T>, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur, b.perm,
-                                                      (T*)c->part_grid);
+        k_p2g<T, D, PM, FL><<<kP2GWGs<T, FL>, kP2GBlock<T, FL>, 0, st>>>(g, P, b.meta, b.active, c->tmp, c->tmpk, cur,
+                                                                        b.perm, (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
-        k_grid<T, D><<<kTileWGs * kBlock / kGridBlock, kGridBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,
-                                                  b.gv, b.gmass, b.gvt);
+        k_grid<T, D, FL><<<kTileWGs * kBlock / kGridBlock, kGridBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,
+                                                  b.gv, b.gmass, b.gvt, (T*)c->gvo);
         prof_mark(c, MPM_PROF_GRID);
-        k_g2p<T, D, MAT><<<kTileWGs * kBlock / kG2PBlock<T>, kG2PBlock<T>, 0, st>>>(g, P, b.meta, b.active, b.perm, cur, nxt, (const T*)b.gv,
-                                                      c->key, c->count, c->status);
+        k_g2p<T, D, MAT, XF><<<kTileWGs * kBlock / kG2PBlock<T>, kG2PBlock<T>, 0, st>>>(g, P, b.meta, b.active, b.perm, cur, nxt, (const T*)b.gv,
+                                                      (const T*)c->gvo, c->key, c->count, c->status);
         prof_mark(c, MPM_PROF_G2P);
     }
 
-    template <int MAT>
+    template <int MAT, int XF = XF_APIC>
     static void step_views(mpm_ctx* c, const Phys<T>& P, const PView<T>& cur, const PView<T>& nxt)
     {
-        step_views<MAT>(c, P, cur, nxt, ctx_bufs(c));
+        step_views<MAT, XF>(c, P, cur, nxt, ctx_bufs(c));
     }
 
-    template <int MAT>
+    template <int MAT, int XF>
     static void one_step(mpm_ctx* c, const Phys<T>& P)
     {
-        step_views<MAT>(c, P, view<T>(c, c->cur), view<T>(c, 1 - c->cur));
+        step_views<MAT, XF>(c, P, view<T>(c, c->cur), view<T>(c, 1 - c->cur));
         c->cur = 1 - c->cur;
+    }
+
+    template <int XF>
+    static void one_step_x(mpm_ctx* c, const Phys<T>& P)
+    {
+        switch (c->mat) {
+        case MAT_FLUID: one_step<MAT_FLUID, XF>(c, P); break;
+        case MAT_SAND: one_step<MAT_SAND, XF>(c, P); break;
+        case MAT_VFLUID: one_step<MAT_VFLUID, XF>(c, P); break;
+        case MAT_JAUMANN: one_step<MAT_JAUMANN, XF>(c, P); break;
+        default: one_step<MAT_ELASTIC, XF>(c, P); break;
+        }
     }
 
     static int step(mpm_ctx* c, int n, double dt)
     {
         Phys<T> P = make_phys<T>(c, dt);
         for (int i = 0; i < n; ++i) {
-            switch (c->cfg.material) {
-            case MAT_FLUID: one_step<MAT_FLUID>(c, P); break;
-            case MAT_SAND: one_step<MAT_SAND>(c, P); break;
-            default: one_step<MAT_ELASTIC>(c, P); break;
+            switch (c->xfer) {
+            case XF_PIC: one_step_x<XF_PIC>(c, P); break;
+            case XF_FLIP: one_step_x<XF_FLIP>(c, P); break;
+            case XF_TPIC: one_step_x<XF_TPIC>(c, P); break;
+            default: one_step_x<XF_APIC>(c, P); break;
             }
         }
         return launch_err(c, "step");
@@ -1265,7 +1414,8 @@ struct Solver {
     static int field_desc(mpm_ctx* c, int field, T** ptr, int* ncomp, int* conv)
     {
         PView<T> s = view<T>(c, c->cur);
-        bool fluid = c->cfg.material == MAT_FLUID;
+        const bool fluid = !mat_has_F(c->mat);   // carries J instead of F
+        const bool iso = mat_iso_stress(c->mat);
         switch (field) {
         case MPM_FIELD_X: *ptr = s.x; *ncomp = D; *conv = CONV_COPY; return MPM_OK;
         case MPM_FIELD_V: *ptr = s.v; *ncomp = D; *conv = CONV_COPY; return MPM_OK;
@@ -1283,7 +1433,7 @@ struct Solver {
             if (!fluid) break;
             *ptr = s.G; *ncomp = 1; *conv = CONV_COPY; return MPM_OK;
         case MPM_FIELD_STRESS:
-            *ptr = s.S; *ncomp = D * D; *conv = fluid ? CONV_ISO : CONV_SYM; return MPM_OK;
+            *ptr = s.S; *ncomp = D * D; *conv = iso ? CONV_ISO : CONV_SYM; return MPM_OK;
         default: break;
         }
         return set_err(c, MPM_EINVAL, "field not available for this material");

@@ -69,6 +69,7 @@ struct MlpDesc {
     int offW[MPM_MLP_MAX_LAYERS], offb[MPM_MLP_MAX_LAYERS];
     long long offC[MPM_MLP_MAX_LAYERS];   // per-layer offset in the cache (per sample count n)
     int out_act;
+    int hidden_act;                   // MPM_HIDDEN_TANH or MPM_HIDDEN_RELU
     float scale, shift;
     float in_scale[MPM_MLP_MAX_IN], in_shift[MPM_MLP_MAX_IN];
 };
@@ -116,7 +117,9 @@ __device__ __forceinline__ f4 mfma_tile(int K, FA fa, FB fb)
     return c;
 }
 
-__device__ __forceinline__ float act_hidden(float z) { return tanhf(z); }
+__device__ __forceinline__ float act_hidden(int kind, float z) { return kind == MPM_HIDDEN_RELU ? fmaxf(z, 0.f) : tanhf(z); }
+// derivative of the hidden activation from its output h
+__device__ __forceinline__ float dact_hidden(int kind, float h) { return kind == MPM_HIDDEN_RELU ? (h > 0.f ? 1.f : 0.f) : 1.f - h * h; }
 __device__ __forceinline__ float act_out(int kind, float z) { return kind == MPM_ACT_SIGMOID ? 1.f / (1.f + expf(-z)) : z; }
 
 constexpr int kWaves = 2;   // waves per workgroup in the row kernels
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_fwd(MlpDesc d, const float*
                     float h = 0.f;
                     if (col < wout) {
                         float z = c[i] + bias[col];
-                        h = (l < d.L - 1) ? act_hidden(z) : act_out(d.out_act, z);
+                        h = (l < d.L - 1) ? act_hidden(d.hidden_act, z) : act_out(d.out_act, z);
                         if (r0 + r < n) cache[d.offC[l] * n + (r0 + r) * wout + col] = h;
                     }
                     buf[1 - cur][r][col] = h;
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_bwd_data(MlpDesc d, const f
         wave_sync();
         int cur = 0;
         for (int l = L - 1; l >= 1; --l) {
-            // dh = dz_l W_l (16 x w[l]); dz_{l-1} = dh * (1 - h^2), h = layer l-1 output
+            // dh = dz_l W_l (16 x w[l]); dz_{l-1} = dh * act'(z), from h = layer l-1 output
             const float* W = P + d.offW[l];
             const int win = d.w[l], wout = d.w[l + 1];
             for (int kt = 0; kt < d.wp[l]; kt += 16) {
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_mlp_bwd_data(MlpDesc d, const f
                     float v = 0.f;
                     if (col < win && r0 + r < n) {
                         float h = cache[d.offC[l - 1] * n + (r0 + r) * win + col];
-                        v = c[i] * (1.f - h * h);
+                        v = c[i] * dact_hidden(d.hidden_act, h);
                         work[d.offC[l - 1] * n + (r0 + r) * win + col] = v;
                     }
                     buf[1 - cur][r][col] = v;
@@ -348,6 +351,7 @@ int make_desc(const mpm_mlp* net, MlpDesc* d)
     if (!net || net->n_layers < 1 || net->n_layers > MPM_MLP_MAX_LAYERS) return MPM_EINVAL;
     if (net->math != MPM_MLP_BF16 && net->math != MPM_MLP_F32) return MPM_EINVAL;
     if (net->out_act != MPM_ACT_NONE && net->out_act != MPM_ACT_SIGMOID) return MPM_EINVAL;
+    if (net->hidden_act != MPM_HIDDEN_TANH && net->hidden_act != MPM_HIDDEN_RELU) return MPM_EINVAL;
     if (net->width[0] < 1 || net->width[0] > MPM_MLP_MAX_IN) return MPM_EINVAL;
     d->L = net->n_layers;
     int off = 0;
@@ -367,6 +371,7 @@ int make_desc(const mpm_mlp* net, MlpDesc* d)
         coff += d->w[l + 1];
     }
     d->out_act = net->out_act;
+    d->hidden_act = net->hidden_act;
     d->scale = net->out_scale;
     d->shift = net->out_shift;
     for (int k = 0; k < MPM_MLP_MAX_IN; ++k) {

@@ -40,6 +40,8 @@ struct mpm_ctx {
     int elem = 4;                  // bytes per floating-point scalar
     int nsc = 0;                   // scalars per particle per state buffer
     int nsym = 0;                  // stored stress components
+    int mat = 0;                   // kernel material (mpm::MAT_*)
+    int xfer = 0;                  // transfer (mpm::XF_*)
     const mpm::Ops* ops = nullptr;
 
     // workspace
@@ -67,6 +69,7 @@ struct mpm_ctx {
     void* part_grid = nullptr;     // per active tile: P2G node block, mass + momentum
     void* gv = nullptr;            // nodal velocity after the grid update [dim]
     void* gmass = nullptr;         // nodal mass kept for read-back
+    void* gvo = nullptr;           // FLIP: nodal velocity before the update [dim]
     const void* floor_mu = nullptr;
 
     // forward-plus-adjoint rollout (mpm_forward_loss / mpm_backward)

@@ -3,9 +3,11 @@ observations of a ground-truth run, then fit a parameter field -- a small
 MLP on the matrix cores or the plain per-cell table -- by Adam with a
 decaying step (Sec. 5: Adam with a decaying learning rate).
 
-Every numerical step runs in the HIP library: the field (MLP or table
+Every step of the method runs in the HIP library: the field (MLP or table
 gather), the rollout and its adjoint, the network backward and the Adam
-update.  This module only sequences the calls.
+update.  This module sequences the calls; the only arithmetic it leaves to
+torch is the glue of a parameter form (a scalar times a fixed profile, a
+zero component appended, a clamp onto [0, 1]).
 """
 from __future__ import annotations
 
@@ -58,9 +60,12 @@ def record(solver, x0, v0, mu, steps, frames, obs):
 
 
 def train(solver, x0, steps, frames, obs, targets, field_apply, theta, epochs, lr, decay=0.98,
-          target_field: str = "v0", log_every: int = 0):
+          target_field: str = "v0", log_every: int = 0, trace=None, project=None):
     """Fit theta: field_apply(theta) gives v0 ([dim, N], when target_field is
-    'v0') or the floor friction per node ('mu').  Returns the history."""
+    'v0') or the floor friction per node ('mu').  trace (a list) receives a
+    host copy of theta after every update; project(theta), when given, maps
+    theta back into its admissible set after every update.  Returns the
+    history."""
     torch = solver.torch
     MLPFunction, MPMRollout = native.autograd_functions()
     lag_t, eul_t = targets
@@ -84,6 +89,10 @@ def train(solver, x0, steps, frames, obs, targets, field_apply, theta, epochs, l
             loss = MPMRollout.apply(zeros_v, field.reshape(-1), solver, x0, steps)
         loss.backward()
         native.adam_step(theta, th.grad.contiguous(), m, v, ep + 1, lr * decay ** ep)
+        if project is not None:
+            project(theta)
+        if trace is not None:
+            trace.append(theta.detach().cpu().numpy().copy())
         hist.loss.append(float(loss.item()))
         if log_every and (ep % log_every == 0 or ep == epochs - 1):
             print(f"  epoch {ep:4d} loss {hist.loss[-1]:.6e}", flush=True)
@@ -199,6 +208,132 @@ def learned_friction_3d(scale_div: int = 1, epochs: int = 30, steps: int = 2000,
             "cells": {"loss": hc.loss, "field_err": err_cell, "seconds": hc.seconds}}
 
 
+# ---------------------------------------------------------------------------
+# The paper's own inverse experiments (Sec. 5.1-5.3), synthetic reproductions
+# ---------------------------------------------------------------------------
+
+ALPHA_CASES = {1: "all particle positions (Lagrangian)", 2: "100 particle positions (Lagrangian)",
+               3: "mean velocity in 9 monitors (Eulerian)"}
+
+
+def _last_frames(steps, count, every):
+    return list(range(steps - (count - 1) * every, steps + 1, every))
+
+
+def alpha_inverse(case: int, epochs: int = 60, alpha0: float = 0.1, alpha_true: float = 2.0, lr: float = 0.1,
+                  decay: float = 0.98, precision: str = "f64", seed: int = 11, steps: int = 10000,
+                  log_every: int = 0):
+    """Sec. 5.1: the scalar alpha of the initial velocity v_x = alpha (H0 - y),
+    v_y = 0, of a 0.5 x 0.5 m water column, recovered from observations of a
+    run with alpha = 2 over its last 100 frames (every 10 steps of the last
+    1000 of 10,000 steps, t = 0.3 s): case 1 every particle's position,
+    case 2 the positions of 100 random particles, case 3 the mean velocity
+    in the nine monitors.  Adam with a decaying rate from alpha = 0.1.
+    Returns the loss and alpha histories."""
+    import torch
+    cfg, x0, H0 = W.inverse_dam_break_2d()
+    n = x0.shape[1]
+    frames = _last_frames(steps, 100, 10)
+    if case == 1:
+        obs = dict(tracer_pid=np.arange(n, dtype=np.int32), lag_field="x")
+    elif case == 2:
+        obs = dict(tracer_pid=W.pick_tracers(n, 100, seed), lag_field="x")
+    elif case == 3:
+        lo, hi = W.velocity_monitors_2d()
+        obs = dict(box_lo=lo, box_hi=hi, eul_field="v")
+    else:
+        raise ValueError("case is 1, 2 or 3")
+    prof = np.stack([H0 - x0[1], np.zeros(n)])
+    s = native.Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=100)
+    targets = record(s, x0, alpha_true * prof, None, steps, frames, obs)
+    prof_t = torch.as_tensor(prof, dtype=torch.float32, device=s.device)
+    theta = torch.tensor([alpha0], dtype=torch.float32, device=s.device)
+    trace = []
+    h = train(s, x0, steps, frames, obs, targets, lambda th: th[0] * prof_t, theta, epochs, lr, decay,
+              log_every=log_every, trace=trace)
+    s.close()
+    return {"case": case, "observations": ALPHA_CASES[case], "particles": n, "steps": steps, "epochs": epochs,
+            "loss": h.loss, "alpha": [float(a[0]) for a in trace], "alpha_true": alpha_true,
+            "seconds": h.seconds}
+
+
+def profile_inverse(n_obs: int = 1000, epochs: int = 400, lr: float = 1e-2, decay: float = 0.995,
+                    precision: str = "f64", math: str = "f32", seed: int = 12, steps: int = 10000,
+                    log_every: int = 0):
+    """Sec. 5.2: the initial horizontal velocity profile v_x(y) = 2 (1 -
+    (y/H0)^2) + 0.2 sin(4 pi y/H0) of the same water column, represented by a
+    1-30-30-30-1 ReLU network of y (MFMA kernels), recovered from the
+    positions of n_obs random particles over the last 100 frames.  Returns
+    the loss history and the relative L2 error of the profile over the
+    particles."""
+    import torch
+    MLPFunction, _ = native.autograd_functions()
+    cfg, x0, H0 = W.inverse_dam_break_2d()
+    n = x0.shape[1]
+    frames = _last_frames(steps, 100, 10)
+    obs = dict(tracer_pid=W.pick_tracers(n, n_obs, seed), lag_field="x")
+    v_true = np.stack([W.velocity_profile(x0[1], H0), np.zeros(n)])
+    s = native.Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=100)
+    targets = record(s, x0, v_true, None, steps, frames, obs)
+    widths = [1, 30, 30, 30, 1]
+    net = native.MLP(widths, in_scale=[2.0 / H0], in_shift=[-1.0], math=math, hidden_act="relu")
+    y_in = torch.as_tensor(x0[1:2], dtype=torch.float32, device=s.device).contiguous()
+    zeros = torch.zeros((1, n), dtype=torch.float32, device=s.device)
+    theta = torch.as_tensor(W.mlp_init_params(widths, seed + 1), device=s.device)
+
+    def field(th):
+        return torch.cat([MLPFunction.apply(th, y_in, net), zeros], dim=0)
+
+    with torch.no_grad():
+        err0 = rel_err(field(theta)[0], v_true[0])
+    errs = []
+    h = train(s, x0, steps, frames, obs, targets, field, theta, epochs, lr, decay, log_every=log_every)
+    with torch.no_grad():
+        est = field(theta)[0]
+        err = rel_err(est, v_true[0])
+        # the learned profile on a uniform grid of heights, for the record
+        yg = torch.linspace(0.0, H0, 51, device=s.device, dtype=torch.float32).reshape(1, -1).contiguous()
+        prof = MLPFunction.apply(theta, yg, net)[0].cpu().numpy()
+    s.close()
+    errs.append(err)
+    return {"n_obs": n_obs, "particles": n, "epochs": epochs, "loss": h.loss, "start_err": err0,
+            "field_err": err, "profile_y": np.linspace(0.0, H0, 51).tolist(), "profile": prof.tolist(),
+            "profile_true": W.velocity_profile(np.linspace(0.0, H0, 51), H0).tolist(), "seconds": h.seconds}
+
+
+def friction_segments_inverse(n_tracers: int = 500, epochs: int = 100, mu0: float = 0.3, lr: float = 0.1,
+                              decay: float = 0.98, precision: str = "f64", seed: int = 13, steps: int = 10000,
+                              frame_every: int = 10, log_every: int = 0):
+    """Sec. 5.3: the Coulomb friction of four equal floor segments under a
+    dam-break (truth 0.0, 0.5, 0.1, 0.2), recovered from the positions of
+    n_tracers random particles at 1000 frames over 10,000 steps (t = 0.4 s).
+    The segments are a 4 x 1 piecewise-constant field over the floor nodes
+    (gather/scatter kernels); Adam with a decaying rate from mu0, projected
+    onto [0, 1] after every update.  Returns the loss and segment
+    histories."""
+    import torch
+    cfg, x0, seg = W.friction_segments_2d()
+    n = x0.shape[1]
+    frames = list(range(frame_every, steps + 1, frame_every))
+    obs = dict(tracer_pid=W.pick_tracers(n, n_tracers, seed), lag_field="x")
+    true = np.asarray(W.FRICTION_SEGMENTS_TRUE)
+    mu_true = W.segment_mu(cfg, true, seg_len=seg)
+    s = native.Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=100)
+    targets = record(s, x0, None, mu_true, steps, frames, obs)
+    nd = cfg.node_dims()
+    xs = (np.arange(nd[0]) - cfg.ghost) * cfg.dx
+    nodes = torch.as_tensor(np.stack([xs, np.zeros_like(xs)]), dtype=torch.float32, device=s.device).contiguous()
+    L = cfg.n[0] * cfg.dx
+    cf = native.CellField(1, len(true), 1, (0.0, -1.0), (L, 1.0))
+    theta = torch.full((len(true),), mu0, dtype=torch.float32, device=s.device)
+    trace = []
+    h = train(s, x0, steps, frames, obs, targets, cell_field(cf, nodes), theta, epochs, lr, decay,
+              target_field="mu", log_every=log_every, trace=trace, project=lambda t: t.clamp_(0.0, 1.0))
+    s.close()
+    return {"n_tracers": n_tracers, "particles": n, "steps": steps, "frames": len(frames), "epochs": epochs,
+            "loss": h.loss, "mu": [a.tolist() for a in trace], "mu_true": true.tolist(), "seconds": h.seconds}
+
+
 def mlp_field(net, x_in):
     """field_apply for a network evaluated at fixed inputs x_in [d_in, n]."""
     MLPFunction, _ = native.autograd_functions()
@@ -214,7 +349,10 @@ def main(argv=None):
     import argparse
     import json
     ap = argparse.ArgumentParser(description="Learned-field inverse problems through the MPM adjoint")
-    ap.add_argument("case", choices=["velocity2d", "friction3d"])
+    ap.add_argument("case", choices=["velocity2d", "friction3d", "alpha", "profile", "segments"])
+    ap.add_argument("--alpha-case", type=int, default=3, help="alpha: 1, 2 or 3 (observation strategy)")
+    ap.add_argument("--n-obs", type=int, default=500, help="profile: observed particles; segments: tracers")
+    ap.add_argument("--out", default=None, help="also write the result as JSON to this file")
     ap.add_argument("--epochs", type=int, default=None)
     ap.add_argument("--scale-div", type=int, default=1, help="friction3d: shrink the dam-break")
     ap.add_argument("--steps", type=int, default=2000, help="friction3d: rollout length")
@@ -222,6 +360,12 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.case == "velocity2d":
         r = learned_velocity_2d(epochs=a.epochs or 60, log_every=a.log_every)
+    elif a.case == "alpha":
+        r = alpha_inverse(a.alpha_case, epochs=a.epochs or 60, log_every=a.log_every)
+    elif a.case == "profile":
+        r = profile_inverse(n_obs=a.n_obs, epochs=a.epochs or 400, log_every=a.log_every)
+    elif a.case == "segments":
+        r = friction_segments_inverse(n_tracers=a.n_obs, epochs=a.epochs or 100, log_every=a.log_every)
     else:
         r = learned_friction_3d(scale_div=a.scale_div, epochs=a.epochs or 30, steps=a.steps,
                                 log_every=a.log_every)
@@ -230,6 +374,11 @@ def main(argv=None):
             continue
         r[k]["loss_first"], r[k]["loss_last"] = r[k]["loss"][0], r[k]["loss"][-1]
         del r[k]["loss"]
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(r, f)
+    if "loss" in r:
+        r = dict(r, loss=[r["loss"][0], r["loss"][-1]])
     print(json.dumps(r), flush=True)
 
 

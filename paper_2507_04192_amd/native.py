@@ -21,7 +21,9 @@ MPM_OK, MPM_EINVAL, MPM_ENOMEM, MPM_EHIP, MPM_ENONFINITE, MPM_EDOMAIN, MPM_ESTAT
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "EDOMAIN",
                 -6: "ESTATE", -7: "ECONVERGE"}
 MPM_F32, MPM_F64 = 0, 1
-MATERIAL = {"fluid": 0, "sand": 1, "elastic": 2}
+MATERIAL = {"fluid": 0, "sand": 1, "elastic": 2, "dp_jaumann": 3}
+TRANSFER = {"apic": 0, "pic": 1, "flip": 2, "tpic": 3}
+MAX_OBSTACLES = 4
 WALL = {"slip": 0, "stick": 1, "coulomb": 2}
 FIELD = {"x": 0, "v": 1, "C": 2, "F": 3, "FmI": 4, "J": 5, "Jm1": 6, "stress": 7, "pid": 8}
 ORDER = {"memory": 0, "pid": 1}
@@ -48,7 +50,7 @@ class MpmMlp(ct.Structure):
     _fields_ = [
         ("n_layers", ct.c_int32), ("width", ct.c_int32 * 5), ("out_act", ct.c_int32), ("math", ct.c_int32),
         ("out_scale", ct.c_float), ("out_shift", ct.c_float),
-        ("in_scale", ct.c_float * 4), ("in_shift", ct.c_float * 4),
+        ("in_scale", ct.c_float * 4), ("in_shift", ct.c_float * 4), ("hidden_act", ct.c_int32),
     ]
 
 
@@ -60,6 +62,10 @@ class MpmConfig(ct.Structure):
         ("dx", ct.c_double), ("gravity", ct.c_double * 3), ("wall_mu", ct.c_double * 6),
         ("rho0", ct.c_double), ("bulk", ct.c_double), ("gamma", ct.c_double),
         ("youngs", ct.c_double), ("poisson", ct.c_double), ("phi_deg", ct.c_double),
+        ("transfer", ct.c_int32), ("n_obstacles", ct.c_int32),
+        ("flip_alpha", ct.c_double), ("viscosity", ct.c_double),
+        ("psi_deg", ct.c_double), ("cohesion", ct.c_double), ("tension", ct.c_double),
+        ("obst_lo", (ct.c_double * 3) * MAX_OBSTACLES), ("obst_hi", (ct.c_double * 3) * MAX_OBSTACLES),
     ]
 
 
@@ -147,6 +153,18 @@ def make_config(cfg, precision: str = "f64", keep_grid: bool = False) -> MpmConf
     c.dx = float(cfg.dx)
     c.rho0, c.bulk, c.gamma = float(cfg.rho0), float(cfg.bulk), float(cfg.gamma)
     c.youngs, c.poisson, c.phi_deg = float(cfg.youngs), float(cfg.poisson), float(cfg.phi_deg)
+    c.transfer = TRANSFER[cfg.transfer]
+    c.flip_alpha = float(cfg.flip_alpha)
+    c.viscosity = float(cfg.viscosity)
+    c.psi_deg, c.cohesion, c.tension = float(cfg.psi_deg), float(cfg.cohesion), float(cfg.tension)
+    obs = list(cfg.obstacles)
+    if len(obs) > MAX_OBSTACLES:
+        raise ValueError(f"at most {MAX_OBSTACLES} obstacles")
+    c.n_obstacles = len(obs)
+    for o, (lo, hi) in enumerate(obs):
+        for a in range(3):
+            c.obst_lo[o][a] = float(lo[a]) if a < len(lo) else 0.0
+            c.obst_hi[o][a] = float(hi[a]) if a < len(hi) else 0.0
     return c
 
 
@@ -376,8 +394,8 @@ class Solver:
     def state_numpy(self, order="pid"):
         """All state fields as float64 numpy arrays (synchronizes)."""
         out = {}
-        fluid = self.cfg.material == "fluid"
-        names = ["x", "v", "C", "stress"] + (["Jm1"] if fluid else ["FmI"])
+        carries_j = self.cfg.material in ("fluid", "dp_jaumann")
+        names = ["x", "v", "C", "stress"] + (["Jm1"] if carries_j else ["FmI"])
         for f in names:
             out[f] = self.mpm_read_state(f, order).cpu().numpy().astype(np.float64)
         if order == "memory":
@@ -392,12 +410,13 @@ class Solver:
 class MLP:
     """alpha(x) = N_theta(x) evaluated by the MFMA kernels (mpm_mlp_*).
 
-    widths: [d_in, hidden..., d_out]; hidden tanh; output 'none' or 'sigmoid'
-    followed by out_shift + out_scale * act.  Inputs are mapped feature-wise
-    to in_scale * x + in_shift inside the kernel.  math: 'bf16' or 'f32'."""
+    widths: [d_in, hidden..., d_out]; hidden 'tanh' or 'relu'; output 'none'
+    or 'sigmoid' followed by out_shift + out_scale * act.  Inputs are mapped
+    feature-wise to in_scale * x + in_shift inside the kernel.  math: 'bf16'
+    or 'f32'."""
 
     def __init__(self, widths, out_act="none", out_scale=1.0, out_shift=0.0, in_scale=None, in_shift=None,
-                 math="bf16"):
+                 math="bf16", hidden_act="tanh"):
         import torch
         self.torch = torch
         d = MpmMlp()
@@ -405,6 +424,7 @@ class MLP:
         for i, wv in enumerate(widths):
             d.width[i] = int(wv)
         d.out_act = {"none": 0, "sigmoid": 1}[out_act]
+        d.hidden_act = {"tanh": 0, "relu": 1}[hidden_act]
         d.math = {"bf16": 0, "f32": 1}[math]
         d.out_scale, d.out_shift = float(out_scale), float(out_shift)
         for k in range(4):

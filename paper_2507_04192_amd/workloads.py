@@ -312,3 +312,56 @@ def mlp_init_params(widths, seed: int) -> np.ndarray:
         parts.append(rng.uniform(-r, r, size=o))
     return np.concatenate(parts).astype(np.float32)
 
+
+
+# ---------------------------------------------------------------------------
+# The paper's own inverse experiments (Sec. 5), synthetic reproductions
+# ---------------------------------------------------------------------------
+
+def inverse_dam_break_2d(seed: int = 0):
+    """Dam-break of the initial-velocity inverse problems (Sec. 5.1, 5.2):
+    water column H0 = L0 = 0.5 m at dx = 0.01 m, 2 x 2 particles per cell
+    (10,000 particles), inviscid fluid with the numerical sound speed
+    c0 = 50 m/s (the linear EOS: gamma = 1, K = rho0 c0^2), dt = 3e-5 s,
+    slip walls.  The paper does not give the domain; it is 2.0 x 0.6 m here
+    (200 x 60 cells), long enough that the front stays off the far wall
+    until t = 0.3 s.  Returns (cfg, x, H0)."""
+    c0, rho0 = 50.0, 1000.0
+    cfg = SimConfig(dim=2, n=(200, 60, 1), dx=0.01, dt=3e-5, material=FLUID, ppc=4,
+                    gravity=(0.0, -9.8, 0.0), rho0=rho0, bulk=rho0 * c0 * c0, gamma=1.0)
+    H0 = L0 = 0.5
+    x = lattice_particles(cfg, box_inside((0.0, 0.0), (L0, H0)), (0.0, 0.0), (L0, H0), seed)
+    return cfg, x, H0
+
+
+def velocity_monitors_2d(half: float = 0.01):
+    """The nine Eulerian monitors of Sec. 5.1: squares of half-side 0.01 m
+    centred on {0.2, 0.3, 0.4} x {0.1, 0.2, 0.3} m.  Returns (lo, hi)."""
+    C = np.array([[cx, cy] for cy in (0.1, 0.2, 0.3) for cx in (0.2, 0.3, 0.4)])
+    return C - half, C + half
+
+
+def velocity_profile(y, H0: float = 0.5):
+    """The hidden initial horizontal velocity of Sec. 5.2:
+    v_x(y) = 2 (1 - (y/H0)^2) + 0.2 sin(4 pi y / H0)."""
+    y = np.asarray(y, dtype=np.float64)
+    return 2.0 * (1.0 - (y / H0) ** 2) + 0.2 * np.sin(4.0 * np.pi * y / H0)
+
+
+def friction_segments_2d(seed: int = 0):
+    """Dam-break of the segmented-friction inverse problem (Sec. 5.3):
+    domain L = 1.6 m x H = 0.4 m at dx = 0.01 m (160 x 40 cells), water
+    column L0 = 0.5 m x H0 = 0.3 m at 2 x 2 particles per cell (6,000
+    particles, the count of the paper's table), dt = 4e-5 s, the floor in
+    four equal Coulomb segments, the other walls slip.  The sound speed is
+    not given for this problem; it takes the 50 m/s of Sec. 5.1.  Returns
+    (cfg, x, segment length)."""
+    c0, rho0 = 50.0, 1000.0
+    cfg = SimConfig(dim=2, n=(160, 40, 1), dx=0.01, dt=4e-5, material=FLUID, ppc=4,
+                    gravity=(0.0, -9.8, 0.0), rho0=rho0, bulk=rho0 * c0 * c0, gamma=1.0,
+                    wall_mode=(SLIP, SLIP, COULOMB, SLIP, SLIP, SLIP))
+    x = lattice_particles(cfg, box_inside((0.0, 0.0), (0.5, 0.3)), (0.0, 0.0), (0.5, 0.3), seed)
+    return cfg, x, 0.4
+
+
+FRICTION_SEGMENTS_TRUE = (0.0, 0.5, 0.1, 0.2)     # Sec. 5.3 ground truth

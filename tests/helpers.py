@@ -53,7 +53,7 @@ def gpu_fields(s):
 def oracle_fields(cfg, st):
     d = cfg.dim
     out = {"x": st.by_pid("x"), "v": st.by_pid("v"), "C": st.by_pid("C"), "stress": st.by_pid("S")}
-    if cfg.material == W.FLUID:
+    if cfg.material in (W.FLUID, W.DP_JAUMANN):
         out["Jm1"] = (st.by_pid("J") - 1.0).reshape(1, -1)
     else:
         F = st.by_pid("F").copy()

@@ -78,3 +78,43 @@ def test_grid_beyond_int32_keys_is_rejected():
     above = below.replace(n=(8192, 8192, 24))
     assert L.mpm_workspace_bytes(ct.byref(native.make_config(below, "f32")), 10, 0, 0, ct.byref(nb)) == 0
     assert L.mpm_workspace_bytes(ct.byref(native.make_config(above, "f32")), 10, 0, 0, ct.byref(nb)) == native.MPM_EINVAL
+
+
+def test_added_physics_validation_without_gpu():
+    """Transfers, obstacles, viscosity and the hypoelastic Drucker-Prager
+    parameters are checked by mpm_workspace_bytes (no GPU needed); a FLIP
+    workspace is larger (its P2G blocks and grid carry the velocity before
+    the update)."""
+    from paper_2507_04192_amd import native
+    from paper_2507_04192_amd import workloads as W
+    L = native.lib()
+    nb = ct.c_size_t()
+    cfg, _ = W.dam_break_2d()
+
+    def rc(c):
+        return L.mpm_workspace_bytes(ct.byref(native.make_config(c, "f32")), 100, 0, 0, ct.byref(nb))
+
+    assert rc(cfg) == 0
+    base = nb.value
+    assert rc(cfg.replace(transfer=W.FLIP, flip_alpha=0.97)) == 0 and nb.value > base
+    for good in (cfg.replace(transfer=W.PIC), cfg.replace(transfer=W.TPIC), cfg.replace(viscosity=1.01e-3),
+                 cfg.replace(obstacles=(((0.6, 0.0), (0.7, 0.3)),))):
+        assert rc(good) == 0
+    bad = native.make_config(cfg, "f32")
+    bad.transfer = 7
+    assert L.mpm_workspace_bytes(ct.byref(bad), 100, 0, 0, ct.byref(nb)) == native.MPM_EINVAL
+    assert b"transfer" in L.mpm_last_error(None)
+    assert rc(cfg.replace(transfer=W.FLIP, flip_alpha=1.5)) == native.MPM_EINVAL
+    assert rc(cfg.replace(obstacles=(((0.7, 0.0), (0.6, 0.3)),))) == native.MPM_EINVAL
+    bad = native.make_config(cfg, "f32")
+    bad.n_obstacles = 5
+    assert L.mpm_workspace_bytes(ct.byref(bad), 100, 0, 0, ct.byref(nb)) == native.MPM_EINVAL
+    assert rc(cfg.replace(viscosity=-1.0)) == native.MPM_EINVAL
+    sand, _ = W.cylinder_collapse_3d(scale_div=8)
+    assert rc(sand.replace(viscosity=1.0)) == native.MPM_EINVAL            # viscosity is the fluid's
+    dp = sand.replace(material=W.DP_JAUMANN, psi_deg=5.0)
+    assert rc(dp) == 0
+    assert rc(dp.replace(psi_deg=40.0)) == native.MPM_EINVAL               # psi above phi
+    assert rc(dp.replace(tension=10.0)) == native.MPM_EINVAL               # above the apex (c = 0)
+    assert rc(dp.replace(cohesion=1000.0, tension=10.0)) == 0              # below it with cohesion
+    assert rc(dp.replace(cohesion=-1.0)) == native.MPM_EINVAL

@@ -7,7 +7,7 @@ against binary64, and the shallow-water solution of the dam-break.
   oracle.
 - Shallow dam-break of Sec. 4.1.1 (H0 = 0.1 m, L0 = 1.0 m, dh = 0.004 m,
   4 particles per cell, linear EOS with c_n = 35 m/s, dt = 1e-5 s, slip
-  walls): the free surface against eq:shallow, the position where the
+  walls; APIC, FLIP and TPIC transfers): the free surface against eq:shallow, the position where the
   depth is y being x = L0 + (2 sqrt(g H0) - 3 sqrt(g y)) t, within 10 % of
   the distance the tip of the analytical wave has travelled,
   2 sqrt(g H0) t, at t = 0.3, 0.4 and 0.5 s (the paper reports agreement
@@ -105,10 +105,14 @@ def _surface_reach(cfg, x, y):
 
 
 @pytest.mark.parametrize("precision", ["f32"])
-def test_shallow_dam_break_against_eq_shallow(precision):
+@pytest.mark.parametrize("transfer", [W.APIC, W.FLIP, W.TPIC])
+def test_shallow_dam_break_against_eq_shallow(precision, transfer):
+    """Sec. 4.1.1 runs the shallow dam-break with FLIP, TPIC and APIC and
+    finds each close to eq:shallow from t = 0.3 s on."""
     cfg, x, H0, L0 = _shallow_setup()
+    cfg = cfg.replace(transfer=transfer)
     g = 9.8
-    print(f"[case] shallow dam-break, N={x.shape[1]}, {precision}", flush=True)
+    print(f"[case] shallow dam-break, {transfer}, N={x.shape[1]}, {precision}", flush=True)
     from paper_2507_04192_amd.native import Solver
     s = Solver(cfg, precision, capacity=x.shape[1])
     s.mpm_init_particles(x)

@@ -12,8 +12,8 @@ from tests.helpers import rel_l2
 
 pytestmark = pytest.mark.gpu
 
-ARCHS = [([2, 64, 64, 2], "none", 1.0, 0.0), ([2, 128, 128, 1], "sigmoid", 1.0, 0.0),
-         ([3, 16, 40, 5], "sigmoid", 0.7, 0.2)]
+ARCHS = [([2, 64, 64, 2], "none", 1.0, 0.0, "tanh"), ([2, 128, 128, 1], "sigmoid", 1.0, 0.0, "tanh"),
+         ([3, 16, 40, 5], "sigmoid", 0.7, 0.2, "tanh"), ([1, 30, 30, 30, 1], "none", 1.0, 0.0, "relu")]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -33,16 +33,17 @@ def _t(a):
 @pytest.mark.parametrize("n", [1000, 4099])
 def test_forward_backward_match_oracle(math, tol, arch, n):
     from paper_2507_04192_amd.native import MLP
-    widths, act, sc, sh = ARCHS[arch]
-    print(f"[case] mlp {widths} {act} {math} n={n}", flush=True)
+    widths, act, sc, sh, hid = ARCHS[arch]
+    print(f"[case] mlp {widths} {hid}/{act} {math} n={n}", flush=True)
     d_in = widths[0]
     rng = np.random.default_rng(100 + arch)
     lo, hi = -0.5, 2.0                       # raw inputs mapped to [-1, 1] in the kernel
     xs = 2.0 / (hi - lo)
     x = rng.uniform(lo, hi, size=(d_in, n)).astype(np.float32)
-    spec = OM.Spec(widths, act, sc, sh)
+    spec = OM.Spec(widths, act, sc, sh, hidden_act=hid)
     p = W.mlp_init_params(widths, 7 + arch)
-    net = MLP(widths, act, sc, sh, in_scale=[xs] * d_in, in_shift=[-1.0 - lo * xs] * d_in, math=math)
+    net = MLP(widths, act, sc, sh, in_scale=[xs] * d_in, in_shift=[-1.0 - lo * xs] * d_in, math=math,
+              hidden_act=hid)
     assert net.n_params == p.size
     y, cache = net.forward(_t(p), _t(x))
     xin = (xs * x.astype(np.float64) + (-1.0 - lo * xs)).T
@@ -53,7 +54,12 @@ def test_forward_backward_match_oracle(math, tol, arch, n):
     g_o = OM.backward(spec, p.astype(np.float64), acts, dy.T.astype(np.float64))
     eg = rel_l2(g, g_o)
     print(f"  y {e:.2e}  dparams {eg:.2e}", flush=True)
-    assert e <= tol and eg <= tol
+    # a ReLU's derivative jumps at z = 0: BF16 operands move pre-activations
+    # within their rounding of zero to the other side, switching those units
+    # for that sample, so the parameter gradient is not held to the smooth
+    # BF16 bound there (measured 3.2e-2 for the 1-30-30-30-1 network)
+    gtol = 5e-2 if (hid == "relu" and math == "bf16") else tol
+    assert e <= tol and eg <= gtol
 
 
 def test_adam_matches_oracle():
