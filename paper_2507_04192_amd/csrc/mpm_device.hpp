@@ -62,15 +62,18 @@ __device__ __forceinline__ int base_of(T x, T inv)
 template <class T, int D>
 __device__ __forceinline__ int cell_key(const Geo& g, const T* xp, T inv)
 {
+    // the tile edge is 4 cells in 3-D and 8 in 2-D (the configuration check
+    // admits no other), so the tile and cell coordinates are a shift and a mask
+    constexpr int TE = (D == 3) ? 4 : 8, SH = (D == 3) ? 2 : 3;
     int tl = 0, cl = 0, ts = 1, cs = 1;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         int B = base_of(xp[a], inv) + g.G;
         B = B < 0 ? 0 : (B > g.bmax[a] ? g.bmax[a] : B);   // memory guard only
-        tl += (B / g.T) * ts;
-        cl += (B % g.T) * cs;
+        tl += (B >> SH) * ts;
+        cl += (B & (TE - 1)) * cs;
         ts *= g.ntile[a];
-        cs *= g.T;
+        cs *= TE;
     }
     return tl * 64 + cl;
 }
@@ -626,7 +629,7 @@ __device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, co
     T trE = E.tr();
     Sym<T, D> Eh = E;
 #pragma unroll
-    for (int i = 0; i < D; ++i) Eh.a[i] -= trE / T(D);
+    for (int i = 0; i < D; ++i) Eh.a[i] -= trE * (T(1) / T(D));
     T n = sqrt(Eh.norm2());
     int cas = 1;
     T r = T(0);   // H = E - r * Ehat (cone), 0 (apex), E (elastic)
