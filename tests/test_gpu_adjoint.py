@@ -238,23 +238,29 @@ def _seg_grad(cfg, gnode, nseg=32, seg_len=0.0625):
     return np.bincount(idx, weights=gnode, minlength=nseg)
 
 
-def test_friction_inverse_full_size_vs_oracle(orc):
-    """Full particle count, 100 steps (checkpoint every 50), binary64: HIP
-    gradient against the oracle's reverse sweep.  The column starts sliding
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_friction_inverse_full_size_vs_oracle(orc, precision):
+    """Full particle count, 100 steps (checkpoint every 50): HIP gradient
+    against the oracle's binary64 reverse sweep (binary64 to 1e-8, binary32
+    to 5e-3, both from the same rounded inputs).  The column starts sliding
     at 0.5 m/s so that the floor friction acts from the first step."""
     from paper_2507_04192_amd.native import Solver
     cfg, x0, tr, mu_true, mu_eval = _c2_setup()
     steps, frames = 100, [50, 100]
     v0 = np.zeros_like(x0)
     v0[0] = 0.5
-    print(f"[case] friction inverse full size N={x0.shape[1]} steps={steps}", flush=True)
+    if precision == "f32":
+        x0, mu_true, mu_eval = (a.astype(np.float32).astype(np.float64) for a in (x0, mu_true, mu_eval))
+    print(f"[case] friction inverse full size {precision} N={x0.shape[1]} steps={steps}", flush=True)
     _, _, qs = orc.rollout(cfg, x0, v0, steps, cfg.dt, mu_true,
                            orc.Observations(frames, tr, "x", np.zeros((2, 2, 64))))
     rng = np.random.default_rng(90)
     tgt = np.stack([q[0] for q in qs]) + rng.normal(0, 1e-3, size=(2, 2, 64))
+    if precision == "f32":
+        tgt = tgt.astype(np.float32).astype(np.float64)
     obs_o = orc.Observations(frames, tr, "x", tgt)
     loss_o, gv_o, gmu_o = orc.rollout_grad(cfg, x0, v0, steps, cfg.dt, mu_eval, obs_o)
-    s = Solver(cfg, "f64", capacity=x0.shape[1], tape_steps=steps, ckpt_every=50)
+    s = Solver(cfg, precision, capacity=x0.shape[1], tape_steps=steps, ckpt_every=50)
     s.mpm_init_particles(x0, v0)
     s.mpm_set_floor_mu(mu_eval)
     s.mpm_set_observations(frames=frames, tracer_pid=tr, lag_field="x", lag_target=tgt)
@@ -263,9 +269,10 @@ def test_friction_inverse_full_size_vs_oracle(orc):
     gv, gmu = _np(gv), _np(gmu)
     print(f"  loss {loss:.4e}: {abs(loss - loss_o) / loss_o:.2e}; dL/dv0 {rel_l2(gv, gv_o):.2e}; "
           f"dL/dmu {rel_l2(gmu, gmu_o):.2e}", flush=True)
-    assert abs(loss - loss_o) <= 1e-10 * loss_o
-    assert rel_l2(gv, gv_o) <= 1e-8
-    assert rel_l2(gmu, gmu_o) <= 1e-8
+    tol = 1e-8 if precision == "f64" else 5e-3
+    assert abs(loss - loss_o) <= (1e-10 if precision == "f64" else 1e-4) * loss_o
+    assert rel_l2(gv, gv_o) <= tol
+    assert rel_l2(gmu, gmu_o) <= tol
     assert np.abs(gmu_o).max() > 0
     # the flow has not reached the far segments: their gradient is exactly 0
     assert _seg_grad(cfg, gmu)[-1] == 0.0 and _seg_grad(cfg, gmu_o)[-1] == 0.0
