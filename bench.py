@@ -143,13 +143,17 @@ def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every
                             f"gradients wrt v0 and the floor friction field"}, prof
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cylinder_f32.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cylinder.txt")
 
 
-# The binary32 3-D sand kernels behind each timed class.
-TRAFFIC_KERNELS = {"p2g": ["k_p2g<float, 3, 1>"], "g2p": ["k_g2p<float, 3, 1>"],
-                   "g2p_adj": ["k_g2p_adj<float, 3, 1>"],
-                   "p2g_adj": ["k_p2g_adj<float, 3, 1>"]}
+def traffic_kernels(cls, elem):
+    """The 3-D sand kernels behind a timed class (template arguments:
+    precision, dimension, material, then FLIP for P2G and the transfer for
+    G2P)."""
+    t = "float" if elem == 4 else "double"
+    names = {"p2g": f"k_p2g<{t}, 3, 1, false>", "g2p": f"k_g2p<{t}, 3, 1, 0>",
+             "g2p_adj": f"k_g2p_adj<{t}, 3, 1>", "p2g_adj": f"k_p2g_adj<{t}, 3, 1>"}
+    return [names.get(cls, cls)]
 
 
 def measured_traffic(kernels):
@@ -359,7 +363,7 @@ def main():
         f"(no events: {t32_noev / args.steps * 1e3:.4f} ms/step)")
     dom, kernels, roof = roofline(prof32, n, 4)
     if args.scale_div == 1:
-        roof["traffic"] = measured_traffic(TRAFFIC_KERNELS.get(dom, dom))
+        roof["traffic"] = measured_traffic(traffic_kernels(dom, 4))
     for k, v in kernels.items():
         log(f"[bench]   {k:7s} {v['avg_ms'] * 1e3:9.2f} us/launch" +
             (f"  {v['gbs']:8.1f} GB/s algorithmic" if "gbs" in v else ""))
@@ -368,7 +372,9 @@ def main():
     if not args.no_f64:
         k64 = args.f64_steps or max(1, args.steps // 2)
         t64, t64_noev, prof64 = run_gpu(cfg, x, "f64", k64, args.warmup)
-        _, kern64, roof64 = roofline(prof64, n, 8)
+        dom64, kern64, roof64 = roofline(prof64, n, 8)
+        if args.scale_div == 1:
+            roof64["traffic"] = measured_traffic(traffic_kernels(dom64, 8))
         out_f64 = {"value": n * k64 / t64, "unit": "particle-steps/s", "steps": k64,
                    "ms_per_step": t64 / k64 * 1e3, "ms_per_step_no_events": t64_noev / k64 * 1e3,
                    "hbm_frac_step": n * k64 / t64 * STEP_SCALARS * 8 / (HBM_PEAK_GBS * 1e9),
@@ -388,8 +394,8 @@ def main():
             torch.cuda.reset_peak_memory_stats()
             r, prof = run_adjoint(cfg, x, prec, T, args.adj_ckpt)
             dom_a, kern, roof_a = roofline({k: prof[k] for k in ("g2p_adj", "p2g_adj") if k in prof}, n, elem)
-            if prec == "f32" and args.scale_div == 1:
-                roof_a["traffic"] = measured_traffic(TRAFFIC_KERNELS.get(dom_a, dom_a))
+            if args.scale_div == 1:
+                roof_a["traffic"] = measured_traffic(traffic_kernels(dom_a, elem))
             r["roofline"] = roof_a
             r["step_roofline"] = step_roofline(r["value"], ADJ_STEP_SCALARS, elem)
             # the forward step runs twice (rollout, segment recompute) and the

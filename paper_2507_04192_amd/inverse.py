@@ -156,7 +156,7 @@ def learned_velocity_2d(epochs: int = 60, seed: int = 5, math: str = "bf16", mlp
 
 
 def learned_friction_3d(scale_div: int = 1, epochs: int = 30, steps: int = 2000, ckpt_every: int = 100,
-                        n_tracers: int = 500, frame_every: int = 100, seed: int = 8, math: str = "bf16",
+                        n_tracers: int = 500, frame_every: int = 20, seed: int = 8, math: str = "bf16",
                         mlp_lr: float = 3e-3, mlp_decay: float = 0.99, cell_lr: float = 0.02,
                         cell_decay: float = 0.98, cells=(48, 24), log_every: int = 0):
     """Hidden base friction under a 3-D dam-break: mu(x, y) = 0.3 + 0.2

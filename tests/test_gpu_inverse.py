@@ -55,3 +55,23 @@ def test_learned_friction_small_dam_break():
     assert m["loss"][-1] < 0.5 * m["loss"][0] and c["loss"][-1] < 0.5 * c["loss"][0]
     assert m["field_err"] < 0.6 * m["start_err"]
     assert m["field_err"] < c["field_err"]
+
+
+def test_learned_friction_full_size():
+    """The learned base-friction problem at its full size (1,843,200
+    particles, 192 x 96 x 64 cells, 2000 steps, checkpoint every 100) with
+    500 tracers observed every 20 steps (100 frames): network and table
+    from mu = 0.5 for 20 epochs each."""
+    from paper_2507_04192_amd import inverse as I
+    print("[case] learned friction, full 3-D dam-break, frames every 20 steps", flush=True)
+    r = I.learned_friction_3d(scale_div=1, steps=2000, epochs=20)
+    m, c = r["mlp"], r["cells"]
+    print(f"  network: field error {m['start_err']:.3f} -> {m['field_err']:.3f}, loss {m['loss'][0]:.3e} -> "
+          f"{m['loss'][-1]:.3e} ({m['seconds']:.1f} s)", flush=True)
+    print(f"  table:   field error {m['start_err']:.3f} -> {c['field_err']:.3f}, loss {c['loss'][0]:.3e} -> "
+          f"{c['loss'][-1]:.3e} ({c['seconds']:.1f} s)", flush=True)
+    print(f"  workspace {r['workspace_bytes'] / 2**30:.1f} GiB, high-water mark "
+          f"{r['max_memory_allocated'] / 2**30:.1f} GiB", flush=True)
+    assert m["loss"][-1] < 0.5 * m["loss"][0] and c["loss"][-1] < 0.5 * c["loss"][0]
+    assert m["field_err"] < 0.75 * m["start_err"]
+    assert m["field_err"] < c["field_err"]
