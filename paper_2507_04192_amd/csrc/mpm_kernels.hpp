@@ -48,6 +48,23 @@ template <class T> constexpr int kG2PBlock = sizeof(T) == 8 ? 128 : 256;
 template <class T> constexpr bool kG2PPrefetch = sizeof(T) == 8;
 constexpr int kGridBlock = 128;  // threads of a grid-update workgroup
 
+// Particle data read once per step (P2G's inputs, G2P's old state) and the
+// part of G2P's output that no later kernel of the step reads (F or J, pid)
+// go through the non-temporal cache hint.  Measured on the 3-D cylinder:
+// binary32 P2G 106 -> 98 us, G2P 140 -> 137 us, binary64 P2G 200 -> 192,
+// G2P 256 -> 246; the hint on the stores that P2G reads next (x, v, C, the
+// stress cache) made G2P slower, so those stay ordinary stores.
+template <class T>
+__device__ __forceinline__ T ld_once(const T* p)
+{
+    return __builtin_nontemporal_load(p);
+}
+template <class T>
+__device__ __forceinline__ void st_late(T v, T* p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
 // Active-list entry handled by this workgroup on iteration `it`.  Workgroup b
 // runs on XCD b % 8; each XCD gets one contiguous chunk of the active list so
 // that neighbouring tiles share that XCD's L2.
@@ -257,13 +274,13 @@ struct P2GIn {
     {
         const long long cap = cur.cap;
 #pragma unroll
-        for (int a = 0; a < D; ++a) x[a] = cur.x[a * cap + j];
+        for (int a = 0; a < D; ++a) x[a] = ld_once(&cur.x[a * cap + j]);
 #pragma unroll
-        for (int a = 0; a < NA; ++a) v[a] = cur.v[(A0 + a) * cap + j];
+        for (int a = 0; a < NA; ++a) v[a] = ld_once(&cur.v[(A0 + a) * cap + j]);
 #pragma unroll
-        for (int q = 0; q < NA * D; ++q) C[q] = cur.C[(A0 * D + q) * cap + j];
+        for (int q = 0; q < NA * D; ++q) C[q] = ld_once(&cur.C[(A0 * D + q) * cap + j]);
 #pragma unroll
-        for (int q = 0; q < NS; ++q) S[q] = cur.S[q * cap + j];
+        for (int q = 0; q < NS; ++q) S[q] = ld_once(&cur.S[q * cap + j]);
     }
 };
 
@@ -902,12 +919,12 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
             int newkey = 0;
             if (valid) {
                 long long s = at.off + k;
-                int j = perm[s];
+                int j = ld_once(&perm[s]);
                 T xp[D], w[D][3], dw[D][3], dd[D][3];
                 int lb[3] = {0, 0, 0};
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    xp[a] = cur.x[a * cap + j];
+                    xp[a] = ld_once(&cur.x[a * cap + j]);
                     int b;
                     T f;
                     stencil_axis(xp[a], P.inv, b, f, w[a], dw[a]);
@@ -994,20 +1011,20 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                     }
                 }
                 if constexpr (MAT == MAT_FLUID) {
-                    T dJ = cur.G[j], si;
+                    T dJ = ld_once(&cur.G[j]), si;
                     fluid_update<T, D>(P, Lm, dJ, si);
                     bad |= !finite(si) || !finite(dJ);
-                    nxt.G[s] = dJ;
+                    st_late(dJ, &nxt.G[s]);
                     nxt.S[s] = si;
                 } else if constexpr (MAT == MAT_VFLUID || MAT == MAT_JAUMANN) {
-                    T dJ = cur.G[j], Sv[NS];
+                    T dJ = ld_once(&cur.G[j]), Sv[NS];
                     if constexpr (MAT == MAT_JAUMANN)   // the viscous fluid's stress is a function of J and L
 #pragma unroll
                         for (int q = 0; q < NS; ++q) Sv[q] = cur.S[q * cap + j];
                     if constexpr (MAT == MAT_VFLUID) vfluid_update<T, D>(P, Lm, dJ, Sv);
                     else jaumann_update<T, D>(P, Lm, dJ, Sv);
                     bad |= !finite(dJ);
-                    nxt.G[s] = dJ;
+                    st_late(dJ, &nxt.G[s]);
 #pragma unroll
                     for (int q = 0; q < NS; ++q) {
                         bad |= !finite(Sv[q]);
@@ -1018,20 +1035,20 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
 #pragma unroll
                     for (int a = 0; a < D; ++a)
 #pragma unroll
-                        for (int b = 0; b < D; ++b) Gm[a][b] = cur.G[(a * D + b) * cap + j];
+                        for (int b = 0; b < D; ++b) Gm[a][b] = ld_once(&cur.G[(a * D + b) * cap + j]);
                     noconv = !hencky_update<T, D>(P, MAT == MAT_SAND, Lm, Gm, Sv);
 #pragma unroll
                     for (int a = 0; a < D; ++a)
 #pragma unroll
-                        for (int b = 0; b < D; ++b) nxt.G[(a * D + b) * cap + s] = Gm[a][b];
+                        for (int b = 0; b < D; ++b) st_late(Gm[a][b], &nxt.G[(a * D + b) * cap + s]);
 #pragma unroll
                     for (int q = 0; q < NS; ++q) {
                         bad |= !finite(Sv[q]);
                         nxt.S[q * cap + s] = Sv[q];
                     }
                 }
-                int pid = cur.pid[j];
-                nxt.pid[s] = pid;
+                int pid = ld_once(&cur.pid[j]);
+                st_late(pid, &nxt.pid[s]);
                 if (bad) {
                     atomicOr(&status[0], 1);
                     atomicMin(&status[1], pid);
