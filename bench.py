@@ -14,6 +14,11 @@ The forward+adjoint leg times a checkpointed rollout with a tracer loss and
 its backward sweep on the same cylinder (FP32 and FP64; 1000 steps with a
 checkpoint every 100 by default).
 
+The variants leg times the other forms of the step: the cylinder with the
+hypoelastic Drucker-Prager material (Jaumann rate, App. A) and with the PIC,
+TPIC and FLIP transfers, and the 3-D dam-break against two rigid columns
+with a viscous fluid (Sec. 4.2.1, 1,920,000 particles on 200 x 100 x 80).
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -216,6 +221,52 @@ def roofline(prof, n_particles, elem):
     }
 
 
+# State scalars per particle of each form of the step (3-D), read once and
+# written once per step: the carried state of the method, nothing else.
+#   sand, APIC or TPIC: x v C F          3 + 3 + 9 + 9 = 24
+#   sand, PIC or FLIP (no carried C):   x v F            15
+#   hypoelastic D-P: x v C J sigma      3 + 3 + 9 + 1 + 6 = 22
+#   (viscous) fluid: x v C J            16
+VARIANT_STATE_SCALARS = {"sand_apic": 24, "sand_tpic": 24, "sand_pic": 15, "sand_flip": 15,
+                         "dp_jaumann": 22, "fluid": 16}
+
+
+def run_variants(steps, steps64, warmup):
+    """Forward throughput of the other forms of the step, each at full size in
+    the bench's launch configuration."""
+    from paper_2507_04192_amd import workloads as W
+    cyl, xc = W.cylinder_collapse_3d(seed=0)
+    col, xd = W.dam_break_columns_3d(seed=0)
+    legs = [
+        ("cylinder, hypoelastic Drucker-Prager (Jaumann rate, App. A)", "dp_jaumann",
+         cyl.replace(material=W.DP_JAUMANN), xc, ("f32", "f64")),
+        ("cylinder, PIC transfer", "sand_pic", cyl.replace(transfer=W.PIC), xc, ("f32",)),
+        ("cylinder, TPIC transfer", "sand_tpic", cyl.replace(transfer=W.TPIC), xc, ("f32",)),
+        ("cylinder, FLIP/PIC blend alpha = 0.95", "sand_flip", cyl.replace(transfer=W.FLIP, flip_alpha=0.95), xc,
+         ("f32",)),
+        ("3-D dam-break against two rigid columns, viscous fluid (Sec. 4.2.1)", "fluid", col, xd, ("f32", "f64")),
+    ]
+    out = []
+    for name, form, cfg, x, precs in legs:
+        n = x.shape[1]
+        r = {"workload": name, "particles": n, "grid": list(cfg.n)}
+        for prec in precs:
+            elem = 4 if prec == "f32" else 8
+            k = steps if prec == "f32" else steps64
+            t, _, prof = run_gpu(cfg, x, prec, k, warmup)
+            val = n * k / t
+            r[prec] = {"value": val, "unit": "particle-steps/s", "steps": k, "ms_per_step": t / k * 1e3,
+                       "step_roofline": step_roofline(val, 2 * VARIANT_STATE_SCALARS[form], elem),
+                       "kernels_us": {kk: round(v[0] / v[1] * 1e3, 2) for kk, v in prof.items() if v[1] > 0}}
+            log(f"[bench] variant {name} {prec}: {t / k * 1e3:.4f} ms/step, {val:.4e} particle-steps/s")
+        if form == "fluid":
+            r["paper_context"] = {"value_f32": 1920000 * 1000 / 8.2, "value_f64": 1920000 * 1000 / 35.1,
+                                  "note": "paper, one A100: 8.2 / 35.1 s per 1000 steps on the same "
+                                          "particle count and grid"}
+        out.append(r)
+    return out
+
+
 def step_roofline(value, scalars, elem):
     """The whole step against HBM: the algorithmic bytes per particle-step
     (the state read once and written once; forward+adjoint: two forward
@@ -336,6 +387,8 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=1000, help="rollout length of the forward+adjoint leg")
     ap.add_argument("--adj-ckpt", type=int, default=100, help="checkpoint interval of the forward+adjoint leg")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other forms of the step")
+    ap.add_argument("--variant-steps", type=int, default=500, help="binary32 steps per variant (binary64: half)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--scale-div", type=int, default=1, help="shrink the cylinder (tests only)")
@@ -409,6 +462,10 @@ def main():
             for k, v in r["kernels_us"].items():
                 log(f"[bench]   {k:8s} {v:9.2f} us/launch")
 
+    variants = None
+    if not args.no_variants and args.scale_div == 1:
+        variants = run_variants(args.variant_steps, max(1, args.variant_steps // 2), args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] timing the oracle for {args.cpu_steps} step(s) on the host ...")
@@ -442,6 +499,7 @@ def main():
         "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kernels.items()},
         "f64": out_f64,
         "fwd_adjoint": adj,
+        "variants": variants,
         "paper_context": {"value_f32": 1.22e8, "value_f64": 2.76e7,
                           "note": "paper, one A100, 2,712,960-particle cylinder on 400x400x100; "
                                   "a different machine and grid, not this workload"},

@@ -737,7 +737,7 @@ __device__ __forceinline__ void wall_node(int mode, T mu, int axis, T sign, T v[
 // to the first face in the order x-, x+, y-, y+, z-, z+).  xi: the node's
 // position.
 template <class T, int D>
-__device__ __forceinline__ void obstacle_node(const Phys<T>& P, const T xi[D], T v[D])
+__device__ __forceinline__ void obstacle_node(const Phys<T>& P, const double xi[D], T v[D])
 {
     for (int o = 0; o < P.n_obst; ++o) {
         bool inside = true;
@@ -745,12 +745,12 @@ __device__ __forceinline__ void obstacle_node(const Phys<T>& P, const T xi[D], T
         for (int a = 0; a < D; ++a) inside &= xi[a] >= P.obst_lo[o][a] && xi[a] <= P.obst_hi[o][a];
         if (!inside) continue;
         int best = -1;
-        T bd = T(0);
+        double bd = 0.0;
 #pragma unroll
         for (int f = 0; f < 2 * D; ++f) {
             if (!((P.obst_face_ok[o] >> f) & 1)) continue;
             const int a = f >> 1;
-            const T depth = (f & 1) ? P.obst_hi[o][a] - xi[a] : xi[a] - P.obst_lo[o][a];
+            const double depth = (f & 1) ? P.obst_hi[o][a] - xi[a] : xi[a] - P.obst_lo[o][a];
             if (best < 0 || depth < bd) {
                 best = f;
                 bd = depth;

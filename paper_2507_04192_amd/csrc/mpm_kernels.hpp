@@ -805,9 +805,9 @@ __global__ __launch_bounds__(kGridBlock) void k_grid(Geo g, Phys<T> P, const int
                     if (ip >= g.n[a]) wall_node<T, D>(P.wall_mode[2 * a + 1], P.wall_mu[2 * a + 1], a, T(1), v);
                 }
                 if (P.n_obst > 0) {
-                    T xi[D];
+                    double xi[D];
 #pragma unroll
-                    for (int a = 0; a < D; ++a) xi[a] = T(I[a] - g.G) * P.h;
+                    for (int a = 0; a < D; ++a) xi[a] = double(I[a] - g.G) * P.obst_h;
                     obstacle_node<T, D>(P, xi, v);
                 }
             } else if (gvt) {
@@ -1259,11 +1259,12 @@ Phys<T> make_phys(const mpm_ctx* c, double dt)
         P.jband2 = (T)(1e-6 * E * 1e-6 * E);
     }
     P.n_obst = k.n_obstacles;
+    P.obst_h = k.dx;
     for (int o = 0; o < kMaxObstacles; ++o) {
         int ok = 0;
         for (int a = 0; a < 3; ++a) {
-            P.obst_lo[o][a] = (T)k.obst_lo[o][a];
-            P.obst_hi[o][a] = (T)k.obst_hi[o][a];
+            P.obst_lo[o][a] = k.obst_lo[o][a];
+            P.obst_hi[o][a] = k.obst_hi[o][a];
             if (a < D) {
                 double ext = (double)k.n[a] * k.dx;
                 if (k.obst_lo[o][a] > 0.0) ok |= 1 << (2 * a);        // lower face inside the domain

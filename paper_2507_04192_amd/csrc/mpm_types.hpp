@@ -60,7 +60,11 @@ struct Phys {
     // resting rigid boxes (Sec. 4.2.1); face_ok bit 2a+s: face (axis a,
     // side s) is not on the domain boundary
     int n_obst;
-    T obst_lo[kMaxObstacles][3], obst_hi[kMaxObstacles][3];
+    // obstacle boxes and the cell size in binary64 in both precisions: which
+    // nodes lie in a box and which face is nearest are decided as the
+    // reference decides them, not by binary32 rounding of positions that sit
+    // on a face
+    double obst_lo[kMaxObstacles][3], obst_hi[kMaxObstacles][3], obst_h;
     int obst_face_ok[kMaxObstacles];
 };
 

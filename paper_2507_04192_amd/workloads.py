@@ -280,6 +280,32 @@ def dam_break_3d(scale_div: int = 1, seed: int = 0):
     return cfg, x
 
 
+def dam_break_columns_3d(scale_div: int = 1, seed: int = 0):
+    """3-D dam-break against two rigid square columns (Sec. 4.2.1):
+    domain 1.0 x 0.5 x 0.4 m at dx = 0.005 m (200 x 100 x 80 cells), water
+    column L0 x W0 x H0 = 0.3 x 0.5 x 0.2 m at 8 particles per cell
+    (1,920,000 particles), weakly compressible Newtonian fluid with
+    mu = 1.01e-3 Pa s and sound speed 35 m/s (Tait, gamma 7, K = rho c^2),
+    gravity -z, slip walls, dt = 4e-5 s (0.28 of the acoustic limit dx/c).
+    The columns have sides 0.04 and 0.06 m, stand on the floor through the
+    domain's height, and are centred at (0.5, 0.3) and (0.6, 0.1) m.
+    scale_div shrinks every length by that factor at the same dx."""
+    s = scale_div
+    n = (200 // s, 100 // s, 80 // s)
+    dx = 0.005
+    c = 35.0
+    zt = n[2] * dx
+    cols = []
+    for (cx, cy), side in (((0.5, 0.3), 0.04), ((0.6, 0.1), 0.06)):
+        r = 0.5 * side / s
+        cols.append(((cx / s - r, cy / s - r, 0.0), (cx / s + r, cy / s + r, zt)))
+    cfg = SimConfig(dim=3, n=n, dx=dx, dt=4e-5, material=FLUID, ppc=8, gravity=(0.0, 0.0, -9.81),
+                    rho0=1000.0, bulk=1000.0 * c * c, gamma=7.0, viscosity=1.01e-3, obstacles=tuple(cols))
+    hi = (0.3 / s, 0.5 / s, 0.2 / s)
+    x = lattice_particles(cfg, box_inside((0, 0, 0), hi), (0, 0, 0), hi, seed)
+    return cfg, x
+
+
 def floor_node_coords(cfg: SimConfig) -> np.ndarray:
     """Positions (x, y) of the floor nodes in the order of the per-node
     friction array (x fastest), shape (2, n_floor)."""

@@ -387,16 +387,23 @@ def test_step_is_deterministic(orc, precision):
         assert np.array_equal(out[0][f], out[1][f]), f
 
 
-@pytest.mark.parametrize("case", ["cylinder", "dambreak3d"])
+@pytest.mark.parametrize("case", ["cylinder", "dambreak3d", "cylinder_jaumann", "columns"])
 def test_full_size_steps_match_oracle(orc, case):
     """Full-size workloads in the launch configuration the bench times: the
-    3-D cylinder collapse (2,780,928 particles, Drucker-Prager sand) and the
-    3-D dam-break of the friction problem (1,843,200 particles, fluid).
-    Ten steps in binary64 and binary32 against one oracle run from the
-    same binary32-rounded input, whole arrays compared (positions,
+    3-D cylinder collapse (2,780,928 particles, Drucker-Prager sand with the
+    Hencky return, and with the hypoelastic material of App. A), the 3-D
+    dam-break of the friction problem (1,843,200 particles, fluid) and the
+    3-D dam-break against two columns (1,920,000 particles, viscous fluid,
+    Sec. 4.2.1).  Ten steps in binary64 and binary32 against one oracle run
+    from the same binary32-rounded input, whole arrays compared (positions,
     displacements, velocities)."""
     from paper_2507_04192_amd.native import Solver
-    cfg, x = (W.cylinder_collapse_3d(scale_div=1, seed=0) if case == "cylinder" else W.dam_break_3d())
+    if case.startswith("cylinder"):
+        cfg, x = W.cylinder_collapse_3d(scale_div=1, seed=0)
+        if case == "cylinder_jaumann":
+            cfg = cfg.replace(material=W.DP_JAUMANN)
+    else:
+        cfg, x = W.dam_break_3d() if case == "dambreak3d" else W.dam_break_columns_3d()
     x = x.astype(np.float32).astype(np.float64)
     N = x.shape[1]
     steps = 10

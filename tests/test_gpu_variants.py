@@ -272,6 +272,28 @@ def test_obstacles_dam_break_3d(orc, precision):
     _run_pair(orc, cfg, precision, x, v, steps=20)
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_dam_break_columns_paper_geometry(orc, precision):
+    """The paper's 3-D dam-break against two square columns (Sec. 4.2.1)
+    with its viscous fluid, at 1/4 scale (30,000 particles), the water
+    pushed towards the columns at a quarter cell per step so that its front
+    (9 cells away) meets them: 50 steps against the oracle, and no particle
+    more than a cell inside the wider column (3 cells across at this scale;
+    the oracle puts 39 particles there without the obstacles)."""
+    cfg, x = W.dam_break_columns_3d(scale_div=4, seed=0)
+    h = cfg.dx
+    print(f"[case] paper's columns, 3-D dam-break / 4, viscous, {precision} N={x.shape[1]}", flush=True)
+    v = _moving_velocity(cfg, x, frac=0.05)
+    v[0] = np.abs(v[0]) + 0.25 * h / cfg.dt
+    g, _, _ = _run_pair(orc, cfg, precision, x, v, steps=50)
+    assert g["x"][0].max() > cfg.obstacles[0][0][0]       # the front has reached the first column
+    lo, hi = cfg.obstacles[1]
+    deep = np.ones(g["x"].shape[1], dtype=bool)
+    for a in range(2):
+        deep &= (g["x"][a] > lo[a] + h) & (g["x"][a] < hi[a] - h)
+    assert not deep.any()
+
+
 def test_reverse_sweep_refuses_other_forms():
     """mpm_forward_loss covers the APIC transfer without obstacles for the
     inviscid fluid, the Hencky materials and the hypoelastic Drucker-Prager
