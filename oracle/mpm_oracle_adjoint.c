@@ -457,6 +457,85 @@ static void jaumann_tangent(const orc_config* c, double dt, const double S[3][3]
     *dJo = dJn;
 }
 
+/* Directional derivative of the Newtonian fluid update of one particle
+ * (Sec. 2.3 eq:stress_strain; the forward map is orc_constitutive's fluid
+ * branch with orc_fluid_stress): inputs J and the velocity gradient L,
+ * outputs J' = J det(I + dt L) and S' = V0 tau(J', L) with
+ * tau = J' (-p(J') I + 2 mu (d - tr(d)/dim I)), d = (L + L^T)/2, along
+ * (dJ, dL).  d det(M)[dM] = cof(M) : dM, and p'(J) = -K J^(-gamma-1). */
+static void viscous_tangent(const orc_config* c, double dt, double J, const double L[3][3], double dJ,
+                            const double dL[3][3], double dS[3][3], double* dJo)
+{
+    int d = c->dim;
+    double M[3][3] = {{0}}, cof[3][3] = {{0}};
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) M[a][b] = (a == b ? 1.0 : 0.0) + dt * L[a][b];
+    double detM;
+    if (d == 2) {
+        cof[0][0] = M[1][1]; cof[0][1] = -M[1][0];
+        cof[1][0] = -M[0][1]; cof[1][1] = M[0][0];
+        detM = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+    } else {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+                cof[i][j] = M[i1][j1] * M[i2][j2] - M[i1][j2] * M[i2][j1];
+            }
+        detM = M[0][0] * cof[0][0] + M[0][1] * cof[0][1] + M[0][2] * cof[0][2];
+    }
+    double ddet = 0.0;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) ddet += cof[a][b] * dt * dL[a][b];
+    double Jn = J * detM, dJn = dJ * detM + J * ddet;
+    *dJo = dJn;
+    double pr = orc_fluid_pressure(c, Jn);
+    double dpr = -c->bulk * pow(Jn, -c->gamma - 1.0) * dJn;
+    double tr = 0.0, dtr = 0.0;
+    for (int a = 0; a < d; ++a) {
+        tr += L[a][a];
+        dtr += dL[a][a];
+    }
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            double sig = 2.0 * c->viscosity * 0.5 * (L[a][b] + L[b][a]);
+            double dsig = 2.0 * c->viscosity * 0.5 * (dL[a][b] + dL[b][a]);
+            if (a == b) {
+                sig += -pr - 2.0 * c->viscosity * tr / d;
+                dsig += -dpr - 2.0 * c->viscosity * dtr / d;
+            }
+            dS[a][b] = c->vol0 * (dJn * sig + Jn * dsig);
+        }
+}
+
+/* Which velocity component the resting obstacle o removes at node I moving
+ * with vel (orc_obstacles' rule for one obstacle), or -1. */
+static int obstacle_component(const orc_config* c, int o, const int32_t I[3], const double vel[3])
+{
+    int d = c->dim;
+    double xi[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) {
+        xi[a] = (double)(I[a] - c->ghost) * c->dx;
+        if (xi[a] < c->obst_lo[o][a] || xi[a] > c->obst_hi[o][a]) return -1;
+    }
+    int best_a = -1, best_side = 0;
+    double best = 0.0;
+    for (int a = 0; a < d; ++a)
+        for (int side = 0; side < 2; ++side) {
+            double face = side == 0 ? c->obst_lo[o][a] : c->obst_hi[o][a];
+            double ext = (double)c->n[a] * c->dx;
+            if ((side == 0 && face <= 0.0) || (side == 1 && face >= ext)) continue;
+            double depth = side == 0 ? xi[a] - face : face - xi[a];
+            if (best_a < 0 || depth < best) {
+                best = depth;
+                best_a = a;
+                best_side = side;
+            }
+        }
+    if (best_a < 0) return -1;
+    double vn = best_side == 0 ? vel[best_a] : -vel[best_a];
+    return vn > 0.0 ? best_a : -1;
+}
+
 /* ------------------------------------------------------------------ */
 /* One step's vector-Jacobian product                                   */
 /* ------------------------------------------------------------------ */
@@ -473,11 +552,12 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
     const int fluid = c->material == ORC_FLUID;
     const int jaumann = c->material == ORC_DP_JAUMANN;
     const int carries_j = fluid || jaumann;
-    /* the reverse sweep covers the APIC transfer without obstacles, the
-     * inviscid fluid, the Hencky materials and the hypoelastic
-     * Drucker-Prager material; other settings are refused */
-    if (c->transfer != ORC_APIC || c->viscosity != 0.0 || c->n_obstacles > 0)
+    /* the reverse sweep covers the APIC, PIC and TPIC transfers, resting
+     * obstacles, the (viscous) fluid, the Hencky materials and the
+     * hypoelastic Drucker-Prager material; FLIP is refused */
+    if (c->transfer == ORC_FLIP)
         return -2;
+    const int viscous = fluid && c->viscosity != 0.0;
     int32_t dims[3];
     int64_t NN = orc_node_dims(c, dims);
     size_t NP = (size_t)(N > 0 ? N : 1);
@@ -549,6 +629,10 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                             wall_fwd(d, c->wall_mode[2 * a + side], mu, nrm, vel);
                         }
                     }
+                    for (int o = 0; o < c->n_obstacles; ++o) {
+                        int a = obstacle_component(c, o, I, vel);
+                        if (a >= 0) vel[a] = 0.0;
+                    }
                 }
                 for (int a = 0; a < d; ++a) gv[a * NN + li] = vel[a];
             }
@@ -616,6 +700,27 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                     Lb[p][q] = sum;
                 }
             jaumann_tangent(c, dt, Sp, Jm[s], Lp, zero, 1.0, zero, dSo, &dJo);
+            double sum = aJ1[s] * dJo;
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) sum += aS1[(a * d + b) * N + s] * dSo[a][b];
+            aJs[s] = sum;
+        } else if (viscous) {
+            /* contract the output adjoints (S', J') with the tangent along
+             * every input direction: J and the L entries */
+            double Lp[3][3] = {{0}}, zero[3][3] = {{0}}, dSo[3][3], dJo;
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) Lp[a][b] = L[a][b];
+            for (int p = 0; p < d; ++p)
+                for (int q = 0; q < d; ++q) {
+                    double e[3][3] = {{0}};
+                    e[p][q] = 1.0;
+                    viscous_tangent(c, dt, Jm[s], Lp, 0.0, e, dSo, &dJo);
+                    double sum = aJ1[s] * dJo;
+                    for (int a = 0; a < d; ++a)
+                        for (int b = 0; b < d; ++b) sum += aS1[(a * d + b) * N + s] * dSo[a][b];
+                    Lb[p][q] = sum;
+                }
+            viscous_tangent(c, dt, Jm[s], Lp, 1.0, zero, dSo, &dJo);
             double sum = aJ1[s] * dJo;
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b) sum += aS1[(a * d + b) * N + s] * dSo[a][b];
@@ -694,6 +799,13 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                 vb[a] += dt * ax1[a * N + s];
             }
         }
+        /* the carried matrix: APIC's C' = Dinv sum phi v_i (x_i - x_p)^T,
+         * TPIC's C' = L (its adjoint joins the constitutive L adjoint),
+         * PIC's C' = 0 (no adjoint flows back) */
+        const int apic = c->transfer == ORC_APIC;
+        if (c->transfer == ORC_TPIC)
+            for (int a = 0; a < d; ++a)
+                for (int b = 0; b < d; ++b) Lb[a][b] += aC1[(a * d + b) * N + s];
         /* G2P reverse */
         for (int k2 = 0; k2 < kz_max; ++k2)
             for (int k1 = 0; k1 < 3; ++k1)
@@ -709,7 +821,7 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                         double acc = phi * vb[a];
                         wb += vi * vb[a];
                         for (int b = 0; b < d; ++b) {
-                            double cb = aC1[(a * d + b) * N + s];
+                            double cb = apic ? aC1[(a * d + b) * N + s] : 0.0;
                             acc += Dinv * phi * cb * dp[b] + Lb[a][b] * g[b];
                             wb += Dinv * cb * vi * dp[b];
                             db[b] += Dinv * phi * cb * vi;
@@ -755,8 +867,20 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                         wall_fwd(d, c->wall_mode[2 * a + side], mu, nrm, vel);
                     }
                 }
+                /* the obstacles, after the walls: each keeps its input velocity */
+                double vob[ORC_MAX_OBSTACLES][3];
+                for (int o = 0; o < c->n_obstacles; ++o) {
+                    for (int q = 0; q < 3; ++q) vob[o][q] = vel[q];
+                    int a = obstacle_component(c, o, I, vel);
+                    if (a >= 0) vel[a] = 0.0;
+                }
                 double vbar[3] = {0, 0, 0};
                 for (int a = 0; a < d; ++a) vbar[a] = gvb[a * NN + li];
+                /* a removed component passes no adjoint back */
+                for (int o = c->n_obstacles - 1; o >= 0; --o) {
+                    int a = obstacle_component(c, o, I, vob[o]);
+                    if (a >= 0) vbar[a] = 0.0;
+                }
                 for (int f = nf - 1; f >= 0; --f) {
                     int face = face_of[f], a = face / 2;
                     double nrm[3] = {0, 0, 0};

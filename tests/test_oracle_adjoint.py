@@ -251,3 +251,72 @@ def test_adjoint_step_jaumann_every_zone(orc, dim):
             fd = (L(sp) - L(sm)) / (2 * eps)
             ad = float((g[f] * delta).sum())
             assert abs(fd - ad) <= 2e-6 * max(abs(fd), 1e-12) + 1e-12, (sel, f, fd, ad)
+
+
+def _other_form(dim, form):
+    if form == "pic":
+        return _cfg(dim, W.SAND, transfer=W.PIC)
+    if form == "tpic":
+        return _cfg(dim, W.SAND, transfer=W.TPIC)
+    if form == "viscous":
+        # viscous stress 2 mu |d| ~ 2 * 10 * 3 Pa against pressures of ~1e2 Pa
+        return _cfg(dim, W.FLUID, viscosity=10.0)
+    # a resting box in the middle of the domain, faces off the node planes
+    n, h = (10, 9, 8) if dim == 3 else (16, 12, 1), 0.02
+    lo = tuple(0.3 * n[a] * h + 0.37 * h for a in range(dim))
+    hi = tuple(0.7 * n[a] * h - 0.41 * h for a in range(dim))
+    return _cfg(dim, W.ELASTIC, obstacles=((lo, hi),))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("form", ["pic", "tpic", "viscous", "obstacle"])
+def test_adjoint_step_other_forms(orc, dim, form):
+    """The reverse step of the step's other forms: the PIC transfer (C' = 0,
+    no adjoint through it), TPIC (C' = grad v, its adjoint joins the
+    velocity-gradient adjoint), the Newtonian viscous fluid (Sec. 2.3
+    eq:stress_strain) and a resting obstacle (Sec. 4.2.1, a removed
+    component passes no adjoint); one step's vector-Jacobian product against
+    central differences of the forward step, for every input field."""
+    cfg = _other_form(dim, form)
+    o = orc.Oracle(cfg)
+    N = 300 if dim == 3 else 400
+    st0 = _state(orc, cfg, N, 90 + dim)
+    rng = np.random.default_rng(95 + dim)
+    st1 = st0.copy()
+    o.step(st1, cfg.dt)
+    if form == "obstacle":
+        # the box changes the step: some nodes lose a velocity component
+        s_free = st0.copy()
+        orc.Oracle(cfg.replace(obstacles=())).step(s_free, cfg.dt)
+        assert np.abs(s_free.v - st1.v).max() > 1e-3
+    w = {k: rng.normal(size=v.shape) for k, v in _outputs(cfg, st1).items()}
+
+    def L(st):
+        s = st.copy()
+        o.step(s, cfg.dt)
+        return sum(float((w[k] * v).sum()) for k, v in _outputs(cfg, s).items())
+
+    g = orc.adjoint_step(cfg, st0, w, cfg.dt)
+    fields = ["x", "v", "C", "S"] + (["J"] if cfg.material == W.FLUID else ["F"])
+    scale = {"x": 1e-4 * cfg.dx, "v": 1e-3, "C": 1e-2, "S": 1e-4, "J": 1e-5, "F": 1e-5}
+    for f in fields:
+        delta = rng.normal(size=getattr(st0, f).shape) * scale[f]
+        ad = float((g[f] * delta).sum())
+        # two step sizes: the larger can cross a wall's stick/slip kink, the
+        # smaller loses digits to rounding in the position direction; the
+        # adjoint must match the difference quotient at one of them
+        errs = []
+        for eps in (1e-2, 1e-3):
+            sp, sm = st0.copy(), st0.copy()
+            setattr(sp, f, getattr(st0, f) + eps * delta)
+            setattr(sm, f, getattr(st0, f) - eps * delta)
+            fd = (L(sp) - L(sm)) / (2 * eps)
+            errs.append(abs(fd - ad) / max(abs(fd), 1e-12))
+        assert min(errs) <= 2e-6, (f, errs, ad)
+
+
+def test_adjoint_step_refuses_flip(orc):
+    cfg = _cfg(2, W.SAND, transfer=W.FLIP)
+    st0 = _state(orc, cfg, 50, 3)
+    with pytest.raises(NotImplementedError):
+        orc.adjoint_step(cfg, st0, {}, cfg.dt)
