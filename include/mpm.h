@@ -245,9 +245,9 @@ int mpm_set_observations(mpm_ctx* ctx, const mpm_obs* obs);
  * on the tape, so that the first mpm_backward after it need not recompute
  * it.  Synchronizes; *host_loss gets the loss.  The state, sort and grid
  * afterwards are those after n_steps, as after mpm_step(n_steps).  The
- * reverse sweep covers the APIC transfer without obstacles, for the
- * inviscid fluid, the Hencky materials and DP_JAUMANN: other configurations
- * (the other transfers, obstacles, a viscous fluid) return EINVAL. */
+ * reverse sweep covers every material (the viscous fluid included), resting
+ * obstacles and the APIC, PIC and TPIC transfers; the FLIP transfer returns
+ * EINVAL. */
 int mpm_forward_loss(mpm_ctx* ctx, int32_t n_steps, double dt, double* host_loss);
 
 /* Gradient of the last mpm_forward_loss by the hand-written reverse sweep:

@@ -513,9 +513,8 @@ int mpm_forward_loss(mpm_ctx* c, int32_t n_steps, double dt, double* host_loss)
     if (n_steps < 1 || n_steps > c->tape_steps) return set_err(c, MPM_EINVAL, "n_steps must be in [1, tape_steps]");
     if (c->N < 1) return set_err(c, MPM_EINVAL, "a rollout needs at least one particle");
     if (!(dt >= 0.0) || !isfinite(dt)) return set_err(c, MPM_EINVAL, "dt must be finite and >= 0");
-    if (c->xfer != XF_APIC || c->cfg.n_obstacles > 0 || c->mat == MAT_VFLUID)
-        return set_err(c, MPM_EINVAL, "the reverse sweep covers the APIC transfer without obstacles, for the "
-                                      "inviscid fluid, the Hencky materials and the hypoelastic Drucker-Prager");
+    if (c->xfer == XF_FLIP)
+        return set_err(c, MPM_EINVAL, "the reverse sweep covers the APIC, PIC and TPIC transfers, not FLIP");
     c->has_tape = false;
     rc = c->ops->forward_loss(c, n_steps, dt, host_loss);
     if (rc) return rc;

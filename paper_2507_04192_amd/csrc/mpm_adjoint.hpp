@@ -128,6 +128,12 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
                     T Jb_in;
                     fluid_vjp<T, D>(P, Lm, st.G[j], aout.G[s], aout.S[s], Lb, Jb_in);
                     mid[ML::G * cap + s] = Jb_in;
+                } else if constexpr (MAT == MAT_VFLUID) {
+                    T sb[NS], Jb_in;
+    #pragma unroll
+                    for (int q = 0; q < NS; ++q) sb[q] = aout.S[q * cap + s];
+                    vfluid_vjp<T, D>(P, Lm, st.G[j], aout.G[s], sb, Lb, Jb_in);
+                    mid[ML::G * cap + s] = Jb_in;
                 } else if constexpr (MAT == MAT_JAUMANN) {
                     T Sv[NS], sb[NS], sb_in[NS], Jb_in;
     #pragma unroll
@@ -191,6 +197,17 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
                         Cb[a][b] = aout.C[(a * D + b) * cap + s];
                         Lb[a][b] = Lb_c[a][b];
                     }
+                }
+                // the carried matrix of the other transfers: TPIC's C' = L
+                // (its adjoint joins that of L), PIC's C' = 0 (none flows back)
+                if (P.xfer != XF_APIC) {
+    #pragma unroll
+                    for (int a = 0; a < D; ++a)
+    #pragma unroll
+                        for (int b = 0; b < D; ++b) {
+                            if (P.xfer == XF_TPIC) Lb[a][b] += Cb[a][b];
+                            Cb[a][b] = T(0);
+                        }
                 }
                 // Line by line along x (per-axis weight factors).  Node adjoint of
                 // the velocity, scattered:
@@ -368,6 +385,21 @@ __global__ __launch_bounds__(kAdjBlock) void k_grid_adj(Geo g, Phys<T> P, const 
                         ++nf;
                         wall_node<T, D>(P.wall_mode[face], mu, a, side == 0 ? T(-1) : T(1), vel);
                     }
+                }
+                // resting obstacles after the walls (Sec. 4.2.1): a component
+                // that one of them removed passes no adjoint back
+                if (P.n_obst > 0) {
+                    double xi[D];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) xi[a] = double(I[a] - g.G) * P.obst_h;
+                    int cut[kMaxObstacles];
+                    for (int o = 0; o < P.n_obst; ++o) {
+                        cut[o] = obstacle_component<T, D>(P, o, xi, vel);
+                        if (cut[o] >= 0) vel[cut[o]] = T(0);
+                    }
+                    for (int o = P.n_obst - 1; o >= 0; --o)
+                        for (int a = 0; a < D; ++a)
+                            if (cut[o] == a) vb[a] = T(0);
                 }
                 for (int f = nf - 1; f >= 0; --f) {
                     int face = fc[f], a = face / 2;
@@ -594,6 +626,22 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
                 for (int a = 0; a < D; ++a) tr += Sbar[a][a];
                 ain.S[j] = tr;
+            } else if constexpr (MAT == MAT_VFLUID) {
+                // J carried; the stress is recomputed from J and L each step,
+                // so its input adjoint is the force's part only
+                ain.G[j] = mid[D * cap + s];
+                if constexpr (D == 3) {
+                    ain.S[0 * cap + j] = Sbar[0][0];
+                    ain.S[1 * cap + j] = Sbar[1][1];
+                    ain.S[2 * cap + j] = Sbar[2][2];
+                    ain.S[3 * cap + j] = Sbar[0][1] + Sbar[1][0];
+                    ain.S[4 * cap + j] = Sbar[0][2] + Sbar[2][0];
+                    ain.S[5 * cap + j] = Sbar[1][2] + Sbar[2][1];
+                } else {
+                    ain.S[0 * cap + j] = Sbar[0][0];
+                    ain.S[1 * cap + j] = Sbar[1][1];
+                    ain.S[2 * cap + j] = Sbar[0][1] + Sbar[1][0];
+                }
             } else if constexpr (MAT == MAT_JAUMANN) {
                 // the force's part of the stress adjoint plus the constitutive part
                 constexpr int S0 = MidLayout<D>::S;
@@ -917,7 +965,7 @@ struct Adjoint {
         return -1;
     }
 
-    template <int MAT>
+    template <int MAT, int XF>
     static int forward_loss_mat(mpm_ctx* c, int n, double dt, double* loss)
     {
         hipStream_t st = c->stream;
@@ -938,7 +986,7 @@ struct Adjoint {
             PView<T> obs_state;
             if (t < tl) {
                 PView<T> cur = view<T>(c, c->cur), nxt = view<T>(c, 1 - c->cur);
-                S::template step_views<MAT>(c, P, cur, nxt);
+                S::template step_views<MAT, XF>(c, P, cur, nxt);
                 c->cur = 1 - c->cur;
                 obs_state = view<T>(c, c->cur);
             } else {
@@ -946,7 +994,7 @@ struct Adjoint {
                     int rc = copy_state(c, tape(c, 0), view<T>(c, c->cur));
                     if (rc) return rc;
                 }
-                S::template step_views<MAT>(c, Pk, tape(c, t - tl), tape(c, t - tl + 1), rec_bufs(c, t - tl));
+                S::template step_views<MAT, XF>(c, Pk, tape(c, t - tl), tape(c, t - tl + 1), rec_bufs(c, t - tl));
                 obs_state = tape(c, t + 1 - tl);
             }
             int fi = frame_index(c, t + 1);
@@ -980,7 +1028,7 @@ struct Adjoint {
         return MPM_OK;
     }
 
-    template <int MAT>
+    template <int MAT, int XF>
     static int backward_mat(mpm_ctx* c, void* grad_v0, void* grad_mu)
     {
         hipStream_t st = c->stream;
@@ -1004,7 +1052,7 @@ struct Adjoint {
                 if (rc) return rc;
                 keys_of(c, tape(c, 0));
                 for (int t = t0; t < t1; ++t)
-                    S::template step_views<MAT>(c, Pk, tape(c, t - t0), tape(c, t - t0 + 1), rec_bufs(c, t - t0));
+                    S::template step_views<MAT, XF>(c, Pk, tape(c, t - t0), tape(c, t - t0 + 1), rec_bufs(c, t - t0));
             }
             for (int t = t1 - 1; t >= t0; --t) {
                 int fi = frame_index(c, t + 1);
@@ -1049,22 +1097,44 @@ struct Adjoint {
         return S::launch_err(c, "extract");
     }
 
+    // the reverse sweep covers the APIC, PIC and TPIC transfers (FLIP is
+    // refused by the caller)
+    template <int MAT>
+    static int forward_loss_x(mpm_ctx* c, int n, double dt, double* loss)
+    {
+        switch (c->xfer) {
+        case XF_PIC: return forward_loss_mat<MAT, XF_PIC>(c, n, dt, loss);
+        case XF_TPIC: return forward_loss_mat<MAT, XF_TPIC>(c, n, dt, loss);
+        default: return forward_loss_mat<MAT, XF_APIC>(c, n, dt, loss);
+        }
+    }
+    template <int MAT>
+    static int backward_x(mpm_ctx* c, void* gv0, void* gmu)
+    {
+        switch (c->xfer) {
+        case XF_PIC: return backward_mat<MAT, XF_PIC>(c, gv0, gmu);
+        case XF_TPIC: return backward_mat<MAT, XF_TPIC>(c, gv0, gmu);
+        default: return backward_mat<MAT, XF_APIC>(c, gv0, gmu);
+        }
+    }
     static int forward_loss(mpm_ctx* c, int n, double dt, double* loss)
     {
         switch (c->mat) {
-        case MAT_FLUID: return forward_loss_mat<MAT_FLUID>(c, n, dt, loss);
-        case MAT_JAUMANN: return forward_loss_mat<MAT_JAUMANN>(c, n, dt, loss);
-        case MAT_SAND: return forward_loss_mat<MAT_SAND>(c, n, dt, loss);
-        default: return forward_loss_mat<MAT_ELASTIC>(c, n, dt, loss);
+        case MAT_FLUID: return forward_loss_x<MAT_FLUID>(c, n, dt, loss);
+        case MAT_VFLUID: return forward_loss_x<MAT_VFLUID>(c, n, dt, loss);
+        case MAT_JAUMANN: return forward_loss_x<MAT_JAUMANN>(c, n, dt, loss);
+        case MAT_SAND: return forward_loss_x<MAT_SAND>(c, n, dt, loss);
+        default: return forward_loss_x<MAT_ELASTIC>(c, n, dt, loss);
         }
     }
     static int backward(mpm_ctx* c, void* gv0, void* gmu)
     {
         switch (c->mat) {
-        case MAT_FLUID: return backward_mat<MAT_FLUID>(c, gv0, gmu);
-        case MAT_JAUMANN: return backward_mat<MAT_JAUMANN>(c, gv0, gmu);
-        case MAT_SAND: return backward_mat<MAT_SAND>(c, gv0, gmu);
-        default: return backward_mat<MAT_ELASTIC>(c, gv0, gmu);
+        case MAT_FLUID: return backward_x<MAT_FLUID>(c, gv0, gmu);
+        case MAT_VFLUID: return backward_x<MAT_VFLUID>(c, gv0, gmu);
+        case MAT_JAUMANN: return backward_x<MAT_JAUMANN>(c, gv0, gmu);
+        case MAT_SAND: return backward_x<MAT_SAND>(c, gv0, gmu);
+        default: return backward_x<MAT_ELASTIC>(c, gv0, gmu);
         }
     }
 };

@@ -845,6 +845,50 @@ __device__ __forceinline__ void fluid_vjp(const Phys<T>& P, const T L[D][D], T d
         for (int j = 0; j < D; ++j) Lb[i][j] = Jb * J * cof[i][j] * dt;
 }
 
+// Reverse of vfluid_update (Newtonian viscous fluid, Sec. 2.3
+// eq:stress_strain): S = s_iso(J') I + c(J') (sym(L) - tr(L)/D I) with
+// c = 2 mu V0 J' and s_iso the Tait part of fluid_update.  Inputs the
+// step's velocity gradient L, the stored J - 1 and the adjoints Jb_out of
+// J' - 1 and sb_out of the packed stress (an off-diagonal entry's adjoint is
+// that of the packed value); outputs Lb and the adjoint Jb_in of J - 1.
+template <class T, int D>
+__device__ __forceinline__ void vfluid_vjp(const Phys<T>& P, const T L[D][D], T dJ, T Jb_out,
+                                           const T sb_out[D * (D + 1) / 2], T Lb[D][D], T& Jb_in)
+{
+    T dJn = dJ, s_unused;
+    fluid_update<T, D>(P, L, dJn, s_unused);
+    const T c = T(2) * P.visc * P.vol0 * (T(1) + dJn);
+    T trd = T(0), trs = T(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        trd += L[a][a];
+        trs += sb_out[a];
+    }
+    // adjoint of c: <sb, sym(L) - tr(L)/D I> over the packed entries
+    T cb = T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = i; j < D; ++j) {
+            const int q = (i == j) ? i : (D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2);
+            T r = T(0.5) * (L[i][j] + L[j][i]);
+            if (i == j) r -= trd / T(D);
+            cb += sb_out[q] * r;
+        }
+    fluid_vjp<T, D>(P, L, dJ, Jb_out + cb * T(2) * P.visc * P.vol0, trs, Lb, Jb_in);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (i == j) {
+                Lb[i][i] += c * (sb_out[i] - trs / T(D));
+            } else {
+                const int q = D == 3 ? (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)) : 2;
+                Lb[i][j] += c * T(0.5) * sb_out[q];
+            }
+        }
+}
+
 // Reverse of wall_node for one face; vin is the velocity entering the face;
 // vb is replaced by the adjoint of vin; returns dL/dmu.
 template <class T, int D>

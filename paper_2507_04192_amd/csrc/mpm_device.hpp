@@ -735,32 +735,40 @@ __device__ __forceinline__ void wall_node(int mode, T mu, int axis, T sign, T v[
 // inside the closed box loses the velocity component that points into the
 // box through its nearest face (faces on the domain boundary excluded; ties
 // to the first face in the order x-, x+, y-, y+, z-, z+).  xi: the node's
-// position.
+// position.  obstacle_component returns the axis of the component that
+// obstacle o removes from a node moving with v, or -1.
+template <class T, int D>
+__device__ __forceinline__ int obstacle_component(const Phys<T>& P, int o, const double xi[D], const T v[D])
+{
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < D; ++a) inside &= xi[a] >= P.obst_lo[o][a] && xi[a] <= P.obst_hi[o][a];
+    if (!inside) return -1;
+    int best = -1;
+    double bd = 0.0;
+#pragma unroll
+    for (int f = 0; f < 2 * D; ++f) {
+        if (!((P.obst_face_ok[o] >> f) & 1)) continue;
+        const int a = f >> 1;
+        const double depth = (f & 1) ? P.obst_hi[o][a] - xi[a] : xi[a] - P.obst_lo[o][a];
+        if (best < 0 || depth < bd) {
+            best = f;
+            bd = depth;
+        }
+    }
+    if (best < 0) return -1;
+    const int a = best >> 1;
+    // the normal points into the obstacle: +e_a through its lower face
+    const T vn = (best & 1) ? -v[a] : v[a];
+    return vn > T(0) ? a : -1;
+}
+
 template <class T, int D>
 __device__ __forceinline__ void obstacle_node(const Phys<T>& P, const double xi[D], T v[D])
 {
     for (int o = 0; o < P.n_obst; ++o) {
-        bool inside = true;
-#pragma unroll
-        for (int a = 0; a < D; ++a) inside &= xi[a] >= P.obst_lo[o][a] && xi[a] <= P.obst_hi[o][a];
-        if (!inside) continue;
-        int best = -1;
-        double bd = 0.0;
-#pragma unroll
-        for (int f = 0; f < 2 * D; ++f) {
-            if (!((P.obst_face_ok[o] >> f) & 1)) continue;
-            const int a = f >> 1;
-            const double depth = (f & 1) ? P.obst_hi[o][a] - xi[a] : xi[a] - P.obst_lo[o][a];
-            if (best < 0 || depth < bd) {
-                best = f;
-                bd = depth;
-            }
-        }
-        if (best < 0) continue;
-        const int a = best >> 1;
-        // the normal points into the obstacle: +e_a through its lower face
-        const T vn = (best & 1) ? -v[a] : v[a];
-        if (vn > T(0)) v[a] = T(0);
+        const int a = obstacle_component<T, D>(P, o, xi, v);
+        if (a >= 0) v[a] = T(0);
     }
 }
 

@@ -549,3 +549,59 @@ def test_dp_jaumann_prestressed_3d_gradient_matches_oracle(orc, precision):
     print(f"  loss {loss:.6e} vs {loss_o:.6e} ({el:.2e}); dL/dv0 {ev:.2e}", flush=True)
     assert el <= (1e-10 if precision == "f64" else 1e-4)
     assert ev <= (1e-8 if precision == "f64" else 5e-3)
+
+
+def _other_form_case(form):
+    """Small 2-D cases of the step's other forms: the granular block with
+    the PIC or TPIC transfer, the dam-break of the friction case with a
+    viscous fluid, or with a resting box just ahead of its front."""
+    if form in ("pic", "tpic"):
+        cfg = W.SimConfig(dim=2, n=(64, 32, 1), dx=1 / 160, dt=1e-5, material=W.SAND, ppc=4,
+                          gravity=(0, -9.81, 0), rho0=2000.0, youngs=1e7, poisson=0.3, phi_deg=35.0,
+                          wall_mode=(W.SLIP, W.SLIP, W.COULOMB, W.SLIP, W.SLIP, W.SLIP),
+                          wall_mu=(0, 0, 0.5, 0, 0, 0), transfer=W.PIC if form == "pic" else W.TPIC)
+        x0 = W.lattice_particles(cfg, W.box_inside((0.1, 0), (0.3, 0.1)), (0.1, 0), (0.3, 0.1), seed=100)
+        v0 = _jaumann_velocity(cfg, x0, frac=0.02, div=0.5)
+        rng = np.random.default_rng(101)
+        mu = rng.uniform(0.3, 0.6, cfg.floor_nodes())
+        N = x0.shape[1]
+        tr = W.pick_tracers(N, 48, 102)
+        steps, k, frames = 24, 7, [6, 12, 18, 24]
+        tgt = np.stack([x0[:, tr] + rng.normal(0, 2e-4, size=(2, 48)) for _ in frames])
+        return cfg, x0, v0, mu, tr, frames, tgt, steps, k
+    cfg, x0, v0, mu, tr, frames, tgt, steps = friction_case()
+    if form == "viscous":
+        cfg = cfg.replace(viscosity=2.0)
+    else:
+        h = cfg.dx
+        cfg = cfg.replace(obstacles=(((0.25 + 0.35 * h, 0.0), (0.25 + 3.3 * h, 0.2)),))
+    return cfg, x0, v0, mu, tr, frames, tgt, steps, 13
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("form", ["pic", "tpic", "viscous", "obstacle"])
+def test_other_forms_gradient_matches_oracle(orc, precision, form):
+    """Gradients through the reverse sweep of the step's other forms (PIC and
+    TPIC transfers, Sec. 2.2 and App. B; the Newtonian viscous fluid, Sec.
+    2.3 eq:stress_strain; a resting obstacle, Sec. 4.2.1) with respect to v0
+    and the per-node floor friction, against the oracle's reverse sweep."""
+    cfg, x0, v0, mu, tr, frames, tgt, steps, k = _other_form_case(form)
+    if precision == "f32":
+        x0, v0, mu, tgt = (a.astype(np.float32).astype(np.float64) for a in (x0, v0, mu, tgt))
+    N = x0.shape[1]
+    print(f"[case] {form} gradient {precision} N={N}", flush=True)
+    obs = dict(frames=frames, tracer_pid=tr, lag_field="x", lag_target=tgt)
+    obs_o = orc.Observations(frames, tr, "x", tgt)
+    loss_o, gv_o, gmu_o = orc.rollout_grad(cfg, x0, v0, steps, cfg.dt, mu, obs_o)
+    loss, gv, gmu, _ = run_gpu(cfg, precision, x0, v0, mu, steps, k, obs)
+    el, ev, em = abs(loss - loss_o) / loss_o, rel_l2(gv, gv_o), rel_l2(gmu, gmu_o)
+    print(f"  loss {loss:.6e} vs {loss_o:.6e} ({el:.2e}); dL/dv0 {ev:.2e}; dL/dmu {em:.2e}", flush=True)
+    assert el <= (1e-10 if precision == "f64" else 1e-4)
+    tol = 1e-8 if precision == "f64" else 5e-3
+    assert ev <= tol and em <= tol
+    assert np.abs(gmu_o).max() > 0
+    if form in ("viscous", "obstacle") and precision == "f64":
+        # the form changes the gradient: the same rollout without it differs
+        base = cfg.replace(viscosity=0.0, obstacles=())
+        _, gv_b, _ = orc.rollout_grad(base, x0, v0, steps, cfg.dt, mu, obs_o)
+        assert rel_l2(gv_b, gv_o) > 1e-3
