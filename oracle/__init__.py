@@ -455,7 +455,7 @@ def adjoint_step(cfg, st_in, adj_out, dt, floor_mu=None, amu=None):
                             _ptr(out["x"]), _ptr(out["v"]), _ptr(out["C"]), _ptr(out["F"]), _ptr(out["J"]),
                             _ptr(out["S"]), _ptr(amu))
     if rc == -2:
-        raise NotImplementedError("the oracle's reverse step does not cover the FLIP transfer")
+        raise NotImplementedError("the oracle's reverse step refused the configuration")
     if rc != 0:
         raise MemoryError("oracle adjoint failed to allocate")
     return out

@@ -552,12 +552,13 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
     const int fluid = c->material == ORC_FLUID;
     const int jaumann = c->material == ORC_DP_JAUMANN;
     const int carries_j = fluid || jaumann;
-    /* the reverse sweep covers the APIC, PIC and TPIC transfers, resting
-     * obstacles, the (viscous) fluid, the Hencky materials and the
-     * hypoelastic Drucker-Prager material; FLIP is refused */
-    if (c->transfer == ORC_FLIP)
-        return -2;
+    /* every transfer, resting obstacles, the (viscous) fluid, the Hencky
+     * materials and the hypoelastic Drucker-Prager material */
     const int viscous = fluid && c->viscosity != 0.0;
+    /* FLIP: v' = sum phi v_i + alpha (v_p - sum phi v_i^n) with the grid
+     * velocity before the update v_i^n = Q_i / m_i, Q the momentum without
+     * the internal force */
+    const int flip = c->transfer == ORC_FLIP;
     int32_t dims[3];
     int64_t NN = orc_node_dims(c, dims);
     size_t NP = (size_t)(N > 0 ? N : 1);
@@ -576,6 +577,9 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
     double* gvb = calloc((size_t)NN * d, sizeof(double));  /* adjoint of gv */
     double* gmb = calloc((size_t)NN, sizeof(double));      /* adjoint of m */
     double* gpb = calloc((size_t)NN * d, sizeof(double));  /* adjoint of P */
+    double* gq = calloc((size_t)NN * d, sizeof(double));   /* FLIP: Q, then v^n = Q / m */
+    double* gvob = calloc((size_t)NN * d, sizeof(double)); /* FLIP: adjoint of v^n */
+    double* gqb = calloc((size_t)NN * d, sizeof(double));  /* FLIP: adjoint of Q */
     double* axs = calloc(NP * d, sizeof(double));          /* sorted-order adjoints */
     double* avs = calloc(NP * d, sizeof(double));
     double* aCs = calloc(NP * dd, sizeof(double));
@@ -583,7 +587,7 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
     double* aJs = calloc(NP, sizeof(double));
     double* aSs = calloc(NP * dd, sizeof(double));
     if (!key || !perm || !X || !V || !Cm || !Fm || !Jm || !Sm || !gm || !gp || !gvt || !gv || !gvb || !gmb ||
-        !gpb || !axs || !avs || !aCs || !aFs || !aJs || !aSs)
+        !gpb || !gq || !gvob || !gqb || !axs || !avs || !aCs || !aFs || !aJs || !aSs)
         return -1;
 
     /* the step's sort, applied to a copy of the input state */
@@ -604,7 +608,10 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
     }
 
     /* forward recomputation: P2G and grid (velocity before and after walls) */
-    orc_p2g(c, N, dt, X, V, Cm, Sm, gm, gp);
+    orc_p2g_ex(c, N, dt, X, V, Cm, Sm, gm, gp, flip ? gq : NULL);
+    if (flip)
+        for (int64_t i = 0; i < NN; ++i)
+            for (int a = 0; a < d; ++a) gq[a * NN + i] = gm[i] > 0.0 ? gq[a * NN + i] / gm[i] : 0.0;
     int fl = d - 1;
     for (int32_t Iz = 0; Iz < dims[2]; ++Iz)
         for (int32_t Iy = 0; Iy < dims[1]; ++Iy)
@@ -788,7 +795,14 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                 }
         }
 
-        /* positions: x' = clamp(x + dt v') */
+        /* FLIP: the particle's own velocity and the gathered v^n */
+        double vob[3] = {0, 0, 0};
+        if (flip)
+            for (int a = 0; a < d; ++a) {
+                avs[a * N + s] += c->flip_alpha * av1[a * N + s];
+                vob[a] = -c->flip_alpha * av1[a * N + s];
+            }
+        /* positions: x' = clamp(x + dt sum phi v_i) */
         double vb[3] = {0, 0, 0};
         for (int a = 0; a < d; ++a) {
             vb[a] = av1[a * N + s];
@@ -820,6 +834,10 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                         double vi = gv[a * NN + li];
                         double acc = phi * vb[a];
                         wb += vi * vb[a];
+                        if (flip) {
+                            gvob[a * NN + li] += phi * vob[a];
+                            wb += gq[a * NN + li] * vob[a];
+                        }
                         for (int b = 0; b < d; ++b) {
                             double cb = apic ? aC1[(a * d + b) * N + s] : 0.0;
                             acc += Dinv * phi * cb * dp[b] + Lb[a][b] * g[b];
@@ -890,11 +908,15 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                     if (amu && floor_mu && a == fl && face % 2 == 0)
                         amu[(d == 3) ? ((int64_t)Iy * dims[0] + Ix) : Ix] += mub;
                 }
-                /* v~ = P/m + dt g */
+                /* v~ = P/m + dt g; FLIP: v^n = Q/m */
                 double dotv = 0.0;
                 for (int a = 0; a < d; ++a) {
                     gpb[a * NN + li] = vbar[a] / m;
                     dotv += vbar[a] * (gvt[a * NN + li] - dt * c->gravity[a]);
+                    if (flip) {
+                        gqb[a * NN + li] = gvob[a * NN + li] / m;
+                        dotv += gvob[a * NN + li] * gq[a * NN + li];
+                    }
                 }
                 gmb[li] = -dotv / m;
             }
@@ -920,13 +942,15 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
                     double gb[3] = {0, 0, 0}, db[3] = {0, 0, 0};
                     for (int a = 0; a < d; ++a) {
                         double pb = gpb[a * NN + li];
+                        /* FLIP's Q shares P's affine momentum, not its force */
+                        double ab = flip ? pb + gqb[a * NN + li] : pb;
                         double aff = vp[a];
                         for (int b = 0; b < d; ++b) aff += Cm[(a * d + b) * N + s] * dp[b];
-                        wb += c->mass * aff * pb;
-                        avs[a * N + s] += phi * c->mass * pb;
+                        wb += c->mass * aff * ab;
+                        avs[a * N + s] += phi * c->mass * ab;
                         for (int b = 0; b < d; ++b) {
-                            aCs[(a * d + b) * N + s] += phi * c->mass * pb * dp[b];
-                            db[b] += phi * c->mass * Cm[(a * d + b) * N + s] * pb;
+                            aCs[(a * d + b) * N + s] += phi * c->mass * ab * dp[b];
+                            db[b] += phi * c->mass * Cm[(a * d + b) * N + s] * ab;
                             aSs[(a * d + b) * N + s] += -dt * pb * g[b];
                             gb[b] += -dt * Sm[(a * d + b) * N + s] * pb;
                         }
@@ -955,7 +979,7 @@ int orc_adjoint_step(const orc_config* c, int64_t N, double dt, const double* fl
     }
 
     free(key); free(perm); free(X); free(V); free(Cm); free(Fm); free(Jm); free(Sm);
-    free(gm); free(gp); free(gvt); free(gv); free(gvb); free(gmb); free(gpb);
+    free(gm); free(gp); free(gvt); free(gv); free(gvb); free(gmb); free(gpb); free(gq); free(gvob); free(gqb);
     free(axs); free(avs); free(aCs); free(aFs); free(aJs); free(aSs);
     return 0;
 }

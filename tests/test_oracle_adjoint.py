@@ -258,6 +258,8 @@ def _other_form(dim, form):
         return _cfg(dim, W.SAND, transfer=W.PIC)
     if form == "tpic":
         return _cfg(dim, W.SAND, transfer=W.TPIC)
+    if form == "flip":
+        return _cfg(dim, W.SAND, transfer=W.FLIP, flip_alpha=0.9)
     if form == "viscous":
         # viscous stress 2 mu |d| ~ 2 * 10 * 3 Pa against pressures of ~1e2 Pa
         return _cfg(dim, W.FLUID, viscosity=10.0)
@@ -269,11 +271,13 @@ def _other_form(dim, form):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("form", ["pic", "tpic", "viscous", "obstacle"])
+@pytest.mark.parametrize("form", ["pic", "tpic", "flip", "viscous", "obstacle"])
 def test_adjoint_step_other_forms(orc, dim, form):
     """The reverse step of the step's other forms: the PIC transfer (C' = 0,
     no adjoint through it), TPIC (C' = grad v, its adjoint joins the
-    velocity-gradient adjoint), the Newtonian viscous fluid (Sec. 2.3
+    velocity-gradient adjoint), the FLIP/PIC blend (v' = sum phi v_i +
+    alpha (v_p - sum phi v_i^n): a direct path to v_p and one through the
+    grid velocity before the update), the Newtonian viscous fluid (Sec. 2.3
     eq:stress_strain) and a resting obstacle (Sec. 4.2.1, a removed
     component passes no adjoint); one step's vector-Jacobian product against
     central differences of the forward step, for every input field."""
@@ -313,10 +317,3 @@ def test_adjoint_step_other_forms(orc, dim, form):
             fd = (L(sp) - L(sm)) / (2 * eps)
             errs.append(abs(fd - ad) / max(abs(fd), 1e-12))
         assert min(errs) <= 2e-6, (f, errs, ad)
-
-
-def test_adjoint_step_refuses_flip(orc):
-    cfg = _cfg(2, W.SAND, transfer=W.FLIP)
-    st0 = _state(orc, cfg, 50, 3)
-    with pytest.raises(NotImplementedError):
-        orc.adjoint_step(cfg, st0, {}, cfg.dt)
