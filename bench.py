@@ -157,7 +157,7 @@ def traffic_kernels(cls, elem):
     G2P)."""
     t = "float" if elem == 4 else "double"
     names = {"p2g": f"k_p2g<{t}, 3, 1, false>", "g2p": f"k_g2p<{t}, 3, 1, 0>",
-             "g2p_adj": f"k_g2p_adj<{t}, 3, 1>", "p2g_adj": f"k_p2g_adj<{t}, 3, 1>"}
+             "g2p_adj": f"k_g2p_adj<{t}, 3, 1, false>", "p2g_adj": f"k_p2g_adj<{t}, 3, 1, false>"}
     return [names.get(cls, cls)]
 
 

@@ -246,8 +246,8 @@ int mpm_set_observations(mpm_ctx* ctx, const mpm_obs* obs);
  * it.  Synchronizes; *host_loss gets the loss.  The state, sort and grid
  * afterwards are those after n_steps, as after mpm_step(n_steps).  The
  * reverse sweep covers every material (the viscous fluid included), resting
- * obstacles and the APIC, PIC and TPIC transfers; the FLIP transfer returns
- * EINVAL. */
+ * obstacles and every transfer (FLIP's also through the grid velocity
+ * before the update, which the tape then records). */
 int mpm_forward_loss(mpm_ctx* ctx, int32_t n_steps, double dt, double* host_loss);
 
 /* Gradient of the last mpm_forward_loss by the hand-written reverse sweep:

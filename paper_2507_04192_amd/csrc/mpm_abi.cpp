@@ -189,7 +189,8 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
         L.tape_pid = take((size_t)(ckpt_every + 1) * ucap * 4);
         L.adj[0] = take(sb);
         L.adj[1] = take(sb);
-        L.mid = take((size_t)(c.dim + c.dim * c.dim) * ucap * elem);   // position and F adjoints
+        // position and F adjoints (FLIP: and the direct velocity adjoint)
+        L.mid = take((size_t)(c.dim + c.dim * c.dim + (is_flip(c) ? c.dim : 0)) * ucap * elem);
         // grid tape: one record per step of a segment
         GridRec& r = L.grec;
         size_t ro = 0;
@@ -201,6 +202,7 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
         r.gv = rtake((size_t)g.NN * c.dim * elem);
         r.gvt = rtake((size_t)g.NN * c.dim * elem);
         r.gmass = rtake((size_t)g.NN * elem);
+        r.gvo = is_flip(c) ? rtake((size_t)g.NN * c.dim * elem) : 0;   // FLIP: velocity before the update
         r.perm = rtake(ucap * 4);
         r.tile_slot = rtake((size_t)g.ntiles * 4);
         r.active = rtake((size_t)g.ntiles * sizeof(ActiveTile));
@@ -513,8 +515,6 @@ int mpm_forward_loss(mpm_ctx* c, int32_t n_steps, double dt, double* host_loss)
     if (n_steps < 1 || n_steps > c->tape_steps) return set_err(c, MPM_EINVAL, "n_steps must be in [1, tape_steps]");
     if (c->N < 1) return set_err(c, MPM_EINVAL, "a rollout needs at least one particle");
     if (!(dt >= 0.0) || !isfinite(dt)) return set_err(c, MPM_EINVAL, "dt must be finite and >= 0");
-    if (c->xfer == XF_FLIP)
-        return set_err(c, MPM_EINVAL, "the reverse sweep covers the APIC, PIC and TPIC transfers, not FLIP");
     c->has_tape = false;
     rc = c->ops->forward_loss(c, n_steps, dt, host_loss);
     if (rc) return rc;

@@ -30,8 +30,10 @@ constexpr int kAdjBlock = 128;   // threads of the reverse per-tile kernels
 //                       hypoelastic Drucker-Prager: [D] J, then the
 //                       constitutive part of the packed stress adjoint in
 //                       [D + 1, D + 1 + D(D+1)/2), which fits the same slots)
+//   [D + D^2, 2D + D^2) FLIP: the direct adjoint of the input velocity,
+//                       alpha times that of v'
 template <int D> struct MidLayout {
-    static constexpr int X = 0, G = D, S = D + 1, N = D + D * D;
+    static constexpr int X = 0, G = D, S = D + 1, V = D + D * D, N = D + D * D;
     static_assert(D + 1 + D * (D + 1) / 2 <= D + D * D, "stress adjoint fits the intermediate");
 };
 
@@ -43,18 +45,26 @@ template <int D> struct MidLayout {
 // and the position adjoint through the weights and x_i - x_p.  The velocity,
 // velocity-gradient and partial position adjoints pass between the parts in
 // registers; the F (or J) adjoint and the position adjoint go to mid.
-template <class T, int D, int MAT>
+// FLIP (FL): v' = sum phi v_i + alpha (v_p - sum phi v_i^n); the adjoint of
+// v^n = sum phi v_i^n is scattered to a second node block (binary64 LDS,
+// written after the first in the tile's partial block), its weights pass
+// an adjoint to the position, and alpha times the adjoint of v' goes to mid
+// as the direct adjoint of v_p.
+template <class T, int D, int MAT, bool FL>
 __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                     const ActiveTile* __restrict__ active,
                                                     const int* __restrict__ perm, PView<T> st, PView<T> aout,
-                                                    const T* __restrict__ gv, T* __restrict__ part,
-                                                    T* __restrict__ mid)
+                                                    const T* __restrict__ gv, const T* __restrict__ gvo,
+                                                    T* __restrict__ part, T* __restrict__ mid)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     constexpr int NS = D * (D + 1) / 2;
+    constexpr int NVA = FL ? 2 * D + 1 : D + 1;   // partial block values per node
     using ML = MidLayout<D>;
     __shared__ T s_v[D][NB];
     __shared__ double s_b[D][NB];
+    __shared__ T s_vo[FL ? D : 1][FL ? NB : 1];
+    __shared__ double s_bo[FL ? D : 1][FL ? NB : 1];
     const int n_active = meta[0];
     const int tid = threadIdx.x;
     const long long cap = st.cap;
@@ -72,13 +82,17 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
             for (int a = 0; a < D; ++a) {
                 s_v[a][i] = gv[a * g.NN + node];
                 s_b[a][i] = 0.0;
+                if constexpr (FL) {
+                    s_vo[a][i] = gvo[a * g.NN + node];
+                    s_bo[a][i] = 0.0;
+                }
             }
         }
         __syncthreads();
         for (int k = tid; k < at.cnt; k += kAdjBlock) {
             long long s = at.off + k;
             int j = perm[s];
-            T xbar_c[D], vt_c[D], Lb_c[D][D];
+            T xbar_c[D], vt_c[D], Lb_c[D][D], vob_c[FL ? D : 1];
             {
                 T xp[D], w[D][3], dw[D][3];
                 int lb[3] = {0, 0, 0};
@@ -169,7 +183,12 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
                     T xn = xp[a] + P.dt * vn[a];
                     bool free_ = (xn >= T(0)) && (xn <= P.ext[a]);
                     xbar_c[a] = free_ ? xb : T(0);
-                    vt_c[a] = aout.v[a * cap + s] + (free_ ? P.dt * xb : T(0));
+                    const T vb_out = aout.v[a * cap + s];
+                    vt_c[a] = vb_out + (free_ ? P.dt * xb : T(0));
+                    if constexpr (FL) {
+                        vob_c[a] = -P.flip_alpha * vb_out;
+                        mid[(ML::V + a) * cap + s] = P.flip_alpha * vb_out;
+                    }
     #pragma unroll
                     for (int b = 0; b < D; ++b) Lb_c[a][b] = Lb[a][b];
                 }
@@ -253,6 +272,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
                             vi[a] = s_v[a][n];
                             T nbv = w[0][kx] * U[a] + w[0][kx] * dd[0][kx] * V[a] + dw[0][kx] * Wl[a];
                             atomicAdd(&s_b[a][n], (double)nbv);
+                            if constexpr (FL) atomicAdd(&s_bo[a][n], (double)(w[0][kx] * wyz * vob_c[a]));
                         }
                         T wbar = T(0), gq[D];
     #pragma unroll
@@ -265,6 +285,7 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
                             }
                             gq[b] = gb;
                             wbar += vi[b] * vt[b] + P.Dinv * ddn[b] * ub;
+                            if constexpr (FL) wbar += s_vo[b][n] * vob_c[b];
                         }
                         A += wbar * dw[0][kx];
                         B += wbar * w[0][kx];
@@ -308,8 +329,10 @@ __global__ __launch_bounds__(kAdjBlock) void k_g2p_adj(Geo g, Phys<T> P, const i
             }
         }
         __syncthreads();
-        T* dst = part + (long long)e * (D + 1) * NB;
+        T* dst = part + (long long)e * NVA * NB;
         for (int i = tid; i < D * NB; i += kAdjBlock) dst[i] = (T)(&s_b[0][0])[i];
+        if constexpr (FL)
+            for (int i = tid; i < D * NB; i += kAdjBlock) dst[D * NB + i] = (T)(&s_bo[0][0])[i];
         __syncthreads();
     }
 }
@@ -319,7 +342,8 @@ __global__ __launch_bounds__(kAdjBlock) void k_grid_adj(Geo g, Phys<T> P, const 
                                                      const ActiveTile* __restrict__ active,
                                                      const int* __restrict__ tile_slot, const T* __restrict__ part,
                                                      T* __restrict__ gmass, const T* __restrict__ gvt,
-                                                     T* __restrict__ gv, double* __restrict__ amu)
+                                                     T* __restrict__ gv, T* __restrict__ gvo,
+                                                     double* __restrict__ amu)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     const int n_active = meta[0];
@@ -342,16 +366,25 @@ __global__ __launch_bounds__(kAdjBlock) void k_grid_adj(Geo g, Phys<T> P, const 
             constexpr int NC = 1 << D;
             int slot[NC], li[NC];
             const int des = node_blocks<D>(g, I, own, down, tile_slot, slot, li);
-            T vb[D];
+            // FLIP (gvo given): the partial blocks also carry the adjoint of
+            // the velocity before the update, v^n = Q / m, after the first D
+            const int nva = gvo ? 2 * D + 1 : D + 1;
+            T vb[D], vob[D];
 #pragma unroll
-            for (int a = 0; a < D; ++a) vb[a] = T(0);
+            for (int a = 0; a < D; ++a) {
+                vb[a] = T(0);
+                vob[a] = T(0);
+            }
             if (des == tile) {
 #pragma unroll
                 for (int msk = 0; msk < NC; ++msk) {
                     if (slot[msk] < 0) continue;
-                    const T* src = part + (long long)slot[msk] * (D + 1) * NB;
+                    const T* src = part + (long long)slot[msk] * nva * NB;
 #pragma unroll
                     for (int a = 0; a < D; ++a) vb[a] += src[a * NB + li[msk]];
+                    if (gvo)
+#pragma unroll
+                        for (int a = 0; a < D; ++a) vob[a] += src[(D + a) * NB + li[msk]];
                 }
             }
             if (des != tile) continue;
@@ -416,27 +449,38 @@ __global__ __launch_bounds__(kAdjBlock) void k_grid_adj(Geo g, Phys<T> P, const 
                 for (int a = 0; a < D; ++a) {
                     pb[a] = vb[a] / m;
                     dot += vb[a] * (gvt[a * g.NN + node] - P.dt * P.g[a]);
+                    if (gvo) dot += vob[a] * gvo[a * g.NN + node];
                 }
                 mb = -dot / m;
             }
 #pragma unroll
             for (int a = 0; a < D; ++a) gv[a * g.NN + node] = pb[a];
             gmass[node] = mb;
+            // FLIP: the adjoint of Q replaces v^n in the record
+            if (gvo)
+#pragma unroll
+                for (int a = 0; a < D; ++a) gvo[a * g.NN + node] = m > T(0) ? vob[a] / m : T(0);
         }
     }
 }
 
 // At least two waves per SIMD: binary64 needs a few more than 256 registers
 // per lane and would otherwise run one wave (measured faster with the spills).
-template <class T, int D, int MAT>
+// FLIP (FL): the force-free momentum Q (for v^n = Q / m) shares P's affine
+// part, so the affine gathers take p + q (q the adjoint of Q, gqb) and the
+// force's gathers p alone; the direct adjoint of v_p comes from mid.
+template <class T, int D, int MAT, bool FL>
 __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_p2g_adj(Geo g, Phys<T> P, const int* __restrict__ meta,
                                                     const ActiveTile* __restrict__ active,
                                                     const int* __restrict__ perm, PView<T> st,
                                                     const T* __restrict__ gpb, const T* __restrict__ gmb,
+                                                    const T* __restrict__ gqb,
                                                     const T* __restrict__ mid, PView<T> ain)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
-    __shared__ T s_p[D][NB];
+    using ML = MidLayout<D>;
+    __shared__ T s_p[D][NB];     // p (FL: p + q)
+    __shared__ T s_f[FL ? D : 1][FL ? NB : 1];   // FL: p
     __shared__ T s_m[NB];
     const int n_active = meta[0];
     const int tid = threadIdx.x;
@@ -453,7 +497,15 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
             long long node = node_index(g, tc[0] * TE + l0, tc[1] * TE + l1, (D == 3) ? tc[2] * TE + l2 : 0);
             s_m[i] = gmb[node];
 #pragma unroll
-            for (int a = 0; a < D; ++a) s_p[a][i] = gpb[a * g.NN + node];
+            for (int a = 0; a < D; ++a) {
+                const T pv = gpb[a * g.NN + node];
+                if constexpr (FL) {
+                    s_f[a][i] = pv;
+                    s_p[a][i] = pv + gqb[a * g.NN + node];
+                } else {
+                    s_p[a][i] = pv;
+                }
+            }
         }
         __syncthreads();
         for (int k = tid; k < at.cnt; k += kAdjBlock) {
@@ -496,6 +548,7 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
             //   xbar += m [ sum grad phi (m_i + (x_i - x_p).(Cp^T p)) + Lp^T v_p
             //              - Cp^T (sum phi p) ] - dt sum Hess(phi) (S_p p).
             T V[D], Bp[D][D], Lp[D][D], X1[D], X2[D];
+            T Lf[FL ? D : 1][FL ? D : 1];   // FL: the force's sum p (grad phi)^T
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 V[a] = T(0);
@@ -504,6 +557,11 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
                 for (int b = 0; b < D; ++b) { Bp[a][b] = T(0); Lp[a][b] = T(0); }
             }
+            if constexpr (FL)
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int b = 0; b < D; ++b) Lf[a][b] = T(0);
             // Both passes run line by line along x: every weight, gradient and
             // Hessian entry of phi is a product of per-axis factors, so each
             // line is first reduced with the x factors, then combined with
@@ -537,6 +595,14 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
                         Bp[a][2] += (lw * dd[2][kz]) * A0;
                         Lp[a][2] += (w[1][ky] * dw[2][kz]) * A0;
                     }
+                    if constexpr (FL) {
+                        T f0 = s_f[a][n0], f1 = s_f[a][n0 + 1], f2 = s_f[a][n0 + 2];
+                        T F0 = w[0][0] * f0 + w[0][1] * f1 + w[0][2] * f2;
+                        T F2 = dw[0][0] * f0 + dw[0][1] * f1 + dw[0][2] * f2;
+                        Lf[a][0] += lw * F2;
+                        Lf[a][1] += ldw1 * F0;
+                        if constexpr (D == 3) Lf[a][2] += (w[1][ky] * dw[2][kz]) * F0;
+                    }
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -554,9 +620,13 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
                 for (int kx = 0; kx < 3; ++kx) {
                     const int n = n0 + kx;
-                    T pb[D];
+                    T pb[D], pf[D];
 #pragma unroll
-                    for (int a = 0; a < D; ++a) pb[a] = s_p[a][n];
+                    for (int a = 0; a < D; ++a) {
+                        pb[a] = s_p[a][n];
+                        if constexpr (FL) pf[a] = s_f[a][n];
+                        else pf[a] = pb[a];
+                    }
                     T sc = s_m[n], sp[D];
                     const T ddn[3] = {dd[0][kx], dd[1][ky], (D == 3) ? dd[D - 1][kz] : T(0)};
 #pragma unroll
@@ -565,7 +635,7 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
                         for (int a = 0; a < D; ++a) {
                             ub += Cp[a][b] * pb[a];
-                            sb += Sp[b][a] * pb[a];
+                            sb += Sp[b][a] * pf[a];
                         }
                         sp[b] = sb;
                         sc += ddn[b] * ub;
@@ -606,10 +676,12 @@ __global__ __launch_bounds__(kAdjBlock) __attribute__((amdgpu_waves_per_eu(2))) 
                 for (int a = 0; a < D; ++a) t += Lp[a][c] * vp[a] - Cp[a][c] * V[a];
                 xbar[c] = mid[c * cap + s] + P.mass * t - P.dt * X2[c];
                 vbar[c] = P.mass * V[c];
+                if constexpr (FL) vbar[c] += mid[(ML::V + c) * cap + s];
 #pragma unroll
                 for (int b = 0; b < D; ++b) {
                     Cbar[c][b] = P.mass * Bp[c][b];
-                    Sbar[c][b] = -P.dt * Lp[c][b];
+                    if constexpr (FL) Sbar[c][b] = -P.dt * Lf[c][b];
+                    else Sbar[c][b] = -P.dt * Lp[c][b];
                 }
             }
             // the particle's adjoint goes to its slot before the step's sort
@@ -886,7 +958,7 @@ struct Adjoint {
         char* r = c->gtape + (size_t)i * c->grec.bytes;
         return {(int32_t*)(r + c->grec.perm), (int32_t*)(r + c->grec.tile_slot), (ActiveTile*)(r + c->grec.active),
                 (int32_t*)(r + c->grec.meta), (T*)(r + c->grec.gv), (T*)(r + c->grec.gmass),
-                (T*)(r + c->grec.gvt)};
+                (T*)(r + c->grec.gvt), c->xfer == XF_FLIP ? (T*)(r + c->grec.gvo) : nullptr};
     }
 
     // Reverse of one step whose sort and grid are in record rb (written by
@@ -900,16 +972,28 @@ struct Adjoint {
         hipStream_t st = c->stream;
         const Geo& g = c->geo;
         prof_mark(c, -1);
-        k_g2p_adj<T, D, MAT><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in,
-                                                              aout, (const T*)rb.gv, (T*)c->part_grid, (T*)c->mid);
+        const bool flip = c->xfer == XF_FLIP;
+        if (flip)
+            k_g2p_adj<T, D, MAT, true><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(
+                g, P, rb.meta, rb.active, rb.perm, st_in, aout, (const T*)rb.gv, (const T*)rb.gvo, (T*)c->part_grid,
+                (T*)c->mid);
+        else
+            k_g2p_adj<T, D, MAT, false><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(
+                g, P, rb.meta, rb.active, rb.perm, st_in, aout, (const T*)rb.gv, nullptr, (T*)c->part_grid,
+                (T*)c->mid);
         prof_mark(c, MPM_PROF_G2P_ADJ);
         k_grid_adj<T, D><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.tile_slot,
                                                       (const T*)c->part_grid, rb.gmass, (const T*)rb.gvt, rb.gv,
-                                                      c->floor_mu ? c->amu : nullptr);
+                                                      flip ? rb.gvo : nullptr, c->floor_mu ? c->amu : nullptr);
         prof_mark(c, MPM_PROF_GRID_ADJ);
-        k_p2g_adj<T, D, MAT><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(g, P, rb.meta, rb.active, rb.perm, st_in,
-                                                          (const T*)rb.gv, (const T*)rb.gmass, (const T*)c->mid,
-                                                          ain);
+        if (flip)
+            k_p2g_adj<T, D, MAT, true><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(
+                g, P, rb.meta, rb.active, rb.perm, st_in, (const T*)rb.gv, (const T*)rb.gmass, (const T*)rb.gvo,
+                (const T*)c->mid, ain);
+        else
+            k_p2g_adj<T, D, MAT, false><<<kTileWGs * kBlock / kAdjBlock, kAdjBlock, 0, st>>>(
+                g, P, rb.meta, rb.active, rb.perm, st_in, (const T*)rb.gv, (const T*)rb.gmass, nullptr,
+                (const T*)c->mid, ain);
         prof_mark(c, MPM_PROF_P2G_ADJ);
     }
 
@@ -1097,14 +1181,14 @@ struct Adjoint {
         return S::launch_err(c, "extract");
     }
 
-    // the reverse sweep covers the APIC, PIC and TPIC transfers (FLIP is
-    // refused by the caller)
+    // the reverse sweep of each transfer
     template <int MAT>
     static int forward_loss_x(mpm_ctx* c, int n, double dt, double* loss)
     {
         switch (c->xfer) {
         case XF_PIC: return forward_loss_mat<MAT, XF_PIC>(c, n, dt, loss);
         case XF_TPIC: return forward_loss_mat<MAT, XF_TPIC>(c, n, dt, loss);
+        case XF_FLIP: return forward_loss_mat<MAT, XF_FLIP>(c, n, dt, loss);
         default: return forward_loss_mat<MAT, XF_APIC>(c, n, dt, loss);
         }
     }
@@ -1114,6 +1198,7 @@ struct Adjoint {
         switch (c->xfer) {
         case XF_PIC: return backward_mat<MAT, XF_PIC>(c, gv0, gmu);
         case XF_TPIC: return backward_mat<MAT, XF_TPIC>(c, gv0, gmu);
+        case XF_FLIP: return backward_mat<MAT, XF_FLIP>(c, gv0, gmu);
         default: return backward_mat<MAT, XF_APIC>(c, gv0, gmu);
         }
     }

@@ -1350,10 +1350,11 @@ struct Solver {
         T* gv;
         T* gmass;
         T* gvt;
+        T* gvo;     // FLIP: nodal velocity before the update
     };
     static StepBufs ctx_bufs(mpm_ctx* c)
     {
-        return {c->perm, c->tile_slot, c->active, c->meta, (T*)c->gv, (T*)c->gmass, nullptr};
+        return {c->perm, c->tile_slot, c->active, c->meta, (T*)c->gv, (T*)c->gmass, nullptr, (T*)c->gvo};
     }
 
     // One step from state view cur into state view nxt with the transfer XF
@@ -1382,10 +1383,10 @@ struct Solver {
                                                                         b.perm, (T*)c->part_grid);
         prof_mark(c, MPM_PROF_P2G);
         k_grid<T, D, FL><<<kTileWGs * kBlock / kGridBlock, kGridBlock, 0, st>>>(g, P, b.meta, b.active, b.tile_slot, (const T*)c->part_grid,
-                                                  b.gv, b.gmass, b.gvt, (T*)c->gvo);
+                                                  b.gv, b.gmass, b.gvt, b.gvo);
         prof_mark(c, MPM_PROF_GRID);
         k_g2p<T, D, MAT, XF><<<kTileWGs * kBlock / kG2PBlock<T>, kG2PBlock<T>, 0, st>>>(g, P, b.meta, b.active, b.perm, cur, nxt, (const T*)b.gv,
-                                                      (const T*)c->gvo, c->key, c->count, c->status);
+                                                      (const T*)b.gvo, c->key, c->count, c->status);
         prof_mark(c, MPM_PROF_G2P);
     }
 

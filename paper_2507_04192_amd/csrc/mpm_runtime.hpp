@@ -27,7 +27,7 @@ struct Ops;
 // needs from that step's forward pass (nodal velocity after and before the
 // walls, nodal mass, the sort permutation and the active-tile list).
 struct GridRec {
-    size_t gv = 0, gvt = 0, gmass = 0, perm = 0, tile_slot = 0, active = 0, meta = 0, bytes = 0;
+    size_t gv = 0, gvt = 0, gmass = 0, gvo = 0, perm = 0, tile_slot = 0, active = 0, meta = 0, bytes = 0;
 };
 
 }  // namespace mpm
@@ -78,7 +78,7 @@ struct mpm_ctx {
     char* tape = nullptr;          // a segment's recomputed states (ckpt_every + 1)
     int32_t* tape_pid = nullptr;
     char* adj[2] = {nullptr, nullptr};   // adjoint states (same layout as a state)
-    void* mid = nullptr;           // per slot: position and F (or J) adjoints between the reverse kernels
+    void* mid = nullptr;           // per slot: position and F (or J) adjoints between the reverse kernels (FLIP: and the direct velocity adjoint)
     char* gtape = nullptr;         // per step of a segment: the grid and sort it used
     mpm::GridRec grec;
     int32_t* inv = nullptr;        // slot of each pid

@@ -553,13 +553,14 @@ def test_dp_jaumann_prestressed_3d_gradient_matches_oracle(orc, precision):
 
 def _other_form_case(form):
     """Small 2-D cases of the step's other forms: the granular block with
-    the PIC or TPIC transfer, the dam-break of the friction case with a
+    the PIC, TPIC or FLIP/PIC (alpha = 0.9) transfer, the dam-break of the friction case with a
     viscous fluid, or with a resting box just ahead of its front."""
-    if form in ("pic", "tpic"):
+    if form in ("pic", "tpic", "flip"):
         cfg = W.SimConfig(dim=2, n=(64, 32, 1), dx=1 / 160, dt=1e-5, material=W.SAND, ppc=4,
                           gravity=(0, -9.81, 0), rho0=2000.0, youngs=1e7, poisson=0.3, phi_deg=35.0,
                           wall_mode=(W.SLIP, W.SLIP, W.COULOMB, W.SLIP, W.SLIP, W.SLIP),
-                          wall_mu=(0, 0, 0.5, 0, 0, 0), transfer=W.PIC if form == "pic" else W.TPIC)
+                          wall_mu=(0, 0, 0.5, 0, 0, 0), transfer={"pic": W.PIC, "tpic": W.TPIC, "flip": W.FLIP}[form],
+                          flip_alpha=0.9)
         x0 = W.lattice_particles(cfg, W.box_inside((0.1, 0), (0.3, 0.1)), (0.1, 0), (0.3, 0.1), seed=100)
         v0 = _jaumann_velocity(cfg, x0, frac=0.02, div=0.5)
         rng = np.random.default_rng(101)
@@ -579,10 +580,10 @@ def _other_form_case(form):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("form", ["pic", "tpic", "viscous", "obstacle"])
+@pytest.mark.parametrize("form", ["pic", "tpic", "flip", "viscous", "obstacle"])
 def test_other_forms_gradient_matches_oracle(orc, precision, form):
-    """Gradients through the reverse sweep of the step's other forms (PIC and
-    TPIC transfers, Sec. 2.2 and App. B; the Newtonian viscous fluid, Sec.
+    """Gradients through the reverse sweep of the step's other forms (PIC,
+    TPIC and the FLIP/PIC blend, Sec. 2.2 and App. B; the Newtonian viscous fluid, Sec.
     2.3 eq:stress_strain; a resting obstacle, Sec. 4.2.1) with respect to v0
     and the per-node floor friction, against the oracle's reverse sweep."""
     cfg, x0, v0, mu, tr, frames, tgt, steps, k = _other_form_case(form)

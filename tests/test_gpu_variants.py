@@ -292,22 +292,3 @@ def test_dam_break_columns_paper_geometry(orc, precision):
     for a in range(2):
         deep &= (g["x"][a] > lo[a] + h) & (g["x"][a] < hi[a] - h)
     assert not deep.any()
-
-
-def test_reverse_sweep_refuses_flip():
-    """mpm_forward_loss covers every material, resting obstacles and the
-    APIC, PIC and TPIC transfers; FLIP returns EINVAL (its forward step
-    runs)."""
-    from paper_2507_04192_amd.native import MPM_EINVAL, MPMError, Solver
-    cfg, x = W.dam_break_2d()
-    c = cfg.replace(transfer=W.FLIP)
-    s = Solver(c, "f64", capacity=x.shape[1], tape_steps=4, ckpt_every=2)
-    s.mpm_init_particles(x)
-    s.mpm_set_observations(frames=[2], tracer_pid=np.arange(4), lag_field="x",
-                           lag_target=np.zeros((1, c.dim, 4)))
-    with pytest.raises(MPMError) as ei:
-        s.mpm_forward_loss(4)
-    assert ei.value.code == MPM_EINVAL
-    s.mpm_step(2)
-    assert s.mpm_sync_status()[0] == 0
-    s.close()
