@@ -14,7 +14,9 @@ The forward+adjoint leg times a checkpointed rollout with a tracer loss and
 its backward sweep on the same cylinder (FP32 and FP64; 1000 steps with a
 checkpoint every 100 by default).
 
-The variants leg times the other forms of the step: the cylinder with the
+The other_configs leg times the forward step of the other benchmark
+configurations (the 2-D dam-breaks and granular block, the 3-D dam-break)
+without per-kernel events.  The variants leg times the other forms of the step: the cylinder with the
 hypoelastic Drucker-Prager material (Jaumann rate, App. A) and with the PIC,
 TPIC and FLIP transfers, and the 3-D dam-break against two rigid columns
 with a viscous fluid (Sec. 4.2.1, 1,920,000 particles on 200 x 100 x 80).
@@ -70,7 +72,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(cfg, x, precision, steps, warmup):
+def run_gpu(cfg, x, precision, steps, warmup, profile=True):
     import torch
     from paper_2507_04192_amd.native import Solver
     s = Solver(cfg, precision, capacity=x.shape[1])
@@ -80,7 +82,7 @@ def run_gpu(cfg, x, precision, steps, warmup):
     if rc != 0:
         raise RuntimeError(f"solver status {rc} (pid {bad}) during warm-up")
     torch.cuda.synchronize()
-    s.mpm_profile_enable(True)
+    s.mpm_profile_enable(profile)
     s.mpm_profile_read()                     # reset
     t0 = time.perf_counter()
     s.mpm_step(steps)
@@ -91,6 +93,9 @@ def run_gpu(cfg, x, precision, steps, warmup):
     rc, bad = s.mpm_sync_status()
     if rc != 0:
         raise RuntimeError(f"solver status {rc} (pid {bad}) in the timed region")
+    if not profile:
+        s.close()
+        return (t1 - t0), None, prof
     # same number of steps without events, to show their cost
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -267,6 +272,30 @@ def run_variants(steps, steps64, warmup):
     return out
 
 
+def run_other_configs(steps, warmup):
+    """Forward throughput of the other benchmark configurations (binary32 and
+    binary64, the same kernels and launch shapes as the cylinder): the 2-D
+    dam-break, the 2-D friction dam-break, the 2-D granular block and the
+    3-D dam-break of the learned-friction problem."""
+    from paper_2507_04192_amd import workloads as W
+    gb = W.granular_block_2d()
+    legs = [("2-D water column (dam-break), 128 x 64 cells", W.dam_break_2d()),
+            ("2-D friction dam-break, 256 x 128 cells", W.friction_dam_break_2d()),
+            ("2-D granular block, 256 x 128 cells", (gb[0], gb[1])),
+            ("3-D dam-break, 192 x 96 x 64 cells", W.dam_break_3d())]
+    out = []
+    for name, (cfg, x) in legs:
+        n = x.shape[1]
+        r = {"workload": name, "particles": n}
+        for prec in ("f32", "f64"):
+            t, _, _ = run_gpu(cfg, x, prec, steps, warmup, profile=False)
+            r[prec] = {"value": n * steps / t, "unit": "particle-steps/s", "steps": steps,
+                       "ms_per_step": t / steps * 1e3}
+            log(f"[bench] {name} {prec}: {t / steps * 1e3:.4f} ms/step, {n * steps / t:.4e} particle-steps/s")
+        out.append(r)
+    return out
+
+
 def step_roofline(value, scalars, elem):
     """The whole step against HBM: the algorithmic bytes per particle-step
     (the state read once and written once; forward+adjoint: two forward
@@ -389,6 +418,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the other forms of the step")
     ap.add_argument("--variant-steps", type=int, default=500, help="binary32 steps per variant (binary64: half)")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other benchmark configurations")
+    ap.add_argument("--config-steps", type=int, default=1000, help="steps per other configuration")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--scale-div", type=int, default=1, help="shrink the cylinder (tests only)")
@@ -465,6 +496,9 @@ def main():
     variants = None
     if not args.no_variants and args.scale_div == 1:
         variants = run_variants(args.variant_steps, max(1, args.variant_steps // 2), args.warmup)
+    configs = None
+    if not args.no_configs and args.scale_div == 1:
+        configs = run_other_configs(args.config_steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -500,6 +534,7 @@ def main():
         "f64": out_f64,
         "fwd_adjoint": adj,
         "variants": variants,
+        "other_configs": configs,
         "paper_context": {"value_f32": 1.22e8, "value_f64": 2.76e7,
                           "note": "paper, one A100, 2,712,960-particle cylinder on 400x400x100; "
                                   "a different machine and grid, not this workload"},
