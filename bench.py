@@ -12,7 +12,9 @@ timed region starts.  Prints one JSON line.
 
 The forward+adjoint leg times a checkpointed rollout with a tracer loss and
 its backward sweep on the same cylinder (FP32 and FP64; 1000 steps with a
-checkpoint every 100 by default).
+checkpoint every 100 by default), keeping as many trailing segments on the
+tape as three quarters of the free device memory holds (the backward sweep
+recomputes only the others).
 
 The other_configs leg times the forward step of the other benchmark
 configurations (the 2-D dam-breaks and granular block, the 3-D dam-break)
@@ -106,17 +108,35 @@ def run_gpu(cfg, x, precision, steps, warmup, profile=True):
     return (t1 - t0), (t3 - t2), prof
 
 
-def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every=20):
+def taped_segments_for(cfg, precision, n, steps, ckpt_every, budget):
+    """The most trailing segments of a rollout that can stay on the tape
+    with the workspace within budget bytes (at least one)."""
+    import ctypes as ct
+    from paper_2507_04192_amd import native
+    L = native.lib()
+    nb = ct.c_size_t()
+    nseg = (steps + ckpt_every - 1) // ckpt_every
+    best = 1
+    for ns in range(1, nseg + 1):
+        c = native.make_config(cfg, precision, tape_segments=ns)
+        if L.mpm_workspace_bytes(ct.byref(c), n, steps, ckpt_every, ct.byref(nb)) != 0 or nb.value > budget:
+            break
+        best = ns
+    return best
+
+
+def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every=20, tape_segments=1):
     """Forward rollout with the loss, then the checkpointed backward sweep:
     tracer positions every frame_every steps against their starting
     positions; gradients with respect to v0 and a per-node floor friction
-    field (uniform at the floor's mu)."""
+    field (uniform at the floor's mu).  The trailing tape_segments segments
+    stay on the tape (the backward sweep recomputes only the others)."""
     import numpy as np
     import torch
     from paper_2507_04192_amd import workloads as W
     from paper_2507_04192_amd.native import Solver
     n = x.shape[1]
-    s = Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=ckpt_every)
+    s = Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=ckpt_every, tape_segments=tape_segments)
     ws_bytes = s.ws.numel()
     s.mpm_set_floor_mu(np.full(cfg.floor_nodes(), cfg.wall_mu[4 if cfg.dim == 3 else 2]))
     tr = W.pick_tracers(n, n_tracers, 7)
@@ -146,7 +166,7 @@ def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every
     ok = bool(np.isfinite(loss) and torch.isfinite(gv).all().item() and torch.isfinite(gm).all().item())
     s.close()
     return {"value": n * steps / (tf + tb), "unit": "particle-steps/s", "steps": steps,
-            "ckpt_every": ckpt_every, "ms_per_step": (tf + tb) / steps * 1e3,
+            "ckpt_every": ckpt_every, "tape_segments": tape_segments, "ms_per_step": (tf + tb) / steps * 1e3,
             "forward_loss_ms": tf * 1e3, "backward_ms": tb * 1e3, "loss": loss, "finite": ok,
             "workspace_bytes": ws_bytes, "max_memory_allocated": torch.cuda.max_memory_allocated(),
             "observations": f"{n_tracers} tracer positions every {frame_every} steps; "
@@ -416,6 +436,9 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=1000, help="rollout length of the forward+adjoint leg")
     ap.add_argument("--adj-ckpt", type=int, default=100, help="checkpoint interval of the forward+adjoint leg")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-memory-frac", type=float, default=0.75,
+                    help="share of the free device memory the forward+adjoint workspace may take "
+                         "(trailing segments kept on the tape instead of recomputed)")
     ap.add_argument("--no-variants", action="store_true", help="skip the other forms of the step")
     ap.add_argument("--variant-steps", type=int, default=500, help="binary32 steps per variant (binary64: half)")
     ap.add_argument("--no-configs", action="store_true", help="skip the other benchmark configurations")
@@ -476,7 +499,9 @@ def main():
                 continue
             torch.cuda.empty_cache()
             torch.cuda.reset_peak_memory_stats()
-            r, prof = run_adjoint(cfg, x, prec, T, args.adj_ckpt)
+            free, _ = torch.cuda.mem_get_info()
+            nts = taped_segments_for(cfg, prec, n, T, args.adj_ckpt, args.adj_memory_frac * free)
+            r, prof = run_adjoint(cfg, x, prec, T, args.adj_ckpt, tape_segments=nts)
             dom_a, kern, roof_a = roofline({k: prof[k] for k in ("g2p_adj", "p2g_adj") if k in prof}, n, elem)
             if args.scale_div == 1:
                 roof_a["traffic"] = measured_traffic(traffic_kernels(dom_a, elem))
@@ -487,7 +512,7 @@ def main():
             r["valu_roofline"] = valu_roofline(r["value"], passes=4.0)
             r["kernels_us"] = {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1] > 0}
             adj[prec] = r
-            log(f"[bench] fwd+adjoint {prec}: {r['ms_per_step']:.4f} ms/step, {r['value']:.4e} particle-steps/s "
+            log(f"[bench] fwd+adjoint {prec}: {nts} taped segment(s), {r['ms_per_step']:.4f} ms/step, {r['value']:.4e} particle-steps/s "
                 f"(forward {r['forward_loss_ms']:.1f} ms, backward {r['backward_ms']:.1f} ms, "
                 f"peak memory {r['max_memory_allocated'] / 2**30:.1f} GiB)")
             for k, v in r["kernels_us"].items():

@@ -117,6 +117,8 @@ enum { MPM_ORDER_MEMORY = 0, MPM_ORDER_PID = 1 };
  * (n[a] + 1 + 2*ghost) nodes per axis, x fastest. */
 enum { MPM_GRID_MASS = 0, MPM_GRID_VEL = 1 };
 
+#define MPM_MAX_TAPE_SEGMENTS 64
+
 typedef struct mpm_config {
     int32_t dim;           /* 2 or 3 */
     int32_t precision;     /* MPM_F32 or MPM_F64 */
@@ -140,6 +142,13 @@ typedef struct mpm_config {
     double cohesion;       /* DP_JAUMANN: c >= 0 */
     double tension;        /* DP_JAUMANN: tensile strength sigma^t, <= k_phi / q_phi (the apex) */
     double obst_lo[MPM_MAX_OBSTACLES][3], obst_hi[MPM_MAX_OBSTACLES][3];   /* lo < hi per used axis */
+    /* memory for speed in a forward-plus-adjoint rollout: the number of
+     * trailing segments kept on the tape, whose steps the backward sweep
+     * does not recompute (0 or 1: the last segment; at most the number of
+     * segments and MPM_MAX_TAPE_SEGMENTS; each costs ckpt_every + 1 states
+     * and ckpt_every grid records of workspace) */
+    int32_t tape_segments;
+    int32_t reserved;      /* 0 */
 } mpm_config;
 
 typedef struct mpm_ctx mpm_ctx;

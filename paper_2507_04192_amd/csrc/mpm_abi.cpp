@@ -6,6 +6,7 @@
 
 #include <string>
 
+#include <algorithm>
 #include "mpm_runtime.hpp"
 
 using namespace mpm;
@@ -70,6 +71,8 @@ int check_config(const mpm_config* c, std::string& why)
         return MPM_EINVAL;
     }
     if (c->n_obstacles < 0 || c->n_obstacles > MPM_MAX_OBSTACLES) { why = "n_obstacles must be in [0, 4]"; return MPM_EINVAL; }
+    if (c->tape_segments < 0 || c->tape_segments > MPM_MAX_TAPE_SEGMENTS) { why = "tape_segments must be in [0, 64]"; return MPM_EINVAL; }
+    if (c->reserved != 0) { why = "reserved must be 0"; return MPM_EINVAL; }
     for (int o = 0; o < c->n_obstacles; ++o)
         for (int a = 0; a < c->dim; ++a)
             if (!isfinite(c->obst_lo[o][a]) || !isfinite(c->obst_hi[o][a]) || !(c->obst_lo[o][a] < c->obst_hi[o][a])) {
@@ -142,6 +145,15 @@ struct Layout {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Trailing segments kept on the tape: at least one, at most the rollout's
+// segments.
+int tape_segs_of(const mpm_config& c, int tape_steps, int ckpt_every)
+{
+    if (tape_steps < 1 || ckpt_every < 1) return 0;
+    int nseg = (tape_steps + ckpt_every - 1) / ckpt_every;
+    return std::max(1, std::min(c.tape_segments, nseg));
+}
+
 Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_steps, int ckpt_every)
 {
     Layout L{};
@@ -183,10 +195,11 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
     if (tape_steps > 0 && ckpt_every > 0) {
         size_t sb = (size_t)nsc_of(c) * ucap * elem;
         size_t nck = (size_t)((tape_steps + ckpt_every - 1) / ckpt_every);
+        size_t nts = (size_t)tape_segs_of(c, tape_steps, ckpt_every);
         L.ckpt = take(nck * sb);
         L.ckpt_pid = take(nck * ucap * 4);
-        L.tape = take((size_t)(ckpt_every + 1) * sb);
-        L.tape_pid = take((size_t)(ckpt_every + 1) * ucap * 4);
+        L.tape = take(nts * (size_t)(ckpt_every + 1) * sb);
+        L.tape_pid = take(nts * (size_t)(ckpt_every + 1) * ucap * 4);
         L.adj[0] = take(sb);
         L.adj[1] = take(sb);
         // position and F adjoints (FLIP: and the direct velocity adjoint)
@@ -208,7 +221,7 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
         r.active = rtake((size_t)g.ntiles * sizeof(ActiveTile));
         r.meta = rtake(64 * 4);
         r.bytes = ro;
-        L.gtape = take((size_t)ckpt_every * r.bytes);
+        L.gtape = take(nts * (size_t)ckpt_every * r.bytes);
         size_t nfl = c.dim == 3 ? (size_t)g.box[0] * g.box[1] : (size_t)g.box[0];
         L.amu = take(nfl * 8);
     }
@@ -314,6 +327,7 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     c->cap = n_particles;
     c->tape_steps = tape_steps;
     c->ckpt_every = ckpt_every;
+    c->tape_segs = tape_segs_of(c->cfg, tape_steps, ckpt_every);
     for (int i = 0; i < 2; ++i) {
         c->st[i] = b + L.st[i];
         c->pid[i] = (int32_t*)(b + L.pid[i]);

@@ -929,9 +929,11 @@ struct Adjoint {
     {
         return slot_view(c, c->ckpt + (size_t)i * state_bytes(c), c->ckpt_pid + (size_t)i * c->cap);
     }
-    static PView<T> tape(const mpm_ctx* c, int i)
+    // State i (0..ckpt_every) of tape slot q (one slot per taped segment).
+    static PView<T> tape(const mpm_ctx* c, int q, int i)
     {
-        return slot_view(c, c->tape + (size_t)i * state_bytes(c), c->tape_pid + (size_t)i * c->cap);
+        const size_t at = (size_t)q * (size_t)(c->ckpt_every + 1) + (size_t)i;
+        return slot_view(c, c->tape + at * state_bytes(c), c->tape_pid + at * c->cap);
     }
     static PView<T> adj(const mpm_ctx* c, int i) { return slot_view(c, c->adj[i], nullptr); }
 
@@ -952,10 +954,10 @@ struct Adjoint {
         k_keys<T, D><<<nblocks(c->N), kBlock, 0, st>>>(c->geo, P, v, c->N, c->key, c->count);
     }
 
-    // The grid-tape record of step i of the current segment.
-    static typename S::StepBufs rec_bufs(const mpm_ctx* c, int i)
+    // The grid-tape record of step i of the segment in tape slot q.
+    static typename S::StepBufs rec_bufs(const mpm_ctx* c, int q, int i)
     {
-        char* r = c->gtape + (size_t)i * c->grec.bytes;
+        char* r = c->gtape + ((size_t)q * (size_t)c->ckpt_every + (size_t)i) * c->grec.bytes;
         return {(int32_t*)(r + c->grec.perm), (int32_t*)(r + c->grec.tile_slot), (ActiveTile*)(r + c->grec.active),
                 (int32_t*)(r + c->grec.meta), (T*)(r + c->grec.gv), (T*)(r + c->grec.gmass),
                 (T*)(r + c->grec.gvt), c->xfer == XF_FLIP ? (T*)(r + c->grec.gvo) : nullptr};
@@ -1056,15 +1058,21 @@ struct Adjoint {
         Phys<T> P = make_phys<T>(c, dt);
         Phys<T> Pk = P;
         Pk.keep_grid = 1;
-        int k = c->ckpt_every;
-        // the last segment runs directly on the tape (states and grid
-        // records), so the backward sweep starts without recomputing it
-        const int tl = ((n + k - 1) / k - 1) * k;
-        c->tail_taped = false;
+        const int k = c->ckpt_every;
+        // the trailing tape_segs segments run directly on the tape (states
+        // and grid records), so the backward sweep reverses them without
+        // recomputing them
+        const int nseg = (n + k - 1) / k;
+        const int nt = std::max(1, std::min(c->tape_segs, nseg));
+        const int first = nseg - nt, tl = first * k;
+        c->taped = 0;
         k_fill<double><<<1, kBlock, 0, st>>>(c->loss, 2, 0.0);
         for (int t = 0; t < n; ++t) {
             if (t % k == 0) {
-                int rc = copy_state(c, ckpt(c, t / k), view<T>(c, c->cur));
+                // the state at t: in the context up to the first taped
+                // segment, then at the end of the previous taped segment
+                const PView<T> now = t <= tl ? view<T>(c, c->cur) : tape(c, t / k - first - 1, k);
+                int rc = copy_state(c, ckpt(c, t / k), now);
                 if (rc) return rc;
             }
             PView<T> obs_state;
@@ -1074,21 +1082,23 @@ struct Adjoint {
                 c->cur = 1 - c->cur;
                 obs_state = view<T>(c, c->cur);
             } else {
-                if (t == tl) {
-                    int rc = copy_state(c, tape(c, 0), view<T>(c, c->cur));
+                const int q = t / k - first, i = t - (t / k) * k;
+                if (i == 0) {
+                    int rc = copy_state(c, tape(c, q, 0), q == 0 ? view<T>(c, c->cur) : tape(c, q - 1, k));
                     if (rc) return rc;
                 }
-                S::template step_views<MAT, XF>(c, Pk, tape(c, t - tl), tape(c, t - tl + 1), rec_bufs(c, t - tl));
-                obs_state = tape(c, t + 1 - tl);
+                S::template step_views<MAT, XF>(c, Pk, tape(c, q, i), tape(c, q, i + 1), rec_bufs(c, q, i));
+                obs_state = tape(c, q, i + 1);
             }
             int fi = frame_index(c, t + 1);
             if (fi >= 0) observe(c, obs_state, fi, nullptr);
         }
         // the context's state, sort and grid again describe the last step
         {
-            int rc = copy_state(c, view<T>(c, c->cur), tape(c, n - tl));
+            const int ql = nt - 1, il = n - (nseg - 1) * k;
+            int rc = copy_state(c, view<T>(c, c->cur), tape(c, ql, il));
             if (rc) return rc;
-            typename S::StepBufs last = rec_bufs(c, n - 1 - tl);
+            typename S::StepBufs last = rec_bufs(c, ql, il - 1);
             const size_t nn = (size_t)c->geo.NN * sizeof(T);
             rc = hip_check(c, hipMemcpyAsync(c->perm, last.perm, (size_t)c->cap * 4, hipMemcpyDeviceToDevice, st),
                            "sort copy");
@@ -1100,7 +1110,7 @@ struct Adjoint {
                 rc = hip_check(c, hipMemcpyAsync(c->gmass, last.gmass, nn, hipMemcpyDeviceToDevice, st), "grid copy");
             if (rc) return rc;
         }
-        c->tail_taped = true;
+        c->taped = nt;
         int rc = S::launch_err(c, "forward loss");
         if (rc) return rc;
         double h[2];
@@ -1124,25 +1134,30 @@ struct Adjoint {
         k_fill<T><<<4096, kBlock, 0, st>>>((T*)c->adj[0], (long long)c->nsc * c->cap, T(0));
         long long nfl = c->geo.dim == 3 ? (long long)c->geo.box[0] * c->geo.box[1] : c->geo.box[0];
         k_fill<double><<<std::min<long long>(nblocks(nfl), 4096), kBlock, 0, st>>>(c->amu, nfl, 0.0);
-        int nseg = (n + k - 1) / k;
-        // the forward pass left the last segment on the tape (once: the
-        // reverse steps overwrite the grid records with adjoints)
-        const bool tail = c->tail_taped;
-        c->tail_taped = false;
+        const int nseg = (n + k - 1) / k;
+        // the forward pass left its trailing segments on the tape (once: the
+        // reverse steps overwrite the grid records with adjoints); earlier
+        // segments are recomputed from their checkpoint into slot 0, which the
+        // taped segments have released by then
+        const int first = nseg - c->taped;
+        c->taped = 0;
         for (int seg = nseg - 1; seg >= 0; --seg) {
             int t0 = seg * k, t1 = std::min(t0 + k, n);
-            if (!(tail && seg == nseg - 1)) {
-                int rc = copy_state(c, tape(c, 0), ckpt(c, seg));
+            const bool on_tape = seg >= first;
+            const int q = on_tape ? seg - first : 0;
+            if (!on_tape) {
+                int rc = copy_state(c, tape(c, 0, 0), ckpt(c, seg));
                 if (rc) return rc;
-                keys_of(c, tape(c, 0));
+                keys_of(c, tape(c, 0, 0));
                 for (int t = t0; t < t1; ++t)
-                    S::template step_views<MAT, XF>(c, Pk, tape(c, t - t0), tape(c, t - t0 + 1), rec_bufs(c, t - t0));
+                    S::template step_views<MAT, XF>(c, Pk, tape(c, 0, t - t0), tape(c, 0, t - t0 + 1),
+                                                    rec_bufs(c, 0, t - t0));
             }
             for (int t = t1 - 1; t >= t0; --t) {
                 int fi = frame_index(c, t + 1);
                 PView<T> aout = adj(c, a), ain = adj(c, 1 - a);
-                if (fi >= 0) observe(c, tape(c, t + 1 - t0), fi, &aout);
-                adjoint_step<MAT>(c, P, tape(c, t - t0), aout, ain, rec_bufs(c, t - t0));
+                if (fi >= 0) observe(c, tape(c, q, t + 1 - t0), fi, &aout);
+                adjoint_step<MAT>(c, P, tape(c, q, t - t0), aout, ain, rec_bufs(c, q, t - t0));
                 a = 1 - a;
             }
         }

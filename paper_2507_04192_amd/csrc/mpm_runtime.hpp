@@ -51,6 +51,7 @@ struct mpm_ctx {
     int64_t N = 0;                 // particles set
     double mass = 0.0, vol0 = 0.0;  // per particle
     int tape_steps = 0, ckpt_every = 0;
+    int tape_segs = 0;             // trailing segments kept on the tape
 
     void* st[2] = {nullptr, nullptr};        // particle state buffers
     int32_t* pid[2] = {nullptr, nullptr};
@@ -75,7 +76,7 @@ struct mpm_ctx {
     // forward-plus-adjoint rollout (mpm_forward_loss / mpm_backward)
     char* ckpt = nullptr;          // checkpoints, one state every ckpt_every steps
     int32_t* ckpt_pid = nullptr;
-    char* tape = nullptr;          // a segment's recomputed states (ckpt_every + 1)
+    char* tape = nullptr;          // states of tape_segs segments (ckpt_every + 1 each)
     int32_t* tape_pid = nullptr;
     char* adj[2] = {nullptr, nullptr};   // adjoint states (same layout as a state)
     void* mid = nullptr;           // per slot: position and F (or J) adjoints between the reverse kernels (FLIP: and the direct velocity adjoint)
@@ -91,7 +92,7 @@ struct mpm_ctx {
     int fwd_steps = 0;
     double fwd_dt = 0.0;
     bool has_tape = false;
-    bool tail_taped = false;       // the tape holds the last segment of the forward rollout
+    int taped = 0;                 // trailing segments of the forward rollout still on the tape
 
     // observations (mpm_set_observations)
     std::vector<int> obs_frames;

@@ -66,6 +66,7 @@ class MpmConfig(ct.Structure):
         ("flip_alpha", ct.c_double), ("viscosity", ct.c_double),
         ("psi_deg", ct.c_double), ("cohesion", ct.c_double), ("tension", ct.c_double),
         ("obst_lo", (ct.c_double * 3) * MAX_OBSTACLES), ("obst_hi", (ct.c_double * 3) * MAX_OBSTACLES),
+        ("tape_segments", ct.c_int32), ("reserved", ct.c_int32),
     ]
 
 
@@ -135,9 +136,11 @@ _HEADER_NAMES = [
 PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p", "g2p_adj", "grid_adj", "p2g_adj"]
 
 
-def make_config(cfg, precision: str = "f64", keep_grid: bool = False) -> MpmConfig:
-    """mpm_config from a workloads.SimConfig."""
+def make_config(cfg, precision: str = "f64", keep_grid: bool = False, tape_segments: int = 0) -> MpmConfig:
+    """mpm_config from a workloads.SimConfig (tape_segments: trailing
+    segments of a forward-plus-adjoint rollout kept on the tape)."""
     c = MpmConfig()
+    c.tape_segments = int(tape_segments)
     c.dim = cfg.dim
     c.precision = MPM_F64 if precision == "f64" else MPM_F32
     for a in range(3):
@@ -182,7 +185,8 @@ class Solver:
     """One solver context with its workspace (a torch uint8 tensor)."""
 
     def __init__(self, cfg, precision: str = "f64", capacity: Optional[int] = None,
-                 tape_steps: int = 0, ckpt_every: int = 0, keep_grid: bool = False, stream=None):
+                 tape_steps: int = 0, ckpt_every: int = 0, keep_grid: bool = False, stream=None,
+                 tape_segments: int = 0):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -191,7 +195,7 @@ class Solver:
         self.np_dtype = np.float64 if precision == "f64" else np.float32
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self._c = make_config(cfg, precision, keep_grid)
+        self._c = make_config(cfg, precision, keep_grid, tape_segments)
         self.L = lib()
         ctx = ct.c_void_p()
         rc = self.L.mpm_create(ct.byref(self._c), ct.c_void_p(self.stream.cuda_stream), ct.byref(ctx))

@@ -118,3 +118,27 @@ def test_added_physics_validation_without_gpu():
     assert rc(dp.replace(tension=10.0)) == native.MPM_EINVAL               # above the apex (c = 0)
     assert rc(dp.replace(cohesion=1000.0, tension=10.0)) == 0              # below it with cohesion
     assert rc(dp.replace(cohesion=-1.0)) == native.MPM_EINVAL
+
+
+def test_tape_segments_workspace_without_gpu():
+    """Each taped segment adds ckpt_every + 1 states and ckpt_every grid
+    records to the workspace; the count is clamped to the rollout's segments
+    and validated."""
+    from paper_2507_04192_amd import native
+    from paper_2507_04192_amd import workloads as W
+    cfg, _ = W.dam_break_2d()
+    L = native.lib()
+    nb = ct.c_size_t()
+    sizes = []
+    for ns in (0, 1, 2, 3, 10, 11):
+        c = native.make_config(cfg, "f64", tape_segments=ns)
+        assert L.mpm_workspace_bytes(ct.byref(c), 8192, 100, 10, ct.byref(nb)) == 0
+        sizes.append(nb.value)
+    assert sizes[0] == sizes[1]                          # 0 and 1: the last segment only
+    per = sizes[2] - sizes[1]
+    assert per > 11 * 8192 * 8 and sizes[3] - sizes[2] == per
+    assert sizes[4] == sizes[1] + 9 * per and sizes[5] == sizes[4]   # at most the 10 segments
+    for bad in (-1, 65):
+        c = native.make_config(cfg, "f64", tape_segments=bad)
+        assert L.mpm_workspace_bytes(ct.byref(c), 8192, 100, 10, ct.byref(nb)) == native.MPM_EINVAL
+        assert b"tape_segments" in L.mpm_last_error(None)

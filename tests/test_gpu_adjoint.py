@@ -40,9 +40,9 @@ def friction_case(scale_steps=60):
     return cfg, x0, v0, mu, tr, frames, tgt, scale_steps
 
 
-def run_gpu(cfg, precision, x0, v0, mu, steps, k, obs):
+def run_gpu(cfg, precision, x0, v0, mu, steps, k, obs, tape_segments=0):
     from paper_2507_04192_amd.native import Solver
-    s = Solver(cfg, precision, capacity=x0.shape[1], tape_steps=steps, ckpt_every=k)
+    s = Solver(cfg, precision, capacity=x0.shape[1], tape_steps=steps, ckpt_every=k, tape_segments=tape_segments)
     s.mpm_init_particles(x0, v0)
     if mu is not None:
         s.mpm_set_floor_mu(mu)
@@ -141,6 +141,31 @@ def test_checkpoint_interval_does_not_change_gradient(orc):
         else:
             assert loss == ref[0]
             assert rel_l2(gv, ref[1]) <= 1e-12 and rel_l2(gmu, ref[2]) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_taped_segments_do_not_change_gradient(orc, precision):
+    """Trailing segments kept on the tape (1, 2, 3 of 6, all 6, more than
+    there are) instead of recomputed: the same loss bit for bit (the forward
+    step is deterministic) and the same gradient up to the order of the
+    reverse step's LDS atomics; a second backward recomputes every segment."""
+    cfg, x0, v0, mu, tr, frames, tgt, steps = friction_case(40)
+    if precision == "f32":
+        x0, v0, mu, tgt = (a.astype(np.float32).astype(np.float64) for a in (x0, v0, mu, tgt))
+    obs = dict(frames=frames, tracer_pid=tr, lag_field="x", lag_target=tgt)
+    tol = 1e-12 if precision == "f64" else 1e-5
+    ref = None
+    for ns in (1, 2, 3, 6, 9):
+        loss, gv, gmu, s = run_gpu(cfg, precision, x0, v0, mu, steps, 7, obs, tape_segments=ns)
+        gv2, gmu2 = s.mpm_backward()
+        assert s.mpm_sync_status()[0] == 0
+        s.close()
+        assert rel_l2(_np(gv2), gv) <= tol and rel_l2(_np(gmu2), gmu) <= tol
+        if ref is None:
+            ref = (loss, gv, gmu)
+        else:
+            assert loss == ref[0], ns
+            assert rel_l2(gv, ref[1]) <= tol and rel_l2(gmu, ref[2]) <= tol, ns
 
 
 def test_second_backward_recomputes_every_segment():
