@@ -16,7 +16,9 @@ checkpoint every 100 by default), keeping as many trailing segments on the
 tape as three quarters of the free device memory holds (the backward sweep
 recomputes only the others).
 
-The other_configs leg times the forward step of the other benchmark
+The late_phase leg times the FP32 step again after 3000 steps, when the
+sand has spread and moves faster (the headline value is the first 1000
+steps from rest).  The other_configs leg times the forward step of the other benchmark
 configurations (the 2-D dam-breaks and granular block, the 3-D dam-break)
 without per-kernel events.  The variants leg times the other forms of the step: the cylinder with the
 hypoelastic Drucker-Prager material (Jaumann rate, App. A) and with the PIC,
@@ -292,6 +294,36 @@ def run_variants(steps, steps64, warmup):
     return out
 
 
+def run_late_phase(cfg, x, precision, before, steps):
+    """The same step later in the collapse: time `steps` steps after
+    `before` untimed ones, when the sand has spread over more tiles and
+    moves faster (per-kernel events on)."""
+    import torch
+    from paper_2507_04192_amd.native import Solver
+    s = Solver(cfg, precision, capacity=x.shape[1])
+    s.mpm_init_particles(x)
+    s.mpm_step(before)
+    rc, bad = s.mpm_sync_status()
+    if rc != 0:
+        raise RuntimeError(f"solver status {rc} (pid {bad}) before the late phase")
+    torch.cuda.synchronize()
+    s.mpm_profile_enable(True)
+    s.mpm_profile_read()
+    t0 = time.perf_counter()
+    s.mpm_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.mpm_profile_read()
+    rc, bad = s.mpm_sync_status()
+    s.close()
+    if rc != 0:
+        raise RuntimeError(f"solver status {rc} (pid {bad}) in the late phase")
+    n = x.shape[1]
+    return {"after_steps": before, "steps": steps, "value": n * steps / (t1 - t0), "unit": "particle-steps/s",
+            "ms_per_step": (t1 - t0) / steps * 1e3,
+            "kernels_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in prof.items() if v[1] > 0}}
+
+
 def run_other_configs(steps, warmup):
     """Forward throughput of the other benchmark configurations (binary32 and
     binary64, the same kernels and launch shapes as the cylinder): the 2-D
@@ -442,6 +474,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the other forms of the step")
     ap.add_argument("--variant-steps", type=int, default=500, help="binary32 steps per variant (binary64: half)")
     ap.add_argument("--no-configs", action="store_true", help="skip the other benchmark configurations")
+    ap.add_argument("--no-late", action="store_true", help="skip the late-phase timing of the collapse")
+    ap.add_argument("--late-after", type=int, default=3000, help="untimed steps before the late-phase timing")
     ap.add_argument("--config-steps", type=int, default=1000, help="steps per other configuration")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (counter calibration)")
@@ -524,6 +558,11 @@ def main():
     configs = None
     if not args.no_configs and args.scale_div == 1:
         configs = run_other_configs(args.config_steps, args.warmup)
+    late = None
+    if not args.no_late:
+        late = run_late_phase(cfg, x, "f32", args.late_after, min(args.steps, 500))
+        log(f"[bench] f32 after {args.late_after} steps: {late['ms_per_step']:.4f} ms/step, "
+            f"{late['value']:.4e} particle-steps/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -558,6 +597,7 @@ def main():
         "kernels_us": {k: round(v["avg_ms"] * 1e3, 2) for k, v in kernels.items()},
         "f64": out_f64,
         "fwd_adjoint": adj,
+        "late_phase": late,
         "variants": variants,
         "other_configs": configs,
         "paper_context": {"value_f32": 1.22e8, "value_f64": 2.76e7,
