@@ -22,8 +22,12 @@ steps from rest).  The other_configs leg times the forward step of the other ben
 configurations (the 2-D dam-breaks and granular block, the 3-D dam-break)
 without per-kernel events.  The variants leg times the other forms of the step: the cylinder with the
 hypoelastic Drucker-Prager material (Jaumann rate, App. A) and with the PIC,
-TPIC and FLIP transfers, and the 3-D dam-break against two rigid columns
-with a viscous fluid (Sec. 4.2.1, 1,920,000 particles on 200 x 100 x 80).
+TPIC and FLIP transfers, the 3-D dam-break against two rigid columns
+with a viscous fluid (Sec. 4.2.1, 1,920,000 particles on 200 x 100 x 80),
+and the paper's two granular timing cases on its own grids: the cylinder
+collapse on 400 x 400 x 100 (2,713,580 particles) and the column of aspect
+ratio 3 on 400 x 32 x 200 (2,408,448 particles), each set beside the
+paper's single-A100 figures.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -256,6 +260,7 @@ def roofline(prof, n_particles, elem):
 #   (viscous) fluid: x v C J            16
 VARIANT_STATE_SCALARS = {"sand_apic": 24, "sand_tpic": 24, "sand_pic": 15, "sand_flip": 15,
                          "dp_jaumann": 22, "fluid": 16}
+FORM_OF = {"paper_cylinder": "dp_jaumann", "paper_column": "dp_jaumann"}
 
 
 def run_variants(steps, steps64, warmup):
@@ -264,6 +269,8 @@ def run_variants(steps, steps64, warmup):
     from paper_2507_04192_amd import workloads as W
     cyl, xc = W.cylinder_collapse_3d(seed=0)
     col, xd = W.dam_break_columns_3d(seed=0)
+    pcy, xpc = W.cylinder_paper_grid(seed=0)
+    pco, xpo = W.granular_column_paper(seed=0)
     legs = [
         ("cylinder, hypoelastic Drucker-Prager (Jaumann rate, App. A)", "dp_jaumann",
          cyl.replace(material=W.DP_JAUMANN), xc, ("f32", "f64")),
@@ -272,7 +279,15 @@ def run_variants(steps, steps64, warmup):
         ("cylinder, FLIP/PIC blend alpha = 0.95", "sand_flip", cyl.replace(transfer=W.FLIP, flip_alpha=0.95), xc,
          ("f32",)),
         ("3-D dam-break against two rigid columns, viscous fluid (Sec. 4.2.1)", "fluid", col, xd, ("f32", "f64")),
+        ("3-D cylinder collapse on the paper's 400 x 400 x 100 grid, hypoelastic Drucker-Prager (Sec. 4.2.3)",
+         "paper_cylinder", pcy, xpc, ("f32", "f64")),
+        ("3-D granular column a = 3 on the paper's 400 x 32 x 200 grid, hypoelastic Drucker-Prager (Sec. 4.2.2)",
+         "paper_column", pco, xpo, ("f32", "f64")),
     ]
+    # the paper's single-A100 timings of the same cases (s per 1000 steps,
+    # FP32 / FP64, Table tab:simulation_params) and its particle counts
+    paper = {"fluid": (1920000, 8.2, 35.1), "paper_cylinder": (2712960, 22.3, 98.4),
+             "paper_column": (2408448, 16.2, 69.3)}
     out = []
     for name, form, cfg, x, precs in legs:
         n = x.shape[1]
@@ -283,13 +298,17 @@ def run_variants(steps, steps64, warmup):
             t, _, prof = run_gpu(cfg, x, prec, k, warmup)
             val = n * k / t
             r[prec] = {"value": val, "unit": "particle-steps/s", "steps": k, "ms_per_step": t / k * 1e3,
-                       "step_roofline": step_roofline(val, 2 * VARIANT_STATE_SCALARS[form], elem),
+                       "step_roofline": step_roofline(val, 2 * VARIANT_STATE_SCALARS[FORM_OF.get(form, form)],
+                                                      elem),
                        "kernels_us": {kk: round(v[0] / v[1] * 1e3, 2) for kk, v in prof.items() if v[1] > 0}}
             log(f"[bench] variant {name} {prec}: {t / k * 1e3:.4f} ms/step, {val:.4e} particle-steps/s")
-        if form == "fluid":
-            r["paper_context"] = {"value_f32": 1920000 * 1000 / 8.2, "value_f64": 1920000 * 1000 / 35.1,
-                                  "note": "paper, one A100: 8.2 / 35.1 s per 1000 steps on the same "
-                                          "particle count and grid"}
+        if form in paper:
+            pn, s32, s64 = paper[form]
+            ctx = {"value_f32": pn * 1000 / s32, "value_f64": pn * 1000 / s64,
+                   "note": f"paper, one A100: {s32} / {s64} s per 1000 steps, {pn:,} particles on the same grid"}
+            for prec in precs:
+                ctx[f"ratio_{prec}"] = r[prec]["value"] / ctx[f"value_{prec}"]
+            r["paper_context"] = ctx
         out.append(r)
     return out
 
@@ -602,7 +621,8 @@ def main():
         "other_configs": configs,
         "paper_context": {"value_f32": 1.22e8, "value_f64": 2.76e7,
                           "note": "paper, one A100, 2,712,960-particle cylinder on 400x400x100; "
-                                  "a different machine and grid, not this workload"},
+                                  "a different machine and grid, not this workload (the variants "
+                                  "leg times that case)"},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -387,18 +387,26 @@ def test_step_is_deterministic(orc, precision):
         assert np.array_equal(out[0][f], out[1][f]), f
 
 
-@pytest.mark.parametrize("case", ["cylinder", "dambreak3d", "cylinder_jaumann", "columns"])
+@pytest.mark.parametrize("case", ["cylinder", "dambreak3d", "cylinder_jaumann", "columns", "paper_cylinder",
+                                  "paper_column"])
 def test_full_size_steps_match_oracle(orc, case):
     """Full-size workloads in the launch configuration the bench times: the
     3-D cylinder collapse (2,780,928 particles, Drucker-Prager sand with the
     Hencky return, and with the hypoelastic material of App. A), the 3-D
     dam-break of the friction problem (1,843,200 particles, fluid) and the
     3-D dam-break against two columns (1,920,000 particles, viscous fluid,
-    Sec. 4.2.1).  Ten steps in binary64 and binary32 against one oracle run
-    from the same binary32-rounded input, whole arrays compared (positions,
+    Sec. 4.2.1), and the paper's two granular timing cases on its own grids
+    (Sec. 4.2.2-4.2.3: the cylinder on 400 x 400 x 100, 2,713,580
+    particles; the column on 400 x 32 x 200, 2,408,448).  Ten steps in
+    binary64 and binary32 against one oracle run from the same
+    binary32-rounded input, whole arrays compared (positions,
     displacements, velocities)."""
     from paper_2507_04192_amd.native import Solver
-    if case.startswith("cylinder"):
+    if case == "paper_cylinder":
+        cfg, x = W.cylinder_paper_grid()
+    elif case == "paper_column":
+        cfg, x = W.granular_column_paper()
+    elif case.startswith("cylinder"):
         cfg, x = W.cylinder_collapse_3d(scale_div=1, seed=0)
         if case == "cylinder_jaumann":
             cfg = cfg.replace(material=W.DP_JAUMANN)

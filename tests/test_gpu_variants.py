@@ -292,3 +292,24 @@ def test_dam_break_columns_paper_geometry(orc, precision):
     for a in range(2):
         deep &= (g["x"][a] > lo[a] + h) & (g["x"][a] < hi[a] - h)
     assert not deep.any()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["cylinder", "column"])
+def test_paper_granular_timing_cases(orc, precision, case):
+    """The paper's two granular timing cases (Sec. 4.2.2-4.2.3: hypoelastic
+    Drucker-Prager sand on a no-slip base, dt = 1e-5 s) at 1/8 scale: the
+    cylinder on 50 x 50 x 12 cells and the column of aspect ratio 3 on
+    50 x 32 x 25, from a sheared, rotating and partly diverging velocity so
+    that the 10 steps leave the elastic zone and reach the base."""
+    if case == "cylinder":
+        cfg, x = W.cylinder_paper_grid(scale_div=8, seed=0)
+    else:
+        cfg, x = W.granular_column_paper(scale_div=8, seed=0)
+    assert cfg.material == W.DP_JAUMANN and cfg.wall_mode[4] == W.STICK
+    print(f"[case] paper's {case} / 8, dp_jaumann, {precision} N={x.shape[1]}", flush=True)
+    v = _moving_velocity(cfg, x, frac=0.02, div=1.0)
+    zones = _zone_counts(orc, cfg, oracle_state(orc, cfg, *_rounded(precision, x, v)), cfg.dt)
+    _run_pair(orc, cfg, precision, x, v)
+    print(f"  zones of the first update (I, II, III): {zones[1:]}", flush=True)
+    assert zones[2] > 0

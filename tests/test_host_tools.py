@@ -60,3 +60,19 @@ def test_measured_traffic_sums_kernels_and_checks_the_sources(tmp_path, monkeypa
     t["csrc_sha256"] = "0" * 64            # counters taken on other sources
     f.write_text(json.dumps(t))
     assert bench.measured_traffic("a") is None
+
+
+def test_paper_timing_cases_match_the_table():
+    """The paper's granular timing cases (Table tab:simulation_params): the
+    column's particle count is the table's exactly, the cylinder's within
+    0.03%; grid, spacing and the App. A material as the paper states."""
+    from paper_2507_04192_amd import workloads as W
+    col, xc = W.granular_column_paper()
+    assert col.n == (400, 32, 200) and xc.shape[1] == 2408448
+    cyl, xy = W.cylinder_paper_grid()
+    assert cyl.n == (400, 400, 100) and abs(xy.shape[1] - 2712960) <= 0.0003 * 2712960
+    for cfg in (col, cyl):
+        assert cfg.dx == 1 / 400 and cfg.dt == 1e-5 and cfg.material == W.DP_JAUMANN
+        assert cfg.rho0 == 2650.0 and cfg.poisson == 0.3 and cfg.phi_deg == 30.0
+        assert abs(cfg.youngs / (3 * (1 - 2 * cfg.poisson)) - 0.7e6) < 1e-6
+        assert cfg.wall_mode[4] == W.STICK
