@@ -7,7 +7,10 @@ imports it and the two share no code: this package and the HIP library are
 independent implementations of the same equations.
 
 ``build()`` compiles ``mpm_oracle.c`` (and the adjoint) with gcc into
-``liborc.so`` beside this file; ``lib()`` loads it.
+``liborc.so`` beside this file; ``lib()`` loads it.  It also compiles the
+forward step a second time with complex binary64 data into
+``liborc_cs.so`` (``cs_lib()``), for complex-step derivatives of the
+forward step that check the hand-written adjoint.
 """
 from __future__ import annotations
 
@@ -20,6 +23,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["mpm_oracle.c", "mpm_oracle_adjoint.c"]
 LIB_PATH = os.path.join(HERE, "liborc.so")
+CS_LIB_PATH = os.path.join(HERE, "liborc_cs.so")
 
 ORC_FLUID, ORC_DP_HENCKY, ORC_HENCKY_ELASTIC, ORC_DP_JAUMANN = 0, 1, 2, 3
 _MAT = {"fluid": ORC_FLUID, "sand": ORC_DP_HENCKY, "elastic": ORC_HENCKY_ELASTIC,
@@ -35,6 +39,12 @@ def build(opt: str = "-O2", extra=()) -> str:
            "-shared", *extra, *srcs, "-o", LIB_PATH + ".tmp", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    # the forward step with complex data; -Bsymbolic keeps its calls inside it
+    cmd = ["gcc", opt, "-ffp-contract=off", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC",
+           "-shared", "-DORC_COMPLEX_STEP", "-Wl,-Bsymbolic", *extra, os.path.join(HERE, "mpm_oracle.c"),
+           "-o", CS_LIB_PATH + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(CS_LIB_PATH + ".tmp", CS_LIB_PATH)
     return LIB_PATH
 
 
@@ -65,6 +75,25 @@ def lib():
         _lib = ct.CDLL(LIB_PATH)
         _declare(_lib)
     return _lib
+
+
+_cs_lib = None
+
+
+def cs_lib():
+    """The complex-step build of the forward step (orc_step and its stages
+    with complex binary64 data; branches taken on the real parts)."""
+    global _cs_lib
+    if _cs_lib is None:
+        if not os.path.exists(CS_LIB_PATH):
+            build()
+        _cs_lib = ct.CDLL(CS_LIB_PATH)
+        P = ct.c_void_p
+        _cs_lib.orc_step.restype = ct.c_int
+        _cs_lib.orc_step.argtypes = [P, ct.c_int64, ct.c_double] + [P] * 12
+        _cs_lib.orc_node_dims.restype = ct.c_int64
+        _cs_lib.orc_node_dims.argtypes = [P, P]
+    return _cs_lib
 
 
 def _declare(L):
@@ -328,6 +357,26 @@ class Oracle:
             return perm, key, gm, gv
         return perm, key
 
+    def step_complex(self, st: State, dt, floor_mu=None):
+        """One step of the complex-step build, in place: st's float fields
+        hold complex128 arrays (a real state plus i h times a direction), as
+        may floor_mu.  The real parts follow step() to rounding (the complex
+        square root, logarithm, exponential and power round differently from
+        the real ones); the imaginary parts divided by h are the step's
+        directional derivative."""
+        c128 = lambda a: np.ascontiguousarray(a, dtype=np.complex128)
+        for k in ("x", "v", "C", "F", "J", "S"):
+            setattr(st, k, c128(getattr(st, k)))
+        perm = np.empty(st.N, dtype=np.int32)
+        key = np.empty(st.N, dtype=np.int32)
+        fm = None if floor_mu is None else c128(floor_mu)
+        rc = cs_lib().orc_step(ct.byref(self.c), st.N, dt, _ptr(fm), _ptr(st.x), _ptr(st.v),
+                               _ptr(st.C), _ptr(st.F), _ptr(st.J), _ptr(st.S), _ptr(st.pid),
+                               _ptr(perm), _ptr(key), None, None)
+        if rc != 0:
+            raise MemoryError("oracle step failed to allocate")
+        return perm, key
+
     def run(self, st: State, steps, dt, floor_mu=None):
         for _ in range(steps):
             self.step(st, dt, floor_mu)
@@ -378,10 +427,11 @@ def observe(st, obs, fi):
     if obs.box_lo is not None:
         z = getattr(st, obs.eul_field)
         nb = obs.box_lo.shape[0]
-        eul = np.zeros((z.shape[0], nb))
+        eul = np.zeros((z.shape[0], nb), dtype=z.dtype)
         cnt = np.zeros(nb, dtype=np.int64)
+        xr = np.real(st.x)   # membership from the positions (their real part in a complex step)
         for b in range(nb):
-            inside = np.all((st.x >= obs.box_lo[b][:, None]) & (st.x < obs.box_hi[b][:, None]), axis=0)
+            inside = np.all((xr >= obs.box_lo[b][:, None]) & (xr < obs.box_hi[b][:, None]), axis=0)
             cnt[b] = inside.sum()
             if cnt[b] > 0:
                 eul[:, b] = z[:, inside].mean(axis=1)

@@ -49,28 +49,50 @@
 
 #include "mpm_oracle.h"
 
+/* The number type of the particle and grid data, orc_real, is binary64
+ * (double) in the oracle proper.  Built with ORC_COMPLEX_STEP it is a
+ * complex binary64 number instead, for the complex-step derivative
+ * f'(a) delta = Im f(a + i h delta) / h of the adjoint's checks: every
+ * branch is then taken on the real part and the functions below are the
+ * analytic continuations of the real ones. */
+#ifdef ORC_COMPLEX_STEP
+#define RE(a) creal(a)
+#define ABS(a) (creal(a) < 0.0 ? -(a) : (a))
+#define SQRT csqrt
+#define LOG clog
+#define EXP cexp
+#define POW cpow
+#else
+#define RE(a) (a)
+#define ABS fabs
+#define SQRT sqrt
+#define LOG log
+#define EXP exp
+#define POW pow
+#endif
+
 /* ------------------------------------------------------------------ */
 /* Quadratic B-spline (Sec. 2.1, the piecewise definition of phi-bar) */
 /* ------------------------------------------------------------------ */
 
-double orc_phibar(double xi)
+orc_real orc_phibar(orc_real xi)
 {
-    double a = fabs(xi);
-    if (a < 0.5)
+    orc_real a = ABS(xi);
+    if (RE(a) < 0.5)
         return 0.75 - a * a;
-    if (a < 1.5)
+    if (RE(a) < 1.5)
         return 0.5 * a * a - 1.5 * a + 1.125;
     return 0.0;
 }
 
 /* d phibar / d xi */
-double orc_dphibar(double xi)
+orc_real orc_dphibar(orc_real xi)
 {
-    double a = fabs(xi);
-    double s = (xi < 0.0) ? -1.0 : 1.0;
-    if (a < 0.5)
+    orc_real a = ABS(xi);
+    double s = (RE(xi) < 0.0) ? -1.0 : 1.0;
+    if (RE(a) < 0.5)
         return -2.0 * xi;
-    if (a < 1.5)
+    if (RE(a) < 1.5)
         return s * (a - 1.5);
     return 0.0;
 }
@@ -78,22 +100,25 @@ double orc_dphibar(double xi)
 /* Base node and the three 1-D weights / derivatives (per unit length) for
  * one coordinate.  key_f32 selects binary32 for t = x*inv so that keys can
  * be compared bit for bit with a binary32 solver. */
-void orc_stencil_1d(double x, double h, int key_f32, int32_t* base,
-                    double w[3], double dw[3])
+void orc_stencil_1d(orc_real x, double h, int key_f32, int32_t* base,
+                    orc_real w[3], orc_real dw[3])
 {
-    double t;
+    orc_real t;
     if (key_f32) {
         float invf = 1.0f / (float)h;
-        float tf = (float)x * invf;
-        t = (double)tf;
+        float tf = (float)RE(x) * invf;
+        t = (orc_real)tf;
+#ifdef ORC_COMPLEX_STEP
+        t += cimag(x) * (1.0 / h) * _Complex_I;
+#endif
     } else {
         double inv = 1.0 / h;
         t = x * inv;
     }
-    int32_t b = (int32_t)floor(t - 0.5);
+    int32_t b = (int32_t)floor(RE(t) - 0.5);
     *base = b;
     for (int k = 0; k < 3; ++k) {
-        double xi = t - (double)(b + k); /* (x - x_i)/h */
+        orc_real xi = t - (orc_real)(b + k); /* (x - x_i)/h */
         w[k] = orc_phibar(xi);
         dw[k] = orc_dphibar(xi) / h;
     }
@@ -152,14 +177,14 @@ int64_t orc_key_of_base(const orc_config* c, const int32_t B[3])
     return tile_lin * cells_stride + cell_lin;
 }
 
-void orc_cell_keys(const orc_config* c, int64_t N, const double* x, int32_t* key)
+void orc_cell_keys(const orc_config* c, int64_t N, const orc_real* x, int32_t* key)
 {
     int d = dimv(c);
     for (int64_t p = 0; p < N; ++p) {
         int32_t B[3] = {0, 0, 0};
         for (int a = 0; a < d; ++a) {
             int32_t b;
-            double w[3], dw[3];
+            orc_real w[3], dw[3];
             orc_stencil_1d(x[a * N + p], c->dx, c->key_f32, &b, w, dw);
             B[a] = b + c->ghost;
         }
@@ -231,12 +256,12 @@ void orc_sort_perm(int64_t N, const int32_t* key, int32_t cpt, int32_t* perm)
     free(ks);
 }
 
-static void gather_d(int64_t N, int ncomp, double* a, const int32_t* perm, double* tmp)
+static void gather_d(int64_t N, int ncomp, orc_real* a, const int32_t* perm, orc_real* tmp)
 {
     for (int c = 0; c < ncomp; ++c) {
         for (int64_t s = 0; s < N; ++s)
             tmp[s] = a[c * N + perm[s]];
-        memcpy(a + c * N, tmp, sizeof(double) * (size_t)N);
+        memcpy(a + c * N, tmp, sizeof(orc_real) * (size_t)N);
     }
 }
 
@@ -254,11 +279,11 @@ static void gather_i(int64_t N, int32_t* a, const int32_t* perm, int32_t* tmp)
 /* Per-particle stencil: node indices and phi, grad phi, x_i - x_p. */
 typedef struct {
     int32_t base[3];
-    double w[3][3];  /* [axis][k] */
-    double dw[3][3];
+    orc_real w[3][3];  /* [axis][k] */
+    orc_real dw[3][3];
 } stencil;
 
-static void make_stencil(const orc_config* c, int64_t N, const double* x, int64_t p, stencil* st)
+static void make_stencil(const orc_config* c, int64_t N, const orc_real* x, int64_t p, stencil* st)
 {
     for (int a = 0; a < 3; ++a) {
         st->base[a] = 0;
@@ -273,11 +298,11 @@ static void make_stencil(const orc_config* c, int64_t N, const double* x, int64_
 }
 
 /* For stencil offset (k0,k1,k2): phi, grad phi and dpos = x_i - x_p. */
-static void stencil_node(const orc_config* c, const double* xp, const stencil* st,
-                         const int k[3], double* phi, double grad[3], double dpos[3], int32_t I[3])
+static void stencil_node(const orc_config* c, const orc_real* xp, const stencil* st,
+                         const int k[3], orc_real* phi, orc_real grad[3], orc_real dpos[3], int32_t I[3])
 {
     int d = c->dim;
-    double ph = 1.0;
+    orc_real ph = 1.0;
     for (int a = 0; a < d; ++a)
         ph *= st->w[a][k[a]];
     *phi = ph;
@@ -287,19 +312,19 @@ static void stencil_node(const orc_config* c, const double* xp, const stencil* s
         I[a] = 0;
     }
     for (int a = 0; a < d; ++a) {
-        double g = st->dw[a][k[a]];
+        orc_real g = st->dw[a][k[a]];
         for (int b = 0; b < d; ++b)
             if (b != a) g *= st->w[b][k[b]];
         grad[a] = g;
         int32_t node = st->base[a] + k[a];
-        dpos[a] = (double)node * c->dx - xp[a];
+        dpos[a] = (orc_real)node * c->dx - xp[a];
         I[a] = node + c->ghost;
     }
 }
 
 void orc_p2g(const orc_config* c, int64_t N, double dt,
-             const double* x, const double* v, const double* C, const double* S,
-             double* gm, double* gp)
+             const orc_real* x, const orc_real* v, const orc_real* C, const orc_real* S,
+             orc_real* gm, orc_real* gp)
 {
     orc_p2g_ex(c, N, dt, x, v, C, S, gm, gp, NULL);
 }
@@ -308,20 +333,20 @@ void orc_p2g(const orc_config* c, int64_t N, double dt,
  * internal force, sum phi m_p (v_p + C_p (x_i - x_p)), from which the grid
  * velocity before the update, v_i^n = gq / m_i, is formed for FLIP. */
 void orc_p2g_ex(const orc_config* c, int64_t N, double dt,
-                const double* x, const double* v, const double* C, const double* S,
-                double* gm, double* gp, double* gq)
+                const orc_real* x, const orc_real* v, const orc_real* C, const orc_real* S,
+                orc_real* gm, orc_real* gp, orc_real* gq)
 {
     int d = dimv(c);
     int32_t dims[3];
     int64_t NN = orc_node_dims(c, dims);
-    memset(gm, 0, sizeof(double) * (size_t)NN);
-    memset(gp, 0, sizeof(double) * (size_t)(NN * d));
-    if (gq) memset(gq, 0, sizeof(double) * (size_t)(NN * d));
+    memset(gm, 0, sizeof(orc_real) * (size_t)NN);
+    memset(gp, 0, sizeof(orc_real) * (size_t)(NN * d));
+    if (gq) memset(gq, 0, sizeof(orc_real) * (size_t)(NN * d));
     int kz_max = (d == 3) ? 3 : 1;
     for (int64_t p = 0; p < N; ++p) {
         stencil st;
         make_stencil(c, N, x, p, &st);
-        double xp[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
+        orc_real xp[3] = {0, 0, 0}, vp[3] = {0, 0, 0};
         for (int a = 0; a < d; ++a) {
             xp[a] = x[a * N + p];
             vp[a] = v[a * N + p];
@@ -330,14 +355,14 @@ void orc_p2g_ex(const orc_config* c, int64_t N, double dt,
             for (int k1 = 0; k1 < 3; ++k1)
                 for (int k0 = 0; k0 < 3; ++k0) {
                     int k[3] = {k0, k1, k2};
-                    double phi, grad[3], dpos[3];
+                    orc_real phi, grad[3], dpos[3];
                     int32_t I[3];
                     stencil_node(c, xp, &st, k, &phi, grad, dpos, I);
                     int64_t li = node_lin(dims, I);
                     gm[li] += phi * c->mass;
                     for (int a = 0; a < d; ++a) {
-                        double aff = 0.0;   /* (C_p (x_i - x_p))_a */
-                        double frc = 0.0;   /* (S_p grad phi)_a */
+                        orc_real aff = 0.0;   /* (C_p (x_i - x_p))_a */
+                        orc_real frc = 0.0;   /* (S_p grad phi)_a */
                         for (int b = 0; b < d; ++b) {
                             aff += C[(a * d + b) * N + p] * dpos[b];
                             frc += S[(a * d + b) * N + p] * grad[b];
@@ -354,14 +379,14 @@ void orc_p2g_ex(const orc_config* c, int64_t N, double dt,
 /* ------------------------------------------------------------------ */
 
 /* Coulomb / slip / stick on one node for the wall with outward normal nrm. */
-static void wall_apply(int d, int mode, double mu, const double nrm[3], double vel[3])
+static void wall_apply(int d, int mode, orc_real mu, const double nrm[3], orc_real vel[3])
 {
-    double vn = 0.0;
+    orc_real vn = 0.0;
     for (int a = 0; a < d; ++a)
         vn += vel[a] * nrm[a];
-    if (!(vn > 0.0))
+    if (!(RE(vn) > 0.0))
         return; /* separating or resting: no constraint */
-    double vt[3] = {0, 0, 0}, vtn2 = 0.0;
+    orc_real vt[3] = {0, 0, 0}, vtn2 = 0.0;
     for (int a = 0; a < d; ++a) {
         vt[a] = vel[a] - vn * nrm[a];
         vtn2 += vt[a] * vt[a];
@@ -378,12 +403,12 @@ static void wall_apply(int d, int mode, double mu, const double nrm[3], double v
     }
     /* Coulomb with a resting wall (v_cm = 0): remove the normal part and
      * reduce the tangential speed by mu * v_n, stopping if it would reverse. */
-    double vtn = sqrt(vtn2);
-    if (vtn <= mu * vn) {
+    orc_real vtn = SQRT(vtn2);
+    if (RE(vtn) <= RE(mu * vn)) {
         for (int a = 0; a < d; ++a)
             vel[a] = 0.0;
     } else {
-        double scale = 1.0 - mu * vn / vtn;
+        orc_real scale = 1.0 - mu * vn / vtn;
         for (int a = 0; a < d; ++a)
             vel[a] = vt[a] * scale;
     }
@@ -397,7 +422,7 @@ static void wall_apply(int d, int mode, double mu, const double nrm[3], double v
  * as for the walls and in the contact method the paper cites, the
  * correction acts only while the node moves into the obstacle; obstacles
  * are applied after the walls, in their order. */
-void orc_obstacles(const orc_config* c, const int32_t I[3], double vel[3])
+void orc_obstacles(const orc_config* c, const int32_t I[3], orc_real vel[3])
 {
     int d = dimv(c);
     for (int o = 0; o < c->n_obstacles; ++o) {
@@ -424,13 +449,13 @@ void orc_obstacles(const orc_config* c, const int32_t I[3], double vel[3])
             }
         if (best_a < 0) continue;
         /* n points into the obstacle: +e_a through its lower face */
-        double vn = best_side == 0 ? vel[best_a] : -vel[best_a];
-        if (vn > 0.0) vel[best_a] = 0.0;
+        orc_real vn = best_side == 0 ? vel[best_a] : -vel[best_a];
+        if (RE(vn) > 0.0) vel[best_a] = 0.0;
     }
 }
 
-void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
-                     const double* gm, const double* gp, double* gv)
+void orc_grid_update(const orc_config* c, double dt, const orc_real* floor_mu,
+                     const orc_real* gm, const orc_real* gp, orc_real* gv)
 {
     int d = dimv(c);
     int32_t dims[3];
@@ -441,8 +466,8 @@ void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
             for (int32_t Ix = 0; Ix < dims[0]; ++Ix) {
                 int32_t I[3] = {Ix, Iy, Iz};
                 int64_t li = node_lin(dims, I);
-                double vel[3] = {0, 0, 0};
-                if (gm[li] > 0.0) {
+                orc_real vel[3] = {0, 0, 0};
+                if (RE(gm[li]) > 0.0) {
                     for (int a = 0; a < d; ++a)
                         vel[a] = gp[a * NN + li] / gm[li] + dt * c->gravity[a];
                 }
@@ -455,7 +480,7 @@ void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
                             continue;
                         double nrm[3] = {0, 0, 0};
                         nrm[a] = side == 0 ? -1.0 : 1.0;
-                        double mu = c->wall_mu[face];
+                        orc_real mu = c->wall_mu[face];
                         if (floor_mu && a == fl && side == 0) {
                             int64_t fi = (d == 3) ? ((int64_t)Iy * dims[0] + Ix) : Ix;
                             mu = floor_mu[fi];
@@ -463,7 +488,7 @@ void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
                         wall_apply(d, c->wall_mode[face], mu, nrm, vel);
                     }
                 }
-                if (gm[li] > 0.0) orc_obstacles(c, I, vel);
+                if (RE(gm[li]) > 0.0) orc_obstacles(c, I, vel);
                 for (int a = 0; a < d; ++a)
                     gv[a * NN + li] = vel[a];
             }
@@ -473,8 +498,8 @@ void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
 /* G2P (Sec. 2.2 PIC velocity, position, velocity gradient; App. B)   */
 /* ------------------------------------------------------------------ */
 
-void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
-             double* x, double* v, double* C, double* L)
+void orc_g2p(const orc_config* c, int64_t N, double dt, const orc_real* gv,
+             orc_real* x, orc_real* v, orc_real* C, orc_real* L)
 {
     orc_g2p_ex(c, N, dt, gv, NULL, x, v, C, L);
 }
@@ -489,8 +514,8 @@ void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
  * v_i^{n+1} after the walls and obstacles and v_i^n = gq / m (gvo), so the
  * boundary conditions reach FLIP particles too.  Every transfer moves the
  * particle with the interpolated new grid velocity. */
-void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const double* gv, const double* gvo,
-                double* x, double* v, double* C, double* L)
+void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const orc_real* gv, const orc_real* gvo,
+                orc_real* x, orc_real* v, orc_real* C, orc_real* L)
 {
     int d = dimv(c);
     int32_t dims[3];
@@ -500,21 +525,21 @@ void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const double* gv, con
     for (int64_t p = 0; p < N; ++p) {
         stencil st;
         make_stencil(c, N, x, p, &st);
-        double xp[3] = {0, 0, 0};
+        orc_real xp[3] = {0, 0, 0};
         for (int a = 0; a < d; ++a)
             xp[a] = x[a * N + p];
-        double vn[3] = {0, 0, 0}, vo[3] = {0, 0, 0}, Bm[3][3] = {{0}}, Lm[3][3] = {{0}};
+        orc_real vn[3] = {0, 0, 0}, vo[3] = {0, 0, 0}, Bm[3][3] = {{0}}, Lm[3][3] = {{0}};
         int flip = c->transfer == ORC_FLIP && gvo;
         for (int k2 = 0; k2 < kz_max; ++k2)
             for (int k1 = 0; k1 < 3; ++k1)
                 for (int k0 = 0; k0 < 3; ++k0) {
                     int k[3] = {k0, k1, k2};
-                    double phi, grad[3], dpos[3];
+                    orc_real phi, grad[3], dpos[3];
                     int32_t I[3];
                     stencil_node(c, xp, &st, k, &phi, grad, dpos, I);
                     int64_t li = node_lin(dims, I);
                     for (int a = 0; a < d; ++a) {
-                        double vi = gv[a * NN + li];
+                        orc_real vi = gv[a * NN + li];
                         vn[a] += phi * vi;
                         if (flip) vo[a] += phi * gvo[a * NN + li];
                         for (int b = 0; b < d; ++b) {
@@ -524,16 +549,16 @@ void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const double* gv, con
                     }
                 }
         for (int a = 0; a < d; ++a) {
-            double vnew = vn[a];
+            orc_real vnew = vn[a];
             if (flip) vnew = vn[a] + c->flip_alpha * (v[a * N + p] - vo[a]);
             v[a * N + p] = vnew;
-            double xn = xp[a] + dt * vn[a];
+            orc_real xn = xp[a] + dt * vn[a];
             double hi = (double)c->n[a] * c->dx;
-            if (xn < 0.0) xn = 0.0;
-            if (xn > hi) xn = hi;
+            if (RE(xn) < 0.0) xn = 0.0;
+            if (RE(xn) > hi) xn = hi;
             x[a * N + p] = xn;
             for (int b = 0; b < d; ++b) {
-                double cab;
+                orc_real cab;
                 switch (c->transfer) {
                 case ORC_APIC: cab = Dinv * Bm[a][b]; break;
                 case ORC_TPIC: cab = Lm[a][b]; break;
@@ -550,18 +575,18 @@ void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const double* gv, con
 /* Small dense linear algebra                                           */
 /* ------------------------------------------------------------------ */
 
-static void matmul(int d, const double A[3][3], const double B[3][3], double R[3][3])
+static void matmul(int d, const orc_real A[3][3], const orc_real B[3][3], orc_real R[3][3])
 {
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
-            double s = 0.0;
+            orc_real s = 0.0;
             for (int k = 0; k < d; ++k)
                 s += A[i][k] * B[k][j];
             R[i][j] = s;
         }
 }
 
-static double det(int d, const double A[3][3])
+static orc_real det(int d, const orc_real A[3][3])
 {
     if (d == 2)
         return A[0][0] * A[1][1] - A[0][1] * A[1][0];
@@ -575,43 +600,43 @@ static double det(int d, const double A[3][3])
  * below 1e-15 of the matrix norm (a few units of rounding of the diagonal;
  * a smaller bound is below what rounding lets the rotations reach, and then
  * every call runs out its sweep budget). */
-void orc_sym_eig(int d, const double Ain[9], double ev[3], double Vout[9])
+void orc_sym_eig(int d, const orc_real Ain[9], orc_real ev[3], orc_real Vout[9])
 {
-    double A[3][3], V[3][3];
+    orc_real A[3][3], V[3][3];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
             A[i][j] = (i < d && j < d) ? Ain[i * d + j] : 0.0;
             V[i][j] = (i == j) ? 1.0 : 0.0;
         }
     for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, tot = 0.0;
+        orc_real off = 0.0, tot = 0.0;
         for (int i = 0; i < d; ++i)
             for (int j = 0; j < d; ++j) {
                 tot += A[i][j] * A[i][j];
                 if (i != j) off += A[i][j] * A[i][j];
             }
-        if (off <= 1e-30 * tot || off == 0.0)
+        if (RE(off) <= 1e-30 * RE(tot) || RE(off) == 0.0)
             break;
         for (int p = 0; p < d - 1; ++p)
             for (int q = p + 1; q < d; ++q) {
-                if (A[p][q] == 0.0)
+                if (RE(A[p][q]) == 0.0)
                     continue;
-                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
-                double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                orc_real theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                orc_real t = (RE(theta) >= 0.0 ? 1.0 : -1.0) / (ABS(theta) + SQRT(theta * theta + 1.0));
+                orc_real cs = 1.0 / SQRT(t * t + 1.0), sn = t * cs;
                 /* A <- J^T A J with J the rotation in the (p,q) plane */
                 for (int k = 0; k < d; ++k) {
-                    double akp = A[k][p], akq = A[k][q];
+                    orc_real akp = A[k][p], akq = A[k][q];
                     A[k][p] = cs * akp - sn * akq;
                     A[k][q] = sn * akp + cs * akq;
                 }
                 for (int k = 0; k < d; ++k) {
-                    double apk = A[p][k], aqk = A[q][k];
+                    orc_real apk = A[p][k], aqk = A[q][k];
                     A[p][k] = cs * apk - sn * aqk;
                     A[q][k] = sn * apk + cs * aqk;
                 }
                 for (int k = 0; k < d; ++k) {
-                    double vkp = V[k][p], vkq = V[k][q];
+                    orc_real vkp = V[k][p], vkq = V[k][q];
                     V[k][p] = cs * vkp - sn * vkq;
                     V[k][q] = sn * vkp + cs * vkq;
                 }
@@ -630,9 +655,9 @@ void orc_sym_eig(int d, const double Ain[9], double ev[3], double Vout[9])
 
 /* Tait form of the weakly compressible EOS; gamma = 1 with K = rho0 c^2
  * is eq:eos of Sec. 2.3 written in J = rho0/rho. */
-double orc_fluid_pressure(const orc_config* c, double J)
+orc_real orc_fluid_pressure(const orc_config* c, orc_real J)
 {
-    return (c->bulk / c->gamma) * (pow(1.0 / J, c->gamma) - 1.0);
+    return (c->bulk / c->gamma) * (POW(1.0 / J, c->gamma) - 1.0);
 }
 
 double orc_cone_alpha(const orc_config* c)
@@ -646,58 +671,58 @@ double orc_cone_alpha(const orc_config* c)
  * Ftr: trial elastic deformation gradient (d x d, row-major).
  * Outputs the returned elastic F, the Kirchhoff stress tau and the case
  * (0 apex, 1 elastic, 2 cone).  elastic_only forces the elastic case. */
-int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9],
-                      double Fe[9], double tau[9], double* dgamma)
+int orc_hencky_return(const orc_config* c, int elastic_only, const orc_real Ftr[9],
+                      orc_real Fe[9], orc_real tau[9], orc_real* dgamma)
 {
     int d = c->dim;
     double E = c->youngs, nu = c->poisson;
     double lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
     double mu = E / (2.0 * (1.0 + nu));
-    double F[3][3] = {{0}}, b[9] = {0};
+    orc_real F[3][3] = {{0}}, b[9] = {0};
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j)
             F[i][j] = Ftr[i * d + j];
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
-            double s = 0.0;
+            orc_real s = 0.0;
             for (int k = 0; k < d; ++k)
                 s += F[i][k] * F[j][k];
             b[i * d + j] = s;
         }
-    double ev[3], U[9];
+    orc_real ev[3], U[9];
     orc_sym_eig(d, b, ev, U);
-    double eps[3] = {0, 0, 0}, sv[3] = {1, 1, 1}, tr = 0.0;
+    orc_real eps[3] = {0, 0, 0}, sv[3] = {1, 1, 1}, tr = 0.0;
     for (int i = 0; i < d; ++i) {
-        sv[i] = sqrt(ev[i]);
-        eps[i] = log(sv[i]);
+        sv[i] = SQRT(ev[i]);
+        eps[i] = LOG(sv[i]);
         tr += eps[i];
     }
-    double dev[3] = {0, 0, 0}, devn = 0.0;
+    orc_real dev[3] = {0, 0, 0}, devn = 0.0;
     for (int i = 0; i < d; ++i) {
         dev[i] = eps[i] - tr / d;
         devn += dev[i] * dev[i];
     }
-    devn = sqrt(devn);
-    double H[3] = {0, 0, 0};
+    devn = SQRT(devn);
+    orc_real H[3] = {0, 0, 0};
     int cas;
-    double dg = 0.0;
-    double en2 = 0.0;
+    orc_real dg = 0.0;
+    orc_real en2 = 0.0;
     for (int i = 0; i < d; ++i) en2 += eps[i] * eps[i];
-    if (elastic_only || en2 <= ORC_EPS_ELASTIC * ORC_EPS_ELASTIC) {
+    if (elastic_only || RE(en2) <= ORC_EPS_ELASTIC * ORC_EPS_ELASTIC) {
         /* elastic material, or a strain below the elastic band (reading:
          * the return is not differentiable at zero strain, so the case is
          * fixed there instead of being left to rounding) */
         cas = 1;
         for (int i = 0; i < d; ++i) H[i] = eps[i];
-    } else if (tr > 0.0) {
+    } else if (RE(tr) > 0.0) {
         cas = 0; /* apex: stress free */
-        double en = 0.0;
+        orc_real en = 0.0;
         for (int i = 0; i < d; ++i) en += eps[i] * eps[i];
-        dg = sqrt(en);
+        dg = SQRT(en);
     } else {
         double alpha = orc_cone_alpha(c);
         dg = devn + (d * lam + 2.0 * mu) / (2.0 * mu) * alpha * tr;
-        if (dg <= 0.0) {
+        if (RE(dg) <= 0.0) {
             cas = 1;
             dg = 0.0;
             for (int i = 0; i < d; ++i) H[i] = eps[i];
@@ -706,21 +731,21 @@ int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9]
             for (int i = 0; i < d; ++i) H[i] = eps[i] - dg * dev[i] / devn;
         }
     }
-    double trH = 0.0;
+    orc_real trH = 0.0;
     for (int i = 0; i < d; ++i) trH += H[i];
-    /* Fe = U diag(exp(H)/s) U^T Ftr ; tau = U diag(2 mu H + lam trH) U^T */
-    double M[3][3] = {{0}}, T[3][3] = {{0}};
+    /* Fe = U diag(EXP(H)/s) U^T Ftr ; tau = U diag(2 mu H + lam trH) U^T */
+    orc_real M[3][3] = {{0}}, T[3][3] = {{0}};
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
-            double m = 0.0, t = 0.0;
+            orc_real m = 0.0, t = 0.0;
             for (int k = 0; k < d; ++k) {
-                m += U[i * d + k] * (exp(H[k]) / sv[k]) * U[j * d + k];
+                m += U[i * d + k] * (EXP(H[k]) / sv[k]) * U[j * d + k];
                 t += U[i * d + k] * (2.0 * mu * H[k] + lam * trH) * U[j * d + k];
             }
             M[i][j] = m;
             T[i][j] = t;
         }
-    double R[3][3];
+    orc_real R[3][3];
     if (cas == 1) {
         for (int i = 0; i < d; ++i)
             for (int j = 0; j < d; ++j)
@@ -742,16 +767,16 @@ int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9]
  * Readings: the printed increment Delta d stands where the rate d is meant
  * (a stress needs the rate, units Pa = Pa s * 1/s); in 2-D the 3 is the
  * dimension, so that the viscous stress stays traceless there too. */
-void orc_fluid_stress(const orc_config* c, double J, const double L[9], double tau[9])
+void orc_fluid_stress(const orc_config* c, orc_real J, const orc_real L[9], orc_real tau[9])
 {
     int d = dimv(c);
-    double pr = orc_fluid_pressure(c, J);
-    double trd = 0.0;
+    orc_real pr = orc_fluid_pressure(c, J);
+    orc_real trd = 0.0;
     for (int a = 0; a < d; ++a) trd += L[a * d + a];
     for (int a = 0; a < d; ++a)
         for (int b = 0; b < d; ++b) {
-            double rate = 0.5 * (L[a * d + b] + L[b * d + a]);
-            double sig = 2.0 * c->viscosity * rate;
+            orc_real rate = 0.5 * (L[a * d + b] + L[b * d + a]);
+            orc_real sig = 2.0 * c->viscosity * rate;
             if (a == b) sig += -pr - 2.0 * c->viscosity * trd / d;
             tau[a * d + b] = J * sig;
         }
@@ -766,7 +791,7 @@ void orc_fluid_stress(const orc_config* c, double J, const double L[9], double t
  *   (1) Delta d = dt (L + L^T)/2, Delta w = dt (L - L^T)/2,
  *       sigma^R_ij = sigma_ij + sigma_ik Dw_jk + sigma_jk Dw_ik,
  *       trial = sigma^R + lam tr(Delta d) I + 2 G Delta d;
- *   (2) sigma_m = tr/d, tau = sqrt(s:s / 2);
+ *   (2) sigma_m = tr/d, tau = SQRT(s:s / 2);
  *   (3) f^s = tau - k_phi + q_phi sigma_m, f^t = sigma_m - sigma^t,
  *       h = tau - tau^P - alpha^P (sigma_m - sigma^t);
  *   (4) zone II: dl = f^s / (G + K q_phi q_psi), sigma_m -= K q_psi dl,
@@ -779,8 +804,8 @@ void orc_fluid_stress(const orc_config* c, double J, const double L[9], double t
  * (sigma^t, tau^P); a trial stress of Frobenius norm at or below 1e-6 E is
  * elastic whatever its zone (the zones meet at zero stress, where a body at
  * rest sits). */
-int orc_dp_jaumann(const orc_config* c, double dt, const double L[9], double sigma[9],
-                   double* deps_eq)
+int orc_dp_jaumann(const orc_config* c, double dt, const orc_real L[9], orc_real sigma[9],
+                   orc_real* deps_eq)
 {
     int d = dimv(c);
     double E = c->youngs, nu = c->poisson;
@@ -796,50 +821,50 @@ int orc_dp_jaumann(const orc_config* c, double dt, const double L[9], double sig
     double tauP = k_phi - q_phi * st;
     double alphaP = sqrt(1.0 + q_phi * q_phi) - q_phi;
 
-    double Dd[3][3] = {{0}}, Dw[3][3] = {{0}}, S0[3][3] = {{0}};
+    orc_real Dd[3][3] = {{0}}, Dw[3][3] = {{0}}, S0[3][3] = {{0}};
     for (int a = 0; a < d; ++a)
         for (int b = 0; b < d; ++b) {
             Dd[a][b] = 0.5 * dt * (L[a * d + b] + L[b * d + a]);
             Dw[a][b] = 0.5 * dt * (L[a * d + b] - L[b * d + a]);
             S0[a][b] = sigma[a * d + b];
         }
-    double trD = 0.0;
+    orc_real trD = 0.0;
     for (int a = 0; a < d; ++a) trD += Dd[a][a];
-    double Tr[3][3];
+    orc_real Tr[3][3];
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
-            double r = S0[i][j];
+            orc_real r = S0[i][j];
             for (int k = 0; k < d; ++k) r += S0[i][k] * Dw[j][k] + S0[j][k] * Dw[i][k];
             Tr[i][j] = r + 2.0 * G * Dd[i][j] + (i == j ? lam * trD : 0.0);
         }
-    double sm = 0.0;
+    orc_real sm = 0.0;
     for (int a = 0; a < d; ++a) sm += Tr[a][a];
     sm /= d;
-    double s[3][3], ss2 = 0.0, nrm2 = 0.0;
+    orc_real s[3][3], ss2 = 0.0, nrm2 = 0.0;
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
             s[i][j] = Tr[i][j] - (i == j ? sm : 0.0);
             ss2 += s[i][j] * s[i][j];
             nrm2 += Tr[i][j] * Tr[i][j];
         }
-    double tau = sqrt(0.5 * ss2);
-    double fs = tau - k_phi + q_phi * sm;
-    double ft = sm - st;
-    double h = tau - tauP - alphaP * (sm - st);
+    orc_real tau = SQRT(0.5 * ss2);
+    orc_real fs = tau - k_phi + q_phi * sm;
+    orc_real ft = sm - st;
+    orc_real h = tau - tauP - alphaP * (sm - st);
     int zone;
-    if (sqrt(nrm2) <= 1e-6 * E) zone = 1;
-    else if (ft < 0.0) zone = fs <= 0.0 ? 1 : 2;
-    else zone = h > 0.0 ? 2 : 3;
-    double sm_n = sm, scale = 1.0, de = 0.0;
+    if (RE(SQRT(nrm2)) <= 1e-6 * E) zone = 1;
+    else if (RE(ft) < 0.0) zone = RE(fs) <= 0.0 ? 1 : 2;
+    else zone = RE(h) > 0.0 ? 2 : 3;
+    orc_real sm_n = sm, scale = 1.0, de = 0.0;
     if (zone == 2) {
-        double dl = fs / (G + K * q_phi * q_psi);
+        orc_real dl = fs / (G + K * q_phi * q_psi);
         sm_n = sm - K * q_psi * dl;
-        double tau_n = k_phi - q_phi * sm_n;
-        if (sm_n > st) {          /* beyond the cutoff: the corner */
+        orc_real tau_n = k_phi - q_phi * sm_n;
+        if (RE(sm_n) > st) {          /* beyond the cutoff: the corner */
             sm_n = st;
             tau_n = tauP;
         }
-        scale = tau > 0.0 ? tau_n / tau : 0.0;
+        scale = RE(tau) > 0.0 ? tau_n / tau : 0.0;
         de = dl * sqrt(1.0 / 3.0 + 2.0 / 9.0 * q_psi * q_psi);
     } else if (zone == 3) {
         sm_n = st;
@@ -857,28 +882,28 @@ int orc_dp_jaumann(const orc_config* c, double dt, const double L[9], double sig
  * volume, equal to V_p sigma_p).  For the hypoelastic Drucker-Prager
  * material the carried stress is S = V_p sigma = V0 J sigma: the Cauchy
  * stress of the step is S / (V0 J) with the J before the update. */
-void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L,
-                      double* F, double* J, double* S)
+void orc_constitutive(const orc_config* c, int64_t N, double dt, const orc_real* L,
+                      orc_real* F, orc_real* J, orc_real* S)
 {
     int d = dimv(c);
     for (int64_t p = 0; p < N; ++p) {
-        double M[3][3] = {{0}}; /* I + dt L */
+        orc_real M[3][3] = {{0}}; /* I + dt L */
         for (int a = 0; a < d; ++a)
             for (int b = 0; b < d; ++b)
                 M[a][b] = (a == b ? 1.0 : 0.0) + dt * L[(a * d + b) * N + p];
-        double tau[3][3] = {{0}};
+        orc_real tau[3][3] = {{0}};
         if (c->material == ORC_FLUID) {
-            double Jn = J[p] * det(d, M);
+            orc_real Jn = J[p] * det(d, M);
             J[p] = Jn;
-            double Lp[9], tu[9];
+            orc_real Lp[9], tu[9];
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b) Lp[a * d + b] = L[(a * d + b) * N + p];
             orc_fluid_stress(c, Jn, Lp, tu);
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b) tau[a][b] = tu[a * d + b];
         } else if (c->material == ORC_DP_JAUMANN) {
-            double Jo = J[p], Jn = Jo * det(d, M);
-            double Lp[9], sg[9];
+            orc_real Jo = J[p], Jn = Jo * det(d, M);
+            orc_real Lp[9], sg[9];
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b) {
                     Lp[a * d + b] = L[(a * d + b) * N + p];
@@ -889,12 +914,12 @@ void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b) tau[a][b] = Jn * sg[a * d + b];
         } else {
-            double Fo[3][3] = {{0}}, Ft[3][3];
+            orc_real Fo[3][3] = {{0}}, Ft[3][3];
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b)
                     Fo[a][b] = F[(a * d + b) * N + p];
             matmul(d, M, Fo, Ft);
-            double ftr[9], fe[9], tu[9];
+            orc_real ftr[9], fe[9], tu[9];
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b)
                     ftr[a * d + b] = Ft[a][b];
@@ -915,10 +940,10 @@ void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L
 /* One full step: sort, P2G, grid update with walls, G2P, constitutive  */
 /* ------------------------------------------------------------------ */
 
-int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
-             double* x, double* v, double* C, double* F, double* J, double* S,
+int orc_step(const orc_config* c, int64_t N, double dt, const orc_real* floor_mu,
+             orc_real* x, orc_real* v, orc_real* C, orc_real* F, orc_real* J, orc_real* S,
              int32_t* pid, int32_t* perm_out, int32_t* key_out,
-             double* grid_m_out, double* grid_v_out)
+             orc_real* grid_m_out, orc_real* grid_v_out)
 {
     int d = dimv(c);
     int32_t dims[3];
@@ -927,11 +952,11 @@ int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
     int32_t* key = (int32_t*)malloc(sizeof(int32_t) * NP);
     int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * NP);
     int32_t* itmp = (int32_t*)malloc(sizeof(int32_t) * NP);
-    double* tmp = (double*)malloc(sizeof(double) * NP);
-    double* L = (double*)malloc(sizeof(double) * NP * (size_t)(d * d));
-    double* gm = (double*)malloc(sizeof(double) * (size_t)NN);
-    double* gp = (double*)malloc(sizeof(double) * (size_t)(NN * d));
-    double* gv = (double*)malloc(sizeof(double) * (size_t)(NN * d));
+    orc_real* tmp = (orc_real*)malloc(sizeof(orc_real) * NP);
+    orc_real* L = (orc_real*)malloc(sizeof(orc_real) * NP * (size_t)(d * d));
+    orc_real* gm = (orc_real*)malloc(sizeof(orc_real) * (size_t)NN);
+    orc_real* gp = (orc_real*)malloc(sizeof(orc_real) * (size_t)(NN * d));
+    orc_real* gv = (orc_real*)malloc(sizeof(orc_real) * (size_t)(NN * d));
     if (!key || !perm || !itmp || !tmp || !L || !gm || !gp || !gv) {
         free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv);
         return -1;
@@ -952,9 +977,9 @@ int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
     if (key_out) memcpy(key_out, key, sizeof(int32_t) * (size_t)N);
 
     /* FLIP needs the grid velocity before the update, v_i^n = gq / m_i */
-    double* gq = NULL;
+    orc_real* gq = NULL;
     if (c->transfer == ORC_FLIP) {
-        gq = (double*)malloc(sizeof(double) * (size_t)(NN * d));
+        gq = (orc_real*)malloc(sizeof(orc_real) * (size_t)(NN * d));
         if (!gq) {
             free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv);
             return -1;
@@ -965,9 +990,9 @@ int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
     if (gq)
         for (int64_t i = 0; i < NN; ++i)
             for (int a = 0; a < d; ++a)
-                gq[a * NN + i] = gm[i] > 0.0 ? gq[a * NN + i] / gm[i] : 0.0;
-    if (grid_m_out) memcpy(grid_m_out, gm, sizeof(double) * (size_t)NN);
-    if (grid_v_out) memcpy(grid_v_out, gv, sizeof(double) * (size_t)(NN * d));
+                gq[a * NN + i] = RE(gm[i]) > 0.0 ? gq[a * NN + i] / gm[i] : 0.0;
+    if (grid_m_out) memcpy(grid_m_out, gm, sizeof(orc_real) * (size_t)NN);
+    if (grid_v_out) memcpy(grid_v_out, gv, sizeof(orc_real) * (size_t)(NN * d));
     orc_g2p_ex(c, N, dt, gv, gq, x, v, C, L);
     orc_constitutive(c, N, dt, L, F, J, S);
 

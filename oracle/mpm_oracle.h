@@ -7,6 +7,17 @@
 #define MPM_ORACLE_H
 #include <stdint.h>
 
+/* Number type of the particle and grid data: binary64, or complex binary64
+ * in the complex-step build of the forward step (ORC_COMPLEX_STEP), which
+ * only the adjoint's checks use. */
+#ifdef ORC_COMPLEX_STEP
+#include <complex.h>
+#undef I /* the oracle names node indices I */
+typedef double _Complex orc_real;
+#else
+typedef double orc_real;
+#endif
+
 enum { ORC_FLUID = 0, ORC_DP_HENCKY = 1, ORC_HENCKY_ELASTIC = 2, ORC_DP_JAUMANN = 3 };
 enum { ORC_WALL_SLIP = 0, ORC_WALL_STICK = 1, ORC_WALL_COULOMB = 2 };
 /* grid-to-particle transfer (Sec. 2.2 G2P; App. B) */
@@ -41,39 +52,39 @@ typedef struct orc_config {
     double obst_lo[ORC_MAX_OBSTACLES][3], obst_hi[ORC_MAX_OBSTACLES][3];
 } orc_config;
 
-double orc_phibar(double xi);
-double orc_dphibar(double xi);
-void orc_stencil_1d(double x, double h, int key_f32, int32_t* base, double w[3], double dw[3]);
+orc_real orc_phibar(orc_real xi);
+orc_real orc_dphibar(orc_real xi);
+void orc_stencil_1d(orc_real x, double h, int key_f32, int32_t* base, orc_real w[3], orc_real dw[3]);
 int64_t orc_node_dims(const orc_config* c, int32_t dims[3]);
 int64_t orc_num_keys(const orc_config* c);
 int64_t orc_key_of_base(const orc_config* c, const int32_t B[3]);
-void orc_cell_keys(const orc_config* c, int64_t N, const double* x, int32_t* key);
+void orc_cell_keys(const orc_config* c, int64_t N, const orc_real* x, int32_t* key);
 int32_t orc_cells_per_tile(const orc_config* c);
 void orc_sort_perm(int64_t N, const int32_t* key, int32_t cpt, int32_t* perm);
-void orc_p2g(const orc_config* c, int64_t N, double dt, const double* x, const double* v,
-             const double* C, const double* S, double* gm, double* gp);
-void orc_p2g_ex(const orc_config* c, int64_t N, double dt, const double* x, const double* v,
-                const double* C, const double* S, double* gm, double* gp, double* gq);
-void orc_grid_update(const orc_config* c, double dt, const double* floor_mu,
-                     const double* gm, const double* gp, double* gv);
-void orc_g2p(const orc_config* c, int64_t N, double dt, const double* gv,
-             double* x, double* v, double* C, double* L);
-void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const double* gv, const double* gvo,
-                double* x, double* v, double* C, double* L);
-void orc_obstacles(const orc_config* c, const int32_t I[3], double vel[3]);
-int orc_dp_jaumann(const orc_config* c, double dt, const double L[9], double sigma[9],
-                   double* deps_eq);
-void orc_fluid_stress(const orc_config* c, double J, const double L[9], double tau[9]);
-void orc_sym_eig(int d, const double A[9], double ev[3], double V[9]);
-double orc_fluid_pressure(const orc_config* c, double J);
+void orc_p2g(const orc_config* c, int64_t N, double dt, const orc_real* x, const orc_real* v,
+             const orc_real* C, const orc_real* S, orc_real* gm, orc_real* gp);
+void orc_p2g_ex(const orc_config* c, int64_t N, double dt, const orc_real* x, const orc_real* v,
+                const orc_real* C, const orc_real* S, orc_real* gm, orc_real* gp, orc_real* gq);
+void orc_grid_update(const orc_config* c, double dt, const orc_real* floor_mu,
+                     const orc_real* gm, const orc_real* gp, orc_real* gv);
+void orc_g2p(const orc_config* c, int64_t N, double dt, const orc_real* gv,
+             orc_real* x, orc_real* v, orc_real* C, orc_real* L);
+void orc_g2p_ex(const orc_config* c, int64_t N, double dt, const orc_real* gv, const orc_real* gvo,
+                orc_real* x, orc_real* v, orc_real* C, orc_real* L);
+void orc_obstacles(const orc_config* c, const int32_t I[3], orc_real vel[3]);
+int orc_dp_jaumann(const orc_config* c, double dt, const orc_real L[9], orc_real sigma[9],
+                   orc_real* deps_eq);
+void orc_fluid_stress(const orc_config* c, orc_real J, const orc_real L[9], orc_real tau[9]);
+void orc_sym_eig(int d, const orc_real A[9], orc_real ev[3], orc_real V[9]);
+orc_real orc_fluid_pressure(const orc_config* c, orc_real J);
 double orc_cone_alpha(const orc_config* c);
-int orc_hencky_return(const orc_config* c, int elastic_only, const double Ftr[9],
-                      double Fe[9], double tau[9], double* dgamma);
-void orc_constitutive(const orc_config* c, int64_t N, double dt, const double* L,
-                      double* F, double* J, double* S);
-int orc_step(const orc_config* c, int64_t N, double dt, const double* floor_mu,
-             double* x, double* v, double* C, double* F, double* J, double* S,
+int orc_hencky_return(const orc_config* c, int elastic_only, const orc_real Ftr[9],
+                      orc_real Fe[9], orc_real tau[9], orc_real* dgamma);
+void orc_constitutive(const orc_config* c, int64_t N, double dt, const orc_real* L,
+                      orc_real* F, orc_real* J, orc_real* S);
+int orc_step(const orc_config* c, int64_t N, double dt, const orc_real* floor_mu,
+             orc_real* x, orc_real* v, orc_real* C, orc_real* F, orc_real* J, orc_real* S,
              int32_t* pid, int32_t* perm_out, int32_t* key_out,
-             double* grid_m_out, double* grid_v_out);
+             orc_real* grid_m_out, orc_real* grid_v_out);
 
 #endif
