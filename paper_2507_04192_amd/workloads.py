@@ -167,14 +167,14 @@ def cylinder_collapse_3d(scale_div: int = 1, seed: int = 0):
     return cfg, x
 
 
-def paper_granular_material(cfg: SimConfig) -> SimConfig:
+def paper_granular_material(cfg: SimConfig, phi_deg: float) -> SimConfig:
     """The granular material of the paper's 3-D collapses (Sec. 4.1.2, kept
     in Sec. 4.2.2-4.2.3): the hypoelastic Drucker-Prager model of App. A
     with rho = 2650 kg/m^3, K = 0.7 MPa (E = 3K(1 - 2nu) = 0.84 MPa),
-    nu = 0.3, c = 0, psi = 0; phi = 30 deg (the paper varies it over
-    20-40 deg); a no-slip base, slip walls elsewhere; dt = 1e-5 s."""
+    nu = 0.3, c = 0, psi = 0 and the friction angle phi_deg; a no-slip
+    base, slip walls elsewhere; dt = 1e-5 s."""
     return cfg.replace(material=DP_JAUMANN, rho0=2650.0, youngs=3 * 0.7e6 * (1 - 2 * 0.3), poisson=0.3,
-                       phi_deg=30.0, psi_deg=0.0, cohesion=0.0, dt=1e-5,
+                       phi_deg=float(phi_deg), psi_deg=0.0, cohesion=0.0, dt=1e-5,
                        wall_mode=(SLIP, SLIP, SLIP, SLIP, STICK, SLIP), wall_mu=(0.0,) * 6)
 
 
@@ -185,12 +185,13 @@ def cylinder_paper_grid(scale_div: int = 1, seed: int = 0):
     domain centre, 2x2x2 particles per cell: 2,713,580 particles, the
     table's 2,712,960 within 0.03% (the text gives neither dimension; this
     radius is the one whose lattice count comes closest), with the paper's
-    granular material.  scale_div shrinks every length."""
+    granular material at phi = 20 deg (the first of the friction angles the
+    section compares).  scale_div shrinks every length."""
     s = scale_div
     n = (400 // s, 400 // s, 100 // s)
     dx = 1.0 / 400.0
     cfg = paper_granular_material(SimConfig(dim=3, n=n, dx=dx, dt=1e-5, material=SAND, ppc=8,
-                                            gravity=(0.0, 0.0, -9.81)))
+                                            gravity=(0.0, 0.0, -9.81)), phi_deg=20.0)
     R = 47.68 * dx / s
     cx, cy = n[0] * dx / 2, n[1] * dx / 2
     x = lattice_particles(cfg, cylinder_inside(cx, cy, R, R), (cx - R, cy - R, 0.0), (cx + R, cy + R, R), seed)
@@ -203,12 +204,13 @@ def granular_column_paper(scale_div: int = 1, seed: int = 0):
     the column of aspect ratio 3 fills the width: L0 = 56 cells (0.14 m),
     H0 = 168 cells (0.42 m), 32 cells wide, at 2x2x2 particles per cell
     (2,408,448 particles, the table's count), with the paper's granular
-    material.  scale_div shrinks the length and the height."""
+    material (phi = 19.8 deg, unchanged from Sec. 4.1.2).  scale_div
+    shrinks the length and the height."""
     s = scale_div
     n = (400 // s, 32, 200 // s)
     dx = 1.0 / 400.0
     cfg = paper_granular_material(SimConfig(dim=3, n=n, dx=dx, dt=1e-5, material=SAND, ppc=8,
-                                            gravity=(0.0, 0.0, -9.81)))
+                                            gravity=(0.0, 0.0, -9.81)), phi_deg=19.8)
     hi = (56 * dx / s, 32 * dx, 168 * dx / s)
     x = lattice_particles(cfg, box_inside((0, 0, 0), hi), (0, 0, 0), hi, seed)
     return cfg, x

@@ -73,6 +73,7 @@ def test_paper_timing_cases_match_the_table():
     assert cyl.n == (400, 400, 100) and abs(xy.shape[1] - 2712960) <= 0.0003 * 2712960
     for cfg in (col, cyl):
         assert cfg.dx == 1 / 400 and cfg.dt == 1e-5 and cfg.material == W.DP_JAUMANN
-        assert cfg.rho0 == 2650.0 and cfg.poisson == 0.3 and cfg.phi_deg == 30.0
+        assert cfg.rho0 == 2650.0 and cfg.poisson == 0.3 and cfg.psi_deg == 0.0 and cfg.cohesion == 0.0
         assert abs(cfg.youngs / (3 * (1 - 2 * cfg.poisson)) - 0.7e6) < 1e-6
         assert cfg.wall_mode[4] == W.STICK
+    assert col.phi_deg == 19.8 and cyl.phi_deg == 20.0
