@@ -27,7 +27,9 @@ with a viscous fluid (Sec. 4.2.1, 1,920,000 particles on 200 x 100 x 80),
 and the paper's two granular timing cases on its own grids: the cylinder
 collapse on 400 x 400 x 100 (2,713,580 particles) and the column of aspect
 ratio 3 on 400 x 32 x 200 (2,408,448 particles), each set beside the
-paper's single-A100 figures.
+paper's single-A100 figures.  The paper_inverse leg times forward+gradient
+in binary64 on the 2-D dam-breaks of the paper's inverse problems (10,000,
+40,000 and 6,000 particles) beside its "sim + grad" figures.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -177,6 +179,65 @@ def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every
             "workspace_bytes": ws_bytes, "max_memory_allocated": torch.cuda.max_memory_allocated(),
             "observations": f"{n_tracers} tracer positions every {frame_every} steps; "
                             f"gradients wrt v0 and the floor friction field"}, prof
+
+
+def run_paper_inverse(steps=1000, ckpt_every=100):
+    """The paper's "sim + grad" timing cases (Table tab:simulation_params,
+    binary64): forward rollout with the loss and the checkpointed backward
+    sweep on the 2-D dam-breaks of its inverse problems, with their
+    observations: the velocity problem (Sec. 5.1-5.2) at 10,000 particles
+    (150 x 60 cells) and 40,000 (300 x 120), observed by the nine velocity
+    monitors every 10 steps, gradients with respect to v0; the friction
+    problem (Sec. 5.3, 6,000 particles) observed by 500 tracers every 10
+    steps, gradients with respect to v0 and the floor friction.  Seconds
+    per 1000 steps beside the paper's single-A100 figures (its network or
+    segment parameters add a few small kernels per epoch, not timed)."""
+    import numpy as np
+    import torch
+    from paper_2507_04192_amd import workloads as W
+    from paper_2507_04192_amd.native import Solver
+    cases = []
+    for name, fine, paper_s in (("velocity inverse, 10,000 particles, 150 x 60 cells", False, 0.62),
+                                ("velocity inverse, 40,000 particles, 300 x 120 cells", True, 1.52)):
+        cfg, x, H0 = W.inverse_dam_break_2d(fine=fine)
+        v0 = np.stack([2.0 * (H0 - x[1]), np.zeros(x.shape[1])])
+        lo, hi = W.velocity_monitors_2d()
+        cases.append((name, cfg, x, v0, dict(box_lo=lo, box_hi=hi, eul_field="v"), False, paper_s))
+    cfg, x, seg = W.friction_segments_2d()
+    cases.append(("friction inverse, 6,000 particles, 160 x 40 cells", cfg, x, None,
+                  dict(tracer_pid=W.pick_tracers(x.shape[1], 500, 13), lag_field="x"), True, 0.59))
+    out = []
+    for name, cfg, x, v0, obs, fric, paper_s in cases:
+        n = x.shape[1]
+        s = Solver(cfg, "f64", capacity=n, tape_steps=steps, ckpt_every=ckpt_every)
+        if fric:
+            s.mpm_set_floor_mu(W.segment_mu(cfg, np.asarray(W.FRICTION_SEGMENTS_TRUE), seg_len=seg))
+        frames = list(range(10, steps + 1, 10))
+        if "box_lo" in obs:
+            tgt = np.zeros((len(frames), cfg.dim, obs["box_lo"].shape[0]))
+            s.mpm_set_observations(frames=frames, eul_target=tgt, **obs)
+        else:
+            tgt = np.repeat(x[:, obs["tracer_pid"]][None], len(frames), axis=0)
+            s.mpm_set_observations(frames=frames, lag_target=tgt, **obs)
+        times = []
+        for _ in range(3):                       # the first is the warm-up
+            s.mpm_init_particles(x, v0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.mpm_forward_loss(steps)
+            s.mpm_backward(True, fric)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        s.close()
+        best = min(times[1:])
+        per1000 = best / steps * 1000
+        out.append({"workload": name, "particles": n, "grid": list(cfg.n), "precision": "f64",
+                    "steps": steps, "ckpt_every": ckpt_every, "s_per_1000_steps": per1000,
+                    "value": n * steps / best, "unit": "particle-steps/s",
+                    "paper_context": {"s_per_1000_steps": paper_s, "ratio": paper_s / per1000,
+                                      "note": "paper, one A100, sim + grad in binary64"}})
+        log(f"[bench] paper inverse {name}: {per1000:.4f} s per 1000 steps (paper {paper_s})")
+    return out
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_cylinder.txt")
@@ -493,6 +554,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the other forms of the step")
     ap.add_argument("--variant-steps", type=int, default=500, help="binary32 steps per variant (binary64: half)")
     ap.add_argument("--no-configs", action="store_true", help="skip the other benchmark configurations")
+    ap.add_argument("--no-paper-inverse", action="store_true",
+                    help="skip the paper's forward+gradient timing cases of its inverse problems")
     ap.add_argument("--no-late", action="store_true", help="skip the late-phase timing of the collapse")
     ap.add_argument("--late-after", type=int, default=3000, help="untimed steps before the late-phase timing")
     ap.add_argument("--config-steps", type=int, default=1000, help="steps per other configuration")
@@ -577,6 +640,9 @@ def main():
     configs = None
     if not args.no_configs and args.scale_div == 1:
         configs = run_other_configs(args.config_steps, args.warmup)
+    paper_inv = None
+    if not args.no_paper_inverse and args.scale_div == 1:
+        paper_inv = run_paper_inverse()
     late = None
     if not args.no_late:
         late = run_late_phase(cfg, x, "f32", args.late_after, min(args.steps, 500))
@@ -619,6 +685,7 @@ def main():
         "late_phase": late,
         "variants": variants,
         "other_configs": configs,
+        "paper_inverse": paper_inv,
         "paper_context": {"value_f32": 1.22e8, "value_f64": 2.76e7,
                           "note": "paper, one A100, 2,712,960-particle cylinder on 400x400x100; "
                                   "a different machine and grid, not this workload (the variants "

@@ -393,16 +393,19 @@ def mlp_init_params(widths, seed: int) -> np.ndarray:
 # The paper's own inverse experiments (Sec. 5), synthetic reproductions
 # ---------------------------------------------------------------------------
 
-def inverse_dam_break_2d(seed: int = 0):
+def inverse_dam_break_2d(seed: int = 0, fine: bool = False):
     """Dam-break of the initial-velocity inverse problems (Sec. 5.1, 5.2):
-    water column H0 = L0 = 0.5 m at dx = 0.01 m, 2 x 2 particles per cell
-    (10,000 particles), inviscid fluid with the numerical sound speed
-    c0 = 50 m/s (the linear EOS: gamma = 1, K = rho0 c0^2), dt = 3e-5 s,
-    slip walls.  The paper does not give the domain; it is 2.0 x 0.6 m here
-    (200 x 60 cells), long enough that the front stays off the far wall
-    until t = 0.3 s.  Returns (cfg, x, H0)."""
+    water column H0 = L0 = 0.5 m at 2 x 2 particles per cell, inviscid
+    fluid with the numerical sound speed c0 = 50 m/s (the linear EOS:
+    gamma = 1, K = rho0 c0^2), dt = 3e-5 s, slip walls, in the domain of the
+    paper's table, 1.5 x 0.6 m: 150 x 60 cells at dx = 0.01 m (10,000
+    particles), or with fine=True 300 x 120 cells at dx = 0.005 m (40,000
+    particles, the table's second size).  With the ground-truth initial
+    velocity of Sec. 5.1 (alpha = 2) the front is at 1.37 m at t = 0.3 s,
+    short of the far wall.  Returns (cfg, x, H0)."""
     c0, rho0 = 50.0, 1000.0
-    cfg = SimConfig(dim=2, n=(200, 60, 1), dx=0.01, dt=3e-5, material=FLUID, ppc=4,
+    n, dx = ((300, 120, 1), 0.005) if fine else ((150, 60, 1), 0.01)
+    cfg = SimConfig(dim=2, n=n, dx=dx, dt=3e-5, material=FLUID, ppc=4,
                     gravity=(0.0, -9.8, 0.0), rho0=rho0, bulk=rho0 * c0 * c0, gamma=1.0)
     H0 = L0 = 0.5
     x = lattice_particles(cfg, box_inside((0.0, 0.0), (L0, H0)), (0.0, 0.0), (L0, H0), seed)
