@@ -17,6 +17,10 @@ against binary64, and the shallow-water solution of the dam-break.
   binary32 against binary64 within h after 1000 steps and within 2h after
   10,000 steps (t = 0.2 s); the 1/8-scale cylinder against the oracle for
   1000 steps.
+- The paper's granular timing cases with the hypoelastic material (the a = 3
+  column, runout along x; the cylinder on 400 x 400 x 100): binary32 against
+  binary64 within 2h after 30,000 steps (t = 0.3 s); the cylinder at 1/8
+  scale against the oracle for 2000 steps.
 """
 import numpy as np
 import pytest
@@ -170,6 +174,66 @@ def test_small_cylinder_long_run_vs_oracle(orc):
     orc.Oracle(cfg).run(st, steps, cfg.dt)
     xr = st.by_pid("x")
     rr = _runout(cfg, xr, axis)
+    for precision in ("f64", "f32"):
+        xg = _gpu_run(cfg, precision, xs, steps)
+        rg = _runout(cfg, xg, axis)
+        e = rel_l2(xg - xs, xr - xs)
+        print(f"  {precision}: runout {rg[0]:.5f} vs {rr[0]:.5f}, p99.9 {rg[1]:.5f} vs {rr[1]:.5f}; "
+              f"rel L2 displacement {e:.2e}", flush=True)
+        assert abs(rg[0] - rr[0]) <= cfg.dx and abs(rg[1] - rr[1]) <= cfg.dx
+        assert e <= (1e-8 if precision == "f64" else 1e-2)
+
+
+def _runout_x(cfg, x):
+    low = x[2] < 2 * cfg.dx
+    return float(x[0][low].max()), float(np.percentile(x[0][low], 99.9))
+
+
+@pytest.mark.parametrize("case", ["column", "cylinder"])
+def test_paper_cases_runout_binary32_vs_binary64(case):
+    """The paper's granular timing cases at full size with the hypoelastic
+    Drucker-Prager material (Sec. 4.2.2-4.2.3, App. A): runout binary32
+    against binary64 within 2h after 30,000 steps (t = 0.3 s), by when the
+    a = 3 column has run out to more than three times its base length and
+    the cylinder's base has spread by more than half its radius (measured
+    differences: 0.43h and 0.03h)."""
+    if case == "column":
+        cfg, x = W.granular_column_paper()
+        runout = _runout_x
+        spread = lambda r: r > 4 * 56 * cfg.dx
+    else:
+        cfg, x = W.cylinder_paper_grid()
+        axis = (cfg.n[0] * cfg.dx / 2, cfg.n[1] * cfg.dx / 2)
+        runout = lambda c, p: _runout(c, p, axis)
+        spread = lambda r: r > 1.5 * 47.68 * cfg.dx
+    h = cfg.dx
+    steps = 30000
+    print(f"[case] paper's {case}, runout after {steps} steps, N={x.shape[1]}", flush=True)
+    xs = x.astype(np.float32).astype(np.float64)
+    r = {p: runout(cfg, _gpu_run(cfg, p, xs, steps, chunk=5000)) for p in ("f64", "f32")}
+    print(f"  runout max {r['f32'][0]:.4f} (f32) vs {r['f64'][0]:.4f} (f64), "
+          f"p99.9 {r['f32'][1]:.4f} vs {r['f64'][1]:.4f}", flush=True)
+    assert abs(r["f32"][0] - r["f64"][0]) <= 2 * h
+    assert abs(r["f32"][1] - r["f64"][1]) <= 2 * h
+    assert spread(r["f64"][0])
+
+
+def test_small_paper_cylinder_long_run_vs_oracle(orc):
+    """The paper's cylinder at 1/8 scale (5,376 particles on 50 x 50 x 12
+    cells, hypoelastic Drucker-Prager, stick base) for 2000 steps (t = 0.02
+    s, the base spread beyond the initial radius) against the oracle:
+    runout within h, displacements to 1e-8 (binary64) and 1e-2
+    (binary32)."""
+    cfg, x = W.cylinder_paper_grid(scale_div=8)
+    steps = 2000
+    axis = (cfg.n[0] * cfg.dx / 2, cfg.n[1] * cfg.dx / 2)
+    print(f"[case] paper's cylinder / 8, {steps} steps, N={x.shape[1]} (oracle first)", flush=True)
+    xs = x.astype(np.float32).astype(np.float64)
+    st = orc.State(cfg, xs)
+    orc.Oracle(cfg).run(st, steps, cfg.dt)
+    xr = st.by_pid("x")
+    rr = _runout(cfg, xr, axis)
+    assert rr[0] > 47.68 / 8 * cfg.dx             # the base has spread
     for precision in ("f64", "f32"):
         xg = _gpu_run(cfg, precision, xs, steps)
         rg = _runout(cfg, xg, axis)
