@@ -189,9 +189,11 @@ def run_paper_inverse(steps=1000, ckpt_every=100):
     (150 x 60 cells) and 40,000 (300 x 120), observed by the nine velocity
     monitors every 10 steps, gradients with respect to v0; the friction
     problem (Sec. 5.3, 6,000 particles) observed by 500 tracers every 10
-    steps, gradients with respect to v0 and the floor friction.  Seconds
-    per 1000 steps beside the paper's single-A100 figures (its network or
-    segment parameters add a few small kernels per epoch, not timed)."""
+    steps, gradients with respect to v0 and the floor friction.  Every
+    segment stays on the tape (at most 5 GB here), so the backward
+    sweep recomputes none.  Seconds per 1000 steps beside the paper's
+    single-A100 figures (its network or segment parameters add a few small
+    kernels per epoch, not timed)."""
     import numpy as np
     import torch
     from paper_2507_04192_amd import workloads as W
@@ -209,7 +211,10 @@ def run_paper_inverse(steps=1000, ckpt_every=100):
     out = []
     for name, cfg, x, v0, obs, fric, paper_s in cases:
         n = x.shape[1]
-        s = Solver(cfg, "f64", capacity=n, tape_steps=steps, ckpt_every=ckpt_every)
+        # small problems: every segment fits on the tape, so the backward
+        # sweep recomputes none
+        ns = taped_segments_for(cfg, "f64", n, steps, ckpt_every, 8 << 30)
+        s = Solver(cfg, "f64", capacity=n, tape_steps=steps, ckpt_every=ckpt_every, tape_segments=ns)
         if fric:
             s.mpm_set_floor_mu(W.segment_mu(cfg, np.asarray(W.FRICTION_SEGMENTS_TRUE), seg_len=seg))
         frames = list(range(10, steps + 1, 10))
@@ -232,7 +237,7 @@ def run_paper_inverse(steps=1000, ckpt_every=100):
         best = min(times[1:])
         per1000 = best / steps * 1000
         out.append({"workload": name, "particles": n, "grid": list(cfg.n), "precision": "f64",
-                    "steps": steps, "ckpt_every": ckpt_every, "s_per_1000_steps": per1000,
+                    "steps": steps, "ckpt_every": ckpt_every, "tape_segments": ns, "s_per_1000_steps": per1000,
                     "value": n * steps / best, "unit": "particle-steps/s",
                     "paper_context": {"s_per_1000_steps": paper_s, "ratio": paper_s / per1000,
                                       "note": "paper, one A100, sim + grad in binary64"}})

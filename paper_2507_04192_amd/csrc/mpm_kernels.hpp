@@ -1373,7 +1373,9 @@ struct Solver {
         const Geo& g = c->geo;
         unsigned nsb = (unsigned)((g.ntiles + kScanChunk - 1) / kScanChunk);
         prof_mark(c, -1);
-        k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
+        // one chunk has no earlier chunks to sum: the down-sweep alone (a
+        // launch fewer for the small grids, whose steps are launch-bound)
+        if (nsb > 1) k_scan_reduce<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part);
         k_scan_down<0><<<nsb, kBlock, 0, st>>>(c->count, g.ntiles, c->part, c->tile_off, b.tile_slot, b.active, b.meta);
         prof_mark(c, MPM_PROF_SCAN);
         k_bucket<0><<<(unsigned)((c->N + kBlock * kBucketPer - 1) / (kBlock * kBucketPer)), kBlock, 0, st>>>(
