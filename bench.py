@@ -116,23 +116,6 @@ def run_gpu(cfg, x, precision, steps, warmup, profile=True):
     return (t1 - t0), (t3 - t2), prof
 
 
-def taped_segments_for(cfg, precision, n, steps, ckpt_every, budget):
-    """The most trailing segments of a rollout that can stay on the tape
-    with the workspace within budget bytes (at least one)."""
-    import ctypes as ct
-    from paper_2507_04192_amd import native
-    L = native.lib()
-    nb = ct.c_size_t()
-    nseg = (steps + ckpt_every - 1) // ckpt_every
-    best = 1
-    for ns in range(1, nseg + 1):
-        c = native.make_config(cfg, precision, tape_segments=ns)
-        if L.mpm_workspace_bytes(ct.byref(c), n, steps, ckpt_every, ct.byref(nb)) != 0 or nb.value > budget:
-            break
-        best = ns
-    return best
-
-
 def run_adjoint(cfg, x, precision, steps, ckpt_every, n_tracers=500, frame_every=20, tape_segments=1):
     """Forward rollout with the loss, then the checkpointed backward sweep:
     tracer positions every frame_every steps against their starting
@@ -197,7 +180,7 @@ def run_paper_inverse(steps=1000, ckpt_every=100):
     import numpy as np
     import torch
     from paper_2507_04192_amd import workloads as W
-    from paper_2507_04192_amd.native import Solver
+    from paper_2507_04192_amd.native import Solver, max_tape_segments
     cases = []
     for name, fine, paper_s in (("velocity inverse, 10,000 particles, 150 x 60 cells", False, 0.62),
                                 ("velocity inverse, 40,000 particles, 300 x 120 cells", True, 1.52)):
@@ -213,7 +196,7 @@ def run_paper_inverse(steps=1000, ckpt_every=100):
         n = x.shape[1]
         # small problems: every segment fits on the tape, so the backward
         # sweep recomputes none
-        ns = taped_segments_for(cfg, "f64", n, steps, ckpt_every, 8 << 30)
+        ns = max_tape_segments(cfg, "f64", n, steps, ckpt_every, 8 << 30)
         s = Solver(cfg, "f64", capacity=n, tape_steps=steps, ckpt_every=ckpt_every, tape_segments=ns)
         if fric:
             s.mpm_set_floor_mu(W.segment_mu(cfg, np.asarray(W.FRICTION_SEGMENTS_TRUE), seg_len=seg))
@@ -621,7 +604,8 @@ def main():
             torch.cuda.empty_cache()
             torch.cuda.reset_peak_memory_stats()
             free, _ = torch.cuda.mem_get_info()
-            nts = taped_segments_for(cfg, prec, n, T, args.adj_ckpt, args.adj_memory_frac * free)
+            from paper_2507_04192_amd.native import max_tape_segments
+            nts = max_tape_segments(cfg, prec, n, T, args.adj_ckpt, args.adj_memory_frac * free)
             r, prof = run_adjoint(cfg, x, prec, T, args.adj_ckpt, tape_segments=nts)
             dom_a, kern, roof_a = roofline({k: prof[k] for k in ("g2p_adj", "p2g_adj") if k in prof}, n, elem)
             if args.scale_div == 1:

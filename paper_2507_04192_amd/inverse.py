@@ -101,6 +101,15 @@ def train(solver, x0, steps, frames, obs, targets, field_apply, theta, epochs, l
     return hist
 
 
+def paper_solver(cfg, precision, n, steps, ckpt_every=200, budget=32 << 30):
+    """Solver for the paper's 2-D inverse problems (10,000 steps): a
+    checkpoint every 200 steps and as many trailing segments on the tape as
+    fit in budget bytes -- all 50 at these sizes (8-13 GiB in binary64) --
+    so the backward sweep recomputes none."""
+    ns = native.max_tape_segments(cfg, precision, n, steps, ckpt_every, budget)
+    return native.Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=ckpt_every, tape_segments=ns)
+
+
 def rel_err(est, true, mask=None):
     """Relative L2 error of a field estimate (arrays or tensors)."""
     e = np.asarray(est.detach().cpu().numpy() if hasattr(est, "detach") else est, dtype=np.float64)
@@ -244,7 +253,7 @@ def alpha_inverse(case: int, epochs: int = 60, alpha0: float = 0.1, alpha_true: 
     else:
         raise ValueError("case is 1, 2 or 3")
     prof = np.stack([H0 - x0[1], np.zeros(n)])
-    s = native.Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=100)
+    s = paper_solver(cfg, precision, n, steps)
     targets = record(s, x0, alpha_true * prof, None, steps, frames, obs)
     prof_t = torch.as_tensor(prof, dtype=torch.float32, device=s.device)
     theta = torch.tensor([alpha0], dtype=torch.float32, device=s.device)
@@ -273,7 +282,7 @@ def profile_inverse(n_obs: int = 1000, epochs: int = 400, lr: float = 1e-2, deca
     frames = _last_frames(steps, 100, 10)
     obs = dict(tracer_pid=W.pick_tracers(n, n_obs, seed), lag_field="x")
     v_true = np.stack([W.velocity_profile(x0[1], H0), np.zeros(n)])
-    s = native.Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=100)
+    s = paper_solver(cfg, precision, n, steps)
     targets = record(s, x0, v_true, None, steps, frames, obs)
     widths = [1, 30, 30, 30, 1]
     net = native.MLP(widths, in_scale=[2.0 / H0], in_shift=[-1.0], math=math, hidden_act="relu")
@@ -318,7 +327,7 @@ def friction_segments_inverse(n_tracers: int = 500, epochs: int = 100, mu0: floa
     obs = dict(tracer_pid=W.pick_tracers(n, n_tracers, seed), lag_field="x")
     true = np.asarray(W.FRICTION_SEGMENTS_TRUE)
     mu_true = W.segment_mu(cfg, true, seg_len=seg)
-    s = native.Solver(cfg, precision, capacity=n, tape_steps=steps, ckpt_every=100)
+    s = paper_solver(cfg, precision, n, steps)
     targets = record(s, x0, None, mu_true, steps, frames, obs)
     nd = cfg.node_dims()
     xs = (np.arange(nd[0]) - cfg.ghost) * cfg.dx

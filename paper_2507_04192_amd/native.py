@@ -171,6 +171,23 @@ def make_config(cfg, precision: str = "f64", keep_grid: bool = False, tape_segme
     return c
 
 
+def max_tape_segments(cfg, precision, n, steps, ckpt_every, budget):
+    """The most trailing segments of a steps-long rollout, checkpointed
+    every ckpt_every steps, that can stay on the tape with the workspace of
+    n particles within budget bytes (mpm_workspace_bytes; at least one)."""
+    L = lib()
+    nb = ct.c_size_t()
+    nseg = (steps + ckpt_every - 1) // ckpt_every
+    best = 1
+    for ns in range(1, nseg + 1):
+        c = make_config(cfg, precision, tape_segments=ns)
+        if L.mpm_workspace_bytes(ct.byref(c), int(n), int(steps), int(ckpt_every), ct.byref(nb)) != MPM_OK \
+                or nb.value > budget:
+            break
+        best = ns
+    return best
+
+
 def _check(ctx, rc):
     if rc != MPM_OK:
         msg = lib().mpm_last_error(ctx)

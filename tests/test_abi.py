@@ -142,3 +142,24 @@ def test_tape_segments_workspace_without_gpu():
         c = native.make_config(cfg, "f64", tape_segments=bad)
         assert L.mpm_workspace_bytes(ct.byref(c), 8192, 100, 10, ct.byref(nb)) == native.MPM_EINVAL
         assert b"tape_segments" in L.mpm_last_error(None)
+
+
+def test_max_tape_segments_within_budget():
+    """The binding's choice of taped segments: every segment within a large
+    budget, one within a tiny one, and in between the most whose workspace
+    fits."""
+    from paper_2507_04192_amd import native
+    from paper_2507_04192_amd import workloads as W
+    cfg, _ = W.dam_break_2d()
+    L = native.lib()
+    nb = ct.c_size_t()
+
+    def ws(ns):
+        c = native.make_config(cfg, "f64", tape_segments=ns)
+        assert L.mpm_workspace_bytes(ct.byref(c), 8192, 100, 10, ct.byref(nb)) == 0
+        return nb.value
+
+    assert native.max_tape_segments(cfg, "f64", 8192, 100, 10, 1 << 40) == 10
+    assert native.max_tape_segments(cfg, "f64", 8192, 100, 10, 1) == 1
+    assert native.max_tape_segments(cfg, "f64", 8192, 100, 10, ws(4)) == 4
+    assert native.max_tape_segments(cfg, "f64", 8192, 100, 10, ws(5) - 1) == 4
