@@ -160,3 +160,65 @@ def test_rollout_gradient_matches_complex_step(orc, material):
     cs = lc.imag / H
     ad = float((gv0 * dv).sum()) + float((amu * dmu).sum())
     assert abs(cs - ad) <= 1e-11 * abs(cs), (cs, ad)
+
+
+def test_planted_mistake_below_finite_differences_is_caught(orc, tmp_path, monkeypatch):
+    """A mistake of relative size 1e-7 planted in a copy of the oracle's
+    reverse step (the APIC factor D^-1 = 4/h^2 of App. B in the adjoint of
+    the affine transfer) passes the central-difference check of one step at
+    its 2e-6 bound but not the complex-step dot test."""
+    import ctypes as ct
+    import os
+    import shutil
+    import subprocess
+    src = os.path.dirname(orc.__file__)
+    for f in ("mpm_oracle.c", "mpm_oracle_adjoint.c", "mpm_oracle.h"):
+        shutil.copy(os.path.join(src, f), tmp_path / f)
+    p = tmp_path / "mpm_oracle_adjoint.c"
+    text = p.read_text()
+    line = "double Dinv = 4.0 / (c->dx * c->dx);"
+    assert text.count(line) == 1
+    p.write_text(text.replace(line, "double Dinv = 4.0000004 / (c->dx * c->dx);"))
+    so = str(tmp_path / "liborc_planted.so")
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+                    str(tmp_path / "mpm_oracle.c"), str(p), "-o", so, "-lm"], check=True)
+    planted = ct.CDLL(so)
+    orc._declare(planted)
+
+    cfg = _form(3, "sand")
+    o = orc.Oracle(cfg)
+    st0 = _state(orc, cfg, 300, 33)
+    rng = np.random.default_rng(23)
+    st1 = st0.copy()
+    o.step(st1, cfg.dt)
+    w = {k: rng.normal(size=v.shape) for k, v in _outputs(cfg, st1).items()}
+    dC = rng.normal(size=st0.C.shape) * 10.0
+
+    def grad(lib):
+        monkeypatch.setattr(orc, "_lib", lib)
+        return orc.adjoint_step(cfg, st0, w, cfg.dt)["C"]
+
+    g_true, g_planted = grad(orc.lib()), grad(planted)
+    monkeypatch.undo()
+    sc = st0.copy()
+    sc.C = st0.C + 1j * H * dC
+    o.step_complex(sc, cfg.dt)
+    cs = sum(complex((w[k] * getattr(sc, k)).sum()) for k in w).imag / H
+
+    def loss(st):
+        s = st.copy()
+        o.step(s, cfg.dt)
+        return sum(float((w[k] * v).sum()) for k, v in _outputs(cfg, s).items())
+
+    eps = 1e-2
+    sp, sm = st0.copy(), st0.copy()
+    sp.C, sm.C = st0.C + eps * 1e-3 * dC, st0.C - eps * 1e-3 * dC
+    fd = (loss(sp) - loss(sm)) / (2 * eps * 1e-3)
+    ad_true = float((g_true * dC).sum())
+    ad_planted = float((g_planted * dC).sum())
+    assert abs(cs - ad_true) <= TOL_DOT * abs(cs)                   # the oracle as it is
+    assert abs(fd - ad_planted) <= 2e-6 * abs(fd)                   # finite differences miss the mistake
+    print(f"  complex step {cs:.15e}, adjoint {ad_true:.15e} (rel {abs(cs - ad_true) / abs(cs):.1e}), planted "
+          f"{ad_planted:.15e} (rel {abs(cs - ad_planted) / abs(cs):.1e}); central differences {fd:.15e} "
+          f"(rel {abs(fd - ad_planted) / abs(fd):.1e} to the planted adjoint)", flush=True)
+    assert abs(cs - ad_planted) > 1e3 * TOL_DOT * abs(cs)           # the complex step does not
