@@ -90,7 +90,7 @@ def cs_lib():
         _cs_lib = ct.CDLL(CS_LIB_PATH)
         P = ct.c_void_p
         _cs_lib.orc_step.restype = ct.c_int
-        _cs_lib.orc_step.argtypes = [P, ct.c_int64, ct.c_double] + [P] * 12
+        _cs_lib.orc_step.argtypes = [P, ct.c_int64, ct.c_double] + [P] * 13
         _cs_lib.orc_node_dims.restype = ct.c_int64
         _cs_lib.orc_node_dims.argtypes = [P, P]
     return _cs_lib
@@ -128,9 +128,9 @@ def _declare(L):
     L.orc_cone_alpha.argtypes = [P]
     L.orc_hencky_return.restype = ct.c_int
     L.orc_hencky_return.argtypes = [P, ct.c_int, P, P, P, P]
-    L.orc_constitutive.argtypes = [P, i64, f64, P, P, P, P]
+    L.orc_constitutive.argtypes = [P, i64, f64, P, P, P, P, P]
     L.orc_step.restype = ct.c_int
-    L.orc_step.argtypes = [P, i64, f64, P, P, P, P, P, P, P, P, P, P, P, P]
+    L.orc_step.argtypes = [P, i64, f64, P, P, P, P, P, P, P, P, P, P, P, P, P]
     if hasattr(L, "orc_adjoint_step"):
         _declare_adjoint(L)
 
@@ -184,9 +184,10 @@ def _f64(a):
 
 
 class State:
-    """Particle state in the oracle's layout (component-major float64)."""
+    """Particle state in the oracle's layout (component-major float64);
+    eps is the accumulated equivalent plastic strain."""
 
-    def __init__(self, cfg, x, v=None, C=None, F=None, J=None, S=None, pid=None):
+    def __init__(self, cfg, x, v=None, C=None, F=None, J=None, S=None, pid=None, eps=None):
         d = cfg.dim
         x = _f64(x).reshape(d, -1)
         N = x.shape[1]
@@ -203,11 +204,12 @@ class State:
         self.S = np.zeros((d * d, N)) if S is None else _f64(S).reshape(d * d, N).copy()
         self.pid = np.arange(N, dtype=np.int32) if pid is None else \
             np.ascontiguousarray(pid, dtype=np.int32).copy()
+        self.eps = np.zeros(N) if eps is None else _f64(eps).reshape(N).copy()
 
     def copy(self):
         s = State.__new__(State)
         s.N = self.N
-        for k in ("x", "v", "C", "F", "J", "S", "pid"):
+        for k in ("x", "v", "C", "F", "J", "S", "pid", "eps"):
             setattr(s, k, getattr(self, k).copy())
         return s
 
@@ -312,7 +314,7 @@ class Oracle:
 
     def constitutive(self, st: State, L, dt):
         self.L.orc_constitutive(ct.byref(self.c), st.N, dt, _ptr(_f64(L)), _ptr(st.F),
-                                _ptr(st.J), _ptr(st.S))
+                                _ptr(st.J), _ptr(st.S), _ptr(st.eps))
 
     def hencky_return(self, Ftr, elastic_only=False):
         d = self.cfg.dim
@@ -350,7 +352,7 @@ class Oracle:
         fm = None if floor_mu is None else _f64(floor_mu)
         rc = self.L.orc_step(ct.byref(self.c), st.N, dt, _ptr(fm), _ptr(st.x), _ptr(st.v),
                              _ptr(st.C), _ptr(st.F), _ptr(st.J), _ptr(st.S), _ptr(st.pid),
-                             _ptr(perm), _ptr(key), _ptr(gm), _ptr(gv))
+                             _ptr(perm), _ptr(key), _ptr(gm), _ptr(gv), _ptr(st.eps))
         if rc != 0:
             raise MemoryError("oracle step failed to allocate")
         if want_grid:
@@ -365,14 +367,14 @@ class Oracle:
         the real ones); the imaginary parts divided by h are the step's
         directional derivative."""
         c128 = lambda a: np.ascontiguousarray(a, dtype=np.complex128)
-        for k in ("x", "v", "C", "F", "J", "S"):
+        for k in ("x", "v", "C", "F", "J", "S", "eps"):
             setattr(st, k, c128(getattr(st, k)))
         perm = np.empty(st.N, dtype=np.int32)
         key = np.empty(st.N, dtype=np.int32)
         fm = None if floor_mu is None else c128(floor_mu)
         rc = cs_lib().orc_step(ct.byref(self.c), st.N, dt, _ptr(fm), _ptr(st.x), _ptr(st.v),
                                _ptr(st.C), _ptr(st.F), _ptr(st.J), _ptr(st.S), _ptr(st.pid),
-                               _ptr(perm), _ptr(key), None, None)
+                               _ptr(perm), _ptr(key), None, None, _ptr(st.eps))
         if rc != 0:
             raise MemoryError("oracle step failed to allocate")
         return perm, key

@@ -881,9 +881,14 @@ int orc_dp_jaumann(const orc_config* c, double dt, const orc_real L[9], orc_real
  * stress of the material; S = V0 * tau (Kirchhoff stress times initial
  * volume, equal to V_p sigma_p).  For the hypoelastic Drucker-Prager
  * material the carried stress is S = V_p sigma = V0 J sigma: the Cauchy
- * stress of the step is S / (V0 J) with the J before the update. */
+ * stress of the step is S / (V0 J) with the J before the update.
+ * eps (may be NULL) accumulates the equivalent plastic strain: for the
+ * hypoelastic material App. A's increment (zone II: dl sqrt(1/3 + 2/9
+ * q_psi^2), zone III: sqrt(2)/3 (sigma_m - sigma^t)/K); for the Hencky
+ * return (reading) the von Mises equivalent sqrt(2/3) |dE_p| of the plastic
+ * log-strain increment dE_p = eps - H, whose norm is the return's dgamma. */
 void orc_constitutive(const orc_config* c, int64_t N, double dt, const orc_real* L,
-                      orc_real* F, orc_real* J, orc_real* S)
+                      orc_real* F, orc_real* J, orc_real* S, orc_real* eps)
 {
     int d = dimv(c);
     for (int64_t p = 0; p < N; ++p) {
@@ -909,7 +914,9 @@ void orc_constitutive(const orc_config* c, int64_t N, double dt, const orc_real*
                     Lp[a * d + b] = L[(a * d + b) * N + p];
                     sg[a * d + b] = S[(a * d + b) * N + p] / (c->vol0 * Jo);
                 }
-            orc_dp_jaumann(c, dt, Lp, sg, NULL);
+            orc_real de = 0.0;
+            orc_dp_jaumann(c, dt, Lp, sg, &de);
+            if (eps) eps[p] += de;
             J[p] = Jn;
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b) tau[a][b] = Jn * sg[a * d + b];
@@ -923,7 +930,9 @@ void orc_constitutive(const orc_config* c, int64_t N, double dt, const orc_real*
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b)
                     ftr[a * d + b] = Ft[a][b];
-            orc_hencky_return(c, c->material == ORC_HENCKY_ELASTIC, ftr, fe, tu, NULL);
+            orc_real dg = 0.0;
+            orc_hencky_return(c, c->material == ORC_HENCKY_ELASTIC, ftr, fe, tu, &dg);
+            if (eps) eps[p] += sqrt(2.0 / 3.0) * dg;
             for (int a = 0; a < d; ++a)
                 for (int b = 0; b < d; ++b) {
                     F[(a * d + b) * N + p] = fe[a * d + b];
@@ -943,7 +952,7 @@ void orc_constitutive(const orc_config* c, int64_t N, double dt, const orc_real*
 int orc_step(const orc_config* c, int64_t N, double dt, const orc_real* floor_mu,
              orc_real* x, orc_real* v, orc_real* C, orc_real* F, orc_real* J, orc_real* S,
              int32_t* pid, int32_t* perm_out, int32_t* key_out,
-             orc_real* grid_m_out, orc_real* grid_v_out)
+             orc_real* grid_m_out, orc_real* grid_v_out, orc_real* eps)
 {
     int d = dimv(c);
     int32_t dims[3];
@@ -972,6 +981,8 @@ int orc_step(const orc_config* c, int64_t N, double dt, const orc_real* floor_mu
         gather_d(N, 1, J, perm, tmp);
     if (c->material != ORC_FLUID)
         gather_d(N, d * d, F, perm, tmp);
+    if (eps)
+        gather_d(N, 1, eps, perm, tmp);
     gather_i(N, pid, perm, itmp);
     if (perm_out) memcpy(perm_out, perm, sizeof(int32_t) * (size_t)N);
     if (key_out) memcpy(key_out, key, sizeof(int32_t) * (size_t)N);
@@ -994,7 +1005,7 @@ int orc_step(const orc_config* c, int64_t N, double dt, const orc_real* floor_mu
     if (grid_m_out) memcpy(grid_m_out, gm, sizeof(orc_real) * (size_t)NN);
     if (grid_v_out) memcpy(grid_v_out, gv, sizeof(orc_real) * (size_t)(NN * d));
     orc_g2p_ex(c, N, dt, gv, gq, x, v, C, L);
-    orc_constitutive(c, N, dt, L, F, J, S);
+    orc_constitutive(c, N, dt, L, F, J, S, eps);
 
     free(key); free(perm); free(itmp); free(tmp); free(L); free(gm); free(gp); free(gv); free(gq);
     return 0;

@@ -81,10 +81,10 @@ double orc_cone_alpha(const orc_config* c);
 int orc_hencky_return(const orc_config* c, int elastic_only, const orc_real Ftr[9],
                       orc_real Fe[9], orc_real tau[9], orc_real* dgamma);
 void orc_constitutive(const orc_config* c, int64_t N, double dt, const orc_real* L,
-                      orc_real* F, orc_real* J, orc_real* S);
+                      orc_real* F, orc_real* J, orc_real* S, orc_real* eps);
 int orc_step(const orc_config* c, int64_t N, double dt, const orc_real* floor_mu,
              orc_real* x, orc_real* v, orc_real* C, orc_real* F, orc_real* J, orc_real* S,
              int32_t* pid, int32_t* perm_out, int32_t* key_out,
-             orc_real* grid_m_out, orc_real* grid_v_out);
+             orc_real* grid_m_out, orc_real* grid_v_out, orc_real* eps);
 
 #endif
