@@ -108,7 +108,14 @@ enum {
     MPM_FIELD_J = 5,      /* volume ratio J = rho0/rho, 1 comp (fluid, DP_JAUMANN) */
     MPM_FIELD_JM1 = 6,    /* J - 1, 1 comp (fluid, DP_JAUMANN); stored form, exact */
     MPM_FIELD_STRESS = 7, /* V0 * Kirchhoff stress = V_p sigma_p, dim*dim */
-    MPM_FIELD_PID = 8     /* original particle index, int32 */
+    MPM_FIELD_PID = 8,    /* original particle index, int32 */
+    MPM_FIELD_EPS_EQ = 9  /* equivalent plastic strain accumulated by mpm_step, 1 comp
+                           * (needs track_eps_eq): DP_JAUMANN App. A's increment
+                           * (zone II: dl sqrt(1/3 + 2/9 q_psi^2); zone III:
+                           * sqrt(2)/3 (sigma_m - sigma^t)/K), DP_HENCKY the von Mises
+                           * equivalent sqrt(2/3)|dE_p| of the plastic log-strain
+                           * increment (|dE_p| = the return's dgamma); 0 for the other
+                           * materials.  Starts at 0 at mpm_init_particles. */
 };
 enum { MPM_ORDER_MEMORY = 0, MPM_ORDER_PID = 1 };
 
@@ -148,7 +155,11 @@ typedef struct mpm_config {
      * segments and MPM_MAX_TAPE_SEGMENTS; each costs ckpt_every + 1 states
      * and ckpt_every grid records of workspace) */
     int32_t tape_segments;
-    int32_t reserved;      /* 0 */
+    /* 1: carry the equivalent plastic strain (MPM_FIELD_EPS_EQ) through
+     * mpm_step: two more scalars per particle of workspace, and G2P reads and
+     * writes one more per step (plastic materials); mpm_forward_loss then
+     * returns EINVAL.  0: not carried. */
+    int32_t track_eps_eq;
 } mpm_config;
 
 typedef struct mpm_ctx mpm_ctx;
@@ -256,7 +267,9 @@ int mpm_set_observations(mpm_ctx* ctx, const mpm_obs* obs);
  * afterwards are those after n_steps, as after mpm_step(n_steps).  The
  * reverse sweep covers every material (the viscous fluid included), resting
  * obstacles and every transfer (FLIP's also through the grid velocity
- * before the update, which the tape then records). */
+ * before the update, which the tape then records).  EINVAL with
+ * track_eps_eq set (the equivalent plastic strain is a forward diagnostic,
+ * carried by mpm_step only). */
 int mpm_forward_loss(mpm_ctx* ctx, int32_t n_steps, double dt, double* host_loss);
 
 /* Gradient of the last mpm_forward_loss by the hand-written reverse sweep:

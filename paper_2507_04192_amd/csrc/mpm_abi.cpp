@@ -72,7 +72,7 @@ int check_config(const mpm_config* c, std::string& why)
     }
     if (c->n_obstacles < 0 || c->n_obstacles > MPM_MAX_OBSTACLES) { why = "n_obstacles must be in [0, 4]"; return MPM_EINVAL; }
     if (c->tape_segments < 0 || c->tape_segments > MPM_MAX_TAPE_SEGMENTS) { why = "tape_segments must be in [0, 64]"; return MPM_EINVAL; }
-    if (c->reserved != 0) { why = "reserved must be 0"; return MPM_EINVAL; }
+    if (c->track_eps_eq != 0 && c->track_eps_eq != 1) { why = "track_eps_eq must be 0 or 1"; return MPM_EINVAL; }
     for (int o = 0; o < c->n_obstacles; ++o)
         for (int a = 0; a < c->dim; ++a)
             if (!isfinite(c->obst_lo[o][a]) || !isfinite(c->obst_hi[o][a]) || !(c->obst_lo[o][a] < c->obst_hi[o][a])) {
@@ -135,7 +135,7 @@ Geo make_geo(const mpm_config& c)
 }
 
 struct Layout {
-    size_t st[2], pid[2], key, perm, tmp, tmpk, count, tile_off, tile_slot, active, part, meta, status;
+    size_t st[2], pid[2], eps[2], key, perm, tmp, tmpk, count, tile_off, tile_slot, active, part, meta, status;
     size_t part_grid, gv, gmass, gvo;
     size_t inv, loss, box_sum, box_cnt, box_coef;
     size_t ckpt, ckpt_pid, tape, tape_pid, adj[2], mid, gtape, amu;
@@ -167,6 +167,7 @@ Layout make_layout(const mpm_config& c, const Geo& g, int64_t cap, int tape_step
     size_t ucap = (size_t)(cap > 0 ? cap : 1);
     for (int b = 0; b < 2; ++b) L.st[b] = take((size_t)nsc_of(c) * ucap * elem);
     for (int b = 0; b < 2; ++b) L.pid[b] = take(ucap * 4);
+    for (int b = 0; b < 2; ++b) L.eps[b] = c.track_eps_eq ? take(ucap * elem) : 0;
     L.key = take(ucap * 4);
     L.perm = take(ucap * 4);
     L.tmp = take(ucap * 4);
@@ -331,6 +332,7 @@ int mpm_bind_workspace(mpm_ctx* c, void* dev_ptr, size_t bytes, int64_t n_partic
     for (int i = 0; i < 2; ++i) {
         c->st[i] = b + L.st[i];
         c->pid[i] = (int32_t*)(b + L.pid[i]);
+        c->eps[i] = c->cfg.track_eps_eq ? b + L.eps[i] : nullptr;
     }
     c->key = (int32_t*)(b + L.key);
     c->perm = (int32_t*)(b + L.perm);
@@ -525,6 +527,7 @@ int mpm_forward_loss(mpm_ctx* c, int32_t n_steps, double dt, double* host_loss)
     int rc = need_particles(c);
     if (rc) return rc;
     if (!host_loss) return set_err(c, MPM_EINVAL, "host_loss is NULL");
+    if (c->cfg.track_eps_eq) return set_err(c, MPM_EINVAL, "track_eps_eq applies to mpm_step only");
     if (!c->ckpt) return set_err(c, MPM_ENOMEM, "no tape: bind the workspace with tape_steps > 0");
     if (n_steps < 1 || n_steps > c->tape_steps) return set_err(c, MPM_EINVAL, "n_steps must be in [1, tape_steps]");
     if (c->N < 1) return set_err(c, MPM_EINVAL, "a rollout needs at least one particle");

@@ -302,8 +302,12 @@ __device__ __forceinline__ void vfluid_update(const Phys<T>& P, const T L[D][D],
 //           sigma_m' = sigma_m - K q_psi dl, tau' = k_phi - q_phi sigma_m', s
 //           scaled to tau'; a return beyond the cutoff ends at (sigma^t, tau^P)
 //   zone III (f^t >= 0, h <= 0): sigma_m' = sigma^t, s kept
+// de (optional) receives App. A's equivalent plastic strain increment:
+// zone II dl sqrt(1/3 + 2/9 q_psi^2), zone III sqrt(2)/3 (sigma_m -
+// sigma^t)/K, zone I 0.
 template <class T, int D>
-__device__ __forceinline__ void jaumann_update(const Phys<T>& P, const T L[D][D], T& dJ, T S[D * (D + 1) / 2])
+__device__ __forceinline__ void jaumann_update(const Phys<T>& P, const T L[D][D], T& dJ, T S[D * (D + 1) / 2],
+                                               T* de = nullptr)
 {
     constexpr int NS = D * (D + 1) / 2;
     const T Jo = T(1) + dJ;
@@ -361,8 +365,10 @@ __device__ __forceinline__ void jaumann_update(const Phys<T>& P, const T L[D][D]
     else if (ft < T(0)) zone = fs <= T(0) ? 1 : 2;
     else zone = hh > T(0) ? 2 : 3;
     T sm_n = sm, scale = T(1);
+    if (de) *de = T(0);
     if (zone == 2) {
         const T dl = fs / (P.mu + P.jK * P.jq_phi * P.jq_psi);
+        if (de) *de = dl * sqrt(T(1) / T(3) + T(2) / T(9) * P.jq_psi * P.jq_psi);
         sm_n = sm - P.jK * P.jq_psi * dl;
         T tau_n = P.jk_phi - P.jq_phi * sm_n;
         if (sm_n > P.jst) {
@@ -371,6 +377,7 @@ __device__ __forceinline__ void jaumann_update(const Phys<T>& P, const T L[D][D]
         }
         scale = tau > T(0) ? tau_n / tau : T(0);
     } else if (zone == 3) {
+        if (de) *de = sqrt(T(2)) / T(3) * (sm - P.jst) / P.jK;
         sm_n = P.jst;
     }
     const T back = P.vol0 * Jn;
@@ -388,7 +395,7 @@ __device__ __forceinline__ void jaumann_update(const Phys<T>& P, const T L[D][D]
 // F_e' = U diag(exp(H - eps)) U^T F_tr and tau = U diag(2 mu H + lam tr H) U^T.
 template <class T, int D>
 __device__ __forceinline__ bool hencky_eig(const Phys<T>& P, bool plastic, const T Gt[D][D], T G[D][D],
-                                       T S[D * (D + 1) / 2])
+                                       T S[D * (D + 1) / 2], T* dgam = nullptr)
 {
     bool conv = true;
     // b - I
@@ -432,11 +439,13 @@ __device__ __forceinline__ bool hencky_eig(const Phys<T>& P, bool plastic, const
     T en2 = T(0);
 #pragma unroll
     for (int i = 0; i < D; ++i) en2 += eps[i] * eps[i];
+    if (dgam) *dgam = T(0);
     if (!plastic || en2 <= eps_elastic2<T>()) {
 #pragma unroll
         for (int i = 0; i < D; ++i) H[i] = eps[i];
     } else if (tr > T(0)) {
         cas = 0;
+        if (dgam) *dgam = sqrt(en2);
 #pragma unroll
         for (int i = 0; i < D; ++i) H[i] = T(0);
     } else {
@@ -453,6 +462,7 @@ __device__ __forceinline__ bool hencky_eig(const Phys<T>& P, bool plastic, const
             for (int i = 0; i < D; ++i) H[i] = eps[i];
         } else {
             cas = 2;
+            if (dgam) *dgam = dg;
             T r = dg / dn;
 #pragma unroll
             for (int i = 0; i < D; ++i) H[i] = eps[i] - r * dev[i];
@@ -607,7 +617,7 @@ __device__ __forceinline__ Sym<T, D> expm1_sym(const Sym<T, D>& Y)
 // Returns false when they are not (the caller then takes hencky_eig).
 template <class T, int D>
 __device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, const T Gt[D][D], T G[D][D],
-                                              T S[D * (D + 1) / 2])
+                                              T S[D * (D + 1) / 2], T* dgam = nullptr)
 {
     constexpr int NS = D * (D + 1) / 2;
     Sym<T, D> X;   // b - I = Gt + Gt^T + Gt Gt^T
@@ -633,13 +643,17 @@ __device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, co
     T n = sqrt(Eh.norm2());
     int cas = 1;
     T r = T(0);   // H = E - r * Ehat (cone), 0 (apex), E (elastic)
+    T dgv = T(0);
     if (plastic && E.norm2() > eps_elastic2<T>()) {
-        if (trE > T(0)) cas = 0;
-        else {
+        if (trE > T(0)) {
+            cas = 0;
+            dgv = sqrt(E.norm2());
+        } else {
             T dg = n + P.cone_coef * trE;
             if (dg > T(0)) {
                 cas = 2;
                 r = dg / n;
+                dgv = dg;
             }
         }
     }
@@ -652,6 +666,7 @@ __device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, co
         for (int q = 0; q < NS; ++q) Y.a[q] = -r * Eh.a[q];
     }
     if (cas != 1 && !(Y.norm2() < lim2)) return false;
+    if (dgam) *dgam = dgv;
     // stress: tau = 2 mu H + lam tr(H) I
     T trH = (cas == 0) ? T(0) : trE;
 #pragma unroll
@@ -684,7 +699,7 @@ __device__ __forceinline__ bool hencky_series(const Phys<T>& P, bool plastic, co
 // converge within its sweep budget (the caller latches it).
 template <class T, int D>
 __device__ __forceinline__ bool hencky_update(const Phys<T>& P, bool plastic, const T L[D][D],
-                                              T G[D][D], T S[D * (D + 1) / 2])
+                                              T G[D][D], T S[D * (D + 1) / 2], T* dgam = nullptr)
 {
     T dt = P.dt;
     T Gt[D][D];
@@ -697,8 +712,8 @@ __device__ __forceinline__ bool hencky_update(const Phys<T>& P, bool plastic, co
             for (int k = 0; k < D; ++k) lg += L[i][k] * G[k][j];
             Gt[i][j] = G[i][j] + dt * lg;
         }
-    if (hencky_series<T, D>(P, plastic, Gt, G, S)) return true;
-    return hencky_eig<T, D>(P, plastic, Gt, G, S);
+    if (hencky_series<T, D>(P, plastic, Gt, G, S, dgam)) return true;
+    return hencky_eig<T, D>(P, plastic, Gt, G, S, dgam);
 }
 
 // ---------------------------------------------------------------------------

@@ -859,7 +859,8 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                                                 PView<T> cur, PView<T> nxt, const T* __restrict__ gv,
                                                 const T* __restrict__ gvo,
                                                 int* __restrict__ key_out, int* __restrict__ count,
-                                                int* __restrict__ status)
+                                                int* __restrict__ status, const T* __restrict__ eps_in,
+                                                T* __restrict__ eps_out)
 {
     constexpr int TE = TileShape<D>::TE, BE = TileShape<D>::BE, NB = TileShape<D>::NB;
     constexpr int NS = D * (D + 1) / 2;
@@ -1022,7 +1023,12 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
 #pragma unroll
                         for (int q = 0; q < NS; ++q) Sv[q] = cur.S[q * cap + j];
                     if constexpr (MAT == MAT_VFLUID) vfluid_update<T, D>(P, Lm, dJ, Sv);
-                    else jaumann_update<T, D>(P, Lm, dJ, Sv);
+                    else {
+                        // equivalent plastic strain (when carried): App. A's increment
+                        T de;
+                        jaumann_update<T, D>(P, Lm, dJ, Sv, &de);
+                        if (eps_out) eps_out[s] = ld_once(&eps_in[j]) + de;
+                    }
                     bad |= !finite(dJ);
                     st_late(dJ, &nxt.G[s]);
 #pragma unroll
@@ -1036,7 +1042,10 @@ __global__ __launch_bounds__(kG2PBlock<T>) void k_g2p(Geo g, Phys<T> P, const in
                     for (int a = 0; a < D; ++a)
 #pragma unroll
                         for (int b = 0; b < D; ++b) Gm[a][b] = ld_once(&cur.G[(a * D + b) * cap + j]);
-                    noconv = !hencky_update<T, D>(P, MAT == MAT_SAND, Lm, Gm, Sv);
+                    T dgam;
+                    noconv = !hencky_update<T, D>(P, MAT == MAT_SAND, Lm, Gm, Sv, &dgam);
+                    // equivalent plastic strain (when carried): sqrt(2/3) |dE_p|
+                    if (MAT == MAT_SAND && eps_out) eps_out[s] = ld_once(&eps_in[j]) + T(0.816496580927726) * dgam;
 #pragma unroll
                     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -1311,6 +1320,8 @@ struct Solver {
         long long rest = (long long)(c->nsc - 2 * D) * cap;
         if (rest > 0) k_fill<T><<<std::min<long long>(nblocks(rest), 4096), kBlock, 0, st>>>(s.C, rest, T(0));
         if (N > 0) k_iota<0><<<nblocks(N), kBlock, 0, st>>>(s.pid, N);
+        for (int i = 0; i < 2; ++i)
+            if (c->eps[i]) k_fill<T><<<std::min<long long>(nblocks(cap), 4096), kBlock, 0, st>>>((T*)c->eps[i], cap, T(0));
         return recompute_keys(c);
     }
 
@@ -1351,6 +1362,8 @@ struct Solver {
         T* gmass;
         T* gvt;
         T* gvo;     // FLIP: nodal velocity before the update
+        const T* eps_in = nullptr;   // equivalent plastic strain, when carried
+        T* eps_out = nullptr;
     };
     static StepBufs ctx_bufs(mpm_ctx* c)
     {
@@ -1388,7 +1401,7 @@ struct Solver {
                                                   b.gv, b.gmass, b.gvt, b.gvo);
         prof_mark(c, MPM_PROF_GRID);
         k_g2p<T, D, MAT, XF><<<kTileWGs * kBlock / kG2PBlock<T>, kG2PBlock<T>, 0, st>>>(g, P, b.meta, b.active, b.perm, cur, nxt, (const T*)b.gv,
-                                                      (const T*)b.gvo, c->key, c->count, c->status);
+                                                      (const T*)b.gvo, c->key, c->count, c->status, b.eps_in, b.eps_out);
         prof_mark(c, MPM_PROF_G2P);
     }
 
@@ -1401,7 +1414,12 @@ struct Solver {
     template <int MAT, int XF>
     static void one_step(mpm_ctx* c, const Phys<T>& P)
     {
-        step_views<MAT, XF>(c, P, view<T>(c, c->cur), view<T>(c, 1 - c->cur));
+        StepBufs b = ctx_bufs(c);
+        if ((MAT == MAT_SAND || MAT == MAT_JAUMANN) && c->eps[0]) {
+            b.eps_in = (const T*)c->eps[c->cur];
+            b.eps_out = (T*)c->eps[1 - c->cur];
+        }
+        step_views<MAT, XF>(c, P, view<T>(c, c->cur), view<T>(c, 1 - c->cur), b);
         c->cur = 1 - c->cur;
     }
 
@@ -1455,6 +1473,9 @@ struct Solver {
             *ptr = s.G; *ncomp = 1; *conv = CONV_COPY; return MPM_OK;
         case MPM_FIELD_STRESS:
             *ptr = s.S; *ncomp = D * D; *conv = iso ? CONV_ISO : CONV_SYM; return MPM_OK;
+        case MPM_FIELD_EPS_EQ:
+            if (!c->eps[c->cur]) return set_err(c, MPM_EINVAL, "EPS_EQ needs track_eps_eq = 1");
+            *ptr = (T*)c->eps[c->cur]; *ncomp = 1; *conv = CONV_COPY; return MPM_OK;
         default: break;
         }
         return set_err(c, MPM_EINVAL, "field not available for this material");

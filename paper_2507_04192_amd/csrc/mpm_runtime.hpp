@@ -55,6 +55,7 @@ struct mpm_ctx {
 
     void* st[2] = {nullptr, nullptr};        // particle state buffers
     int32_t* pid[2] = {nullptr, nullptr};
+    void* eps[2] = {nullptr, nullptr};       // equivalent plastic strain (track_eps_eq), same slots as st
     int cur = 0;
     int32_t* key = nullptr;
     int32_t* perm = nullptr;

@@ -25,7 +25,7 @@ MATERIAL = {"fluid": 0, "sand": 1, "elastic": 2, "dp_jaumann": 3}
 TRANSFER = {"apic": 0, "pic": 1, "flip": 2, "tpic": 3}
 MAX_OBSTACLES = 4
 WALL = {"slip": 0, "stick": 1, "coulomb": 2}
-FIELD = {"x": 0, "v": 1, "C": 2, "F": 3, "FmI": 4, "J": 5, "Jm1": 6, "stress": 7, "pid": 8}
+FIELD = {"x": 0, "v": 1, "C": 2, "F": 3, "FmI": 4, "J": 5, "Jm1": 6, "stress": 7, "pid": 8, "eps_eq": 9}
 ORDER = {"memory": 0, "pid": 1}
 GRID = {"mass": 0, "vel": 1}
 
@@ -66,7 +66,7 @@ class MpmConfig(ct.Structure):
         ("flip_alpha", ct.c_double), ("viscosity", ct.c_double),
         ("psi_deg", ct.c_double), ("cohesion", ct.c_double), ("tension", ct.c_double),
         ("obst_lo", (ct.c_double * 3) * MAX_OBSTACLES), ("obst_hi", (ct.c_double * 3) * MAX_OBSTACLES),
-        ("tape_segments", ct.c_int32), ("reserved", ct.c_int32),
+        ("tape_segments", ct.c_int32), ("track_eps_eq", ct.c_int32),
     ]
 
 
@@ -136,11 +136,13 @@ _HEADER_NAMES = [
 PROF_CLASSES = ["scan", "bucket", "p2g", "grid", "g2p", "g2p_adj", "grid_adj", "p2g_adj"]
 
 
-def make_config(cfg, precision: str = "f64", keep_grid: bool = False, tape_segments: int = 0) -> MpmConfig:
+def make_config(cfg, precision: str = "f64", keep_grid: bool = False, tape_segments: int = 0,
+                track_eps_eq: bool = False) -> MpmConfig:
     """mpm_config from a workloads.SimConfig (tape_segments: trailing
     segments of a forward-plus-adjoint rollout kept on the tape)."""
     c = MpmConfig()
     c.tape_segments = int(tape_segments)
+    c.track_eps_eq = 1 if track_eps_eq else 0
     c.dim = cfg.dim
     c.precision = MPM_F64 if precision == "f64" else MPM_F32
     for a in range(3):
@@ -203,7 +205,7 @@ class Solver:
 
     def __init__(self, cfg, precision: str = "f64", capacity: Optional[int] = None,
                  tape_steps: int = 0, ckpt_every: int = 0, keep_grid: bool = False, stream=None,
-                 tape_segments: int = 0):
+                 tape_segments: int = 0, track_eps_eq: bool = False):
         import torch
         self.torch = torch
         self.cfg = cfg
@@ -212,7 +214,7 @@ class Solver:
         self.np_dtype = np.float64 if precision == "f64" else np.float32
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self._c = make_config(cfg, precision, keep_grid, tape_segments)
+        self._c = make_config(cfg, precision, keep_grid, tape_segments, track_eps_eq)
         self.L = lib()
         ctx = ct.c_void_p()
         rc = self.L.mpm_create(ct.byref(self._c), ct.c_void_p(self.stream.cuda_stream), ct.byref(ctx))
@@ -280,7 +282,7 @@ class Solver:
         N = self.num_particles()
         d = self.cfg.dim
         ncomp = {"x": d, "v": d, "C": d * d, "F": d * d, "FmI": d * d, "J": 1, "Jm1": 1,
-                 "stress": d * d, "pid": 1}[field]
+                 "stress": d * d, "pid": 1, "eps_eq": 1}[field]
         dt = torch.int32 if field == "pid" else self.dtype
         out = torch.empty((ncomp, N), dtype=dt, device=self.device)
         _check(self.ctx, self.L.mpm_read_state(self.ctx, FIELD[field], ORDER[order], _ptr(out)))

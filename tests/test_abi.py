@@ -163,3 +163,25 @@ def test_max_tape_segments_within_budget():
     assert native.max_tape_segments(cfg, "f64", 8192, 100, 10, 1) == 1
     assert native.max_tape_segments(cfg, "f64", 8192, 100, 10, ws(4)) == 4
     assert native.max_tape_segments(cfg, "f64", 8192, 100, 10, ws(5) - 1) == 4
+
+
+def test_track_eps_eq_workspace_without_gpu():
+    """Carrying the equivalent plastic strain adds two scalars per particle
+    of workspace; any value other than 0 or 1 is refused."""
+    from paper_2507_04192_amd import native
+    from paper_2507_04192_amd import workloads as W
+    cfg, _ = W.cylinder_collapse_3d(scale_div=8)
+    L = native.lib()
+    nb = ct.c_size_t()
+    sizes = {}
+    for prec, elem in (("f32", 4), ("f64", 8)):
+        for t in (0, 1):
+            c = native.make_config(cfg, prec, track_eps_eq=t)
+            assert L.mpm_workspace_bytes(ct.byref(c), 100000, 0, 0, ct.byref(nb)) == 0
+            sizes[prec, t] = nb.value
+        extra = sizes[prec, 1] - sizes[prec, 0]
+        assert 2 * 100000 * elem <= extra <= 2 * 100000 * elem + 512
+    c = native.make_config(cfg, "f32")
+    c.track_eps_eq = 2
+    assert L.mpm_workspace_bytes(ct.byref(c), 100, 0, 0, ct.byref(nb)) == native.MPM_EINVAL
+    assert b"track_eps_eq" in L.mpm_last_error(None)

@@ -1,0 +1,128 @@
+"""The equivalent plastic strain (MPM_FIELD_EPS_EQ, carried with
+track_eps_eq) against the oracle's, through the C-ABI: Hencky sand (the
+von Mises equivalent of the plastic log-strain increment, a reading) and
+the hypoelastic material of App. A (its own increment), from sheared,
+rotating and diverging starts that yield within the 10 steps.  Bounds as
+for the other non-kinematic fields: relative L2 <= 1e-8 (binary64) and
+<= 5e-3 (binary32 against binary64 on the same rounded inputs).  Carrying
+it changes nothing else, bit for bit."""
+import numpy as np
+import pytest
+
+from paper_2507_04192_amd import workloads as W
+from tests.helpers import oracle_state, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOLF = {"f64": 1e-8, "f32": 5e-3}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _moving(cfg, x, frac=0.02, div=1.0):
+    a = frac * cfg.dx / cfg.dt
+    L = cfg.n[0] * cfg.dx
+    v = np.empty_like(x)
+    v[0] = a * (0.8 + 0.4 * np.sin(2 * np.pi * x[1] / L) + div * np.sin(4 * np.pi * x[0] / L))
+    v[1] = a * 0.5 * np.cos(2 * np.pi * x[0] / L)
+    if x.shape[0] == 3:
+        v[2] = a * 0.3 * np.sin(2 * np.pi * (x[0] + x[1]) / L)
+    return v
+
+
+def _case(name):
+    if name == "sand3d":
+        cfg, x = W.cylinder_collapse_3d(scale_div=8, seed=0)
+    elif name == "sand2d":
+        cfg, x, _, _ = W.granular_block_2d(seed=0)
+    else:
+        cfg, x, _, _ = W.granular_block_2d(seed=0)
+        cfg = cfg.replace(material=W.DP_JAUMANN, psi_deg=5.0)
+    return cfg, x
+
+
+def _solver(cfg, precision, x, v, track):
+    from paper_2507_04192_amd.native import Solver
+    s = Solver(cfg, precision, capacity=x.shape[1], track_eps_eq=track)
+    s.mpm_init_particles(x, v)
+    return s
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["sand3d", "sand2d", "jaumann2d"])
+def test_plastic_strain_matches_oracle(orc, precision, name):
+    cfg, x = _case(name)
+    v = _moving(cfg, x)
+    if precision == "f32":
+        x, v = (a.astype(np.float32).astype(np.float64) for a in (x, v))
+    print(f"[case] equivalent plastic strain, {name} {precision} N={x.shape[1]}", flush=True)
+    st = oracle_state(orc, cfg, x, v=v)
+    orc.Oracle(cfg).run(st, 10, cfg.dt)
+    ref = st.by_pid("eps")
+    assert (ref > 0).mean() > 0.1                   # the start yields
+    s = _solver(cfg, precision, x, v, True)
+    s.mpm_step(10)
+    rc, bad = s.mpm_sync_status()
+    assert rc == 0, (rc, bad)
+    got = s.mpm_read_state("eps_eq", "pid").cpu().numpy()[0].astype(np.float64)
+    mem = s.mpm_read_state("eps_eq", "memory").cpu().numpy()[0]
+    pid = s.mpm_read_state("pid", "memory").cpu().numpy()[0]
+    s.close()
+    e = rel_l2(got, ref)
+    print(f"  rel L2 eps_eq={e:.3e}, yielded {(ref > 0).mean():.1%}, max {ref.max():.3e}", flush=True)
+    assert e <= TOLF[precision]
+    assert (got >= 0).all()
+    assert np.array_equal(mem, got[pid].astype(mem.dtype))   # memory order is pid order permuted
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_carrying_it_changes_nothing_else(precision):
+    """The same 10 steps with and without the field: every other field and
+    the sort bit for bit equal."""
+    cfg, x = _case("sand3d")
+    v = _moving(cfg, x)
+    out = []
+    for track in (False, True):
+        s = _solver(cfg, precision, x, v, track)
+        s.mpm_step(10)
+        assert s.mpm_sync_status()[0] == 0
+        out.append({f: s.mpm_read_state(f, "memory").cpu().numpy() for f in ("x", "v", "C", "FmI", "stress", "pid")})
+        out[-1]["perm"], out[-1]["key"] = (t.cpu().numpy() for t in s.mpm_read_sort())
+        s.close()
+    for f in out[0]:
+        assert np.array_equal(out[0][f], out[1][f]), f
+
+
+def test_field_rules():
+    """Without track_eps_eq the field is refused; with it a fluid's stays
+    zero, it can be written and read back in pid order, and a forward-plus-
+    adjoint rollout is refused."""
+    from paper_2507_04192_amd.native import MPMError, Solver
+    cfg, x = _case("sand2d")
+    s = _solver(cfg, "f64", x, None, False)
+    with pytest.raises(MPMError):
+        s.mpm_read_state("eps_eq")
+    s.close()
+    fcfg, fx = W.dam_break_2d()
+    s = _solver(fcfg, "f64", fx, None, True)
+    s.mpm_step(20)
+    assert s.mpm_sync_status()[0] == 0
+    assert not s.mpm_read_state("eps_eq", "pid").cpu().numpy().any()
+    s.close()
+    s = _solver(cfg, "f64", x, None, True)
+    val = np.linspace(0.0, 1.0, x.shape[1]).reshape(1, -1)
+    s.mpm_write_state("eps_eq", val, "pid")
+    assert np.array_equal(s.mpm_read_state("eps_eq", "pid").cpu().numpy(), val)
+    s.close()
+    t = Solver(cfg, "f64", capacity=x.shape[1], tape_steps=10, ckpt_every=5, track_eps_eq=True)
+    t.mpm_init_particles(x)
+    t.mpm_set_observations(frames=[10], tracer_pid=np.arange(4), lag_field="x",
+                           lag_target=np.zeros((1, 2, 4)))
+    with pytest.raises(MPMError):
+        t.mpm_forward_loss(10)
+    t.close()
