@@ -2,7 +2,8 @@
 track_eps_eq) against the oracle's, through the C-ABI: Hencky sand (the
 von Mises equivalent of the plastic log-strain increment, a reading) and
 the hypoelastic material of App. A (its own increment), from sheared,
-rotating and diverging starts that yield within the 10 steps.  Bounds as
+rotating and diverging starts that yield within the 10 steps, with the APIC,
+FLIP/PIC-blend and TPIC transfers.  Bounds as
 for the other non-kinematic fields: relative L2 <= 1e-8 (binary64) and
 <= 5e-3 (binary32 against binary64 on the same rounded inputs).  Carrying
 it changes nothing else, bit for bit."""
@@ -40,6 +41,12 @@ def _case(name):
         cfg, x = W.cylinder_collapse_3d(scale_div=8, seed=0)
     elif name == "sand2d":
         cfg, x, _, _ = W.granular_block_2d(seed=0)
+    elif name == "sand2d_flip":
+        cfg, x, _, _ = W.granular_block_2d(seed=0)
+        cfg = cfg.replace(transfer=W.FLIP, flip_alpha=0.95)
+    elif name == "jaumann3d_tpic":
+        cfg, x = W.cylinder_collapse_3d(scale_div=8, seed=0)
+        cfg = cfg.replace(material=W.DP_JAUMANN, psi_deg=5.0, transfer=W.TPIC)
     else:
         cfg, x, _, _ = W.granular_block_2d(seed=0)
         cfg = cfg.replace(material=W.DP_JAUMANN, psi_deg=5.0)
@@ -54,7 +61,7 @@ def _solver(cfg, precision, x, v, track):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("name", ["sand3d", "sand2d", "jaumann2d"])
+@pytest.mark.parametrize("name", ["sand3d", "sand2d", "jaumann2d", "sand2d_flip", "jaumann3d_tpic"])
 def test_plastic_strain_matches_oracle(orc, precision, name):
     cfg, x = _case(name)
     v = _moving(cfg, x)
