@@ -312,9 +312,10 @@ VARIANT_STATE_SCALARS = {"sand_apic": 24, "sand_tpic": 24, "sand_pic": 15, "sand
 FORM_OF = {"paper_cylinder": "dp_jaumann", "paper_column": "dp_jaumann"}
 
 
-def run_variants(steps, steps64, warmup):
+def run_variants(steps, steps64, warmup, only=""):
     """Forward throughput of the other forms of the step, each at full size in
-    the bench's launch configuration."""
+    the bench's launch configuration (only: run just the legs whose form
+    name contains it, e.g. "paper_" for the paper's two timing cases)."""
     from paper_2507_04192_amd import workloads as W
     cyl, xc = W.cylinder_collapse_3d(seed=0)
     col, xd = W.dam_break_columns_3d(seed=0)
@@ -339,6 +340,8 @@ def run_variants(steps, steps64, warmup):
              "paper_column": (2408448, 16.2, 69.3)}
     out = []
     for name, form, cfg, x, precs in legs:
+        if only and only not in form:
+            continue
         n = x.shape[1]
         r = {"workload": name, "particles": n, "grid": list(cfg.n)}
         for prec in precs:
@@ -541,6 +544,7 @@ def main():
                          "(trailing segments kept on the tape instead of recomputed)")
     ap.add_argument("--no-variants", action="store_true", help="skip the other forms of the step")
     ap.add_argument("--variant-steps", type=int, default=500, help="binary32 steps per variant (binary64: half)")
+    ap.add_argument("--variant-filter", default="", help="run only the variants whose form name contains this")
     ap.add_argument("--no-configs", action="store_true", help="skip the other benchmark configurations")
     ap.add_argument("--no-paper-inverse", action="store_true",
                     help="skip the paper's forward+gradient timing cases of its inverse problems")
@@ -625,7 +629,8 @@ def main():
 
     variants = None
     if not args.no_variants and args.scale_div == 1:
-        variants = run_variants(args.variant_steps, max(1, args.variant_steps // 2), args.warmup)
+        variants = run_variants(args.variant_steps, max(1, args.variant_steps // 2), args.warmup,
+                                args.variant_filter)
     configs = None
     if not args.no_configs and args.scale_div == 1:
         configs = run_other_configs(args.config_steps, args.warmup)
